@@ -1,0 +1,204 @@
+"""Benchmark of the batched VibeLSD decoder on one MI355X.
+
+Workload: the 6.6.6 colour code at d = 9 over 9 rounds of a fixed-CNOT-order
+X/Z syndrome-extraction circuit with uniform depolarising noise p = 1e-3,
+as a detector error model from synth/ (m = 540 detectors, n = 16782
+mechanisms, 70811 edges); L = 32 serial schedules, M = 5, T_max = 20,
+alpha = 0.625, LSD-0.  Synthetic, seeded syndromes stand in for the paper's
+circuits and data.
+
+One step = vibe_decode over one batch of B shots (all of BP ensemble,
+selection, LSD and observables), syndromes already resident in HBM.
+Prints one JSON line.  Extra legs: the plain per-shot-launch path (shots/s
+and per-shot latency), the oracle on a bounded sample of the host cores, and
+the dominant kernel's roofline from HIP events around its launches.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# algorithmic HBM bytes of one edge-update of the serial sweep: the previous
+# message of the edge is read (its sign) and the new one written, FP32 each
+BYTES_PER_EDGE_UPDATE = 8.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=1 << 17)
+    ap.add_argument("--plain-shots", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--seed", type=int, default=2025)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the decoder shards by shots with no exchange, "
+              "so a multi-GPU figure is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2508_15743_amd as P
+    from synth.dem import circuit_dem
+    from synth.sample import permutations, sample
+
+    dev = torch.device("cuda:0")
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 3 copies of 1 GiB")
+        return
+
+    d, rounds, p = 9, 9, 1e-3
+    L, M, T, alpha = 32, 5, 20, 0.625
+    t0 = time.time()
+    dem = circuit_dem(d, rounds, p)
+    perms = permutations(dem.n, L, args.seed)
+    batch = sample(dem, args.batch, args.seed + 1)
+    log(f"workload {dem.name}: m={dem.m} n={dem.n} nnz={dem.nnz}; sampled {args.batch} shots "
+        f"in {time.time() - t0:.1f}s")
+    G = P.Graph.from_dem(dem, perms, L=L, M=M, T_max=T, alpha=alpha)
+    info = G.info()
+    synd = torch.from_numpy(batch.syndromes).to(dev)
+    B = synd.shape[0]
+    words = (dem.n + 63) // 64
+    corr = torch.empty((B, words), dtype=torch.int64, device=dev)
+    obs = torch.empty((B, 1), dtype=torch.uint8, device=dev)
+    st = torch.empty((B, 8), dtype=torch.int32, device=dev)
+    out = (corr, obs, st)
+
+    for i in range(args.warmup):
+        G.decode(synd, out=out)
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+
+    P.vibe_profile_enable(G.handle, True)
+    P.vibe_profile_read(G.handle)  # clear
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    member_iters = 0
+    for i in range(args.steps):
+        G.decode(synd, out=out)
+        torch.cuda.synchronize()
+        member_iters += int(st[:, 7].sum().item())
+        log(f"step {i + 1}/{args.steps} done at {time.perf_counter() - t_start:.2f}s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = P.vibe_profile_read(G.handle)
+    P.vibe_profile_enable(G.handle, False)
+    shots_per_s = B * args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    stats = st.cpu().numpy()
+    flags = stats[:, 0]
+    lsd_frac = float(((flags & 2) != 0).mean())
+    ler = float((obs.cpu().numpy() != batch.observables).any(1).mean())
+
+    # dominant kernel: the BP ensemble; algorithmic bytes = edge-updates x 8 B
+    bp_ms, bp_launches = prof["bp_ensemble"]
+    edge_updates = member_iters * dem.nnz
+    bp_s = bp_ms / 1e3
+    achieved = BYTES_PER_EDGE_UPDATE * edge_updates / bp_s / 1e9 if bp_s > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "bp_ensemble_kernel",
+                "avg_launch_ms": round(bp_ms / max(bp_launches, 1), 3),
+                "edge_updates_per_s": edge_updates / bp_s if bp_s > 0 else 0.0,
+                "kernel_ms": {k: round(v[0], 2) for k, v in prof.items()}}
+
+    result = {
+        "metric": "decoded shots/s at d=9 circuit-level p=1e-3, batched vs plain; p99 latency",
+        "value": round(shots_per_s, 1),
+        "unit": "shots/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded colour-code circuit-level DEM samples)",
+        "config": {"workload": f"colour666_d{d}_r{rounds}_circuit_uniform_p{p:g}", "batch": B,
+                   "m": dem.m, "n": dem.n, "nnz": dem.nnz, "L": L, "M": M, "T_max": T,
+                   "alpha": alpha, "lsd_order": 0, "levels": [info["levels_min"], info["levels_max"]]},
+        "roofline": roofline,
+        "lsd_fraction": round(lsd_frac, 5),
+        "logical_error_rate": ler,
+        "mean_member_iterations_per_shot": member_iters / (B * args.steps),
+    }
+
+    if not args.no_plain:
+        n_plain = min(args.plain_shots, B)
+        sp = synd[:n_plain]
+        outp = (torch.empty((n_plain, words), dtype=torch.int64, device=dev),
+                torch.empty((n_plain, 1), dtype=torch.uint8, device=dev),
+                torch.empty((n_plain, 8), dtype=torch.int32, device=dev))
+        G.decode(sp[:4], plain=True)
+        torch.cuda.synchronize()
+        lat = []
+        for i in range(n_plain):
+            t1 = time.perf_counter()
+            G.decode(sp[i:i + 1], plain=True,
+                     out=(outp[0][i:i + 1], outp[1][i:i + 1], outp[2][i:i + 1]))
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t1)
+        lat = np.array(lat)
+        plain_rate = n_plain / lat.sum()
+        same = bool(torch.equal(outp[0], corr[:n_plain]))
+        result["plain"] = {"value": round(plain_rate, 1), "unit": "shots/s", "shots": n_plain,
+                           "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+                           "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+                           "identical_to_batched": same}
+        result["batched_over_plain"] = round(shots_per_s / plain_rate, 1)
+        result["p99_latency_ms"] = result["plain"]["p99_ms"]
+        log(f"plain: {plain_rate:.1f} shots/s over {n_plain} shots")
+
+    if not args.no_cpu:
+        from oracle import oracle as O
+
+        g = O.OracleGraph(dem)
+        threads = min(16, os.cpu_count() or 1)
+        done = 0
+        t1 = time.perf_counter()
+        chunk = threads * 2
+        while time.perf_counter() - t1 < args.cpu_seconds and done + chunk <= B:
+            O.decode(g, perms, batch.syndromes[done:done + chunk], L=L, M=M, T=T, alpha=alpha,
+                     threads=threads)
+            done += chunk
+        dt = time.perf_counter() - t1
+        result["cpu_baseline"] = {"value": round(done / dt, 3), "unit": "shots/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": f"first {done} shots of the batch, {dt:.1f}s, "
+                                            f"{threads} threads, FP64 oracle"}
+        log(f"cpu oracle: {done / dt:.2f} shots/s on {threads} threads")
+
+    print(json.dumps(result), flush=True)
+    G.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * vibelsd.h -- C ABI of the MI355X (gfx950) VibeLSD decoder.
+ *
+ * VibeLSD (arXiv 2508.15743): every syndrome is decoded by an ensemble of L
+ * min-sum belief-propagation decoders, each with its own serial-V schedule
+ * (a fixed permutation of the columns, Sec. III.D.1 and Appendix A,
+ * Algorithm 1).  Once M members have converged the rest are not needed; the
+ * converged candidate of least prior weight is taken (Sec. III.D.2).  If no
+ * member converges, the members' normalised posteriors are averaged and
+ * localised statistics decoding (LSD-0, Sec. III.C) produces the correction.
+ *
+ * Conventions used by every entry point:
+ *   - H is given in CSR form: row c (a detector) lists the columns (error
+ *     mechanisms) it touches, strictly ascending.  Lobs (the k logical
+ *     observables) likewise.  All host arrays are read during the call only.
+ *   - Device pointers are caller-owned (for example allocated by PyTorch) and
+ *     must stay valid until the work queued on `stream` has finished.  The
+ *     library allocates its own device workspace, cached in the handle.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Decode calls
+ *     are asynchronous: argument errors are reported synchronously before
+ *     anything is queued, and nothing is written then; HIP launch errors are
+ *     reported as VIBE_EHIP.
+ *   - Calls on one handle must not overlap in time (they share its
+ *     workspace): queue them on one stream, or use one handle per stream.
+ *   - Every function returns VIBE_OK (0) or a negative status; the message
+ *     of the last error on the calling thread is vibe_last_error().
+ *   - Bit-packed vectors: bit j of a vector lives in word j / 64 at bit
+ *     position j % 64 (little-endian uint64 words); a shot's vector occupies
+ *     ceil(len / 64) words.
+ */
+#ifndef VIBELSD_H
+#define VIBELSD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VIBE_OK 0
+#define VIBE_EINVAL (-1)       /* bad argument; nothing was written */
+#define VIBE_ENOMEM (-2)       /* a device or host allocation failed */
+#define VIBE_EHIP (-3)         /* a HIP runtime call or launch failed */
+#define VIBE_EUNSUPPORTED (-4) /* the graph exceeds a supported size limit */
+
+/* per-shot flags */
+#define VIBE_FLAG_BP_CONVERGED 1u /* the correction is a converged member's */
+#define VIBE_FLAG_LSD_USED 2u     /* no member converged; LSD produced it */
+#define VIBE_FLAG_LSD_FAILED 4u   /* some cluster could not be made valid */
+
+typedef struct vibe_graph vibe_graph;
+
+typedef struct vibe_config {
+    uint32_t L;         /* ensemble size, 1..64 (Sec. III.D.1 step 1) */
+    uint32_t M;         /* correction limit, 1..L (step 2) */
+    uint32_t T_max;     /* iteration limit of every member, 1..64 */
+    uint32_t lsd_order; /* 0 = LSD-0 (the only order implemented) */
+    double alpha;       /* min-sum scaling factor applied to every check message */
+    double clamp;       /* bound on |messages|, |posteriors| and |lambda|; also
+                           the magnitude sent by a check with no other
+                           neighbour.  1e6 (exact in FP32) is the default. */
+} vibe_config;
+
+typedef struct vibe_shot_stats {
+    uint32_t flags;        /* VIBE_FLAG_* */
+    int32_t winner;        /* member whose correction was taken, -1 if LSD ran */
+    uint32_t t_win;        /* that member's convergence iteration, 0 if LSD ran */
+    uint32_t n_conv;       /* members seen converged before the shot finished */
+    uint32_t lsd_clusters; /* final LSD clusters (0 if LSD did not run) */
+    uint32_t lsd_largest;  /* columns in the largest final cluster */
+    uint32_t lsd_rounds;   /* LSD growth rounds */
+    uint32_t member_iters; /* BP iterations run, summed over members */
+} vibe_shot_stats;
+
+typedef struct vibe_graph_info {
+    uint32_t m, n, k, L, M, T_max;
+    uint64_t nnz;          /* edges of the Tanner graph */
+    uint32_t max_row_degree, max_col_degree;
+    uint32_t levels_min, levels_max; /* dependency levels per member schedule */
+    uint64_t device_bytes; /* graph + schedules resident on the device */
+} vibe_graph_info_t;
+
+/*
+ * Offline stage (Sec. III.D.1): validate the detector error model, compute the
+ * channel LLRs lambda_v = ln((1 - p_v) / p_v) (clamped to +-cfg->clamp),
+ * build the CSR/CSC copies and, for every member i, the dependency levels of
+ * its serial schedule perms[i*n .. i*n+n-1] (a permutation of 0..n-1; the
+ * paper draws them uniformly at random), then upload everything to the
+ * current HIP device, where it stays until vibe_graph_destroy.
+ *
+ *   m, n            detectors (rows) and error mechanisms (columns), n >= 1
+ *   h_indptr        m + 1 entries, h_indptr[0] = 0, non-decreasing
+ *   h_indices       h_indptr[m] column indices, < n, strictly ascending per row
+ *   priors          n probabilities, each strictly between 0 and 1
+ *   k, l_indptr, l_indices   the observable matrix in the same CSR form
+ *   perms           L x n uint32 permutations (host)
+ *   cfg             decoder settings (copied)
+ *   out             receives the handle
+ * Limits (VIBE_EUNSUPPORTED beyond them): m < 65536, n < 2^24, every column
+ * in at most 15 checks, every row shorter than 65536, nnz < 2^31.
+ */
+int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indptr, const uint32_t* h_indices,
+                      const double* priors, uint32_t k, const uint32_t* l_indptr,
+                      const uint32_t* l_indices, const uint32_t* perms, const vibe_config* cfg,
+                      vibe_graph** out);
+
+/* Frees the handle, its device copies and its workspace (synchronises the
+   device first).  NULL is accepted. */
+void vibe_graph_destroy(vibe_graph* g);
+
+/* Sizes and footprint of a graph. */
+int vibe_graph_info(const vibe_graph* g, vibe_graph_info_t* info);
+
+/*
+ * Online stage, batched (Sec. III.D.2): decode B syndromes in one launch
+ * sequence on `stream`.
+ *   syndromes    device, B x m uint8 (0/1), row-major
+ *   corrections  device, B x ceil(n/64) uint64 words: the bit-packed e-hat,
+ *                which always satisfies H e-hat = s for converged shots and
+ *                for LSD shots without VIBE_FLAG_LSD_FAILED
+ *   observables  device, B x k uint8: Lobs * e-hat mod 2
+ *   stats        device, B records, or NULL
+ * B = 0 is accepted and does nothing.
+ */
+int vibe_decode(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint64_t* corrections,
+                uint8_t* observables, vibe_shot_stats* stats, void* stream);
+
+/*
+ * The same decoder with one launch sequence per shot: every shot is decoded
+ * on its own (ensemble, selection, LSD if needed, observables) before the
+ * next one starts.  Same arguments, same results as vibe_decode; this is the
+ * per-shot-launch baseline the batched form is measured against.
+ */
+int vibe_decode_plain(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint64_t* corrections,
+                      uint8_t* observables, vibe_shot_stats* stats, void* stream);
+
+/*
+ * The BP ensemble alone (Algorithm 1, serial-V, every member), for B shots,
+ * without the correction limit: every member runs until its own hard
+ * decision satisfies the syndrome (if stop_on_converge) or for exactly
+ * T_run iterations (1 <= T_run <= 64).
+ *   t_conv       device, B x L int32: iteration at which the member's decision
+ *                first satisfied the syndrome, 0 if it never did
+ *   posteriors   device, B x L x n float, or NULL: L_v after the member's
+ *                last iteration
+ *   ehat         device, B x L x ceil(n/64) uint64, or NULL: the member's
+ *                decision after its last iteration
+ */
+int vibe_bp_ensemble(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint32_t T_run,
+                     int stop_on_converge, int32_t* t_conv, float* posteriors, uint64_t* ehat,
+                     void* stream);
+
+/*
+ * LSD-0 alone (Sec. III.C) on caller-given soft information.
+ *   soft         device, B x n float: lower = more likely flipped; columns are
+ *                ranked by (soft, index) ascending
+ *   corrections  device, B x ceil(n/64) uint64 (bit-packed e-hat)
+ *   stats        device, B records or NULL (lsd_* fields and flags)
+ */
+int vibe_lsd(vibe_graph* g, const uint8_t* syndromes, const float* soft, uint64_t B,
+             uint64_t* corrections, vibe_shot_stats* stats, void* stream);
+
+/*
+ * Kernel timing, for measurement: while enabled, every launch of the BP
+ * ensemble kernel, of the selection kernel and of the LSD kernel made through
+ * this handle is bracketed by HIP events recorded on the launch stream.
+ * vibe_profile_read waits for those events and returns, per kernel, the
+ * summed duration in milliseconds and the number of launches, then clears
+ * the record.  Arrays are indexed 0 = BP ensemble, 1 = selection, 2 = LSD.
+ */
+int vibe_profile_enable(vibe_graph* g, int enable);
+int vibe_profile_read(vibe_graph* g, double* ms /*[3]*/, uint64_t* launches /*[3]*/);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* vibe_last_error(void);
+
+/* Library version string. */
+const char* vibe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VIBELSD_H */

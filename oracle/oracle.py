@@ -46,7 +46,7 @@ def _p(a, t):
 I32, U8, U32, F64 = C.c_int32, C.c_uint8, C.c_uint32, C.c_double
 
 
-def prior_llr(priors, lim: float = 1e30) -> np.ndarray:
+def prior_llr(priors, lim: float = 1e6) -> np.ndarray:
     """Channel LLR of each column: ln((1 - p) / p), clamped to +-lim."""
     p = np.asarray(priors, dtype=np.float64)
     if np.any(p <= 0) or np.any(p >= 1):
@@ -79,7 +79,7 @@ class OracleGraph:
                 _p(self.ci, I32), _p(self.ce, I32))
 
 
-def bp(g: OracleGraph, s, perm=None, T=20, alpha=0.625, lim=1e30, stop=True, trace=False,
+def bp(g: OracleGraph, s, perm=None, T=20, alpha=0.625, lim=1e6, stop=True, trace=False,
        lam=None):
     """One min-sum decoder (Algorithm 1).  perm=None -> parallel schedule."""
     L = lib()
@@ -124,7 +124,7 @@ def lsd(g: OracleGraph, s, q):
             "check_label": cl, "bit_label": bl}
 
 
-def decode(g: OracleGraph, perms, synd, L=32, M=5, T=20, alpha=0.625, lim=1e30,
+def decode(g: OracleGraph, perms, synd, L=32, M=5, T=20, alpha=0.625, lim=1e6,
            schedule="serial", threads=None, want_members=False, want_q=False):
     """The full VibeLSD decoder over a batch of syndromes [B, m]."""
     lb = lib()

@@ -1,0 +1,252 @@
+"""Python binding of libvibelsd (the MI355X VibeLSD decoder).
+
+Argument marshalling only: every step of the decode path runs in the HIP
+kernels of libvibelsd.so.  PyTorch provides device memory and the stream.
+The C entry points keep their names here (vibe_graph_create, vibe_decode,
+...); `Graph` wraps them for convenience.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvibelsd.so")
+
+VIBE_OK, VIBE_EINVAL, VIBE_ENOMEM, VIBE_EHIP, VIBE_EUNSUPPORTED = 0, -1, -2, -3, -4
+FLAG_BP_CONVERGED, FLAG_LSD_USED, FLAG_LSD_FAILED = 1, 2, 4
+STATS_FIELDS = ("flags", "winner", "t_win", "n_conv", "lsd_clusters", "lsd_largest",
+                "lsd_rounds", "member_iters")
+
+
+class VibeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"vibelsd error {code}: {msg}")
+        self.code = code
+
+
+class vibe_config(C.Structure):
+    _fields_ = [("L", C.c_uint32), ("M", C.c_uint32), ("T_max", C.c_uint32),
+                ("lsd_order", C.c_uint32), ("alpha", C.c_double), ("clamp", C.c_double)]
+
+
+class vibe_graph_info_t(C.Structure):
+    _fields_ = [("m", C.c_uint32), ("n", C.c_uint32), ("k", C.c_uint32), ("L", C.c_uint32),
+                ("M", C.c_uint32), ("T_max", C.c_uint32), ("nnz", C.c_uint64),
+                ("max_row_degree", C.c_uint32), ("max_col_degree", C.c_uint32),
+                ("levels_min", C.c_uint32), ("levels_max", C.c_uint32),
+                ("device_bytes", C.c_uint64)]
+
+
+_lib = None
+
+EXPORTS = {
+    "vibe_graph_create": (C.c_int, [C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.POINTER(vibe_config), C.POINTER(C.c_void_p)]),
+    "vibe_graph_destroy": (None, [C.c_void_p]),
+    "vibe_graph_info": (C.c_int, [C.c_void_p, C.POINTER(vibe_graph_info_t)]),
+    "vibe_decode": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_void_p]),
+    "vibe_decode_plain": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]),
+    "vibe_bp_ensemble": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_int,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vibe_lsd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
+                           C.c_void_p, C.c_void_p]),
+    "vibe_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "vibe_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
+    "vibe_last_error": (C.c_char_p, []),
+    "vibe_version": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libvibelsd.so; there is no fallback if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "or python paper_2508_15743_amd/_build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != VIBE_OK:
+        raise VibeError(rc, lib().vibe_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _u32(a):
+    return np.ascontiguousarray(a, dtype=np.uint32)
+
+
+def vibe_version() -> str:
+    return lib().vibe_version().decode()
+
+
+def vibe_graph_create(m, n, h_indptr, h_indices, priors, k, l_indptr, l_indices, perms, cfg):
+    hp, hi, lp, li, pp = _u32(h_indptr), _u32(h_indices), _u32(l_indptr), _u32(l_indices), _u32(perms)
+    pr = np.ascontiguousarray(priors, dtype=np.float64)
+    out = C.c_void_p()
+    _check(lib().vibe_graph_create(m, n, hp.ctypes.data, hi.ctypes.data if hi.size else None,
+                                   pr.ctypes.data, k, lp.ctypes.data, li.ctypes.data if li.size else None,
+                                   pp.ctypes.data, C.byref(cfg), C.byref(out)))
+    return out
+
+
+def vibe_graph_destroy(handle):
+    lib().vibe_graph_destroy(handle)
+
+
+def vibe_graph_info(handle) -> dict:
+    info = vibe_graph_info_t()
+    _check(lib().vibe_graph_info(handle, C.byref(info)))
+    return {f: getattr(info, f) for f, _ in info._fields_}
+
+
+def vibe_decode(handle, syndromes, B, corrections, observables, stats, stream):
+    _check(lib().vibe_decode(handle, _ptr(syndromes), B, _ptr(corrections), _ptr(observables),
+                             _ptr(stats), stream))
+
+
+def vibe_decode_plain(handle, syndromes, B, corrections, observables, stats, stream):
+    _check(lib().vibe_decode_plain(handle, _ptr(syndromes), B, _ptr(corrections), _ptr(observables),
+                                   _ptr(stats), stream))
+
+
+def vibe_bp_ensemble(handle, syndromes, B, T_run, stop, t_conv, posteriors, ehat, stream):
+    _check(lib().vibe_bp_ensemble(handle, _ptr(syndromes), B, T_run, 1 if stop else 0, _ptr(t_conv),
+                                  _ptr(posteriors), _ptr(ehat), stream))
+
+
+def vibe_lsd(handle, syndromes, soft, B, corrections, stats, stream):
+    _check(lib().vibe_lsd(handle, _ptr(syndromes), _ptr(soft), B, _ptr(corrections), _ptr(stats),
+                          stream))
+
+
+def vibe_profile_enable(handle, enable):
+    _check(lib().vibe_profile_enable(handle, 1 if enable else 0))
+
+
+def vibe_profile_read(handle):
+    ms = (C.c_double * 3)()
+    n = (C.c_uint64 * 3)()
+    _check(lib().vibe_profile_read(handle, ms, n))
+    names = ("bp_ensemble", "select", "lsd")
+    return {names[i]: (ms[i], n[i]) for i in range(3)}
+
+
+def unpack_bits(words, n: int) -> np.ndarray:
+    """[..., ceil(n/64)] int64 words (any device) -> [..., n] uint8 bits."""
+    w = words.detach().cpu().numpy() if hasattr(words, "detach") else np.asarray(words)
+    w = np.ascontiguousarray(w).view(np.uint64)
+    b = np.unpackbits(w.view(np.uint8).reshape(*w.shape[:-1], -1), axis=-1, bitorder="little")
+    return b[..., :n]
+
+
+class Graph:
+    """A detector error model resident on the current GPU, with its member
+    schedules.  `perms` is [L, n]: the serial schedules of the members."""
+
+    def __init__(self, h_indptr, h_indices, priors, l_indptr, l_indices, perms, m=None, n=None,
+                 L=32, M=5, T_max=20, alpha=0.625, clamp=1e6, lsd_order=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libvibelsd needs a ROCm GPU (torch.cuda is not available)")
+        lib()
+        h_indptr = _u32(h_indptr)
+        self.m = len(h_indptr) - 1 if m is None else m
+        self.n = int(len(priors)) if n is None else n
+        self.k = len(l_indptr) - 1
+        self.L, self.M, self.T_max = L, M, T_max
+        self.words = (self.n + 63) // 64
+        self.cfg = vibe_config(L, M, T_max, lsd_order, alpha, clamp)
+        self.handle = vibe_graph_create(self.m, self.n, h_indptr, h_indices, priors, self.k,
+                                        l_indptr, l_indices, perms, self.cfg)
+
+    @classmethod
+    def from_dem(cls, dem, perms, **cfg):
+        return cls(dem.h_indptr, dem.h_indices, dem.priors, dem.l_indptr, dem.l_indices, perms,
+                   m=dem.m, n=dem.n, **cfg)
+
+    def info(self) -> dict:
+        return vibe_graph_info(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            vibe_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _synd(self, syndromes):
+        import torch
+        if syndromes.dtype != torch.uint8 or syndromes.dim() != 2 or syndromes.shape[1] != self.m:
+            raise ValueError(f"syndromes must be uint8 [B, {self.m}]")
+        if not syndromes.is_cuda:
+            raise ValueError("syndromes must be a device tensor")
+        return syndromes.contiguous()
+
+    def decode(self, syndromes, plain=False, with_stats=True, stream=None, out=None):
+        """-> (corrections int64 [B, words], observables uint8 [B, k], stats int32 [B, 8])"""
+        import torch
+        s = self._synd(syndromes)
+        B = s.shape[0]
+        dev = s.device
+        if out is None:
+            corr = torch.empty((B, self.words), dtype=torch.int64, device=dev)
+            obs = torch.empty((B, max(self.k, 1)), dtype=torch.uint8, device=dev)
+            st = torch.empty((B, 8), dtype=torch.int32, device=dev) if with_stats else None
+        else:
+            corr, obs, st = out
+        fn = vibe_decode_plain if plain else vibe_decode
+        fn(self.handle, s, B, corr, obs, st, _stream(stream))
+        return corr, obs, st
+
+    def bp_ensemble(self, syndromes, T_run=None, stop=True, posteriors=True, ehat=True, stream=None):
+        """-> (t_conv int32 [B, L], posteriors float32 [B, L, n] or None, ehat int64 [B, L, words] or None)"""
+        import torch
+        s = self._synd(syndromes)
+        B = s.shape[0]
+        dev = s.device
+        T_run = self.T_max if T_run is None else T_run
+        t = torch.empty((B, self.L), dtype=torch.int32, device=dev)
+        p = torch.empty((B, self.L, self.n), dtype=torch.float32, device=dev) if posteriors else None
+        e = torch.empty((B, self.L, self.words), dtype=torch.int64, device=dev) if ehat else None
+        vibe_bp_ensemble(self.handle, s, B, T_run, stop, t, p, e, _stream(stream))
+        return t, p, e
+
+    def lsd(self, syndromes, soft, stream=None):
+        """-> (corrections int64 [B, words], stats int32 [B, 8])"""
+        import torch
+        s = self._synd(syndromes)
+        B = s.shape[0]
+        soft = soft.to(torch.float32).contiguous()
+        if soft.shape != (B, self.n) or not soft.is_cuda:
+            raise ValueError(f"soft must be a float32 device tensor [B, {self.n}]")
+        corr = torch.empty((B, self.words), dtype=torch.int64, device=s.device)
+        st = torch.empty((B, 8), dtype=torch.int32, device=s.device)
+        vibe_lsd(self.handle, s, soft, B, corr, st, _stream(stream))
+        return corr, st

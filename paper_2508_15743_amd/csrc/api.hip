@@ -1,0 +1,354 @@
+// Online stage (paper Sec. III.D.2): launch sequences of the C ABI.
+//
+// Batched decode, per chunk of shots: K1 (BP ensemble, persistent grid, one
+// wavefront per (shot, member), correction limit applied on the fly, the
+// normalised posteriors of unconverged members accumulated in fixed point),
+// K2 (selection by prior weight; shots with no converged member are queued),
+// K3 (LSD-0 on the queued shots); then K4 (observables) over the whole batch.
+#include <algorithm>
+#include <cstring>
+
+#include "internal.h"
+
+namespace vibe {
+
+namespace {
+
+struct ChunkBufs {
+    int32_t* t_conv;
+    double* weight;
+    uint64_t* cand;
+    uint64_t* cmask;     // per shot: members converged at each iteration
+    uint32_t* iters;
+    int64_t* qfix;
+    uint32_t* fail_list;
+    uint32_t* counters;  // [0] BP work counter, [1] failed-shot count
+    uint32_t* slab;
+    float* post_slab;
+    void* lsd_scratch;
+};
+
+size_t per_shot_bytes(const DevGraph& g, bool decode) {
+    size_t b = 4ull * g.L + 8ull * (kMaxT + 1) + 4 + 4;
+    if (decode) b += 8ull * g.L + 8ull * g.L * g.words_n + 8ull * g.n;
+    return b;
+}
+
+inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int ensure_workspace(vibe_graph* G, size_t bytes) {
+    if (G->ws.bytes >= bytes) return VIBE_OK;
+    if (G->ws.base) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before growing the workspace");
+        (void)hipFree(G->ws.base);
+        G->ws.base = nullptr;
+        G->ws.bytes = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return fail(VIBE_ENOMEM, "workspace allocation failed");
+    G->ws.base = p;
+    G->ws.bytes = bytes;
+    return VIBE_OK;
+}
+
+// Carve the workspace for chunks of up to `bc` shots.
+// slab_blocks: blocks that need a message slab in global memory (0 when the
+// slab lives in LDS); post_blocks: blocks of the BP grid (posterior slabs).
+int carve(vibe_graph* G, uint32_t bc, bool decode, int slab_blocks, int post_blocks, int lsd_grid,
+          ChunkBufs* B) {
+    const DevGraph& g = G->h.dg;
+    size_t sizes[11] = {
+        4ull * bc * g.L,                                   // t_conv
+        decode ? 8ull * bc * g.L : 0,                      // weight
+        decode ? 8ull * bc * g.L * g.words_n : 0,          // cand
+        8ull * bc * (kMaxT + 1),                           // convergence masks
+        4ull * bc,                                         // iters
+        decode ? 8ull * bc * g.n : 0,                      // qfix
+        4ull * bc,                                         // fail_list
+        64,                                                // counters
+        4ull * slab_blocks * (g.E ? g.E : 1),              // message slabs
+        4ull * post_blocks * g.n,                          // posterior slabs
+        decode ? lsd_scratch_per_block(g) * lsd_grid : 0,  // LSD scratch
+    };
+    size_t total = 0;
+    for (size_t s : sizes) total += al256(s);
+    int rc = ensure_workspace(G, total);
+    if (rc) return rc;
+    unsigned char* p = static_cast<unsigned char*>(G->ws.base);
+    void* ptrs[11];
+    for (int i = 0; i < 11; i++) {
+        ptrs[i] = sizes[i] ? p : nullptr;
+        p += al256(sizes[i]);
+    }
+    B->t_conv = (int32_t*)ptrs[0];
+    B->weight = (double*)ptrs[1];
+    B->cand = (uint64_t*)ptrs[2];
+    B->cmask = (uint64_t*)ptrs[3];
+    B->iters = (uint32_t*)ptrs[4];
+    B->qfix = (int64_t*)ptrs[5];
+    B->fail_list = (uint32_t*)ptrs[6];
+    B->counters = (uint32_t*)ptrs[7];
+    B->slab = (uint32_t*)ptrs[8];
+    B->post_slab = (float*)ptrs[9];
+    B->lsd_scratch = ptrs[10];
+    return VIBE_OK;
+}
+
+int lsd_grid_for(uint64_t B) {
+    uint64_t g = std::min<uint64_t>(B ? B : 1, 512);
+    return (int)g;
+}
+
+int memset_async(void* p, size_t bytes, hipStream_t st) { return launch_zero(p, bytes, st); }
+
+// One chunk of the decoder: shots [shot0, shot0 + n).
+int decode_chunk(vibe_graph* G, const ChunkBufs& W, const uint8_t* synd, uint64_t shot0, uint32_t n,
+                 uint64_t* corr, vibe_shot_stats* stats, int bp_blocks, int lsd_grid, hipStream_t st) {
+    const DevGraph& g = G->h.dg;
+    int rc;
+    if ((rc = memset_async(W.cmask, 8ull * n * (kMaxT + 1), st)) ||
+        (rc = memset_async(W.iters, 4ull * n, st)) || (rc = memset_async(W.qfix, 8ull * n * g.n, st)) ||
+        (rc = memset_async(W.counters, 64, st)))
+        return rc;
+    BpLaunch b{};
+    b.member_major = 1;
+    b.slab_in_lds = bp_slab_fits_lds(g) ? 1 : 0;
+    b.syndromes = synd;
+    b.shot0 = shot0;
+    b.n_shots = n;
+    b.T_run = g.T;
+    b.use_M = 1;
+    b.stop_on_converge = 1;
+    b.accumulate_q = 1;
+    b.fast_zero = 1;
+    b.t_conv = W.t_conv;
+    b.weight = W.weight;
+    b.cand = W.cand;
+    b.post_out = nullptr;
+    b.conv_mask = W.cmask;
+    b.iters = W.iters;
+    b.qfix = W.qfix;
+    b.slab = W.slab;
+    b.post_slab = W.post_slab;
+    b.counter = W.counters;
+    b.grid = (int)std::min<uint64_t>((uint64_t)bp_blocks, (uint64_t)n * g.L);
+    begin_timed(G, 0, st);
+    if ((rc = launch_bp(g, b, st))) return rc;
+    end_timed(G, 0, st);
+    SelectLaunch s{};
+    s.n_shots = n;
+    s.shot0 = shot0;
+    s.t_conv = W.t_conv;
+    s.weight = W.weight;
+    s.cand = W.cand;
+    s.iters = W.iters;
+    s.corrections = corr;
+    s.stats = stats;
+    s.fail_list = W.fail_list;
+    s.fail_count = W.counters + 1;
+    begin_timed(G, 1, st);
+    if ((rc = launch_select(g, s, st))) return rc;
+    end_timed(G, 1, st);
+    LsdLaunch l{};
+    l.syndromes = synd;
+    l.shot0 = shot0;
+    l.list = W.fail_list;
+    l.list_count = W.counters + 1;
+    l.n_list = n;
+    l.soft_f32 = nullptr;
+    l.soft_fix = W.qfix;
+    l.corrections = corr;
+    l.stats = stats;
+    l.scratch = W.lsd_scratch;
+    l.scratch_per_block = lsd_scratch_per_block(g);
+    l.grid = std::min(lsd_grid, (int)n);
+    begin_timed(G, 2, st);
+    if ((rc = launch_lsd(g, l, st))) return rc;
+    end_timed(G, 2, st);
+    return VIBE_OK;
+}
+
+int check_common(vibe_graph* G, const void* synd, uint64_t B) {
+    if (!G) return fail(VIBE_EINVAL, "graph handle is NULL");
+    if (B && !synd) return fail(VIBE_EINVAL, "syndromes is NULL");
+    if (B > (1ull << 40)) return fail(VIBE_EINVAL, "B is too large");
+    return VIBE_OK;
+}
+
+uint32_t chunk_for(const DevGraph& g, uint64_t B, bool decode) {
+    const size_t budget = 4ull << 30;  // workspace of the per-chunk buffers
+    uint64_t bc = budget / per_shot_bytes(g, decode);
+    bc = std::max<uint64_t>(256, std::min<uint64_t>(bc, 65536));
+    bc = std::min<uint64_t>(bc, (uint64_t)UINT32_MAX / std::max<uint32_t>(g.L, 1));
+    return (uint32_t)std::min<uint64_t>(bc, B);
+}
+
+}  // namespace
+
+void begin_timed(vibe_graph* G, int which, hipStream_t st) {
+    if (!G->profiling) return;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+    }
+    (void)hipEventRecord(a, st);
+    G->ev[which].push_back({a, b});
+}
+
+void end_timed(vibe_graph* G, int which, hipStream_t st) {
+    if (!G->profiling || G->ev[which].empty()) return;
+    (void)hipEventRecord(G->ev[which].back().second, st);
+}
+
+}  // namespace vibe
+
+using namespace vibe;
+
+extern "C" int vibe_profile_enable(vibe_graph* G, int enable) {
+    if (!G) return fail(VIBE_EINVAL, "graph handle is NULL");
+    G->profiling = enable != 0;
+    return VIBE_OK;
+}
+
+extern "C" int vibe_profile_read(vibe_graph* G, double* ms, uint64_t* launches) {
+    if (!G || !ms || !launches) return fail(VIBE_EINVAL, "NULL argument");
+    for (int k = 0; k < 3; k++) {
+        double tot = 0.0;
+        for (auto& pr : G->ev[k]) {
+            hipError_t e = hipEventSynchronize(pr.second);
+            if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+            float t = 0.0f;
+            e = hipEventElapsedTime(&t, pr.first, pr.second);
+            if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+            tot += t;
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        ms[k] = tot;
+        launches[k] = G->ev[k].size();
+        G->ev[k].clear();
+    }
+    return VIBE_OK;
+}
+
+extern "C" int vibe_decode(vibe_graph* G, const uint8_t* syndromes, uint64_t B, uint64_t* corrections,
+                           uint8_t* observables, vibe_shot_stats* stats, void* stream) {
+    set_error("");
+    int rc = check_common(G, syndromes, B);
+    if (rc) return rc;
+    if (B && (!corrections || (!observables && G->h.k))) return fail(VIBE_EINVAL, "an output pointer is NULL");
+    if (!B) return VIBE_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const DevGraph& g = G->h.dg;
+    const uint32_t bc = chunk_for(g, B, true);
+    const bool in_lds = bp_slab_fits_lds(g);
+    const int bpg = bp_grid(g, in_lds);
+    const int lg = lsd_grid_for(bc);
+    ChunkBufs W;
+    if ((rc = carve(G, bc, true, in_lds ? 0 : bpg, bpg, lg, &W))) return rc;
+    for (uint64_t s0 = 0; s0 < B; s0 += bc) {
+        const uint32_t n = (uint32_t)std::min<uint64_t>(bc, B - s0);
+        if ((rc = decode_chunk(G, W, syndromes, s0, n, corrections, stats, bpg, lg, st))) return rc;
+    }
+    return launch_observables(g, corrections, 0, (uint32_t)std::min<uint64_t>(B, UINT32_MAX), observables, st);
+}
+
+extern "C" int vibe_decode_plain(vibe_graph* G, const uint8_t* syndromes, uint64_t B,
+                                 uint64_t* corrections, uint8_t* observables, vibe_shot_stats* stats,
+                                 void* stream) {
+    set_error("");
+    int rc = check_common(G, syndromes, B);
+    if (rc) return rc;
+    if (B && (!corrections || (!observables && G->h.k))) return fail(VIBE_EINVAL, "an output pointer is NULL");
+    if (!B) return VIBE_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const DevGraph& g = G->h.dg;
+    ChunkBufs W;
+    const int blocks = (int)g.L;  // one block per member of the one shot
+    if ((rc = carve(G, 1, true, bp_slab_fits_lds(g) ? 0 : blocks, blocks, 1, &W))) return rc;
+    for (uint64_t s0 = 0; s0 < B; s0++) {
+        if ((rc = decode_chunk(G, W, syndromes, s0, 1, corrections, stats, blocks, 1, st))) return rc;
+        if ((rc = launch_observables(g, corrections, s0, 1, observables, st))) return rc;
+    }
+    return VIBE_OK;
+}
+
+extern "C" int vibe_bp_ensemble(vibe_graph* G, const uint8_t* syndromes, uint64_t B, uint32_t T_run,
+                                int stop_on_converge, int32_t* t_conv, float* posteriors,
+                                uint64_t* ehat, void* stream) {
+    set_error("");
+    int rc = check_common(G, syndromes, B);
+    if (rc) return rc;
+    if (T_run < 1 || T_run > (uint32_t)kMaxT) return fail(VIBE_EINVAL, "T_run must be in 1..64");
+    if (B && !t_conv) return fail(VIBE_EINVAL, "t_conv is NULL");
+    if (!B) return VIBE_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const DevGraph& g = G->h.dg;
+    const uint32_t bc = chunk_for(g, B, false);
+    const bool in_lds = bp_slab_fits_lds(g);
+    const int bpg = bp_grid(g, in_lds);
+    ChunkBufs W;
+    if ((rc = carve(G, bc, false, in_lds ? 0 : bpg, bpg, 0, &W))) return rc;
+    for (uint64_t s0 = 0; s0 < B; s0 += bc) {
+        const uint32_t n = (uint32_t)std::min<uint64_t>(bc, B - s0);
+        if ((rc = memset_async(W.cmask, 8ull * n * (kMaxT + 1), st)) ||
+            (rc = memset_async(W.iters, 4ull * n, st)) || (rc = memset_async(W.counters, 64, st)))
+            return rc;
+        BpLaunch b{};
+        b.member_major = 0;
+        b.slab_in_lds = in_lds ? 1 : 0;
+        b.syndromes = syndromes;
+        b.shot0 = s0;
+        b.n_shots = n;
+        b.T_run = T_run;
+        b.use_M = 0;
+        b.stop_on_converge = stop_on_converge ? 1 : 0;
+        b.accumulate_q = 0;
+        b.fast_zero = 0;
+        b.t_conv = t_conv + s0 * g.L;
+        b.weight = nullptr;
+        b.cand = ehat ? ehat + s0 * g.L * g.words_n : nullptr;
+        b.post_out = posteriors ? posteriors + s0 * g.L * g.n : nullptr;
+        b.conv_mask = W.cmask;
+        b.iters = W.iters;
+        b.qfix = nullptr;
+        b.slab = W.slab;
+        b.post_slab = W.post_slab;
+        b.counter = W.counters;
+        b.grid = (int)std::min<uint64_t>((uint64_t)bpg, (uint64_t)n * g.L);
+        if ((rc = launch_bp(g, b, st))) return rc;
+    }
+    return VIBE_OK;
+}
+
+extern "C" int vibe_lsd(vibe_graph* G, const uint8_t* syndromes, const float* soft, uint64_t B,
+                        uint64_t* corrections, vibe_shot_stats* stats, void* stream) {
+    set_error("");
+    int rc = check_common(G, syndromes, B);
+    if (rc) return rc;
+    if (B && (!soft || !corrections)) return fail(VIBE_EINVAL, "soft or corrections is NULL");
+    if (!B) return VIBE_OK;
+    if (B > UINT32_MAX) return fail(VIBE_EINVAL, "B must be < 2^32 for vibe_lsd");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const DevGraph& g = G->h.dg;
+    const int lg = lsd_grid_for(B);
+    const size_t per = lsd_scratch_per_block(g);
+    if ((rc = ensure_workspace(G, per * lg))) return rc;
+    LsdLaunch l{};
+    l.syndromes = syndromes;
+    l.shot0 = 0;
+    l.list = nullptr;
+    l.list_count = nullptr;
+    l.n_list = (uint32_t)B;
+    l.soft_f32 = soft;
+    l.soft_fix = nullptr;
+    l.corrections = corrections;
+    l.stats = stats;
+    l.scratch = G->ws.base;
+    l.scratch_per_block = per;
+    l.grid = lg;
+    return launch_lsd(g, l, st);
+}

@@ -1,0 +1,170 @@
+// Internal definitions shared by the HIP translation units of libvibelsd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/vibelsd.h"
+
+namespace vibe {
+
+constexpr int kWave = 64;
+constexpr int kMaxColDeg = 15;
+constexpr int kMaxL = 64;
+constexpr int kMaxT = 64;
+constexpr double kQScale = 72057594037927936.0;  // 2^56: fixed point of the LLR average
+
+// One schedule slot = one edge (v, c) of the member's serial sweep.  Slots are
+// grouped in chunks of at most 64 that hold whole columns of one dependency
+// level; inside a column the slots follow ascending check index.
+//   pos  : position of the edge in the member's message layout, where every
+//          row keeps its edges in the order the member's sweep visits them
+//   meta : c | seg << 16 | deg << 20 | last << 24   (seg = slot index inside
+//          the column's run, deg = number of checks of the column, last = the
+//          edge is the last of its row in the member's order)
+//   v    : the column
+struct Slot {
+    uint32_t pos, meta, v;
+};
+
+// Row state word: the float bits of a magnitude (>= 0) with a parity bit in
+// the sign position.  Magnitudes compare like unsigned integers, so
+// combining two states is an integer min of the low 31 bits and an xor of
+// bit 31.
+__host__ __device__ inline uint32_t rs_combine(uint32_t a, uint32_t b) {
+    uint32_t ma = a & 0x7fffffffu, mb = b & 0x7fffffffu;
+    return (ma < mb ? ma : mb) | ((a ^ b) & 0x80000000u);
+}
+
+// Everything a kernel needs to know about a resident graph (passed by value).
+struct DevGraph {
+    uint32_t m, n, k, L, M, T;
+    uint32_t E;
+    uint32_t words_n, words_m;  // ceil(n/64), ceil(m/64)
+    float alpha, clamp;
+    uint32_t ident;             // row state of "no message": clamp, parity 0
+    int all_lam_positive;
+    const uint32_t* rp;           // m + 1
+    const uint32_t* ri;           // E, CSR column of each edge
+    const uint32_t* cp;           // n + 1
+    const uint32_t* ci;           // E, CSC check of each edge
+    const float* lam;             // n, FP32 channel LLR
+    const double* lam64;          // n, FP64 channel LLR (candidate weights)
+    const uint64_t* e0;           // words_n: decisions of columns without checks
+    const uint64_t* row_last;     // ceil(E/64): bit e = position e ends its row
+    const uint32_t* init_suf;     // L x E: suffix states of the initial messages
+    const Slot* slots;            // L x E
+    const uint32_t* chunk_off;    // concatenated chunk offsets (into slots)
+    const uint32_t* member_chunk; // L + 1: chunk range of each member
+    const uint64_t* lobs;         // k x words_n, bit-packed observable rows
+};
+
+struct GraphHost {
+    vibe_config cfg;
+    uint32_t m, n, k;
+    uint64_t E;
+    uint32_t max_row, max_col;
+    uint32_t levels_min, levels_max;
+    uint64_t device_bytes;
+    DevGraph dg;
+    std::vector<void*> allocations;
+};
+
+// Per-handle workspace, grown on demand and reused across calls.
+struct Workspace {
+    size_t bytes = 0;
+    void* base = nullptr;
+};
+
+}  // namespace vibe
+
+struct vibe_graph {
+    vibe::GraphHost h;
+    vibe::Workspace ws;
+    int device = 0;
+    // kernel timing (vibe_profile_enable): event pairs per kernel class
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
+};
+
+namespace vibe {
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+// launchers (each returns VIBE_OK or VIBE_EHIP)
+struct BpLaunch {
+    const uint8_t* syndromes;  // B x m
+    uint64_t shot0;            // first shot of this launch (index into syndromes)
+    uint32_t n_shots;
+    uint32_t T_run;
+    int use_M;                 // apply the correction limit
+    int stop_on_converge;
+    int accumulate_q;          // add normalised posteriors of unconverged members
+    int fast_zero;             // decide s = 0 shots without running BP
+    int member_major;          // work item order: member-major (1) or shot-major (0)
+    // outputs, indexed by local shot (0 .. n_shots-1) and member
+    int32_t* t_conv;           // n_shots x L
+    double* weight;            // n_shots x L (candidate weight), may be null
+    uint64_t* cand;            // n_shots x L x words_n, may be null
+    float* post_out;           // n_shots x L x n, may be null (every iteration)
+    uint64_t* conv_mask;       // n_shots x (kMaxT + 1): members converged at t
+    uint32_t* iters;           // n_shots: iterations run, summed over members
+    int64_t* qfix;             // n_shots x n, may be null
+    // scratch
+    uint32_t* slab;            // grid x E row states / messages (global variant)
+    float* post_slab;          // grid x n
+    uint32_t* counter;         // work counter
+    int grid;
+    int slab_in_lds;           // which kernel variant to launch
+};
+int launch_bp(const DevGraph& g, const BpLaunch& a, hipStream_t st);
+int bp_grid(const DevGraph& g, bool slab_in_lds);
+size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds);
+bool bp_slab_fits_lds(const DevGraph& g);
+int launch_zero(void* p, size_t bytes, hipStream_t st);
+
+struct SelectLaunch {
+    uint32_t n_shots;
+    uint64_t shot0;
+    const int32_t* t_conv;
+    const double* weight;
+    const uint64_t* cand;
+    const uint32_t* iters;
+    uint64_t* corrections;        // global B x words_n (indexed by shot0 + i)
+    vibe_shot_stats* stats;       // global, may be null
+    uint32_t* fail_list;          // local shot indices that need LSD
+    uint32_t* fail_count;
+};
+int launch_select(const DevGraph& g, const SelectLaunch& a, hipStream_t st);
+
+struct LsdLaunch {
+    const uint8_t* syndromes;     // global B x m
+    uint64_t shot0;
+    const uint32_t* list;         // local shot indices, or null = all n_list shots
+    const uint32_t* list_count;   // device count (if list != null)
+    uint32_t n_list;              // upper bound on the list length
+    const float* soft_f32;        // global B x n (indexed by shot0 + i), or
+    const int64_t* soft_fix;      // local n_shots x n fixed point
+    uint64_t* corrections;        // global B x words_n
+    vibe_shot_stats* stats;       // global, may be null
+    void* scratch;
+    size_t scratch_per_block;
+    int grid;
+};
+int launch_lsd(const DevGraph& g, const LsdLaunch& a, hipStream_t st);
+size_t lsd_scratch_per_block(const DevGraph& g);
+
+// Record a start event before a launch of kernel class `which` (0 BP,
+// 1 selection, 2 LSD) when profiling is on; end_timed records the end event.
+void begin_timed(vibe_graph* G, int which, hipStream_t st);
+void end_timed(vibe_graph* G, int which, hipStream_t st);
+
+int launch_observables(const DevGraph& g, const uint64_t* corrections, uint64_t shot0,
+                       uint32_t n_shots, uint8_t* observables, hipStream_t st);
+
+}  // namespace vibe

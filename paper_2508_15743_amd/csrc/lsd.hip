@@ -1,0 +1,408 @@
+// K3: LSD-0 post-processing (paper Sec. III.C), one wavefront per shot.
+//
+// Clusters start as the flipped checks.  In every round each cluster that is
+// still invalid adds its best boundary column (lowest soft value, then lowest
+// index), judged on the state at the start of the round; clusters that come
+// to share a check merge (union-find, smallest slot is the root).  A cluster
+// is valid when s restricted to its checks lies in the span of its columns.
+// Validity uses one pool of bit-packed basis vectors over the checks, kept in
+// insertion order: vectors of different clusters have disjoint supports, so
+// reducing a cluster's syndrome by the whole pool only ever touches that
+// cluster's own vectors.  At the end, the columns of valid clusters are
+// ranked and eliminated in rank order; a column is a pivot iff it is
+// independent of the earlier ones, and every basis vector carries its
+// combination of pivot columns, so reducing s yields the solution.
+#include "internal.h"
+
+namespace vibe {
+
+namespace {
+
+constexpr uint32_t kValid = 1u, kFailed = 2u;
+
+struct LsdMem {
+    int32_t* chk_cl;    // m
+    int32_t* parent;    // m
+    uint32_t* cstate;   // m
+    int64_t* best_q;    // m
+    int32_t* best_v;    // m
+    int32_t* ccount;    // m
+    int32_t* picks;     // 2m (slot, column)
+    int32_t* added;     // m
+    int32_t* pool_piv;  // m
+    int32_t* piv2;      // m
+    int32_t* pivcol;    // m
+    int32_t* cols;      // n
+    int32_t* sorted;    // n
+    int64_t* ckey;      // n
+    uint64_t* in_bits;  // words_n
+    uint64_t* ebits;    // words_n
+    uint64_t* xbuf;     // words_m
+    uint64_t* cbuf;     // words_m
+    uint64_t* pool;     // m x words_m
+    uint64_t* basis2;   // m x 2 words_m (vector, combination)
+};
+
+__host__ __device__ inline size_t al8(size_t x) { return (x + 7) & ~(size_t)7; }
+
+__host__ __device__ inline size_t lsd_layout(const DevGraph& g, unsigned char* base, LsdMem* out) {
+    const size_t m = g.m ? g.m : 1, n = g.n, wn = g.words_n, wm = g.words_m ? g.words_m : 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* p = base ? base + off : nullptr;
+        off += al8(bytes);
+        return p;
+    };
+    LsdMem M;
+    M.chk_cl = (int32_t*)take(4 * m);
+    M.parent = (int32_t*)take(4 * m);
+    M.cstate = (uint32_t*)take(4 * m);
+    M.best_q = (int64_t*)take(8 * m);
+    M.best_v = (int32_t*)take(4 * m);
+    M.ccount = (int32_t*)take(4 * m);
+    M.picks = (int32_t*)take(8 * m);
+    M.added = (int32_t*)take(4 * m);
+    M.pool_piv = (int32_t*)take(4 * m);
+    M.piv2 = (int32_t*)take(4 * m);
+    M.pivcol = (int32_t*)take(4 * m);
+    M.cols = (int32_t*)take(4 * n);
+    M.sorted = (int32_t*)take(4 * n);
+    M.ckey = (int64_t*)take(8 * n);
+    M.in_bits = (uint64_t*)take(8 * wn);
+    M.ebits = (uint64_t*)take(8 * wn);
+    M.xbuf = (uint64_t*)take(8 * wm);
+    M.cbuf = (uint64_t*)take(8 * wm);
+    M.pool = (uint64_t*)take(8 * wm * m);
+    M.basis2 = (uint64_t*)take(16 * wm * m);
+    if (out) *out = M;
+    return off;
+}
+
+// order-preserving map of a float to int64 (-0 and +0 map to the same key)
+__device__ inline int64_t float_key(float f) {
+    uint32_t b = __float_as_uint(f);
+    int64_t mag = (int64_t)(b & 0x7fffffffu);
+    return (b >> 31) ? -mag : mag;
+}
+
+__device__ inline int32_t find_root(int32_t* parent, int32_t x) {
+    while (parent[x] != x) x = parent[x];
+    return x;
+}
+
+__device__ inline bool key_less(int64_t qa, int32_t a, int64_t qb, int32_t b) {
+    return qa < qb || (qa == qb && a < b);
+}
+
+// xbuf ^= pool vectors in insertion order wherever xbuf has the vector's
+// pivot bit set; optionally the combination words follow along.
+__device__ void reduce_by(uint64_t* x, uint64_t* comb, const uint64_t* vecs, size_t stride,
+                          const int32_t* piv, int count, uint32_t wm, int lane) {
+    for (int i = 0; i < count; i++) {
+        const int32_t p = piv[i];
+        __syncthreads();
+        const bool hit = (x[p >> 6] >> (p & 63)) & 1ull;
+        if (!hit) continue;
+        const uint64_t* b = vecs + (size_t)i * stride;
+        for (uint32_t w = lane; w < wm; w += kWave) {
+            x[w] ^= b[w];
+            if (comb) comb[w] ^= b[wm + w];
+        }
+    }
+    __syncthreads();
+}
+
+// lowest set bit of a words_m vector, or -1
+__device__ int lowest_bit(const uint64_t* x, uint32_t wm, int lane) {
+    int best = 0x7fffffff;
+    for (uint32_t w = lane; w < wm; w += kWave)
+        if (x[w]) {
+            int b = (int)(w * 64 + __ffsll((long long)x[w]) - 1);
+            if (b < best) best = b;
+        }
+    for (int off = kWave / 2; off > 0; off >>= 1) best = min(best, __shfl_xor(best, off));
+    return best == 0x7fffffff ? -1 : best;
+}
+
+__device__ void column_vector(const DevGraph& g, uint64_t* x, uint32_t v, int lane) {
+    for (uint32_t w = lane; w < g.words_m; w += kWave) x[w] = 0;
+    __syncthreads();
+    if (lane == 0)
+        for (uint32_t j = g.cp[v]; j < g.cp[v + 1]; j++) {
+            uint32_t c = g.ci[j];
+            x[c >> 6] |= 1ull << (c & 63);
+        }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
+    const int lane = threadIdx.x;
+    LsdMem S;
+    lsd_layout(g, static_cast<unsigned char*>(a.scratch) + a.scratch_per_block * blockIdx.x, &S);
+    const uint32_t count = a.list ? *a.list_count : a.n_list;
+    const uint32_t wm = g.words_m;
+    for (uint32_t it = blockIdx.x; it < count && it < a.n_list; it += gridDim.x) {
+        const uint32_t local = a.list ? a.list[it] : it;
+        const uint64_t gshot = a.shot0 + local;
+        const uint8_t* s = a.syndromes + gshot * g.m;
+        auto key = [&](uint32_t v) -> int64_t {
+            return a.soft_f32 ? float_key(a.soft_f32[gshot * g.n + v]) : a.soft_fix[(size_t)local * g.n + v];
+        };
+
+        // ---- one cluster per flipped check, slots in ascending check order
+        int nk = 0;
+        for (uint32_t base = 0; base < g.m; base += kWave) {
+            const uint32_t c = base + lane;
+            const bool f = c < g.m && s[c] != 0;
+            const uint64_t mask = __ballot(f);
+            const int pre = __popcll(mask & ((1ull << lane) - 1ull));
+            if (c < g.m) {
+                if (f) {
+                    const int slot = nk + pre;
+                    S.chk_cl[c] = slot;
+                    S.parent[slot] = slot;
+                    S.cstate[slot] = 0;
+                    S.ccount[slot] = 0;
+                } else {
+                    S.chk_cl[c] = -1;
+                }
+            }
+            nk += __popcll(mask);
+        }
+        for (uint32_t w = lane; w < g.words_n; w += kWave) {
+            S.in_bits[w] = 0;
+            S.ebits[w] = 0;
+        }
+        __syncthreads();
+        int pool_n = 0, rounds = 0;
+
+        for (;;) {
+            // 1. best boundary column of every invalid, growing cluster
+            for (int K = lane; K < nk; K += kWave) {
+                S.best_q[K] = INT64_MAX;
+                S.best_v[K] = -1;
+            }
+            __syncthreads();
+            for (uint32_t c = 0; c < g.m; c++) {
+                const int32_t cl = S.chk_cl[c];
+                if (cl < 0) continue;
+                const int32_t R = find_root(S.parent, cl);
+                if (S.cstate[R] & (kValid | kFailed)) continue;
+                int64_t bq = INT64_MAX;
+                int32_t bv = 0x7fffffff;
+                for (uint32_t p = g.rp[c] + lane; p < g.rp[c + 1]; p += kWave) {
+                    const uint32_t v = g.ri[p];
+                    if ((S.in_bits[v >> 6] >> (v & 63)) & 1ull) continue;
+                    const int64_t kq = key(v);
+                    if (key_less(kq, (int32_t)v, bq, bv)) {
+                        bq = kq;
+                        bv = (int32_t)v;
+                    }
+                }
+                for (int off = kWave / 2; off > 0; off >>= 1) {
+                    const int64_t oq = __shfl_xor(bq, off);
+                    const int32_t ov = __shfl_xor(bv, off);
+                    if (key_less(oq, ov, bq, bv)) {
+                        bq = oq;
+                        bv = ov;
+                    }
+                }
+                if (lane == 0 && bv != 0x7fffffff &&
+                    (S.best_v[R] < 0 || key_less(bq, bv, S.best_q[R], S.best_v[R]))) {
+                    S.best_q[R] = bq;
+                    S.best_v[R] = bv;
+                }
+                __syncthreads();
+            }
+            // 2. clusters with an empty boundary fail; collect the picks
+            int npick = 0;
+            if (lane == 0) {
+                for (int K = 0; K < nk; K++) {
+                    if (S.parent[K] != K || (S.cstate[K] & (kValid | kFailed))) continue;
+                    if (S.best_v[K] < 0) {
+                        S.cstate[K] |= kFailed;
+                    } else {
+                        S.picks[2 * npick] = K;
+                        S.picks[2 * npick + 1] = S.best_v[K];
+                        npick++;
+                    }
+                }
+            }
+            npick = __shfl(npick, 0);
+            __syncthreads();
+            if (!npick) break;
+            rounds++;
+            // 3. apply every pick: the column joins, its checks join, clusters
+            //    that now share a check merge
+            int nadd = 0;
+            if (lane == 0) {
+                for (int i = 0; i < npick; i++) {
+                    const int32_t K = S.picks[2 * i];
+                    const uint32_t j = (uint32_t)S.picks[2 * i + 1];
+                    if (!((S.in_bits[j >> 6] >> (j & 63)) & 1ull)) {
+                        S.in_bits[j >> 6] |= 1ull << (j & 63);
+                        S.added[nadd++] = (int32_t)j;
+                    }
+                    for (uint32_t q = g.cp[j]; q < g.cp[j + 1]; q++) {
+                        const uint32_t c = g.ci[q];
+                        if (S.chk_cl[c] < 0) {
+                            S.chk_cl[c] = K;
+                        } else {
+                            int32_t ra = find_root(S.parent, K), rb = find_root(S.parent, S.chk_cl[c]);
+                            if (ra != rb) {
+                                const int32_t lo = min(ra, rb), hi = max(ra, rb);
+                                S.parent[hi] = lo;
+                                S.cstate[lo] |= S.cstate[hi] & kFailed;
+                            }
+                        }
+                    }
+                }
+            }
+            nadd = __shfl(nadd, 0);
+            __syncthreads();
+            // 4. extend the basis pool with the new columns
+            for (int i = 0; i < nadd; i++) {
+                column_vector(g, S.xbuf, (uint32_t)S.added[i], lane);
+                reduce_by(S.xbuf, nullptr, S.pool, wm, S.pool_piv, pool_n, wm, lane);
+                const int p = lowest_bit(S.xbuf, wm, lane);
+                if (p >= 0) {
+                    for (uint32_t w = lane; w < wm; w += kWave) S.pool[(size_t)pool_n * wm + w] = S.xbuf[w];
+                    if (lane == 0) S.pool_piv[pool_n] = p;
+                    pool_n++;
+                }
+                __syncthreads();
+            }
+            // 5. validity of every live cluster that has not failed
+            for (int K = 0; K < nk; K++) {
+                if (S.parent[K] != K || (S.cstate[K] & kFailed)) continue;
+                for (uint32_t base = 0; base < g.m; base += kWave) {
+                    const uint32_t c = base + lane;
+                    bool in = false;
+                    if (c < g.m && s[c]) {
+                        const int32_t cl = S.chk_cl[c];
+                        in = cl >= 0 && find_root(S.parent, cl) == K;
+                    }
+                    const uint64_t mask = __ballot(in);
+                    if (lane == 0) S.xbuf[base / kWave] = mask;
+                }
+                __syncthreads();
+                reduce_by(S.xbuf, nullptr, S.pool, wm, S.pool_piv, pool_n, wm, lane);
+                const bool valid = lowest_bit(S.xbuf, wm, lane) < 0;
+                if (lane == 0) S.cstate[K] = valid ? (S.cstate[K] | kValid) : (S.cstate[K] & ~kValid);
+                __syncthreads();
+            }
+        }
+
+        // ---- gather the columns of valid clusters, rank them, solve
+        int ncol = 0;
+        bool failed = false;
+        if (lane == 0) {
+            for (uint32_t w = 0; w < g.words_n; w++) {
+                uint64_t x = S.in_bits[w];
+                while (x) {
+                    const int b = __ffsll((long long)x) - 1;
+                    x &= x - 1;
+                    const uint32_t v = w * 64 + b;
+                    const int32_t R = find_root(S.parent, S.chk_cl[g.ci[g.cp[v]]]);
+                    S.ccount[R]++;
+                    if (S.cstate[R] & kValid) S.cols[ncol++] = (int32_t)v;
+                }
+            }
+        }
+        ncol = __shfl(ncol, 0);
+        __syncthreads();
+        for (int i = lane; i < ncol; i += kWave) S.ckey[i] = key((uint32_t)S.cols[i]);
+        __syncthreads();
+        for (int i = lane; i < ncol; i += kWave) {
+            const int64_t qi = S.ckey[i];
+            const int32_t vi = S.cols[i];
+            int r = 0;
+            for (int j = 0; j < ncol; j++)
+                if (key_less(S.ckey[j], S.cols[j], qi, vi)) r++;
+            S.sorted[r] = vi;
+        }
+        __syncthreads();
+        int nb = 0;
+        for (int i = 0; i < ncol; i++) {
+            const uint32_t v = (uint32_t)S.sorted[i];
+            column_vector(g, S.xbuf, v, lane);
+            for (uint32_t w = lane; w < wm; w += kWave) S.cbuf[w] = 0;
+            reduce_by(S.xbuf, S.cbuf, S.basis2, 2 * (size_t)wm, S.piv2, nb, wm, lane);
+            const int p = lowest_bit(S.xbuf, wm, lane);
+            if (p >= 0) {
+                if (lane == 0) S.cbuf[nb >> 6] ^= 1ull << (nb & 63);
+                __syncthreads();
+                uint64_t* dst = S.basis2 + (size_t)nb * 2 * wm;
+                for (uint32_t w = lane; w < wm; w += kWave) {
+                    dst[w] = S.xbuf[w];
+                    dst[wm + w] = S.cbuf[w];
+                }
+                if (lane == 0) {
+                    S.piv2[nb] = p;
+                    S.pivcol[nb] = (int32_t)v;
+                }
+                nb++;
+            }
+            __syncthreads();
+        }
+        // target: s on the checks of valid clusters
+        for (uint32_t base = 0; base < g.m; base += kWave) {
+            const uint32_t c = base + lane;
+            bool in = false;
+            if (c < g.m && s[c]) {
+                const int32_t cl = S.chk_cl[c];
+                in = cl >= 0 && (S.cstate[find_root(S.parent, cl)] & kValid);
+            }
+            const uint64_t mask = __ballot(in);
+            if (lane == 0) S.xbuf[base / kWave] = mask;
+        }
+        for (uint32_t w = lane; w < wm; w += kWave) S.cbuf[w] = 0;
+        __syncthreads();
+        reduce_by(S.xbuf, S.cbuf, S.basis2, 2 * (size_t)wm, S.piv2, nb, wm, lane);
+        if (lane == 0)
+            for (int i = 0; i < nb; i++)
+                if ((S.cbuf[i >> 6] >> (i & 63)) & 1ull) {
+                    const uint32_t v = (uint32_t)S.pivcol[i];
+                    S.ebits[v >> 6] |= 1ull << (v & 63);
+                }
+        __syncthreads();
+        uint64_t* out = a.corrections + gshot * g.words_n;
+        for (uint32_t w = lane; w < g.words_n; w += kWave) out[w] = S.ebits[w];
+        int nclus = 0, largest = 0;
+        if (lane == 0) {
+            for (int K = 0; K < nk; K++) {
+                if (S.parent[K] != K) continue;
+                nclus++;
+                largest = max(largest, S.ccount[K]);
+                if (!(S.cstate[K] & kValid)) failed = true;
+            }
+            if (a.stats) {
+                vibe_shot_stats* st = a.stats + gshot;
+                if (!a.list) {
+                    st->winner = -1;
+                    st->t_win = 0;
+                    st->n_conv = 0;
+                    st->member_iters = 0;
+                }
+                st->flags = VIBE_FLAG_LSD_USED | (failed ? VIBE_FLAG_LSD_FAILED : 0u);
+                st->lsd_clusters = (uint32_t)nclus;
+                st->lsd_largest = (uint32_t)largest;
+                st->lsd_rounds = (uint32_t)rounds;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+size_t lsd_scratch_per_block(const DevGraph& g) { return al8(lsd_layout(g, nullptr, nullptr)) + 256; }
+
+int launch_lsd(const DevGraph& g, const LsdLaunch& a, hipStream_t st) {
+    if (!a.n_list) return VIBE_OK;
+    hipLaunchKernelGGL(lsd_kernel, dim3(a.grid), dim3(kWave), 0, st, g, a);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? VIBE_OK : hip_fail(e, "lsd_kernel launch");
+}
+
+}  // namespace vibe

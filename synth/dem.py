@@ -195,9 +195,10 @@ def circuit_dem(d: int, rounds: int, p: float, return_stats: bool = False):
     """X-memory circuit-level DEM with the Uniform noise model at rate p.
 
     Qubits: data 0..n-1, X ancillas n..n+P-1, Z ancillas n+P..n+2P-1.
-    One round: reset ancillas (X ones in |+>, Z ones in |0>); six CNOT layers
-    ancilla->data for the X checks (slot order of the plaquette offsets); six
-    CNOT layers data->ancilla for the Z checks; measure ancillas.  The data
+    One round: reset the X ancillas in |+>; six CNOT layers ancilla->data
+    (slot order of the plaquette offsets); read the X ancillas out and reset
+    the Z ancillas in |0>; six CNOT layers data->ancilla; read the Z ancillas
+    out.  Every qubit that no operation touches in a layer idles in it.  The data
     start in |+> (reset with the first round's ancillas) and end with an
     X-basis measurement.  Detectors, round-major with X before Z inside a
     round: X checks in rounds 1..R and a final one from the data readout; Z
@@ -299,20 +300,9 @@ def circuit_dem(d: int, rounds: int, p: float, return_stats: bool = False):
         add(sz[qb], p)  # readout flip
 
     all_q = list(range(nq))
-    for r in range(R, 0, -1):
-        # measure layer: (noise then measure) -> backward: measure, then noise
-        for c in range(P):
-            sz[xa[c]] = dets_mx(c, r)
-            sx[xa[c]] = 0
-            sx[za[c]] = dets_mz(c, r)
-            sz[za[c]] = 0
-        for c in range(P):
-            add(sz[xa[c]], p)  # X-basis readout flip
-            add(sx[za[c]], p)  # Z-basis readout flip
-        for qb in range(n):
-            depol1(qb)  # data idle during the readout
-        # Z-check CNOT layers, reversed
-        for layer in reversed(z_layers):
+
+    def cnot_layers_backward(layers):
+        for layer in reversed(layers):
             busy = set()
             for (ctl, tgt) in layer:
                 depol2(ctl, tgt)
@@ -320,37 +310,47 @@ def circuit_dem(d: int, rounds: int, p: float, return_stats: bool = False):
                 busy.add(tgt)
             for q in all_q:
                 if q not in busy:
-                    depol1(q)
+                    depol1(q)  # idle in this layer
             for (ctl, tgt) in layer:
                 # backward through CNOT: X_ctl -> X_ctl X_tgt, Z_tgt -> Z_ctl Z_tgt
                 sx[ctl] ^= sx[tgt]
                 sz[tgt] ^= sz[ctl]
-        for layer in reversed(x_layers):
-            busy = set()
-            for (ctl, tgt) in layer:
-                depol2(ctl, tgt)
-                busy.add(ctl)
-                busy.add(tgt)
-            for q in all_q:
-                if q not in busy:
-                    depol1(q)
-            for (ctl, tgt) in layer:
-                sx[ctl] ^= sx[tgt]
-                sz[tgt] ^= sz[ctl]
-        # reset layer: (reset then noise) -> backward: noise, then reset
+
+    for r in range(R, 0, -1):
+        # layer: Z-ancilla readout (flip before it); data idle
         for c in range(P):
-            add(sz[xa[c]], p)  # |+> prepared with a phase flip
-            add(sx[za[c]], p)  # |0> prepared with a bit flip
+            sx[za[c]] = dets_mz(c, r)
+            sz[za[c]] = 0
+        for c in range(P):
+            add(sx[za[c]], p)
+        for qb in range(n):
+            depol1(qb)
+        cnot_layers_backward(z_layers)
+        # layer: X-ancilla readout (flip before it) and Z-ancilla reset (flip
+        # after it); data idle
+        for c in range(P):
+            add(sx[za[c]], p)
+            sx[za[c]] = sz[za[c]] = 0
+        for c in range(P):
+            sz[xa[c]] = dets_mx(c, r)
+            sx[xa[c]] = 0
+        for c in range(P):
+            add(sz[xa[c]], p)
+        for qb in range(n):
+            depol1(qb)
+        cnot_layers_backward(x_layers)
+        # layer: X-ancilla reset (flip after it); data reset in round 1,
+        # otherwise idle
+        for c in range(P):
+            add(sz[xa[c]], p)
+            sx[xa[c]] = sz[xa[c]] = 0
         if r == 1:
             for qb in range(n):
                 add(sz[qb], p)  # data prepared in |+> with a phase flip
                 sx[qb] = sz[qb] = 0
         else:
             for qb in range(n):
-                depol1(qb)  # data idle during the ancilla reset
-        for c in range(P):
-            sx[xa[c]] = sz[xa[c]] = 0
-            sx[za[c]] = sz[za[c]] = 0
+                depol1(qb)
 
     det_mask = obs_bit - 1
     undetectable = [s for s in sigs if (s & det_mask) == 0]
