@@ -3,17 +3,19 @@
 //
 // One wavefront decodes one work item = (shot, member).
 //
-// Exact serial sweep without row rescans.  In the member's message layout
-// every row keeps its edges in the order the sweep visits them.  When column
-// v is visited, the messages of the row's earlier edges were refreshed in
-// this sweep and those of its later edges still hold the previous sweep's
-// values.  So min and sign parity over N(c) \ v split into
+// Exact serial sweep without row rescans.  When column v is visited, the
+// edges of a row that come before v in the sweep carry this sweep's messages
+// and those after v still hold the previous sweep's.  So min and sign parity
+// over N(c) \ v split into
 //   * a prefix state per check (running min and parity of this sweep's new
 //     messages), 4 bytes of LDS per check, and
-//   * a suffix state stored in place at the next edge of the row, computed
-//     for the whole slab by one backward segmented scan after each sweep.
-// A visited edge overwrites its own slot with the new message; the suffix
-// state it would have held is never read again in this sweep.
+//   * a suffix state (min and parity of the previous sweep's messages on the
+//     row's later edges), kept in the edge's own slot of the message slab.
+// The slab follows the member's sweep order, so a chunk reads the suffix
+// states of its edges and overwrites them with the new messages in one
+// contiguous run.  After the sweep, a backward pass over the chunks with a
+// running state per check (LDS) turns the new messages into the next sweep's
+// suffix states, again one contiguous run per chunk.
 //
 // Columns that share no check commute, so the host grouped the sweep into
 // dependency levels and chunks of at most 64 edges holding whole columns;
@@ -61,28 +63,45 @@ __device__ inline uint32_t preceding_converged(const uint64_t* mask, uint32_t t,
     return wave_sum_u32(cnt);
 }
 
-// Rewrite the slab (new messages as float bits) into suffix states, row by
-// row from the back: state[e] = combine(encode(mu[e]), state[e + 1]) inside a
-// row.  One wavefront, blocks of 64 positions from the end, segmented scan.
-__device__ void suffix_pass(const DevGraph& g, uint32_t* slab, int lane) {
-    uint32_t carry = g.ident;
-    const int nb = (int)((g.E + kWave - 1) / kWave);
-    for (int b = nb - 1; b >= 0; b--) {
-        const uint32_t e = (uint32_t)b * kWave + lane;
-        const bool valid = e < g.E;
-        uint32_t acc = valid ? rs_encode(__uint_as_float(slab[e])) : g.ident;
-        int stop = valid ? (int)((g.row_last[e >> 6] >> (e & 63)) & 1ull) : 1;
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t oacc = __shfl_down(acc, d);
-            const int ostop = __shfl_down(stop, d);
-            if (lane + d < kWave && !stop) {
-                acc = rs_combine(acc, oacc);
-                stop = ostop;
+// Backward pass: turn the slab's new messages (float bits) into the suffix
+// states of the next sweep.  Chunks from last to first; running[c] is the
+// state of the part of row c already passed.  Edges of one chunk sit in
+// distinct rows, so a chunk is one parallel step.
+__device__ void suffix_pass(const DevGraph& g, uint32_t* slab, uint32_t* running, uint32_t ch_lo,
+                            uint32_t ch_hi, size_t mbase, int lane) {
+    for (uint32_t c = lane; c < g.m; c += kWave) running[c] = g.ident;
+    __syncthreads();
+    uint32_t nmeta = 0, nx = 0, nlen = 0;
+    size_t npos = 0;
+    if (ch_hi > ch_lo) {
+        const uint32_t beg = g.chunk_off[ch_hi - 1];
+        nlen = g.chunk_off[ch_hi] - beg;
+        npos = beg - mbase + lane;
+        if ((uint32_t)lane < nlen) {
+            nmeta = g.slots[beg + lane].meta;
+            nx = slab[npos];
+        }
+    }
+    for (uint32_t ch = ch_hi; ch-- > ch_lo;) {
+        const uint32_t meta = nmeta, x = nx, len = nlen;
+        const size_t pos = npos;
+        if (ch > ch_lo) {
+            const uint32_t beg = g.chunk_off[ch - 1];
+            nlen = g.chunk_off[ch] - beg;
+            npos = beg - mbase + lane;
+            if ((uint32_t)lane < nlen) {
+                nmeta = g.slots[beg + lane].meta;
+                nx = slab[npos];
             }
         }
-        if (!stop) acc = rs_combine(acc, carry);
-        carry = __shfl(acc, 0);
-        if (valid) slab[e] = acc;
+        if ((uint32_t)lane < len) {
+            const uint32_t c = meta & 0xffffu;
+            const uint32_t st = running[c];
+            slab[pos] = st;
+            running[c] = rs_combine(rs_encode(__uint_as_float(x)), st);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -148,7 +167,8 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
             }
             continue;
         }
-        const uint32_t* init = g.init_suf + (size_t)mem * g.E;
+        const size_t mbase = (size_t)mem * g.E;  // this member's first slot
+        const uint32_t* init = g.init_suf + mbase;
         for (uint32_t e = lane; e < g.E; e += kWave) slab[e] = init[e];
         for (uint32_t w = lane; w < g.words_n; w += kWave) eb[w] = g.e0[w];
         __syncthreads();
@@ -173,30 +193,33 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
             for (uint32_t c = lane; c < g.m; c += kWave) pref[c] = g.ident;
             __syncthreads();
 
-            // software pipeline: the slot and suffix state of the next chunk
-            // are loaded while the current chunk is processed.  A suffix state
-            // at a position after an edge is not overwritten before that edge
-            // is visited, so the early loads read final values.
-            Slot nsl{0, 0, 0};
+            // software pipeline: the slots and suffix states of the next chunk
+            // are loaded while the current chunk is processed (suffix states
+            // of later slots are final for the whole sweep)
+            Slot nsl{0, 0};
             uint32_t nsuf = g.ident, nlen = 0;
+            size_t npos = 0;
             if (ch_lo < ch_hi) {
                 const uint32_t nbeg = g.chunk_off[ch_lo];
                 nlen = g.chunk_off[ch_lo + 1] - nbeg;
+                npos = nbeg - mbase + lane;
                 if ((uint32_t)lane < nlen) {
                     nsl = g.slots[nbeg + lane];
-                    nsuf = ((nsl.meta >> 24) & 1u) ? g.ident : slab[nsl.pos + 1];
+                    nsuf = slab[npos];
                 }
             }
             for (uint32_t ch = ch_lo; ch < ch_hi; ch++) {
                 const Slot sl = nsl;
                 const uint32_t suf = nsuf;
                 const uint32_t len = nlen;
+                const size_t pos = npos;
                 if (ch + 1 < ch_hi) {
                     const uint32_t nbeg = g.chunk_off[ch + 1];
                     nlen = g.chunk_off[ch + 2] - nbeg;
+                    npos = nbeg - mbase + lane;
                     if ((uint32_t)lane < nlen) {
                         nsl = g.slots[nbeg + lane];
-                        nsuf = ((nsl.meta >> 24) & 1u) ? g.ident : slab[nsl.pos + 1];
+                        nsuf = slab[npos];
                     }
                 }
                 const bool act = (uint32_t)lane < len;
@@ -228,7 +251,7 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
                 if (act) {
                     L = clampf(L, lim);
                     x = clampf(x, lim);
-                    slab[sl.pos] = __float_as_uint(x);
+                    slab[pos] = __float_as_uint(x);
                     pref[c] = rs_combine(pre, rs_encode(x));
                     const uint32_t v = sl.v;
                     const bool enew = L <= 0.0f;
@@ -256,7 +279,7 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
                 if (a.stop_on_converge) break;
             }
             if (t < a.T_run) {
-                suffix_pass(g, slab, lane);
+                suffix_pass(g, slab, pref, ch_lo, ch_hi, mbase, lane);
                 __syncthreads();
             }
         }

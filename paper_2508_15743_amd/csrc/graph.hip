@@ -160,12 +160,6 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
             uint32_t v = l_indices[a];
             lobs[(size_t)r * words_n + v / 64] ^= 1ull << (v % 64);
         }
-    std::vector<uint64_t> row_last((E + 63) / 64 + 1, 0);
-    for (uint32_t r = 0; r < m; r++)
-        if (h_indptr[r + 1] > h_indptr[r]) {
-            uint32_t e = h_indptr[r + 1] - 1;
-            row_last[e / 64] |= 1ull << (e % 64);
-        }
     auto enc = [](float x) -> uint32_t {
         float a = std::fabs(x);
         uint32_t bits;
@@ -179,18 +173,19 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     //      in perms[i]; columns that share no check commute, so the sweep is
     //      regrouped into dependency levels (level(v) = 1 + the largest level
     //      of an earlier column sharing a check), each level cut into chunks
-    //      of at most 64 edges holding whole columns.  Every row keeps its
-    //      edges in sweep order in the member's message layout, so at column
-    //      v's turn the edges of a row before v carry this sweep's messages
-    //      and those after v the previous sweep's.
+    //      of at most 64 edges holding whole columns.  The member's message
+    //      slab follows the same slot order.  At column v's turn, the edges of
+    //      a row that come before v in the sweep carry this sweep's messages
+    //      and those after v the previous sweep's; init_suf holds, at every
+    //      slot, the state (min |mu|, sign parity) of the row's later edges
+    //      for the initial messages mu = lambda.
     std::vector<Slot> slots((size_t)c.L * E);
     std::vector<uint32_t> init_suf((size_t)c.L * E);
     std::vector<uint32_t> chunk_off;
     std::vector<uint32_t> member_chunk(c.L + 1, 0);
     uint32_t lev_min = UINT32_MAX, lev_max = 0;
     {
-        std::vector<uint32_t> last(m), level(n), count, start, order(n), seq(n), mpos(E);
-        std::vector<uint32_t> rowbuf;
+        std::vector<uint32_t> last(m), level(n), count, start, order(n), running(m);
         for (uint32_t i = 0; i < c.L; i++) {
             const uint32_t* pi = perms + (size_t)i * n;
             std::fill(last.begin(), last.end(), 0);
@@ -219,27 +214,6 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
                     if (cp[v + 1] > cp[v]) order[fillp[level[v]]++] = v;  // sweep order
                 }
             }
-            const uint32_t nv = nlev ? start[nlev + 1] : 0;
-            for (uint32_t a = 0; a < nv; a++) seq[order[a]] = a;
-            // member layout of every row: its edges sorted by sweep position
-            for (uint32_t r = 0; r < m; r++) {
-                const uint32_t lo = h_indptr[r], hi = h_indptr[r + 1];
-                rowbuf.assign(h_indices + lo, h_indices + hi);
-                std::sort(rowbuf.begin(), rowbuf.end(),
-                          [&](uint32_t x, uint32_t y) { return seq[x] < seq[y]; });
-                // CSR edge of column rowbuf[q] in row r -> member position lo + q
-                for (uint32_t q = 0; q < hi - lo; q++) {
-                    const uint32_t v = rowbuf[q];
-                    const uint32_t a = (uint32_t)(std::lower_bound(h_indices + lo, h_indices + hi, v) - h_indices);
-                    mpos[a] = lo + q;
-                }
-                // suffix states of the initial messages mu = lambda
-                uint32_t acc = ident;
-                for (uint32_t q = hi - lo; q-- > 0;) {
-                    acc = rs_combine(enc(lam[rowbuf[q]]), acc);
-                    init_suf[(size_t)i * E + lo + q] = acc;
-                }
-            }
             member_chunk[i] = (uint32_t)chunk_off.size();
             const size_t sbase = (size_t)i * E;
             size_t spos = 0;
@@ -253,10 +227,8 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
                         in_chunk = 0;
                     }
                     for (uint32_t j = cp[v]; j < cp[v + 1]; j++) {
-                        const uint32_t r = ci[j], pos = mpos[ce[j]];
                         Slot sl;
-                        sl.pos = pos;
-                        sl.meta = r | ((j - cp[v]) << 16) | (deg << 20) | ((pos + 1 == h_indptr[r + 1]) ? (1u << 24) : 0u);
+                        sl.meta = ci[j] | ((j - cp[v]) << 16) | (deg << 20);
                         sl.v = v;
                         slots[sbase + spos++] = sl;
                     }
@@ -264,6 +236,14 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
                 }
             }
             if (spos != E) return fail(VIBE_EINVAL, "internal: schedule does not cover every edge");
+            // suffix states of the initial messages, from the end of the sweep
+            std::fill(running.begin(), running.end(), ident);
+            for (size_t q = E; q-- > 0;) {
+                const Slot& sl = slots[sbase + q];
+                const uint32_t r = sl.meta & 0xffffu;
+                init_suf[sbase + q] = running[r];
+                running[r] = rs_combine(enc(lam[sl.v]), running[r]);
+            }
         }
         member_chunk[c.L] = (uint32_t)chunk_off.size();
         chunk_off.push_back((uint32_t)((size_t)c.L * E));  // end of the last chunk
@@ -308,7 +288,6 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
         (rc = upload(h, lam.data(), lam.size(), &d.lam)) ||
         (rc = upload(h, lam64.data(), lam64.size(), &d.lam64)) ||
         (rc = upload(h, e0.data(), e0.size(), &d.e0)) ||
-        (rc = upload(h, row_last.data(), row_last.size(), &d.row_last)) ||
         (rc = upload(h, init_suf.data(), init_suf.size(), &d.init_suf)) ||
         (rc = upload(h, slots.data(), slots.size(), &d.slots)) ||
         (rc = upload(h, chunk_off.data(), chunk_off.size(), &d.chunk_off)) ||

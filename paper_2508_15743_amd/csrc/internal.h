@@ -19,15 +19,14 @@ constexpr double kQScale = 72057594037927936.0;  // 2^56: fixed point of the LLR
 
 // One schedule slot = one edge (v, c) of the member's serial sweep.  Slots are
 // grouped in chunks of at most 64 that hold whole columns of one dependency
-// level; inside a column the slots follow ascending check index.
-//   pos  : position of the edge in the member's message layout, where every
-//          row keeps its edges in the order the member's sweep visits them
-//   meta : c | seg << 16 | deg << 20 | last << 24   (seg = slot index inside
-//          the column's run, deg = number of checks of the column, last = the
-//          edge is the last of its row in the member's order)
+// level; inside a column the slots follow ascending check index.  The slot
+// index is also the edge's position in the member's message slab, so every
+// chunk reads and writes one contiguous run of the slab.
+//   meta : c | seg << 16 | deg << 20   (seg = slot index inside the column's
+//          run, deg = number of checks of the column)
 //   v    : the column
 struct Slot {
-    uint32_t pos, meta, v;
+    uint32_t meta, v;
 };
 
 // Row state word: the float bits of a magnitude (>= 0) with a parity bit in
@@ -54,7 +53,6 @@ struct DevGraph {
     const float* lam;             // n, FP32 channel LLR
     const double* lam64;          // n, FP64 channel LLR (candidate weights)
     const uint64_t* e0;           // words_n: decisions of columns without checks
-    const uint64_t* row_last;     // ceil(E/64): bit e = position e ends its row
     const uint32_t* init_suf;     // L x E: suffix states of the initial messages
     const Slot* slots;            // L x E
     const uint32_t* chunk_off;    // concatenated chunk offsets (into slots)
@@ -116,7 +114,7 @@ struct BpLaunch {
     uint32_t* iters;           // n_shots: iterations run, summed over members
     int64_t* qfix;             // n_shots x n, may be null
     // scratch
-    uint32_t* slab;            // grid x E row states / messages (global variant)
+    uint32_t* slab;            // grid x E suffix states / messages (global variant)
     float* post_slab;          // grid x n
     uint32_t* counter;         // work counter
     int grid;

@@ -1,0 +1,253 @@
+"""Parity of the HIP decode path (through the C ABI) with the FP64 oracle.
+
+Bars (the device computes BP messages in FP32, the oracle in FP64):
+  * BP, per member: the convergence iteration and the hard decision are
+    identical; the final posteriors agree to 1e-4 of the largest posterior
+    magnitude of that member.  Rounding in FP32 sums of <= 16 terms adds
+    about 2^-24 of the largest term per operation; over <= 50 iterations of
+    min-sum, which is 1-Lipschitz in its inputs apart from the alpha and
+    column-degree factors that also scale the magnitudes, that stays near
+    1e-6 of the largest magnitude, so 1e-4 leaves two decades of margin.
+  * LSD on identical soft input: bit-exact corrections and cluster stats.
+  * whole decoder: identical corrections on every shot whose oracle tie
+    witnesses are clear, i.e. the smallest |L_v| of any BP decision is
+    >= 1e-3 (the FP32 error of a decision near zero) and the smallest gap
+    between soft values LSD compared is >= 1e-9 of the largest |q| (FP32
+    posteriors resolve about 1e-7 relative); the logical error rate lies in
+    the oracle's 95% interval.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth.dem import circuit_dem, code_capacity_dem, dem_from_dense, phenomenological_dem
+from synth.sample import permutations, sample
+
+pytestmark = pytest.mark.gpu
+
+NT = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_15743_amd as P
+
+    P.lib()  # fails loudly if the library is missing
+    return torch
+
+
+def _graph(dem, L, M, T, seed, **kw):
+    import paper_2508_15743_amd as P
+
+    perms = permutations(dem.n, L, seed)
+    return P.Graph.from_dem(dem, perms, L=L, M=M, T_max=T, **kw), perms
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _bp_parity(torch, dem, L, T, shots, seed, stop):
+    import paper_2508_15743_amd as P
+
+    G, perms = _graph(dem, L, min(5, L), T, seed)
+    b = sample(dem, shots, seed + 1)
+    tc, post, eh = G.bp_ensemble(_dev(torch, b.syndromes), T_run=T, stop=stop)
+    tc, post, eh = tc.cpu().numpy(), post.cpu().numpy(), P.unpack_bits(eh, dem.n)
+    g = O.OracleGraph(dem)
+    for i in range(shots):
+        for j in range(L):
+            r = O.bp(g, b.syndromes[i], perm=perms[j], T=T, stop=stop)
+            if r["min_abs_post"] < 1e-3:
+                continue  # a decision within FP32 error of zero
+            assert r["t_conv"] == tc[i, j], (i, j)
+            assert np.array_equal(r["ehat"], eh[i, j]), (i, j)
+            scale = max(np.abs(r["post"]).max(), 1.0)
+            err = np.abs(post[i, j].astype(np.float64) - r["post"]).max()
+            assert err <= 1e-4 * scale, (i, j, err, scale)
+    G.close()
+
+
+def test_bp_members_code_capacity(torch_cuda):
+    _bp_parity(torch_cuda, code_capacity_dem(5, 0.05), 16, 32, 60, 1, stop=True)
+
+
+def test_bp_members_phenomenological_no_stop(torch_cuda):
+    # several tiles of 64 edges per level and degree-1 checks; no early stop
+    _bp_parity(torch_cuda, phenomenological_dem(11, 11, 0.01, 0.01), 4, 12, 8, 2, stop=False)
+
+
+def test_bp_members_circuit_full_size(torch_cuda):
+    # the benchmark graph itself: ~900 levels, rows of up to 194 edges
+    _bp_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 2, 3, 2, 3, stop=False)
+
+
+def _lsd_parity(torch, dem, shots, seed, noise=2.0):
+    import paper_2508_15743_amd as P
+
+    G, _ = _graph(dem, 2, 1, 5, seed)
+    b = sample(dem, shots, seed)
+    lam = np.log((1 - dem.priors) / dem.priors)
+    e = b.errors_dense(dem.n)
+    rng = np.random.default_rng(seed)
+    soft = (lam[None, :] * (1 - 2 * e.astype(np.float64)) +
+            rng.normal(scale=noise, size=e.shape)).astype(np.float32)
+    corr, st = G.lsd(_dev(torch, b.syndromes), _dev(torch, soft))
+    got, st = P.unpack_bits(corr, dem.n), st.cpu().numpy()
+    g = O.OracleGraph(dem)
+    for i in range(shots):
+        r = O.lsd(g, b.syndromes[i], soft[i].astype(np.float64))
+        assert np.array_equal(r["ehat"], got[i]), i
+        assert (r["clusters"], r["largest"], r["rounds"]) == tuple(st[i, 4:7]), i
+        assert bool(st[i, 0] & 4) == r["failed"], i
+    G.close()
+
+
+def test_lsd_bit_exact_code_capacity(torch_cuda):
+    _lsd_parity(torch_cuda, code_capacity_dem(5, 0.08), 400, 5)
+
+
+def test_lsd_bit_exact_phenomenological(torch_cuda):
+    _lsd_parity(torch_cuda, phenomenological_dem(11, 11, 0.01, 0.01), 120, 6)
+
+
+def test_lsd_bit_exact_circuit_full_size(torch_cuda):
+    _lsd_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 40, 7)
+
+
+def test_lsd_edge_cases(torch_cuda):
+    """Zero syndrome: nothing to do.  A flipped check with no columns: the
+    cluster cannot grow, LSD reports failure and leaves it unexplained."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    H = np.array([[1, 1, 0], [0, 1, 1], [0, 0, 0]], np.uint8)
+    dem = dem_from_dense(H, [0.1, 0.1, 0.1], np.ones((1, 3), np.uint8))
+    G = P.Graph.from_dem(dem, np.array([[0, 1, 2], [2, 1, 0]]), L=2, M=1, T_max=5)
+    s = np.array([[0, 0, 0], [0, 0, 1], [1, 0, 1]], np.uint8)
+    soft = np.zeros((3, 3), np.float32)
+    corr, st = G.lsd(_dev(torch, s), _dev(torch, soft))
+    e = P.unpack_bits(corr, 3)
+    st = st.cpu().numpy()
+    assert not e[0].any() and st[0, 4] == 0
+    assert st[1, 0] & 4 and not e[1].any()
+    assert st[2, 0] & 4 and e[2].tolist() == [1, 0, 0]  # c0 explained by v0
+    G.close()
+
+
+def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots):
+    import paper_2508_15743_amd as P
+
+    G, perms = _graph(dem, L, M, T, seed)
+    b = sample(dem, shots, seed + 7)
+    corr, obs, st = G.decode(_dev(torch, b.syndromes))
+    e, obs, st = P.unpack_bits(corr, dem.n), obs.cpu().numpy(), st.cpu().numpy()
+    H = dem.dense_h().astype(np.int64)
+    ok = (st[:, 0] & 4) == 0
+    assert np.array_equal((e[ok].astype(np.int64) @ H.T) % 2, b.syndromes[ok])
+    assert np.array_equal(obs, (e.astype(np.int64) @ dem.dense_l().T.astype(np.int64) % 2).astype(np.uint8))
+    ref = O.decode(O.OracleGraph(dem), perms, b.syndromes[:oracle_shots], L=L, M=M, T=T,
+                   threads=NT, want_q=True)
+    agree = (ref["ehat"] == e[:oracle_shots]).all(1)
+    qscale = np.nanmax(np.abs(ref["q"]), axis=1)
+    qscale = np.where(np.isfinite(qscale), qscale, 1.0)
+    tie = (ref["min_abs_post"] < 1e-3) | (ref["min_q_gap"] < 1e-9 * qscale)
+    bad = np.flatnonzero(~agree & ~tie)
+    assert len(bad) == 0, (bad[:10], ref["min_abs_post"][bad[:10]], ref["min_q_gap"][bad[:10]])
+    # logical error rate inside the oracle's 95% (Clopper-Pearson) interval
+    from scipy.stats import beta
+
+    k = int((ref["obs"] != b.observables[:oracle_shots]).any(1).sum())
+    n = oracle_shots
+    lo = beta.ppf(0.025, k, n - k + 1) if k else 0.0
+    hi = beta.ppf(0.975, k + 1, n - k) if k < n else 1.0
+    ler = (obs != b.observables).any(1).mean()
+    assert lo <= ler <= hi, (ler, lo, hi)
+    G.close()
+    return agree.mean()
+
+
+def test_decode_code_capacity(torch_cuda):
+    _decode_parity(torch_cuda, code_capacity_dem(5, 0.05), 16, 5, 32, 10000, 3, 10000)
+
+
+def test_decode_phenomenological(torch_cuda):
+    _decode_parity(torch_cuda, phenomenological_dem(11, 11, 0.01, 0.01), 32, 5, 50, 6000, 4, 600)
+
+
+def test_decode_circuit_full_size(torch_cuda):
+    _decode_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 32, 5, 20, 4096, 5, 32)
+
+
+def test_decode_deterministic_and_batch_invariant(torch_cuda):
+    """Run to run, batch split and shot order do not change any output."""
+    torch = torch_cuda
+    dem = phenomenological_dem(7, 7, 0.02, 0.02)
+    G, _ = _graph(dem, 16, 5, 30, 9)
+    b = sample(dem, 3000, 10)
+    s = _dev(torch, b.syndromes)
+    c1, o1, s1 = G.decode(s)
+    c2, o2, s2 = G.decode(s)
+    assert torch.equal(c1, c2) and torch.equal(o1, o2) and torch.equal(s1[:, :7], s2[:, :7])
+    ca, _, _ = G.decode(s[:1234])
+    cb, _, _ = G.decode(s[1234:])
+    assert torch.equal(torch.cat([ca, cb]), c1)
+    perm = torch.randperm(s.shape[0], generator=torch.Generator().manual_seed(0)).to(s.device)
+    cp, _, _ = G.decode(s[perm].contiguous())
+    assert torch.equal(cp, c1[perm])
+    G.close()
+
+
+def test_decode_zero_and_empty(torch_cuda):
+    """B = 0 is a no-op; an all-zero syndrome decodes to e = 0 via member 0 at
+    iteration 1."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    dem = code_capacity_dem(5, 0.05)
+    G, _ = _graph(dem, 8, 3, 10, 1)
+    s = torch.zeros((0, dem.m), dtype=torch.uint8, device="cuda:0")
+    corr, obs, st = G.decode(s)
+    assert corr.shape[0] == 0
+    s = torch.zeros((5, dem.m), dtype=torch.uint8, device="cuda:0")
+    corr, obs, st = G.decode(s)
+    st = st.cpu().numpy()
+    assert not P.unpack_bits(corr, dem.n).any()
+    assert (st[:, 0] == 1).all() and (st[:, 1] == 0).all() and (st[:, 2] == 1).all()
+    G.close()
+
+
+def test_invalid_arguments_rejected(torch_cuda):
+    import paper_2508_15743_amd as P
+
+    dem = code_capacity_dem(3, 0.1)
+    perms = permutations(dem.n, 4, 0)
+    with pytest.raises(P.VibeError) as ei:
+        P.Graph(dem.h_indptr, dem.h_indices, np.full(dem.n, 1.5), dem.l_indptr, dem.l_indices, perms,
+                m=dem.m, n=dem.n, L=4, M=2, T_max=5)
+    assert ei.value.code == P.VIBE_EINVAL
+    bad = perms.copy()
+    bad[0, 0] = bad[0, 1]
+    with pytest.raises(P.VibeError):
+        P.Graph.from_dem(dem, bad, L=4, M=2, T_max=5)
+    with pytest.raises(P.VibeError):
+        P.Graph.from_dem(dem, perms, L=4, M=5, T_max=5)
+
+
+@pytest.mark.skip(reason="vibe_decode_plain is switched off: its first GPU run stalled and the "
+                         "cause has not been found (see the design notes)")
+def test_plain_equals_batched(torch_cuda):
+    torch = torch_cuda
+    dem = code_capacity_dem(5, 0.05)
+    G, _ = _graph(dem, 16, 5, 32, 3)
+    b = sample(dem, 50, 4)
+    s = _dev(torch, b.syndromes)
+    c1, _, _ = G.decode(s)
+    c2, _, _ = G.decode(s, plain=True)
+    assert torch.equal(c1, c2)
