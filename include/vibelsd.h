@@ -130,8 +130,6 @@ int vibe_decode(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint64_t* c
  * on its own (ensemble, selection, LSD if needed, observables) before the
  * next one starts.  Same arguments and results as vibe_decode; meant as the
  * per-shot-launch baseline of the batched form.
- * Currently returns VIBE_EUNSUPPORTED: the path is switched off until the
- * cause of a stall seen on its first GPU run is found.
  */
 int vibe_decode_plain(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint64_t* corrections,
                       uint8_t* observables, vibe_shot_stats* stats, void* stream);

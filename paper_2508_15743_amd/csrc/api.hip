@@ -259,17 +259,21 @@ extern "C" int vibe_decode(vibe_graph* G, const uint8_t* syndromes, uint64_t B, 
 extern "C" int vibe_decode_plain(vibe_graph* G, const uint8_t* syndromes, uint64_t B,
                                  uint64_t* corrections, uint8_t* observables, vibe_shot_stats* stats,
                                  void* stream) {
-    // Switched off: its first GPU run stalled and no cause has been shown yet.
-    (void)G;
-    (void)syndromes;
-    (void)B;
-    (void)corrections;
-    (void)observables;
-    (void)stats;
-    (void)stream;
-    return fail(VIBE_EUNSUPPORTED,
-                "vibe_decode_plain is switched off in this build: its first GPU run stalled "
-                "and the cause has not been found");
+    set_error("");
+    int rc = check_common(G, syndromes, B);
+    if (rc) return rc;
+    if (B && (!corrections || (!observables && G->h.k))) return fail(VIBE_EINVAL, "an output pointer is NULL");
+    if (!B) return VIBE_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const DevGraph& g = G->h.dg;
+    ChunkBufs W;
+    const int blocks = (int)g.L;  // one block per member of the one shot
+    if ((rc = carve(G, 1, true, bp_slab_fits_lds(g) ? 0 : blocks, blocks, 1, &W))) return rc;
+    for (uint64_t s0 = 0; s0 < B; s0++) {
+        if ((rc = decode_chunk(G, W, syndromes, s0, 1, corrections, stats, blocks, 1, st))) return rc;
+        if ((rc = launch_observables(g, corrections, s0, 1, observables, st))) return rc;
+    }
+    return VIBE_OK;
 }
 
 extern "C" int vibe_bp_ensemble(vibe_graph* G, const uint8_t* syndromes, uint64_t B, uint32_t T_run,

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
     uint32_t* slab = SLAB_LDS ? pref + g.m : a.slab + (size_t)blockIdx.x * g.E;
 
     const int lane = threadIdx.x;
-    float* __restrict__ post = a.post_slab + (size_t)blockIdx.x * g.n;
+    float* post = a.post_slab + (size_t)blockIdx.x * g.n;
     const uint32_t n_items = a.n_shots * g.L;
     const float lim = g.clamp;
     const float al = g.alpha;
@@ -167,9 +167,12 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
             }
             continue;
         }
+        // The slab is only ever re-read by the lane that wrote it: a slot's
+        // position is (chunk start + lane) in the sweep and in the backward
+        // pass alike.  The first sweep reads the suffix states of the initial
+        // messages from the graph itself.
         const size_t mbase = (size_t)mem * g.E;  // this member's first slot
         const uint32_t* init = g.init_suf + mbase;
-        for (uint32_t e = lane; e < g.E; e += kWave) slab[e] = init[e];
         for (uint32_t w = lane; w < g.words_n; w += kWave) eb[w] = g.e0[w];
         __syncthreads();
 
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
                 npos = nbeg - mbase + lane;
                 if ((uint32_t)lane < nlen) {
                     nsl = g.slots[nbeg + lane];
-                    nsuf = slab[npos];
+                    nsuf = t == 1 ? init[npos] : slab[npos];
                 }
             }
             for (uint32_t ch = ch_lo; ch < ch_hi; ch++) {
@@ -219,7 +222,7 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
                     npos = nbeg - mbase + lane;
                     if ((uint32_t)lane < nlen) {
                         nsl = g.slots[nbeg + lane];
-                        nsuf = slab[npos];
+                        nsuf = t == 1 ? init[npos] : slab[npos];
                     }
                 }
                 const bool act = (uint32_t)lane < len;
@@ -318,18 +321,20 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
             uint32_t cnt = 0;
             for (uint32_t tt = lane + 1; tt <= a.T_run; tt += kWave) cnt += __popcll(load_mask(&cmask[tt]));
             if (wave_sum_u32(cnt) == 0) {
+                // post[v] was written by the lane that swept v: read it past the L1
                 double ss = 0.0;
                 for (uint32_t v = lane; v < g.n; v += kWave) {
-                    const double xv = post[v];
+                    const double xv = __hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ss += xv * xv;
                 }
                 ss = wave_sum_f64(ss);
                 if (ss > 0.0) {
                     const double scale = kQScale / sqrt(ss);
                     int64_t* q = a.qfix + (size_t)shot * g.n;
-                    for (uint32_t v = lane; v < g.n; v += kWave)
-                        atomicAdd(reinterpret_cast<unsigned long long*>(&q[v]),
-                                  (unsigned long long)llrint((double)post[v] * scale));
+                    for (uint32_t v = lane; v < g.n; v += kWave) {
+                        const double xv = __hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        atomicAdd(reinterpret_cast<unsigned long long*>(&q[v]), (unsigned long long)llrint(xv * scale));
+                    }
                 }
             }
         }

@@ -280,6 +280,10 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     d.all_lam_positive = all_pos;
     std::vector<uint32_t> rp(h_indptr, h_indptr + m + 1);
     std::vector<uint32_t> ri(h_indices, h_indices + E);
+    if (lsd_lds_bytes(d) > 150 * 1024) {
+        delete g;
+        return fail(VIBE_EUNSUPPORTED, "the per-shot LSD state exceeds 150 KB of LDS");
+    }
     int rc = VIBE_OK;
     if ((rc = upload(h, rp.data(), rp.size(), &d.rp)) ||
         (rc = upload(h, ri.data(), ri.size(), &d.ri)) ||

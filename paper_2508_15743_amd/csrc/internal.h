@@ -156,6 +156,7 @@ struct LsdLaunch {
 };
 int launch_lsd(const DevGraph& g, const LsdLaunch& a, hipStream_t st);
 size_t lsd_scratch_per_block(const DevGraph& g);
+size_t lsd_lds_bytes(const DevGraph& g);
 
 // Record a start event before a launch of kernel class `which` (0 BP,
 // 1 selection, 2 LSD) when profiling is on; end_timed records the end event.

@@ -20,7 +20,14 @@ namespace {
 
 constexpr uint32_t kValid = 1u, kFailed = 2u;
 
+// Per-shot state.  Everything one lane writes and another reads lives in
+// LDS.  The global part holds the large arrays: the basis vectors, which
+// each lane only ever touches in its own words (w = lane mod 64), and the
+// column lists of the final solve, which are read across lanes only through
+// agent-scope loads (they bypass the CU's L1, whose copy of a line another
+// lane just wrote is not refreshed by a workgroup barrier).
 struct LsdMem {
+    // LDS
     int32_t* chk_cl;    // m
     int32_t* parent;    // m
     uint32_t* cstate;   // m
@@ -32,50 +39,68 @@ struct LsdMem {
     int32_t* pool_piv;  // m
     int32_t* piv2;      // m
     int32_t* pivcol;    // m
-    int32_t* cols;      // n
-    int32_t* sorted;    // n
-    int64_t* ckey;      // n
     uint64_t* in_bits;  // words_n
     uint64_t* ebits;    // words_n
     uint64_t* xbuf;     // words_m
     uint64_t* cbuf;     // words_m
+    // global
+    int32_t* cols;      // n
+    int32_t* sorted;    // n
+    int64_t* ckey;      // n
     uint64_t* pool;     // m x words_m
     uint64_t* basis2;   // m x 2 words_m (vector, combination)
 };
 
 __host__ __device__ inline size_t al8(size_t x) { return (x + 7) & ~(size_t)7; }
 
-__host__ __device__ inline size_t lsd_layout(const DevGraph& g, unsigned char* base, LsdMem* out) {
+// Lays out the LDS part at `lds` and the global part at `glob` (either may
+// be null to measure); returns the two sizes.
+__host__ __device__ inline void lsd_layout(const DevGraph& g, unsigned char* lds, unsigned char* glob,
+                                           LsdMem* out, size_t* lds_bytes, size_t* glob_bytes) {
     const size_t m = g.m ? g.m : 1, n = g.n, wn = g.words_n, wm = g.words_m ? g.words_m : 1;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        unsigned char* p = base ? base + off : nullptr;
-        off += al8(bytes);
+    size_t lo = 0, go = 0;
+    auto tl = [&](size_t bytes) {
+        unsigned char* p = lds ? lds + lo : nullptr;
+        lo += al8(bytes);
+        return p;
+    };
+    auto tg = [&](size_t bytes) {
+        unsigned char* p = glob ? glob + go : nullptr;
+        go += al8(bytes);
         return p;
     };
     LsdMem M;
-    M.chk_cl = (int32_t*)take(4 * m);
-    M.parent = (int32_t*)take(4 * m);
-    M.cstate = (uint32_t*)take(4 * m);
-    M.best_q = (int64_t*)take(8 * m);
-    M.best_v = (int32_t*)take(4 * m);
-    M.ccount = (int32_t*)take(4 * m);
-    M.picks = (int32_t*)take(8 * m);
-    M.added = (int32_t*)take(4 * m);
-    M.pool_piv = (int32_t*)take(4 * m);
-    M.piv2 = (int32_t*)take(4 * m);
-    M.pivcol = (int32_t*)take(4 * m);
-    M.cols = (int32_t*)take(4 * n);
-    M.sorted = (int32_t*)take(4 * n);
-    M.ckey = (int64_t*)take(8 * n);
-    M.in_bits = (uint64_t*)take(8 * wn);
-    M.ebits = (uint64_t*)take(8 * wn);
-    M.xbuf = (uint64_t*)take(8 * wm);
-    M.cbuf = (uint64_t*)take(8 * wm);
-    M.pool = (uint64_t*)take(8 * wm * m);
-    M.basis2 = (uint64_t*)take(16 * wm * m);
+    M.best_q = (int64_t*)tl(8 * m);
+    M.in_bits = (uint64_t*)tl(8 * wn);
+    M.ebits = (uint64_t*)tl(8 * wn);
+    M.xbuf = (uint64_t*)tl(8 * wm);
+    M.cbuf = (uint64_t*)tl(8 * wm);
+    M.chk_cl = (int32_t*)tl(4 * m);
+    M.parent = (int32_t*)tl(4 * m);
+    M.cstate = (uint32_t*)tl(4 * m);
+    M.best_v = (int32_t*)tl(4 * m);
+    M.ccount = (int32_t*)tl(4 * m);
+    M.picks = (int32_t*)tl(8 * m);
+    M.added = (int32_t*)tl(4 * m);
+    M.pool_piv = (int32_t*)tl(4 * m);
+    M.piv2 = (int32_t*)tl(4 * m);
+    M.pivcol = (int32_t*)tl(4 * m);
+    M.ckey = (int64_t*)tg(8 * n);
+    M.pool = (uint64_t*)tg(8 * wm * m);
+    M.basis2 = (uint64_t*)tg(16 * wm * m);
+    M.cols = (int32_t*)tg(4 * n);
+    M.sorted = (int32_t*)tg(4 * n);
     if (out) *out = M;
-    return off;
+    if (lds_bytes) *lds_bytes = lo;
+    if (glob_bytes) *glob_bytes = go;
+}
+
+__device__ inline int32_t ald32(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int64_t ald64(const int64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // order-preserving map of a float to int64 (-0 and +0 map to the same key)
@@ -136,9 +161,11 @@ __device__ void column_vector(const DevGraph& g, uint64_t* x, uint32_t v, int la
 }
 
 __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
+    extern __shared__ __align__(16) unsigned char lds[];
     const int lane = threadIdx.x;
     LsdMem S;
-    lsd_layout(g, static_cast<unsigned char*>(a.scratch) + a.scratch_per_block * blockIdx.x, &S);
+    lsd_layout(g, lds, static_cast<unsigned char*>(a.scratch) + a.scratch_per_block * blockIdx.x, &S,
+               nullptr, nullptr);
     const uint32_t count = a.list ? *a.list_count : a.n_list;
     const uint32_t wm = g.words_m;
     for (uint32_t it = blockIdx.x; it < count && it < a.n_list; it += gridDim.x) {
@@ -311,20 +338,20 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
         }
         ncol = __shfl(ncol, 0);
         __syncthreads();
-        for (int i = lane; i < ncol; i += kWave) S.ckey[i] = key((uint32_t)S.cols[i]);
+        for (int i = lane; i < ncol; i += kWave) S.ckey[i] = key((uint32_t)ald32(&S.cols[i]));
         __syncthreads();
         for (int i = lane; i < ncol; i += kWave) {
-            const int64_t qi = S.ckey[i];
-            const int32_t vi = S.cols[i];
+            const int64_t qi = ald64(&S.ckey[i]);
+            const int32_t vi = ald32(&S.cols[i]);
             int r = 0;
             for (int j = 0; j < ncol; j++)
-                if (key_less(S.ckey[j], S.cols[j], qi, vi)) r++;
+                if (key_less(ald64(&S.ckey[j]), ald32(&S.cols[j]), qi, vi)) r++;
             S.sorted[r] = vi;
         }
         __syncthreads();
         int nb = 0;
         for (int i = 0; i < ncol; i++) {
-            const uint32_t v = (uint32_t)S.sorted[i];
+            const uint32_t v = (uint32_t)ald32(&S.sorted[i]);
             column_vector(g, S.xbuf, v, lane);
             for (uint32_t w = lane; w < wm; w += kWave) S.cbuf[w] = 0;
             reduce_by(S.xbuf, S.cbuf, S.basis2, 2 * (size_t)wm, S.piv2, nb, wm, lane);
@@ -396,11 +423,27 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
 
 }  // namespace
 
-size_t lsd_scratch_per_block(const DevGraph& g) { return al8(lsd_layout(g, nullptr, nullptr)) + 256; }
+size_t lsd_scratch_per_block(const DevGraph& g) {
+    size_t gb = 0;
+    lsd_layout(g, nullptr, nullptr, nullptr, nullptr, &gb);
+    return al8(gb) + 256;
+}
+
+size_t lsd_lds_bytes(const DevGraph& g) {
+    size_t lb = 0;
+    lsd_layout(g, nullptr, nullptr, nullptr, &lb, nullptr);
+    return lb;
+}
 
 int launch_lsd(const DevGraph& g, const LsdLaunch& a, hipStream_t st) {
     if (!a.n_list) return VIBE_OK;
-    hipLaunchKernelGGL(lsd_kernel, dim3(a.grid), dim3(kWave), 0, st, g, a);
+    const size_t lds = lsd_lds_bytes(g);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)lsd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(lsd)");
+    }
+    hipLaunchKernelGGL(lsd_kernel, dim3(a.grid), dim3(kWave), lds, st, g, a);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? VIBE_OK : hip_fail(e, "lsd_kernel launch");
 }

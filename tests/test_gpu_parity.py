@@ -12,9 +12,11 @@ Bars (the device computes BP messages in FP32, the oracle in FP64):
   * whole decoder: identical corrections on every shot whose oracle tie
     witnesses are clear, i.e. the smallest |L_v| of any BP decision is
     >= 1e-3 (the FP32 error of a decision near zero) and the smallest gap
-    between soft values LSD compared is >= 1e-9 of the largest |q| (FP32
-    posteriors resolve about 1e-7 relative); the logical error rate lies in
-    the oracle's 95% interval.
+    between soft values that LSD compared is >= 1e-5.  Each soft value is a
+    sum of terms L_v / ||L|| in [-1, 1] whose FP32 error is bounded by the
+    posterior error, <= ~1.5e-6 of the member's largest |L| as measured in
+    the BP tests, so gaps under 1e-5 can be ordered either way; the logical
+    error rate lies in the oracle's 95% interval.
 """
 import os
 
@@ -155,9 +157,7 @@ def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots):
     ref = O.decode(O.OracleGraph(dem), perms, b.syndromes[:oracle_shots], L=L, M=M, T=T,
                    threads=NT, want_q=True)
     agree = (ref["ehat"] == e[:oracle_shots]).all(1)
-    qscale = np.nanmax(np.abs(ref["q"]), axis=1)
-    qscale = np.where(np.isfinite(qscale), qscale, 1.0)
-    tie = (ref["min_abs_post"] < 1e-3) | (ref["min_q_gap"] < 1e-9 * qscale)
+    tie = (ref["min_abs_post"] < 1e-3) | (ref["min_q_gap"] < 1e-5)
     bad = np.flatnonzero(~agree & ~tie)
     assert len(bad) == 0, (bad[:10], ref["min_abs_post"][bad[:10]], ref["min_q_gap"][bad[:10]])
     # logical error rate inside the oracle's 95% (Clopper-Pearson) interval
@@ -169,6 +169,8 @@ def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots):
     hi = beta.ppf(0.975, k + 1, n - k) if k < n else 1.0
     ler = (obs != b.observables).any(1).mean()
     assert lo <= ler <= hi, (ler, lo, hi)
+    print(f"{dem.name}: agreement {agree.mean():.5f} over {oracle_shots} shots, "
+          f"{int((~agree).sum())} disagreements, all tie-witnessed")
     G.close()
     return agree.mean()
 
@@ -240,14 +242,19 @@ def test_invalid_arguments_rejected(torch_cuda):
         P.Graph.from_dem(dem, perms, L=4, M=5, T_max=5)
 
 
-@pytest.mark.skip(reason="vibe_decode_plain is switched off: its first GPU run stalled and the "
-                         "cause has not been found (see the design notes)")
 def test_plain_equals_batched(torch_cuda):
+    """One launch sequence per shot gives the batched results, including on
+    shots that go to LSD alone on the device (a lone LSD block)."""
     torch = torch_cuda
     dem = code_capacity_dem(5, 0.05)
     G, _ = _graph(dem, 16, 5, 32, 3)
-    b = sample(dem, 50, 4)
+    b = sample(dem, 120, 4)
     s = _dev(torch, b.syndromes)
-    c1, _, _ = G.decode(s)
-    c2, _, _ = G.decode(s, plain=True)
-    assert torch.equal(c1, c2)
+    c1, o1, s1 = G.decode(s)
+    assert (s1[:, 0].cpu().numpy() & 2).sum() >= 5  # several LSD shots
+    c2, o2, s2 = G.decode(s, plain=True)
+    assert torch.equal(c1, c2) and torch.equal(o1, o2)
+    for i in range(0, 120, 7):
+        c3, _, _ = G.decode(s[i:i + 1])
+        assert torch.equal(c3, c1[i:i + 1])
+    G.close()
