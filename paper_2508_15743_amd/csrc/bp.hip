@@ -46,12 +46,12 @@ __device__ inline double wave_sum_f64(double x) {
 
 __device__ inline uint32_t wave_sum_u32(uint32_t x) {
     for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
-    return x;
+    return uni(x);
 }
 
 __device__ inline uint32_t wave_max_u32(uint32_t x) {
     for (int off = kWave / 2; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off));
-    return x;
+    return uni(x);
 }
 
 // Members known to precede `mem` in (convergence iteration, index) order:
@@ -59,7 +59,8 @@ __device__ inline uint32_t wave_max_u32(uint32_t x) {
 __device__ inline uint32_t preceding_converged(const uint64_t* mask, uint32_t t, uint32_t mem, int lane) {
     uint32_t cnt = 0;
     for (uint32_t tt = lane + 1; tt < t; tt += kWave) cnt += __popcll(load_mask(&mask[tt]));
-    if (lane == 0) cnt += __popcll(load_mask(&mask[t]) & ((1ull << mem) - 1ull));
+    const uint32_t own = __popcll(load_mask(&mask[t]) & ((1ull << mem) - 1ull));
+    cnt += lane == 0 ? own : 0u;  // a select, not a branch on the lane
     return wave_sum_u32(cnt);
 }
 
@@ -121,9 +122,7 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
     const float al = g.alpha;
 
     for (;;) {
-        uint32_t item = 0;
-        if (lane == 0) item = atomicAdd(a.counter, 1u);
-        item = __shfl(item, 0);
+        const uint32_t item = wave_ticket(a.counter, 1u);
         if (item >= n_items) break;
         uint32_t shot, mem;
         if (a.member_major) {
@@ -328,7 +327,7 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
                     ss += xv * xv;
                 }
                 ss = wave_sum_f64(ss);
-                if (ss > 0.0) {
+                if (uni(ss > 0.0 ? 1u : 0u)) {
                     const double scale = kQScale / sqrt(ss);
                     int64_t* q = a.qfix + (size_t)shot * g.n;
                     for (uint32_t v = lane; v < g.n; v += kWave) {

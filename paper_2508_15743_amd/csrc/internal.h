@@ -29,6 +29,24 @@ struct Slot {
     uint32_t meta, v;
 };
 
+// Wave-uniform values.  A value every lane computes identically (a shuffle
+// broadcast, a wave reduction, an LDS word all lanes read) still lives in a
+// vector register, and the compiler may then treat branches on it as
+// divergent and split loops per lane, so that a later shuffle reads a lane
+// that is on another path.  Every such control value goes through
+// readfirstlane, which makes it a scalar the compiler knows is uniform.
+__device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline int32_t uni(int32_t x) { return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)x); }
+
+// One ticket per wave from a global counter.  Every lane executes the atomic
+// (lane 0 adds v, the others 0), so no branch on the lane index precedes the
+// broadcast: a branch there lets the compiler route lanes 1..63 around the
+// atomic and run the broadcast with lane 0 inactive.
+__device__ inline uint32_t wave_ticket(uint32_t* counter, uint32_t v) {
+    const uint32_t got = atomicAdd(counter, __lane_id() == 0 ? v : 0u);
+    return uni(__shfl(got, 0));
+}
+
 // Row state word: the float bits of a magnitude (>= 0) with a parity bit in
 // the sign position.  Magnitudes compare like unsigned integers, so
 // combining two states is an integer min of the low 31 bits and an xor of

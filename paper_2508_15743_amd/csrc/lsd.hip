@@ -124,9 +124,9 @@ __device__ inline bool key_less(int64_t qa, int32_t a, int64_t qb, int32_t b) {
 __device__ void reduce_by(uint64_t* x, uint64_t* comb, const uint64_t* vecs, size_t stride,
                           const int32_t* piv, int count, uint32_t wm, int lane) {
     for (int i = 0; i < count; i++) {
-        const int32_t p = piv[i];
+        const int32_t p = uni(piv[i]);
         __syncthreads();
-        const bool hit = (x[p >> 6] >> (p & 63)) & 1ull;
+        const uint32_t hit = uni((uint32_t)((x[p >> 6] >> (p & 63)) & 1ull));
         if (!hit) continue;
         const uint64_t* b = vecs + (size_t)i * stride;
         for (uint32_t w = lane; w < wm; w += kWave) {
@@ -146,6 +146,7 @@ __device__ int lowest_bit(const uint64_t* x, uint32_t wm, int lane) {
             if (b < best) best = b;
         }
     for (int off = kWave / 2; off > 0; off >>= 1) best = min(best, __shfl_xor(best, off));
+    best = uni(best);
     return best == 0x7fffffff ? -1 : best;
 }
 
@@ -166,10 +167,10 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
     LsdMem S;
     lsd_layout(g, lds, static_cast<unsigned char*>(a.scratch) + a.scratch_per_block * blockIdx.x, &S,
                nullptr, nullptr);
-    const uint32_t count = a.list ? *a.list_count : a.n_list;
+    const uint32_t count = uni(a.list ? *a.list_count : a.n_list);
     const uint32_t wm = g.words_m;
     for (uint32_t it = blockIdx.x; it < count && it < a.n_list; it += gridDim.x) {
-        const uint32_t local = a.list ? a.list[it] : it;
+        const uint32_t local = uni(a.list ? a.list[it] : it);
         const uint64_t gshot = a.shot0 + local;
         const uint8_t* s = a.syndromes + gshot * g.m;
         auto key = [&](uint32_t v) -> int64_t {
@@ -211,10 +212,10 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
             }
             __syncthreads();
             for (uint32_t c = 0; c < g.m; c++) {
-                const int32_t cl = S.chk_cl[c];
+                const int32_t cl = uni(S.chk_cl[c]);
                 if (cl < 0) continue;
-                const int32_t R = find_root(S.parent, cl);
-                if (S.cstate[R] & (kValid | kFailed)) continue;
+                const int32_t R = uni(find_root(S.parent, cl));
+                if (uni(S.cstate[R]) & (kValid | kFailed)) continue;
                 int64_t bq = INT64_MAX;
                 int32_t bv = 0x7fffffff;
                 for (uint32_t p = g.rp[c] + lane; p < g.rp[c + 1]; p += kWave) {
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                     }
                 }
             }
-            npick = __shfl(npick, 0);
+            npick = uni(__shfl(npick, 0));
             __syncthreads();
             if (!npick) break;
             rounds++;
@@ -285,11 +286,11 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                     }
                 }
             }
-            nadd = __shfl(nadd, 0);
+            nadd = uni(__shfl(nadd, 0));
             __syncthreads();
             // 4. extend the basis pool with the new columns
             for (int i = 0; i < nadd; i++) {
-                column_vector(g, S.xbuf, (uint32_t)S.added[i], lane);
+                column_vector(g, S.xbuf, (uint32_t)uni(S.added[i]), lane);
                 reduce_by(S.xbuf, nullptr, S.pool, wm, S.pool_piv, pool_n, wm, lane);
                 const int p = lowest_bit(S.xbuf, wm, lane);
                 if (p >= 0) {
@@ -301,7 +302,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
             }
             // 5. validity of every live cluster that has not failed
             for (int K = 0; K < nk; K++) {
-                if (S.parent[K] != K || (S.cstate[K] & kFailed)) continue;
+                if (uni(S.parent[K]) != K || (uni(S.cstate[K]) & kFailed)) continue;
                 for (uint32_t base = 0; base < g.m; base += kWave) {
                     const uint32_t c = base + lane;
                     bool in = false;
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                 }
             }
         }
-        ncol = __shfl(ncol, 0);
+        ncol = uni(__shfl(ncol, 0));
         __syncthreads();
         for (int i = lane; i < ncol; i += kWave) S.ckey[i] = key((uint32_t)ald32(&S.cols[i]));
         __syncthreads();
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
         __syncthreads();
         int nb = 0;
         for (int i = 0; i < ncol; i++) {
-            const uint32_t v = (uint32_t)ald32(&S.sorted[i]);
+            const uint32_t v = (uint32_t)uni(ald32(&S.sorted[i]));
             column_vector(g, S.xbuf, v, lane);
             for (uint32_t w = lane; w < wm; w += kWave) S.cbuf[w] = 0;
             reduce_by(S.xbuf, S.cbuf, S.basis2, 2 * (size_t)wm, S.piv2, nb, wm, lane);

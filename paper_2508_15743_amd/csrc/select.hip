@@ -43,6 +43,7 @@ __global__ __launch_bounds__(kWave) void select_kernel(DevGraph g, SelectLaunch 
             who = owho;
         }
     }
+    who = uni(who);
     const size_t gshot = a.shot0 + shot;
     uint64_t* out = a.corrections + gshot * g.words_n;
     if (nconv) {
