@@ -267,14 +267,31 @@ static int cluster_is_valid(const ograph *g, const uint8_t *s, const ocluster *K
     return ok;
 }
 
+/* Soft values that rank LSD columns: either doubles or int64 fixed-point
+   keys (the normalised average, see decode_one).  Rank order is (value,
+   index) ascending. */
+typedef struct {
+    const double *q;
+    const int64_t *k;
+} osoft;
+
+static int soft_less(const osoft *S, int a, int b) {
+    if (S->k) return S->k[a] < S->k[b] || (S->k[a] == S->k[b] && a < b);
+    return rank_less(S->q[a], a, S->q[b], b);
+}
+
+static double soft_val(const osoft *S, int v) {
+    return S->k ? (double)S->k[v] * (1.0 / 72057594037927936.0) : S->q[v];
+}
+
 /* stats layout (int[6]): clusters at the end, largest cluster (columns),
    growth rounds, failed (0/1), columns over all clusters, reserved.
    min_gap (if non-NULL): smallest q gap of any rank decision taken.
    chk_label / bit_label (if non-NULL, lengths m / n): final cluster of every
    check / column, numbered in order of the clusters' first check, or -1. */
-int or_lsd(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci,
-           const uint8_t *s, const double *q, uint8_t *ehat, int *stats, double *min_gap,
-           int *chk_label, int *bit_label) {
+static int lsd_impl(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci,
+                    const uint8_t *s, const osoft *S, uint8_t *ehat, int *stats, double *min_gap,
+                    int *chk_label, int *bit_label) {
     ograph g = {m, n, rp, ri, cp, ci, NULL};
     memset(ehat, 0, (size_t)n);
     double gap = INFINITY;
@@ -310,12 +327,12 @@ int or_lsd(int m, int n, const int *rp, const int *ri, const int *cp, const int 
                 for (int k = cp[v]; k < cp[v + 1]; k++)
                     if (K[i].chk[ci[k]]) adj = 1;
                 if (!adj) continue;
-                if (best < 0 || rank_less(q[v], v, bq, best)) {
+                if (best < 0 || soft_less(S, v, best)) {
                     if (best >= 0) second = fmin(second, bq);
                     best = v;
-                    bq = q[v];
+                    bq = soft_val(S, v);
                 } else {
-                    second = fmin(second, q[v]);
+                    second = fmin(second, soft_val(S, v));
                 }
             }
             if (best < 0) {
@@ -381,14 +398,14 @@ int or_lsd(int m, int n, const int *rp, const int *ri, const int *cp, const int 
         /* insertion sort by (q, index): plain and stable */
         for (int a = 1; a < cols; a++) {
             int x = ord[a], b = a - 1;
-            while (b >= 0 && rank_less(q[x], x, q[ord[b]], ord[b])) {
+            while (b >= 0 && soft_less(S, x, ord[b])) {
                 ord[b + 1] = ord[b];
                 b--;
             }
             ord[b + 1] = x;
         }
         for (int a = 0; a + 1 < cols; a++) {
-            double d = q[ord[a + 1]] - q[ord[a]];
+            double d = soft_val(S, ord[a + 1]) - soft_val(S, ord[a]);
             if (d < gap) gap = d;
         }
         int *rix = (int *)malloc(sizeof(int) * m);
@@ -448,6 +465,22 @@ int or_lsd(int m, int n, const int *rp, const int *ri, const int *cp, const int 
 
 /* ------------------------------------------------------------------------ */
 /* The full decoder for one shot.                                             */
+
+/* LSD-0 on double soft values (rank by (q, index) ascending). */
+int or_lsd(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci,
+           const uint8_t *s, const double *q, uint8_t *ehat, int *stats, double *min_gap,
+           int *chk_label, int *bit_label) {
+    osoft S = {q, NULL};
+    return lsd_impl(m, n, rp, ri, cp, ci, s, &S, ehat, stats, min_gap, chk_label, bit_label);
+}
+
+/* LSD-0 on int64 fixed-point soft values. */
+int or_lsd_key(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci,
+               const uint8_t *s, const int64_t *qk, uint8_t *ehat, int *stats, double *min_gap,
+               int *chk_label, int *bit_label) {
+    osoft S = {NULL, qk};
+    return lsd_impl(m, n, rp, ri, cp, ci, s, &S, ehat, stats, min_gap, chk_label, bit_label);
+}
 
 /* per-shot record written by or_decode_batch, 16 doubles:
    [0] flags: bit0 BP converged, bit1 LSD used, bit2 LSD failed
@@ -526,26 +559,33 @@ static void decode_one(const odec *D, const uint8_t *s, uint8_t *ehat, uint8_t *
         rec[10] = second - bw;
         free(S);
     } else {
-        /* normalised average of the members' final posteriors */
-        double *q = (double *)calloc(n ? n : 1, sizeof(double));
+        /* normalised average of the members' final posteriors,
+           q = (1/L) sum_i LLR^i / ||LLR^i||.  ||LLR^i||^2 is summed in
+           ascending v; each term LLR^i_v / ||LLR^i|| is rounded to a
+           multiple of 2^-56 (as LLR^i_v * (2^56 / ||LLR^i||), to nearest)
+           and the terms are added exactly in int64, so q does not depend on
+           the order of the members.  The factor 1/L does not change the
+           ranking and is applied only to the reported q. */
+        int64_t *qk = (int64_t *)calloc(n ? n : 1, sizeof(int64_t));
         for (int i = 0; i < L; i++) {
             double ss = 0;
             for (int v = 0; v < n; v++) ss += post[(size_t)i * n + v] * post[(size_t)i * n + v];
             double nrm = sqrt(ss);
             if (nrm == 0) continue;
-            for (int v = 0; v < n; v++) q[v] += post[(size_t)i * n + v] / nrm;
+            double scale = 72057594037927936.0 / nrm;
+            for (int v = 0; v < n; v++) qk[v] += llrint(post[(size_t)i * n + v] * scale);
         }
-        for (int v = 0; v < n; v++) q[v] /= L;
-        if (q_out) memcpy(q_out, q, sizeof(double) * n);
+        if (q_out)
+            for (int v = 0; v < n; v++) q_out[v] = (double)qk[v] * (1.0 / 72057594037927936.0) / L;
         int st[6];
         double gap = INFINITY;
-        int f = or_lsd(D->m, n, D->rp, D->ri, D->cp, D->ci, s, q, ehat, st, &gap, NULL, NULL);
+        int f = or_lsd_key(D->m, n, D->rp, D->ri, D->cp, D->ci, s, qk, ehat, st, &gap, NULL, NULL);
         rec[0] = 2 | (f ? 4 : 0);
         rec[4] = st[0];
         rec[5] = st[1];
         rec[6] = st[2];
         rec[8] = gap;
-        free(q);
+        free(qk);
     }
     for (int r = 0; r < D->k; r++) {
         int par = 0;

@@ -245,7 +245,8 @@ def test_selection_is_min_weight_over_first_M():
 
 def test_normalised_average_closed_form():
     """P12: with no member converged, q = (1/L) sum_i LLR^i / ||LLR^i||_2
-    over the members' final posteriors (Sec. III.D.2)."""
+    over the members' final posteriors (Sec. III.D.2), to within the 2^-57
+    rounding of each term."""
     dem = circuit_dem(3, 2, 0.02)
     g = O.OracleGraph(dem)
     L, T = 6, 2
@@ -263,6 +264,13 @@ def test_normalised_average_closed_form():
         r1 = O.lsd(g, b.syndromes[sh], q)
         r2 = O.lsd(g, b.syndromes[sh], 3.5 * q)
         assert np.array_equal(r1["ehat"], r2["ehat"])
+    # the average is summed exactly in 2^-56 fixed point: reversing the order
+    # of the members leaves q bit-identical on every shot that reaches LSD,
+    # and with it the LSD correction
+    rev = O.decode(g, perms[::-1].copy(), b.syndromes, L=L, M=2, T=T, want_q=True)
+    assert np.array_equal(rev["lsd_used"], out["lsd_used"])
+    assert np.array_equal(rev["q"][idx], out["q"][idx])
+    assert np.array_equal(rev["ehat"][idx], out["ehat"][idx])
 
 
 # ---------------------------------------------------------------------------
