@@ -9,15 +9,18 @@ circuits and data.
 
 One step = vibe_decode over one batch of B shots (all of BP ensemble,
 selection, LSD and observables), syndromes already resident in HBM.
-Prints one JSON line.  Extra legs: latency of small batches (64 shots per
-call, wall clock from submission to completion), the oracle on a bounded
-sample of the host cores, and the dominant kernel's roofline from HIP events
-around its launches.  The per-shot-launch form (vibe_decode_plain) is
-switched off in this build, so no batched/plain ratio is reported.
+Prints one JSON line.  Extra legs: the per-shot-launch form
+(vibe_decode_plain, one launch sequence per shot) on the first shots of the
+batch, latency of small batches (64 shots per call, wall clock from
+submission to completion), the oracle on a bounded sample of the host cores,
+and the dominant kernel's roofline from HIP events around its launches.
+HBM traffic per launch comes from the committed rocprofv3 counter summary
+when it was taken on the same kernel source and launch size, else null.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,6 +37,26 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 BYTES_PER_EDGE_UPDATE = 8.0
 
 
+PROFILE = os.path.join(ROOT, "profiles", "bp_ensemble_kernel_circuit_d9_r9_p1e-3.txt")
+KERNEL_SOURCES = ("bp.hip", "internal.h", "graph.hip")
+
+
+def measured_traffic(launch_shots):
+    """HBM bytes per BP launch from the committed counter summary, if it was
+    taken on this kernel source at this launch size; else None."""
+    try:
+        lines = open(PROFILE).read().splitlines()
+    except OSError:
+        return None
+    src = "".join(open(os.path.join(ROOT, "paper_2508_15743_amd", "csrc", f)).read() for f in KERNEL_SOURCES)
+    sha = hashlib.sha256(src.encode()).hexdigest()[:16]
+    vals = dict(l.split()[:2] for l in lines if l.startswith(("source_sha256_16 ", "traffic_launch_shots ",
+                                                                "traffic_bytes_per_launch ")))
+    if vals.get("source_sha256_16") != sha or vals.get("traffic_launch_shots") != str(launch_shots):
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -44,11 +67,13 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=1 << 15)
+    ap.add_argument("--plain-shots", type=int, default=64)
     ap.add_argument("--latency-batches", type=int, default=200)
     ap.add_argument("--latency-batch", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--seed", type=int, default=2025)
@@ -125,8 +150,10 @@ def main():
     edge_updates = member_iters * dem.nnz
     bp_s = bp_ms / 1e3
     achieved = BYTES_PER_EDGE_UPDATE * edge_updates / bp_s / 1e9 if bp_s > 0 else 0.0
+    launch_shots = max(1, B // max(1, bp_launches // args.steps))
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(launch_shots),
                 "kernel": "bp_ensemble_kernel",
                 "avg_launch_ms": round(bp_ms / max(bp_launches, 1), 3),
                 "edge_updates_per_s": edge_updates / bp_s if bp_s > 0 else 0.0,
@@ -156,6 +183,23 @@ def main():
 
     result["plain"] = None
     result["batched_over_plain"] = None
+    if not args.no_plain:
+        n_plain = min(args.plain_shots, B)
+        pouts = (torch.empty((n_plain, words), dtype=torch.int64, device=dev),
+                 torch.empty((n_plain, 1), dtype=torch.uint8, device=dev),
+                 torch.empty((n_plain, 8), dtype=torch.int32, device=dev))
+        G.decode(synd[:1], plain=True, out=tuple(o[:1] for o in pouts))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        G.decode(synd[:n_plain], plain=True, out=pouts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        same = bool(torch.equal(pouts[0], corr[:n_plain]))
+        result["plain"] = {"shots": n_plain, "shots_per_s": round(n_plain / dt, 2),
+                           "same_corrections_as_batched": same}
+        result["batched_over_plain"] = round(shots_per_s / (n_plain / dt), 1)
+        log(f"plain: {n_plain / dt:.2f} shots/s over {n_plain} shots; batched/plain "
+            f"{result['batched_over_plain']}x; identical corrections: {same}")
     if not args.no_latency:
         nb, bs = args.latency_batches, args.latency_batch
         outs = (torch.empty((bs, words), dtype=torch.int64, device=dev),

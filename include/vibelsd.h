@@ -59,6 +59,11 @@ typedef struct vibe_config {
     double clamp;       /* bound on |messages|, |posteriors| and |lambda|; also
                            the magnitude sent by a check with no other
                            neighbour.  1e6 (exact in FP32) is the default. */
+    uint32_t message_bits; /* BP arithmetic: 32 (or 0) = FP32 messages and
+                              posteriors, the production setting; 64 = FP64,
+                              in the same operation order as a plain
+                              column-by-column FP64 decoder, for verification */
+    uint32_t reserved;     /* set to 0 */
 } vibe_config;
 
 typedef struct vibe_shot_stats {
@@ -77,16 +82,21 @@ typedef struct vibe_graph_info {
     uint64_t nnz;          /* edges of the Tanner graph */
     uint32_t max_row_degree, max_col_degree;
     uint32_t levels_min, levels_max; /* dependency levels per member schedule */
+    uint32_t chunks_min, chunks_max; /* parallel steps of one sweep per member */
+    uint32_t message_bits;           /* 32 or 64 */
+    uint32_t reserved;
     uint64_t device_bytes; /* graph + schedules resident on the device */
 } vibe_graph_info_t;
 
 /*
  * Offline stage (Sec. III.D.1): validate the detector error model, compute the
- * channel LLRs lambda_v = ln((1 - p_v) / p_v) (clamped to +-cfg->clamp),
- * build the CSR/CSC copies and, for every member i, the dependency levels of
- * its serial schedule perms[i*n .. i*n+n-1] (a permutation of 0..n-1; the
- * paper draws them uniformly at random), then upload everything to the
- * current HIP device, where it stays until vibe_graph_destroy.
+ * channel LLRs lambda_v = ln((1 - p_v) / p_v) in FP64 (clamped to
+ * +-cfg->clamp), build the CSR/CSC copies and, for every member i, the
+ * parallel steps of its serial schedule perms[i*n .. i*n+n-1] (a permutation
+ * of 0..n-1; the paper draws them uniformly at random): columns that share no
+ * check commute, so each step updates a set of mutually independent columns
+ * while every row keeps the permutation's order.  Everything is uploaded to
+ * the current HIP device, where it stays until vibe_graph_destroy.
  *
  *   m, n            detectors (rows) and error mechanisms (columns), n >= 1
  *   h_indptr        m + 1 entries, h_indptr[0] = 0, non-decreasing
@@ -141,13 +151,14 @@ int vibe_decode_plain(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint6
  * T_run iterations (1 <= T_run <= 64).
  *   t_conv       device, B x L int32: iteration at which the member's decision
  *                first satisfied the syndrome, 0 if it never did
- *   posteriors   device, B x L x n float, or NULL: L_v after the member's
- *                last iteration
+ *   posteriors   device, B x L x n, or NULL: L_v after the member's last
+ *                iteration; float when the graph has message_bits 32, double
+ *                when it has 64
  *   ehat         device, B x L x ceil(n/64) uint64, or NULL: the member's
  *                decision after its last iteration
  */
 int vibe_bp_ensemble(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint32_t T_run,
-                     int stop_on_converge, int32_t* t_conv, float* posteriors, uint64_t* ehat,
+                     int stop_on_converge, int32_t* t_conv, void* posteriors, uint64_t* ehat,
                      void* stream);
 
 /*

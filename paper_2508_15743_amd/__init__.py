@@ -29,7 +29,8 @@ class VibeError(RuntimeError):
 
 class vibe_config(C.Structure):
     _fields_ = [("L", C.c_uint32), ("M", C.c_uint32), ("T_max", C.c_uint32),
-                ("lsd_order", C.c_uint32), ("alpha", C.c_double), ("clamp", C.c_double)]
+                ("lsd_order", C.c_uint32), ("alpha", C.c_double), ("clamp", C.c_double),
+                ("message_bits", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class vibe_graph_info_t(C.Structure):
@@ -37,6 +38,8 @@ class vibe_graph_info_t(C.Structure):
                 ("M", C.c_uint32), ("T_max", C.c_uint32), ("nnz", C.c_uint64),
                 ("max_row_degree", C.c_uint32), ("max_col_degree", C.c_uint32),
                 ("levels_min", C.c_uint32), ("levels_max", C.c_uint32),
+                ("chunks_min", C.c_uint32), ("chunks_max", C.c_uint32),
+                ("message_bits", C.c_uint32), ("reserved", C.c_uint32),
                 ("device_bytes", C.c_uint64)]
 
 
@@ -164,10 +167,12 @@ def unpack_bits(words, n: int) -> np.ndarray:
 
 class Graph:
     """A detector error model resident on the current GPU, with its member
-    schedules.  `perms` is [L, n]: the serial schedules of the members."""
+    schedules.  `perms` is [L, n]: the serial schedules of the members.
+    message_bits=64 runs BP in FP64 (verification); 32 is the production
+    setting."""
 
     def __init__(self, h_indptr, h_indices, priors, l_indptr, l_indices, perms, m=None, n=None,
-                 L=32, M=5, T_max=20, alpha=0.625, clamp=1e6, lsd_order=0):
+                 L=32, M=5, T_max=20, alpha=0.625, clamp=1e6, lsd_order=0, message_bits=32):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libvibelsd needs a ROCm GPU (torch.cuda is not available)")
@@ -178,7 +183,8 @@ class Graph:
         self.k = len(l_indptr) - 1
         self.L, self.M, self.T_max = L, M, T_max
         self.words = (self.n + 63) // 64
-        self.cfg = vibe_config(L, M, T_max, lsd_order, alpha, clamp)
+        self.message_bits = message_bits
+        self.cfg = vibe_config(L, M, T_max, lsd_order, alpha, clamp, message_bits, 0)
         self.handle = vibe_graph_create(self.m, self.n, h_indptr, h_indices, priors, self.k,
                                         l_indptr, l_indices, perms, self.cfg)
 
@@ -226,14 +232,16 @@ class Graph:
         return corr, obs, st
 
     def bp_ensemble(self, syndromes, T_run=None, stop=True, posteriors=True, ehat=True, stream=None):
-        """-> (t_conv int32 [B, L], posteriors float32 [B, L, n] or None, ehat int64 [B, L, words] or None)"""
+        """-> (t_conv int32 [B, L], posteriors [B, L, n] (float32, or float64 when
+        message_bits is 64) or None, ehat int64 [B, L, words] or None)"""
         import torch
         s = self._synd(syndromes)
         B = s.shape[0]
         dev = s.device
         T_run = self.T_max if T_run is None else T_run
         t = torch.empty((B, self.L), dtype=torch.int32, device=dev)
-        p = torch.empty((B, self.L, self.n), dtype=torch.float32, device=dev) if posteriors else None
+        pdt = torch.float64 if self.message_bits == 64 else torch.float32
+        p = torch.empty((B, self.L, self.n), dtype=pdt, device=dev) if posteriors else None
         e = torch.empty((B, self.L, self.words), dtype=torch.int64, device=dev) if ehat else None
         vibe_bp_ensemble(self.handle, s, B, T_run, stop, t, p, e, _stream(stream))
         return t, p, e

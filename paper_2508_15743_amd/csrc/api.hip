@@ -23,10 +23,12 @@ struct ChunkBufs {
     int64_t* qfix;
     uint32_t* fail_list;
     uint32_t* counters;  // [0] BP work counter, [1] failed-shot count
-    uint32_t* slab;
-    float* post_slab;
+    void* slab;
+    void* post_slab;
     void* lsd_scratch;
 };
+
+inline size_t msg_bytes(const DevGraph& g) { return g.fp64 ? 8 : 4; }
 
 size_t per_shot_bytes(const DevGraph& g, bool decode) {
     size_t b = 4ull * g.L + 8ull * (kMaxT + 1) + 4 + 4;
@@ -67,8 +69,8 @@ int carve(vibe_graph* G, uint32_t bc, bool decode, int slab_blocks, int post_blo
         decode ? 8ull * bc * g.n : 0,                      // qfix
         4ull * bc,                                         // fail_list
         64,                                                // counters
-        4ull * slab_blocks * (g.E ? g.E : 1),              // message slabs
-        4ull * post_blocks * g.n,                          // posterior slabs
+        msg_bytes(g) * slab_blocks * std::max<size_t>((size_t)g.max_chunks * kWave, 1),  // message slabs
+        msg_bytes(g) * post_blocks * ((size_t)g.n + kWave),  // posterior slabs
         decode ? lsd_scratch_per_block(g) * lsd_grid : 0,  // LSD scratch
     };
     size_t total = 0;
@@ -89,8 +91,8 @@ int carve(vibe_graph* G, uint32_t bc, bool decode, int slab_blocks, int post_blo
     B->qfix = (int64_t*)ptrs[5];
     B->fail_list = (uint32_t*)ptrs[6];
     B->counters = (uint32_t*)ptrs[7];
-    B->slab = (uint32_t*)ptrs[8];
-    B->post_slab = (float*)ptrs[9];
+    B->slab = ptrs[8];
+    B->post_slab = ptrs[9];
     B->lsd_scratch = ptrs[10];
     return VIBE_OK;
 }
@@ -277,7 +279,7 @@ extern "C" int vibe_decode_plain(vibe_graph* G, const uint8_t* syndromes, uint64
 }
 
 extern "C" int vibe_bp_ensemble(vibe_graph* G, const uint8_t* syndromes, uint64_t B, uint32_t T_run,
-                                int stop_on_converge, int32_t* t_conv, float* posteriors,
+                                int stop_on_converge, int32_t* t_conv, void* posteriors,
                                 uint64_t* ehat, void* stream) {
     set_error("");
     int rc = check_common(G, syndromes, B);
@@ -311,7 +313,8 @@ extern "C" int vibe_bp_ensemble(vibe_graph* G, const uint8_t* syndromes, uint64_
         b.t_conv = t_conv + s0 * g.L;
         b.weight = nullptr;
         b.cand = ehat ? ehat + s0 * g.L * g.words_n : nullptr;
-        b.post_out = posteriors ? posteriors + s0 * g.L * g.n : nullptr;
+        b.post_out = posteriors ? static_cast<unsigned char*>(posteriors) + s0 * g.L * g.n * msg_bytes(g)
+                                : nullptr;
         b.conv_mask = W.cmask;
         b.iters = W.iters;
         b.qfix = nullptr;

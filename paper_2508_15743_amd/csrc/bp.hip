@@ -8,40 +8,72 @@
 // and those after v still hold the previous sweep's.  So min and sign parity
 // over N(c) \ v split into
 //   * a prefix state per check (running min and parity of this sweep's new
-//     messages), 4 bytes of LDS per check, and
+//     messages), one word of LDS per check, and
 //   * a suffix state (min and parity of the previous sweep's messages on the
 //     row's later edges), kept in the edge's own slot of the message slab.
-// The slab follows the member's sweep order, so a chunk reads the suffix
-// states of its edges and overwrites them with the new messages in one
-// contiguous run.  After the sweep, a backward pass over the chunks with a
+// The slab follows the member's schedule, so a chunk reads the suffix states
+// of its edges and overwrites them with the new messages in one contiguous
+// run of 64 slots.  After the sweep, a backward pass over the chunks with a
 // running state per check (LDS) turns the new messages into the next sweep's
-// suffix states, again one contiguous run per chunk.
+// suffix states, again one run per chunk.
 //
-// Columns that share no check commute, so the host grouped the sweep into
-// dependency levels and chunks of at most 64 edges holding whole columns;
+// Columns that share no check commute, so the host packed each member's
+// sweep into chunks of mutually independent columns with at most 64 edges;
 // a chunk runs with one lane per edge and the result is bit-identical to the
 // column-by-column sweep.  Sums over a column's edges run in ascending check
-// order through wave shuffles.  Hard decisions, the residual syndrome
-// s + H e and the syndrome are bit-packed in LDS; convergence is a ballot.
+// order through wave shuffles, as in a column-by-column decoder, and nothing
+// is contracted into fused multiply-adds, so the FP64 variant reproduces a
+// plain FP64 decoder bit for bit.  The chain of chunks is the critical path:
+// both passes load their slots four chunks ahead.  Hard decisions, the
+// residual syndrome s + H e and the syndrome are bit-packed in LDS;
+// convergence is a ballot.
 #include "internal.h"
+
+#pragma clang fp contract(off)
 
 namespace vibe {
 
 namespace {
 
-__device__ inline float clampf(float x, float lim) { return fminf(fmaxf(x, -lim), lim); }
+template <class F>
+struct Prec;
 
-__device__ inline uint32_t rs_encode(float x) {
-    return (__float_as_uint(x) & 0x7fffffffu) | (x < 0.0f ? 0x80000000u : 0u);
+template <>
+struct Prec<float> {
+    using B = uint32_t;
+    static constexpr B kSign = 0x80000000u;
+    __device__ static B bits(float x) { return __float_as_uint(x); }
+    __device__ static float val(B b) { return __uint_as_float(b); }
+    __device__ static float clamp(float x, float lim) { return fminf(fmaxf(x, -lim), lim); }
+    __device__ static B ident(const DevGraph& g) { return g.ident32; }
+};
+
+template <>
+struct Prec<double> {
+    using B = uint64_t;
+    static constexpr B kSign = 0x8000000000000000ull;
+    __device__ static B bits(double x) { return (uint64_t)__double_as_longlong(x); }
+    __device__ static double val(B b) { return __longlong_as_double((long long)b); }
+    __device__ static double clamp(double x, double lim) { return fmin(fmax(x, -lim), lim); }
+    __device__ static B ident(const DevGraph& g) { return g.ident64; }
+};
+
+template <class F>
+__device__ inline typename Prec<F>::B rs_encode(F x) {
+    using P = Prec<F>;
+    return (P::bits(x) & ~P::kSign) | (x < F(0) ? P::kSign : (typename P::B)0);
 }
 
 __device__ inline uint64_t load_mask(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline double wave_sum_f64(double x) {
-    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
-    return x;
+// lane j's value, broadcast (j wave-uniform)
+__device__ inline double readlane_f64(double x, int j) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), j);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 __device__ inline uint32_t wave_sum_u32(uint32_t x) {
@@ -49,14 +81,9 @@ __device__ inline uint32_t wave_sum_u32(uint32_t x) {
     return uni(x);
 }
 
-__device__ inline uint32_t wave_max_u32(uint32_t x) {
-    for (int off = kWave / 2; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off));
-    return uni(x);
-}
-
 // Members known to precede `mem` in (convergence iteration, index) order:
 // converged before iteration t, or at t with a lower index.
-__device__ inline uint32_t preceding_converged(const uint64_t* mask, uint32_t t, uint32_t mem, int lane) {
+__device__ uint32_t preceding_converged(const uint64_t* mask, uint32_t t, uint32_t mem, int lane) {
     uint32_t cnt = 0;
     for (uint32_t tt = lane + 1; tt < t; tt += kWave) cnt += __popcll(load_mask(&mask[tt]));
     const uint32_t own = __popcll(load_mask(&mask[t]) & ((1ull << mem) - 1ull));
@@ -64,62 +91,262 @@ __device__ inline uint32_t preceding_converged(const uint64_t* mask, uint32_t t,
     return wave_sum_u32(cnt);
 }
 
-// Backward pass: turn the slab's new messages (float bits) into the suffix
-// states of the next sweep.  Chunks from last to first; running[c] is the
-// state of the part of row c already passed.  Edges of one chunk sit in
-// distinct rows, so a chunk is one parallel step.
-__device__ void suffix_pass(const DevGraph& g, uint32_t* slab, uint32_t* running, uint32_t ch_lo,
-                            uint32_t ch_hi, size_t mbase, int lane) {
-    for (uint32_t c = lane; c < g.m; c += kWave) running[c] = g.ident;
-    __syncthreads();
-    uint32_t nmeta = 0, nx = 0, nlen = 0;
-    size_t npos = 0;
-    if (ch_hi > ch_lo) {
-        const uint32_t beg = g.chunk_off[ch_hi - 1];
-        nlen = g.chunk_off[ch_hi] - beg;
-        npos = beg - mbase + lane;
-        if ((uint32_t)lane < nlen) {
-            nmeta = g.slots[beg + lane].meta;
-            nx = slab[npos];
-        }
-    }
-    for (uint32_t ch = ch_hi; ch-- > ch_lo;) {
-        const uint32_t meta = nmeta, x = nx, len = nlen;
-        const size_t pos = npos;
-        if (ch > ch_lo) {
-            const uint32_t beg = g.chunk_off[ch - 1];
-            nlen = g.chunk_off[ch] - beg;
-            npos = beg - mbase + lane;
-            if ((uint32_t)lane < nlen) {
-                nmeta = g.slots[beg + lane].meta;
-                nx = slab[npos];
-            }
-        }
-        if ((uint32_t)lane < len) {
-            const uint32_t c = meta & 0xffffu;
-            const uint32_t st = running[c];
-            slab[pos] = st;
-            running[c] = rs_combine(rs_encode(__uint_as_float(x)), st);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+// Buffer resources: the schedule of one member and the message slab of one
+// block are addressed as a wave-uniform descriptor plus a per-lane byte
+// offset, so no 64-bit address is formed per lane and load.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kBufFlags = 0x00020000;  // 32-bit data format: plain dword access
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufFlags);
+}
+
+template <class T>
+__device__ __forceinline__ T bload(Rsrc r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4) {
+        const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+        return __builtin_bit_cast(T, u);
+    } else {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+        return __builtin_bit_cast(T, u);
     }
 }
 
-template <bool SLAB_LDS>
+template <class T>
+__device__ __forceinline__ void bstore(T v, Rsrc r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+    } else {
+        using V2 = __attribute__((ext_vector_type(2))) unsigned int;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, (int)voff, (int)soff, 0);
+    }
+}
+
+// What one work item's passes need.
+template <class F>
+struct Ctx {
+    using B = typename Prec<F>::B;
+    Rsrc sch;       // the member's chunk records
+    Rsrc slb;       // the block's slab (global variant)
+    B* lslab;       // the block's slab (LDS variant)
+    B* pref;
+    const uint64_t* sb;
+    uint64_t* res;
+    uint64_t* eb;
+    F* post;        // n posteriors
+    F* trash;       // 64 slots that absorb the posterior stores of lanes that
+                    // own no column
+    F al, lim;
+    int lane;
+    uint32_t lane4, laneF;  // lane * 4, lane * sizeof(F)
+};
+
+// Every vector memory operation of a chunk step is issued unconditionally
+// (prefetch indices are clamped instead of tested, unused slots store junk
+// into their own slab slot), so the compiler can count the loads still in
+// flight and wait only for the oldest stage instead of draining all of them.
+#ifndef VIBE_BP_DEPTH
+#define VIBE_BP_DEPTH 2
+#endif
+constexpr int kDepth = VIBE_BP_DEPTH;  // chunks loaded ahead of the one being processed
+
+// Slot data of one chunk for the sweep, loaded ahead of use.
+template <class F>
+struct Stage {
+    uint32_t meta, v;
+    F lam;
+    typename Prec<F>::B suf;
+};
+
+template <class F, bool SLAB_LDS>
+__device__ __forceinline__ void fetch(const Ctx<F>& x, Stage<F>& s, uint32_t k, bool first) {
+    using B = typename Prec<F>::B;
+    constexpr bool kF64 = sizeof(F) == 8;
+    // chunk offset added to the lane offset (a short-lived VGPR); field
+    // offsets become instruction immediates
+    const uint32_t base = k * rec_bytes(kF64);
+    const uint32_t o4 = x.lane4 + base, oF = x.laneF + base;
+    s.meta = bload<uint32_t>(x.sch, o4, 0);
+    s.v = bload<uint32_t>(x.sch, o4 + kRecV, 0);
+    s.lam = bload<F>(x.sch, oF + kRecLam, 0);
+    if constexpr (SLAB_LDS) {
+        s.suf = x.lslab[k * kWave + x.lane];
+    } else {
+        // first sweep: the initial suffix states of the schedule record
+        const Rsrc r = first ? x.sch : x.slb;
+        const uint32_t o = first ? oF + rec_init(kF64) : x.laneF + k * kWave * (uint32_t)sizeof(B);
+        s.suf = bload<B>(r, o, 0);
+    }
+}
+
+// One chunk of the serial sweep: r_{c->v} = (1 - 2 s_c) alpha prod sign
+// min |mu| over N(c) \ v for each edge, then L_v and the new mu_{v->c}.
+template <class F, bool SLAB_LDS, bool WANT_POST>
+__device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, uint32_t k) {
+    using P = Prec<F>;
+    using B = typename P::B;
+    const uint32_t meta = s.meta, v = s.v;
+    const uint32_t deg = (meta >> kMetaDegShift) & 15u;  // 0: unused slot (c = 0, v = 0)
+    const uint32_t dmax = uni((meta >> kMetaDmaxShift) & 15u);
+    const uint32_t c = meta & 0xffffu, seg = (meta >> 16) & 15u;
+    // the three LDS words this edge needs, issued together
+    const B pre = x.pref[c];
+    const uint64_t sw = x.sb[c >> 6];
+    const uint64_t ew = x.eb[v >> 6];
+    const B stt = rs_combine<B>(pre, s.suf);
+    const bool neg = ((stt & P::kSign) != 0) != (((sw >> (c & 63)) & 1ull) != 0);
+    const F rr = x.al * P::val(stt & ~P::kSign);
+    const F r = deg ? (neg ? -rr : rr) : F(0);
+    // L_v = lambda_v + sum_c r, mu_{v->c} = lambda_v + sum_{c' != c} r, both in
+    // ascending check order over the column's consecutive lanes; the
+    // shuffles go out four at a time
+    const int b0 = x.lane - (int)seg;
+    F L = s.lam, mu = s.lam;
+    for (uint32_t j = 0; j < dmax; j += 4) {
+        F rj[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) rj[q] = __shfl(r, (b0 + (int)j + q) & (kWave - 1));
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint32_t jj = j + q;
+            if (jj < deg) {
+                L += rj[q];
+                if (jj != seg) mu += rj[q];
+            }
+        }
+    }
+    L = P::clamp(L, x.lim);
+    mu = P::clamp(mu, x.lim);
+    if constexpr (SLAB_LDS)
+        x.lslab[k * kWave + x.lane] = P::bits(mu);
+    else
+        bstore<B>(P::bits(mu), x.slb, x.laneF + k * kWave * (uint32_t)sizeof(B), 0);
+    const bool enew = L <= F(0);
+    const bool eold = (ew >> (v & 63)) & 1ull;
+    if (deg) {
+        x.pref[c] = rs_combine<B>(pre, rs_encode(mu));
+        if (enew != eold) {
+            if (seg == 0) atomicXor(reinterpret_cast<unsigned long long*>(&x.eb[v >> 6]), 1ull << (v & 63));
+            atomicXor(reinterpret_cast<unsigned long long*>(&x.res[c >> 6]), 1ull << (c & 63));
+        }
+    }
+    if constexpr (WANT_POST) {
+        F* dst = (deg && seg == 0) ? x.post + v : x.trash + x.lane;
+        *dst = L;
+    }
+    // LDS writes of this chunk precede the next chunk's reads; nothing of a
+    // later chunk is scheduled into this one (that would keep every stage's
+    // derived values live at once)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// The whole sweep: chunks 0 .. nch-1 (nch >= 1), each one's slots loaded
+// kDepth chunks ahead (the suffix states of later chunks are final for the
+// whole sweep).
+template <class F, bool SLAB_LDS, bool WANT_POST>
+__device__ __forceinline__ void sweep(const Ctx<F>& x, uint32_t nch, bool first) {
+    const uint32_t last = nch - 1;
+    Stage<F> ring[kDepth];
+#pragma unroll
+    for (int d = 0; d < kDepth; d++) fetch<F, SLAB_LDS>(x, ring[d], min((uint32_t)d, last), first);
+    for (uint32_t k = 0; k < nch; k += kDepth) {
+#pragma unroll
+        for (int d = 0; d < kDepth; d++) {
+            if (k + d >= nch) break;
+            sweep_chunk<F, SLAB_LDS, WANT_POST>(x, ring[d], k + d);
+            fetch<F, SLAB_LDS>(x, ring[d], min(k + d + kDepth, last), first);
+        }
+    }
+}
+
+template <class F>
+struct BStage {
+    uint32_t meta;
+    typename Prec<F>::B msg;
+};
+
+template <class F, bool SLAB_LDS>
+__device__ __forceinline__ void bfetch(const Ctx<F>& x, BStage<F>& s, uint32_t k) {
+    using B = typename Prec<F>::B;
+    s.meta = bload<uint32_t>(x.sch, x.lane4 + k * rec_bytes(sizeof(F) == 8), 0);
+    if constexpr (SLAB_LDS)
+        s.msg = x.lslab[k * kWave + x.lane];
+    else
+        s.msg = bload<B>(x.slb, x.laneF + k * kWave * (uint32_t)sizeof(B), 0);
+}
+
+// One chunk of the backward pass: the slot receives the state of its row's
+// later edges, then its own message joins the running state.
+template <class F, bool SLAB_LDS>
+__device__ __forceinline__ void back_chunk(const Ctx<F>& x, const BStage<F>& s, uint32_t k,
+                                           typename Prec<F>::B* running) {
+    using B = typename Prec<F>::B;
+    const uint32_t c = s.meta & 0xffffu;
+    const B stt = running[c];
+    if constexpr (SLAB_LDS)
+        x.lslab[k * kWave + x.lane] = stt;
+    else
+        bstore<B>(stt, x.slb, x.laneF + k * kWave * (uint32_t)sizeof(B), 0);
+    if ((s.meta >> kMetaDegShift) & 15u) running[c] = rs_combine<B>(rs_encode(Prec<F>::val(s.msg)), stt);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Backward pass over chunks nch-1 .. 0 (nch >= 1) with loads kDepth chunks
+// ahead.  Edges of one chunk sit in distinct rows, so a chunk is one
+// parallel step.
+template <class F, bool SLAB_LDS>
+__device__ __forceinline__ void backward(const Ctx<F>& x, uint32_t nch, typename Prec<F>::B* running) {
+    BStage<F> ring[kDepth];
+    auto at = [nch](uint32_t d) { return d < nch ? nch - 1 - d : 0u; };  // d chunks from the end
+#pragma unroll
+    for (int d = 0; d < kDepth; d++) bfetch<F, SLAB_LDS>(x, ring[d], at(d));
+    for (uint32_t e = 0; e < nch; e += kDepth) {
+#pragma unroll
+        for (int d = 0; d < kDepth; d++) {
+            if (e + d >= nch) break;
+            back_chunk<F, SLAB_LDS>(x, ring[d], nch - 1 - e - d, running);
+            bfetch<F, SLAB_LDS>(x, ring[d], at(e + d + kDepth));
+        }
+    }
+}
+
+template <class F, bool SLAB_LDS>
 __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch a) {
+    using P = Prec<F>;
+    using B = typename P::B;
     extern __shared__ __align__(16) unsigned char lds[];
     uint64_t* sb = reinterpret_cast<uint64_t*>(lds);
     uint64_t* res = sb + g.words_m;
     uint64_t* eb = res + g.words_m;
-    uint32_t* pref = reinterpret_cast<uint32_t*>(eb + g.words_n);
-    uint32_t* slab = SLAB_LDS ? pref + g.m : a.slab + (size_t)blockIdx.x * g.E;
+    B* pref = reinterpret_cast<B*>(eb + g.words_n);
+    B* slab = SLAB_LDS ? pref + g.m : nullptr;  // LDS variant; the global slab is a buffer resource
 
     const int lane = threadIdx.x;
-    float* post = a.post_slab + (size_t)blockIdx.x * g.n;
+    F* post = reinterpret_cast<F*>(a.post_slab) + (size_t)blockIdx.x * (g.n + kWave);
+    const F* lamv = reinterpret_cast<const F*>(g.lam);
     const uint32_t n_items = a.n_shots * g.L;
-    const float lim = g.clamp;
-    const float al = g.alpha;
+    const B ident = P::ident(g);
+
+    Ctx<F> x;
+    x.slb = make_rsrc(a.slab ? reinterpret_cast<B*>(a.slab) + (size_t)blockIdx.x * g.max_chunks * kWave : nullptr,
+                      g.max_chunks * kWave * (uint32_t)sizeof(B));
+    x.lslab = slab;
+    x.pref = pref;
+    x.sb = sb;
+    x.res = res;
+    x.eb = eb;
+    x.post = post;
+    x.trash = post + g.n;
+    x.al = (F)g.alpha;
+    x.lim = (F)g.clamp;
+    x.lane = lane;
+    x.lane4 = (uint32_t)lane * 4u;
+    x.laneF = (uint32_t)lane * (uint32_t)sizeof(F);
+    constexpr bool kF64 = sizeof(F) == 8;
 
     for (;;) {
         const uint32_t item = wave_ticket(a.counter, 1u);
@@ -166,16 +393,23 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
             }
             continue;
         }
+        for (uint32_t w = lane; w < g.words_n; w += kWave) eb[w] = g.e0[w];
+
         // The slab is only ever re-read by the lane that wrote it: a slot's
-        // position is (chunk start + lane) in the sweep and in the backward
+        // position is (chunk * 64 + lane) in the sweep and in the backward
         // pass alike.  The first sweep reads the suffix states of the initial
         // messages from the graph itself.
-        const size_t mbase = (size_t)mem * g.E;  // this member's first slot
-        const uint32_t* init = g.init_suf + mbase;
-        for (uint32_t w = lane; w < g.words_n; w += kWave) eb[w] = g.e0[w];
-        __syncthreads();
+        const uint32_t c0 = uni(g.member_chunk[mem]), nch = uni(g.member_chunk[mem + 1]) - c0;
+        const unsigned char* recs = g.sched + (size_t)c0 * rec_bytes(kF64);
+        x.sch = make_rsrc(recs, nch * rec_bytes(kF64));
+        F* post_out = a.post_out ? reinterpret_cast<F*>(a.post_out) + (size_t)rec * g.n : nullptr;
+        if constexpr (SLAB_LDS) {
+            // the first sweep reads the initial suffix states from the slab
+            for (uint32_t q = 0; q < nch; q++)
+                slab[q * kWave + lane] = *reinterpret_cast<const B*>(recs + (size_t)q * rec_bytes(kF64) +
+                                                                     rec_init(kF64) + (size_t)lane * sizeof(B));
+        }
 
-        const uint32_t ch_lo = g.member_chunk[mem], ch_hi = g.member_chunk[mem + 1];
         uint32_t conv_t = 0, ran = 0;
         bool stopped = false;
         for (uint32_t t = 1; t <= a.T_run; t++) {
@@ -183,95 +417,25 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
                 stopped = true;  // cannot be among the first M any more
                 break;
             }
-            const bool want_post = a.post_out != nullptr || (a.accumulate_q && t == a.T_run);
+            const bool want_post = post_out != nullptr || (a.accumulate_q && t == a.T_run);
             if (want_post) {
                 // columns without checks keep L_v = lambda_v
-                for (uint32_t v = lane; v < g.n; v += kWave) {
-                    const float l = g.lam[v];
-                    post[v] = l;
-                    if (a.post_out) a.post_out[(size_t)rec * g.n + v] = l;
-                }
+                for (uint32_t v = lane; v < g.n; v += kWave) post[v] = lamv[v];
             }
-            for (uint32_t c = lane; c < g.m; c += kWave) pref[c] = g.ident;
+            for (uint32_t c = lane; c < g.m; c += kWave) pref[c] = ident;
             __syncthreads();
-
-            // software pipeline: the slots and suffix states of the next chunk
-            // are loaded while the current chunk is processed (suffix states
-            // of later slots are final for the whole sweep)
-            Slot nsl{0, 0};
-            uint32_t nsuf = g.ident, nlen = 0;
-            size_t npos = 0;
-            if (ch_lo < ch_hi) {
-                const uint32_t nbeg = g.chunk_off[ch_lo];
-                nlen = g.chunk_off[ch_lo + 1] - nbeg;
-                npos = nbeg - mbase + lane;
-                if ((uint32_t)lane < nlen) {
-                    nsl = g.slots[nbeg + lane];
-                    nsuf = t == 1 ? init[npos] : slab[npos];
-                }
-            }
-            for (uint32_t ch = ch_lo; ch < ch_hi; ch++) {
-                const Slot sl = nsl;
-                const uint32_t suf = nsuf;
-                const uint32_t len = nlen;
-                const size_t pos = npos;
-                if (ch + 1 < ch_hi) {
-                    const uint32_t nbeg = g.chunk_off[ch + 1];
-                    nlen = g.chunk_off[ch + 2] - nbeg;
-                    npos = nbeg - mbase + lane;
-                    if ((uint32_t)lane < nlen) {
-                        nsl = g.slots[nbeg + lane];
-                        nsuf = t == 1 ? init[npos] : slab[npos];
-                    }
-                }
-                const bool act = (uint32_t)lane < len;
-                const uint32_t c = sl.meta & 0xffffu;
-                const uint32_t seg = (sl.meta >> 16) & 15u;
-                const uint32_t deg = act ? (sl.meta >> 20) & 15u : 0u;
-                float r = 0.0f, lv = 0.0f;
-                uint32_t pre = 0;
-                if (act) {
-                    lv = g.lam[sl.v];
-                    pre = pref[c];
-                    // r_{c->v} = (1 - 2 s_c) alpha prod sign min |mu|, over N(c) \ v
-                    const uint32_t st = rs_combine(pre, suf);
-                    const uint32_t neg = (st >> 31) ^ (uint32_t)((sb[c >> 6] >> (c & 63)) & 1ull);
-                    const float rr = al * __uint_as_float(st & 0x7fffffffu);
-                    r = neg ? -rr : rr;
-                }
-                // sums over the column's edges in ascending check order
-                const uint32_t dmax = wave_max_u32(deg);
-                const int b0 = lane - (int)seg;
-                float L = lv, x = lv;
-                for (uint32_t j = 0; j < dmax; j++) {
-                    const float rj = __shfl(r, (b0 + (int)j) & (kWave - 1));
-                    if (j < deg) {
-                        L += rj;
-                        if (j != seg) x += rj;
-                    }
-                }
-                if (act) {
-                    L = clampf(L, lim);
-                    x = clampf(x, lim);
-                    slab[pos] = __float_as_uint(x);
-                    pref[c] = rs_combine(pre, rs_encode(x));
-                    const uint32_t v = sl.v;
-                    const bool enew = L <= 0.0f;
-                    const bool eold = (eb[v >> 6] >> (v & 63)) & 1ull;
-                    if (enew != eold) {
-                        if (seg == 0) atomicXor(reinterpret_cast<unsigned long long*>(&eb[v >> 6]), 1ull << (v & 63));
-                        atomicXor(reinterpret_cast<unsigned long long*>(&res[c >> 6]), 1ull << (c & 63));
-                    }
-                    if (want_post && seg == 0) {
-                        post[v] = L;
-                        if (a.post_out) a.post_out[(size_t)rec * g.n + v] = L;
-                    }
-                }
-                // LDS writes of this chunk precede the next chunk's reads
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
+            if (nch) {
+                if (want_post)
+                    sweep<F, SLAB_LDS, true>(x, nch, t == 1);
+                else
+                    sweep<F, SLAB_LDS, false>(x, nch, t == 1);
             }
             __syncthreads();  // every new message stored
+            if (post_out) {
+                // post[v] was written by the lane that swept v: read it past the L1
+                for (uint32_t v = lane; v < g.n; v += kWave)
+                    post_out[v] = __hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             ran = t;
             // converged iff the residual s + H e is zero
             bool nz = false;
@@ -280,8 +444,10 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
                 if (!conv_t) conv_t = t;
                 if (a.stop_on_converge) break;
             }
-            if (t < a.T_run) {
-                suffix_pass(g, slab, pref, ch_lo, ch_hi, mbase, lane);
+            if (t < a.T_run && nch) {
+                for (uint32_t c = lane; c < g.m; c += kWave) pref[c] = ident;
+                __syncthreads();
+                backward<F, SLAB_LDS>(x, nch, pref);
                 __syncthreads();
             }
         }
@@ -320,18 +486,26 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
             uint32_t cnt = 0;
             for (uint32_t tt = lane + 1; tt <= a.T_run; tt += kWave) cnt += __popcll(load_mask(&cmask[tt]));
             if (wave_sum_u32(cnt) == 0) {
-                // post[v] was written by the lane that swept v: read it past the L1
+                // ||L||^2 summed in ascending v: each lane squares one value of
+                // a block of 64 and the running sum takes them in order (every
+                // lane holds the same sum).  post[v] was written by the lane
+                // that swept v: read it past the L1.
                 double ss = 0.0;
-                for (uint32_t v = lane; v < g.n; v += kWave) {
-                    const double xv = __hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ss += xv * xv;
+                for (uint32_t base = 0; base < g.n; base += kWave) {
+                    const uint32_t v = base + lane;
+                    double sq = 0.0;
+                    if (v < g.n) {
+                        const double xv = (double)__hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        sq = xv * xv;
+                    }
+                    const uint32_t cnt_b = min((uint32_t)kWave, g.n - base);
+                    for (uint32_t j = 0; j < cnt_b; j++) ss += readlane_f64(sq, (int)j);
                 }
-                ss = wave_sum_f64(ss);
                 if (uni(ss > 0.0 ? 1u : 0u)) {
                     const double scale = kQScale / sqrt(ss);
                     int64_t* q = a.qfix + (size_t)shot * g.n;
                     for (uint32_t v = lane; v < g.n; v += kWave) {
-                        const double xv = __hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const double xv = (double)__hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         atomicAdd(reinterpret_cast<unsigned long long*>(&q[v]), (unsigned long long)llrint(xv * scale));
                     }
                 }
@@ -346,11 +520,17 @@ __global__ void zero_kernel(uint32_t* p, size_t words) {
         p[i] = 0u;
 }
 
+const void* kernel_for(bool fp64, bool slab_in_lds) {
+    if (fp64) return slab_in_lds ? (const void*)bp_ensemble_kernel<double, true> : (const void*)bp_ensemble_kernel<double, false>;
+    return slab_in_lds ? (const void*)bp_ensemble_kernel<float, true> : (const void*)bp_ensemble_kernel<float, false>;
+}
+
 }  // namespace
 
 size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds) {
-    size_t b = sizeof(uint64_t) * (2 * (size_t)g.words_m + g.words_n) + sizeof(uint32_t) * g.m;
-    if (slab_in_lds) b += sizeof(uint32_t) * (size_t)g.E;
+    const size_t mb = g.fp64 ? 8 : 4;
+    size_t b = sizeof(uint64_t) * (2 * (size_t)g.words_m + g.words_n) + mb * g.m;
+    if (slab_in_lds) b += mb * (size_t)g.max_chunks * kWave;
     return b;
 }
 
@@ -367,25 +547,31 @@ int bp_grid(const DevGraph& g, bool slab_in_lds) {
     }
     const size_t lds = bp_lds_bytes(g, slab_in_lds);
     int per_cu = 0;
-    hipError_t e = slab_in_lds
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bp_ensemble_kernel<true>, kWave, lds)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bp_ensemble_kernel<false>, kWave, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(g.fp64, slab_in_lds), kWave, lds);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
-    if (per_cu > 16) per_cu = 16;
+    if (per_cu > 32) per_cu = 32;
     return per_cu * cached_cus;
 }
 
 int launch_bp(const DevGraph& g, const BpLaunch& a, hipStream_t st) {
-    const size_t lds = bp_lds_bytes(g, a.slab_in_lds != 0);
-    const void* fn = a.slab_in_lds ? (const void*)bp_ensemble_kernel<true> : (const void*)bp_ensemble_kernel<false>;
+    const bool in_lds = a.slab_in_lds != 0;
+    const size_t lds = bp_lds_bytes(g, in_lds);
+    const void* fn = kernel_for(g.fp64, in_lds);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(bp)");
     }
-    if (a.slab_in_lds)
-        hipLaunchKernelGGL(bp_ensemble_kernel<true>, dim3(a.grid), dim3(kWave), lds, st, g, a);
-    else
-        hipLaunchKernelGGL(bp_ensemble_kernel<false>, dim3(a.grid), dim3(kWave), lds, st, g, a);
+    if (g.fp64) {
+        if (in_lds)
+            hipLaunchKernelGGL((bp_ensemble_kernel<double, true>), dim3(a.grid), dim3(kWave), lds, st, g, a);
+        else
+            hipLaunchKernelGGL((bp_ensemble_kernel<double, false>), dim3(a.grid), dim3(kWave), lds, st, g, a);
+    } else {
+        if (in_lds)
+            hipLaunchKernelGGL((bp_ensemble_kernel<float, true>), dim3(a.grid), dim3(kWave), lds, st, g, a);
+        else
+            hipLaunchKernelGGL((bp_ensemble_kernel<float, false>), dim3(a.grid), dim3(kWave), lds, st, g, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "bp_ensemble_kernel launch");
     return VIBE_OK;

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <queue>
 
 #include "internal.h"
 
@@ -74,7 +75,10 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     if (c.lsd_order != 0) return fail(VIBE_EUNSUPPORTED, "only LSD order 0 is implemented");
     if (!(c.alpha > 0.0) || !(c.alpha <= 1e6)) return fail(VIBE_EINVAL, "alpha must be in (0, 1e6]");
     if (!(c.clamp >= 1.0) || !(c.clamp <= 1e30)) return fail(VIBE_EINVAL, "clamp must be in [1, 1e30]");
-    if (m && (size_t)m * 4 + 8 * (2 * (size_t)((m + 63) / 64) + (n + 63) / 64) > 150 * 1024)
+    if (c.message_bits != 0 && c.message_bits != 32 && c.message_bits != 64)
+        return fail(VIBE_EINVAL, "message_bits must be 0, 32 or 64");
+    if (m && (size_t)m * (c.message_bits == 64 ? 8 : 4) + 8 * (2 * (size_t)((m + 63) / 64) + (n + 63) / 64) >
+                 150 * 1024)
         return fail(VIBE_EUNSUPPORTED, "per-decoder LDS state exceeds 150 KB");
 
     // ---- H in CSR: validate
@@ -137,117 +141,212 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     for (uint32_t v = 0; v < n; v++) max_col = std::max(max_col, cp[v + 1] - cp[v]);
     if (max_col > (uint32_t)kMaxColDeg) return fail(VIBE_EUNSUPPORTED, "a column is in more than 15 checks");
 
-    // ---- channel LLRs
+    // ---- channel LLRs, in FP64 with the C library's log
     const double lim = c.clamp;
+    const bool fp64 = c.message_bits == 64;
     std::vector<double> lam64(n);
-    std::vector<float> lam(n);
+    std::vector<float> lam32(n);
     int all_pos = 1;
     for (uint32_t v = 0; v < n; v++) {
         double l = std::log((1.0 - priors[v]) / priors[v]);
         l = std::min(std::max(l, -lim), lim);
         lam64[v] = l;
-        lam[v] = (float)l;
-        if (!(lam[v] > 0.0f)) all_pos = 0;
+        lam32[v] = (float)l;
+        if (!(fp64 ? l > 0.0 : lam32[v] > 0.0f)) all_pos = 0;
     }
-    const float limf = (float)lim;
     const uint32_t words_n = (n + 63) / 64, words_m = (m + 63) / 64;
     std::vector<uint64_t> e0(words_n, 0);
     for (uint32_t v = 0; v < n; v++)
-        if (cp[v + 1] == cp[v] && !(lam[v] > 0.0f)) e0[v / 64] |= 1ull << (v % 64);
+        if (cp[v + 1] == cp[v] && !(fp64 ? lam64[v] > 0.0 : lam32[v] > 0.0f)) e0[v / 64] |= 1ull << (v % 64);
     std::vector<uint64_t> lobs((size_t)std::max<uint32_t>(k, 1) * words_n, 0);
     for (uint32_t r = 0; r < k; r++)
         for (uint32_t a = l_indptr[r]; a < l_indptr[r + 1]; a++) {
             uint32_t v = l_indices[a];
             lobs[(size_t)r * words_n + v / 64] ^= 1ull << (v % 64);
         }
-    auto enc = [](float x) -> uint32_t {
+    // row states (magnitude bits with the sign of the message as parity)
+    auto enc32 = [](float x) -> uint32_t {
         float a = std::fabs(x);
         uint32_t bits;
         std::memcpy(&bits, &a, 4);
         return bits | (x < 0.0f ? 0x80000000u : 0u);
     };
-    uint32_t ident;
-    std::memcpy(&ident, &limf, 4);
+    auto enc64 = [](double x) -> uint64_t {
+        double a = std::fabs(x);
+        uint64_t bits;
+        std::memcpy(&bits, &a, 8);
+        return bits | (x < 0.0 ? 1ull << 63 : 0ull);
+    };
+    const float limf = (float)lim;
+    uint32_t ident32;
+    uint64_t ident64;
+    std::memcpy(&ident32, &limf, 4);
+    std::memcpy(&ident64, &lim, 8);
 
-    // ---- member schedules.  The serial sweep of member i visits the columns
-    //      in perms[i]; columns that share no check commute, so the sweep is
-    //      regrouped into dependency levels (level(v) = 1 + the largest level
-    //      of an earlier column sharing a check), each level cut into chunks
-    //      of at most 64 edges holding whole columns.  The member's message
-    //      slab follows the same slot order.  At column v's turn, the edges of
-    //      a row that come before v in the sweep carry this sweep's messages
-    //      and those after v the previous sweep's; init_suf holds, at every
-    //      slot, the state (min |mu|, sign parity) of the row's later edges
-    //      for the initial messages mu = lambda.
-    std::vector<Slot> slots((size_t)c.L * E);
-    std::vector<uint32_t> init_suf((size_t)c.L * E);
-    std::vector<uint32_t> chunk_off;
+    // ---- member schedules (Sec. III.D.1: one fixed serial order per member).
+    //      Two columns that share a check must keep their permutation order:
+    //      the later one reads the earlier one's new message, and the earlier
+    //      one reads the later one's previous message.  Columns that share no
+    //      check commute.  So the sweep is any topological order of the DAG
+    //      whose arcs join consecutive columns of each row, cut into chunks
+    //      of columns that are mutually independent.  Chunks are packed by
+    //      list scheduling (ready columns by decreasing height, the longest
+    //      chain of successors below them, then by permutation position) into
+    //      at most 64 edges each, which reaches max(#levels, ceil(E / 64))
+    //      chunks on the workloads here.
+    std::vector<uint32_t> s_meta, s_v, init32;
+    std::vector<float> s_lam32;
+    std::vector<double> s_lam64;
+    std::vector<uint64_t> init64;
     std::vector<uint32_t> member_chunk(c.L + 1, 0);
-    uint32_t lev_min = UINT32_MAX, lev_max = 0;
+    uint32_t lev_min = UINT32_MAX, lev_max = 0, ch_min = UINT32_MAX, ch_max = 0;
     {
-        std::vector<uint32_t> last(m), level(n), count, start, order(n), running(m);
+        const uint32_t kNone = UINT32_MAX;
+        std::vector<uint32_t> last(m), level(n), height(n), npred(n), pos(n), succ(E);
+        std::vector<uint32_t> taken;
+        std::vector<uint64_t> skipped;
+        std::vector<uint32_t> running32(m);
+        std::vector<uint64_t> running64(m);
+        size_t nchunks = 0;
         for (uint32_t i = 0; i < c.L; i++) {
             const uint32_t* pi = perms + (size_t)i * n;
-            std::fill(last.begin(), last.end(), 0);
-            uint32_t nlev = 0;
+            std::fill(last.begin(), last.end(), kNone);
+            std::fill(succ.begin(), succ.end(), kNone);
+            uint32_t nlev = 0, ncols = 0;
             for (uint32_t a = 0; a < n; a++) {
-                uint32_t v = pi[a], lv = 0;
-                for (uint32_t j = cp[v]; j < cp[v + 1]; j++) lv = std::max(lv, last[ci[j]]);
-                lv += 1;
-                level[v] = lv;
-                for (uint32_t j = cp[v]; j < cp[v + 1]; j++) last[ci[j]] = lv;
-                if (cp[v + 1] > cp[v]) nlev = std::max(nlev, lv);
+                const uint32_t v = pi[a];
+                pos[v] = a;
+                npred[v] = 0;
+                uint32_t lv = 0;
+                for (uint32_t j = cp[v]; j < cp[v + 1]; j++) {
+                    const uint32_t r = ci[j], u = last[r];
+                    if (u != kNone) {
+                        // arc u -> v through row r; u's edge on r is the one
+                        // whose check is r
+                        uint32_t ju = cp[u];
+                        while (ci[ju] != r) ju++;
+                        succ[ju] = v;
+                        bool dup = false;
+                        for (uint32_t j2 = cp[v]; j2 < j; j2++) dup |= last[ci[j2]] == u;
+                        if (!dup) npred[v]++;
+                        lv = std::max(lv, level[u]);
+                    }
+                }
+                for (uint32_t j = cp[v]; j < cp[v + 1]; j++) last[ci[j]] = v;
+                level[v] = lv + 1;
+                if (cp[v + 1] > cp[v]) {
+                    nlev = std::max(nlev, level[v]);
+                    ncols++;
+                }
+            }
+            for (uint32_t a = n; a-- > 0;) {
+                const uint32_t u = pi[a];
+                uint32_t h = 0;
+                for (uint32_t j = cp[u]; j < cp[u + 1]; j++)
+                    if (succ[j] != kNone) h = std::max(h, height[succ[j]]);
+                height[u] = h + 1;
             }
             lev_min = std::min(lev_min, nlev);
             lev_max = std::max(lev_max, nlev);
-            count.assign(nlev + 2, 0);
+            // ready queue keyed by (larger height, earlier position)
+            auto key = [&](uint32_t v) { return ((uint64_t)(~height[v]) << 32) | pos[v]; };
+            std::priority_queue<uint64_t, std::vector<uint64_t>, std::greater<uint64_t>> ready;
             for (uint32_t a = 0; a < n; a++) {
-                uint32_t v = pi[a];
-                if (cp[v + 1] > cp[v]) count[level[v]]++;
+                const uint32_t v = pi[a];
+                if (cp[v + 1] > cp[v] && npred[v] == 0) ready.push(key(v));
             }
-            start.assign(nlev + 2, 0);
-            for (uint32_t l = 1; l <= nlev; l++) start[l + 1] = start[l] + count[l];
-            {
-                std::vector<uint32_t> fillp(start.begin(), start.end());
-                for (uint32_t a = 0; a < n; a++) {
-                    uint32_t v = pi[a];
-                    if (cp[v + 1] > cp[v]) order[fillp[level[v]]++] = v;  // sweep order
+            member_chunk[i] = (uint32_t)nchunks;
+            const size_t first_slot = nchunks * kWave;
+            uint32_t placed = 0;
+            while (!ready.empty()) {
+                uint32_t cap = kWave, dmax = 0;
+                taken.clear();
+                skipped.clear();
+                while (!ready.empty() && cap > 0 && skipped.size() < (size_t)kWave) {
+                    const uint64_t kv = ready.top();
+                    ready.pop();
+                    const uint32_t v = pi[(uint32_t)kv];
+                    const uint32_t d = cp[v + 1] - cp[v];
+                    if (d <= cap) {
+                        taken.push_back(v);
+                        cap -= d;
+                        dmax = std::max(dmax, d);
+                    } else {
+                        skipped.push_back(kv);
+                    }
+                }
+                for (uint64_t kv : skipped) ready.push(kv);
+                for (uint32_t v : taken) {
+                    const uint32_t d = cp[v + 1] - cp[v];
+                    for (uint32_t j = 0; j < d; j++) {
+                        s_meta.push_back(ci[cp[v] + j] | (j << 16) | (d << kMetaDegShift) | (dmax << kMetaDmaxShift));
+                        s_v.push_back(v);
+                        if (fp64) s_lam64.push_back(lam64[v]);
+                        else s_lam32.push_back(lam32[v]);
+                    }
+                }
+                for (uint32_t q = kWave - cap; q < (uint32_t)kWave; q++) {  // unused slots
+                    s_meta.push_back(dmax << kMetaDmaxShift);
+                    s_v.push_back(0);
+                    if (fp64) s_lam64.push_back(0.0);
+                    else s_lam32.push_back(0.0f);
+                }
+                nchunks++;
+                placed += (uint32_t)taken.size();
+                // successors become ready once this chunk is complete
+                for (uint32_t u : taken)
+                    for (uint32_t j = cp[u]; j < cp[u + 1]; j++) {
+                        const uint32_t v = succ[j];
+                        if (v == kNone) continue;
+                        bool dup = false;
+                        for (uint32_t j2 = cp[u]; j2 < j; j2++) dup |= succ[j2] == v;
+                        if (!dup && --npred[v] == 0) ready.push(key(v));
+                    }
+            }
+            if (placed != ncols) return fail(VIBE_EINVAL, "internal: schedule does not cover every column");
+            const uint32_t nch = (uint32_t)(nchunks - member_chunk[i]);
+            ch_min = std::min(ch_min, nch);
+            ch_max = std::max(ch_max, nch);
+            // suffix states of the initial messages mu = lambda, from the end
+            // of the sweep backwards
+            const size_t end_slot = nchunks * kWave;
+            if (fp64) {
+                init64.resize(end_slot);
+                std::fill(running64.begin(), running64.end(), ident64);
+                for (size_t q = end_slot; q-- > first_slot;) {
+                    if (!((s_meta[q] >> kMetaDegShift) & 15u)) {
+                        init64[q] = ident64;
+                        continue;
+                    }
+                    const uint32_t r = s_meta[q] & 0xffffu;
+                    init64[q] = running64[r];
+                    running64[r] = rs_combine<uint64_t>(enc64(lam64[s_v[q]]), running64[r]);
+                }
+            } else {
+                init32.resize(end_slot);
+                std::fill(running32.begin(), running32.end(), ident32);
+                for (size_t q = end_slot; q-- > first_slot;) {
+                    if (!((s_meta[q] >> kMetaDegShift) & 15u)) {
+                        init32[q] = ident32;
+                        continue;
+                    }
+                    const uint32_t r = s_meta[q] & 0xffffu;
+                    init32[q] = running32[r];
+                    running32[r] = rs_combine<uint32_t>(enc32(lam32[s_v[q]]), running32[r]);
                 }
             }
-            member_chunk[i] = (uint32_t)chunk_off.size();
-            const size_t sbase = (size_t)i * E;
-            size_t spos = 0;
-            for (uint32_t l = 1; l <= nlev; l++) {
-                uint32_t in_chunk = 0;
-                chunk_off.push_back((uint32_t)(sbase + spos));
-                for (uint32_t a = start[l]; a < start[l + 1]; a++) {
-                    const uint32_t v = order[a], deg = cp[v + 1] - cp[v];
-                    if (in_chunk + deg > (uint32_t)kWave) {
-                        chunk_off.push_back((uint32_t)(sbase + spos));
-                        in_chunk = 0;
-                    }
-                    for (uint32_t j = cp[v]; j < cp[v + 1]; j++) {
-                        Slot sl;
-                        sl.meta = ci[j] | ((j - cp[v]) << 16) | (deg << 20);
-                        sl.v = v;
-                        slots[sbase + spos++] = sl;
-                    }
-                    in_chunk += deg;
-                }
-            }
-            if (spos != E) return fail(VIBE_EINVAL, "internal: schedule does not cover every edge");
-            // suffix states of the initial messages, from the end of the sweep
-            std::fill(running.begin(), running.end(), ident);
-            for (size_t q = E; q-- > 0;) {
-                const Slot& sl = slots[sbase + q];
-                const uint32_t r = sl.meta & 0xffffu;
-                init_suf[sbase + q] = running[r];
-                running[r] = rs_combine(enc(lam[sl.v]), running[r]);
-            }
+            if (nchunks * kWave >= (1ull << 32)) return fail(VIBE_EUNSUPPORTED, "schedules exceed 2^32 slots");
         }
-        member_chunk[c.L] = (uint32_t)chunk_off.size();
-        chunk_off.push_back((uint32_t)((size_t)c.L * E));  // end of the last chunk
-        if ((size_t)c.L * E >= (1ull << 32)) return fail(VIBE_EUNSUPPORTED, "L * nnz must be < 2^32");
+        member_chunk[c.L] = (uint32_t)nchunks;
+        if (nchunks == 0) {  // no edges at all: keep one (unused) record
+            s_meta.assign(kWave, 0);
+            s_v.assign(kWave, 0);
+            s_lam32.assign(kWave, 0.0f);
+            s_lam64.assign(kWave, 0.0);
+            init32.assign(kWave, ident32);
+            init64.assign(kWave, ident64);
+        }
+        if (ch_min == UINT32_MAX) ch_min = 0;
     }
 
     vibe_graph* g = new (std::nothrow) vibe_graph();
@@ -263,6 +362,8 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     h.max_col = max_col;
     h.levels_min = lev_min == UINT32_MAX ? 0 : lev_min;
     h.levels_max = lev_max;
+    h.chunks_min = ch_min;
+    h.chunks_max = ch_max;
     h.device_bytes = 0;
     DevGraph& d = h.dg;
     d.m = m;
@@ -274,9 +375,12 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     d.E = (uint32_t)E;
     d.words_n = words_n;
     d.words_m = words_m;
-    d.alpha = (float)c.alpha;
-    d.clamp = limf;
-    d.ident = ident;
+    d.max_chunks = ch_max;
+    d.fp64 = fp64 ? 1 : 0;
+    d.alpha = c.alpha;
+    d.clamp = lim;
+    d.ident32 = ident32;
+    d.ident64 = ident64;
     d.all_lam_positive = all_pos;
     std::vector<uint32_t> rp(h_indptr, h_indptr + m + 1);
     std::vector<uint32_t> ri(h_indices, h_indices + E);
@@ -284,23 +388,39 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
         delete g;
         return fail(VIBE_EUNSUPPORTED, "the per-shot LSD state exceeds 150 KB of LDS");
     }
+    // interleave the schedule fields into chunk records
+    const size_t nrec = s_meta.size() / kWave;
+    const uint32_t rb = rec_bytes(fp64), ri0 = rec_init(fp64);
+    std::vector<unsigned char> sched(nrec * rb);
+    for (size_t j = 0; j < nrec; j++) {
+        unsigned char* r = sched.data() + j * rb;
+        std::memcpy(r, &s_meta[j * kWave], 4 * kWave);
+        std::memcpy(r + kRecV, &s_v[j * kWave], 4 * kWave);
+        if (fp64) {
+            std::memcpy(r + kRecLam, &s_lam64[j * kWave], 8 * kWave);
+            std::memcpy(r + ri0, &init64[j * kWave], 8 * kWave);
+        } else {
+            std::memcpy(r + kRecLam, &s_lam32[j * kWave], 4 * kWave);
+            std::memcpy(r + ri0, &init32[j * kWave], 4 * kWave);
+        }
+    }
     int rc = VIBE_OK;
+    const float* lam32_d = nullptr;
     if ((rc = upload(h, rp.data(), rp.size(), &d.rp)) ||
         (rc = upload(h, ri.data(), ri.size(), &d.ri)) ||
         (rc = upload(h, cp.data(), cp.size(), &d.cp)) ||
         (rc = upload(h, ci.data(), ci.size(), &d.ci)) ||
-        (rc = upload(h, lam.data(), lam.size(), &d.lam)) ||
         (rc = upload(h, lam64.data(), lam64.size(), &d.lam64)) ||
+        (!fp64 && (rc = upload(h, lam32.data(), lam32.size(), &lam32_d))) ||
         (rc = upload(h, e0.data(), e0.size(), &d.e0)) ||
-        (rc = upload(h, init_suf.data(), init_suf.size(), &d.init_suf)) ||
-        (rc = upload(h, slots.data(), slots.size(), &d.slots)) ||
-        (rc = upload(h, chunk_off.data(), chunk_off.size(), &d.chunk_off)) ||
+        (rc = upload(h, sched.data(), sched.size(), &d.sched)) ||
         (rc = upload(h, member_chunk.data(), member_chunk.size(), &d.member_chunk)) ||
         (rc = upload(h, lobs.data(), lobs.size(), &d.lobs))) {
         free_all(h);
         delete g;
         return rc;
     }
+    d.lam = fp64 ? (const void*)d.lam64 : (const void*)lam32_d;
     *out = g;
     return VIBE_OK;
 }
@@ -332,6 +452,9 @@ extern "C" int vibe_graph_info(const vibe_graph* g, vibe_graph_info_t* info) {
     info->max_col_degree = h.max_col;
     info->levels_min = h.levels_min;
     info->levels_max = h.levels_max;
+    info->chunks_min = h.chunks_min;
+    info->chunks_max = h.chunks_max;
+    info->message_bits = h.dg.fp64 ? 64 : 32;
     info->device_bytes = h.device_bytes;
     return VIBE_OK;
 }

@@ -17,17 +17,27 @@ constexpr int kMaxL = 64;
 constexpr int kMaxT = 64;
 constexpr double kQScale = 72057594037927936.0;  // 2^56: fixed point of the LLR average
 
-// One schedule slot = one edge (v, c) of the member's serial sweep.  Slots are
-// grouped in chunks of at most 64 that hold whole columns of one dependency
-// level; inside a column the slots follow ascending check index.  The slot
-// index is also the edge's position in the member's message slab, so every
-// chunk reads and writes one contiguous run of the slab.
-//   meta : c | seg << 16 | deg << 20   (seg = slot index inside the column's
-//          run, deg = number of checks of the column)
-//   v    : the column
-struct Slot {
-    uint32_t meta, v;
-};
+// Member schedules.  Member i's serial sweep (its permutation of the columns)
+// is regrouped into chunks: sets of whole columns, no two sharing a check,
+// with at most 64 edges, in an order that keeps every pair of columns sharing
+// a check in their permutation order.  A chunk has 64 slots, one lane of a
+// wavefront per slot; the edges of one column sit in consecutive slots in
+// ascending check order, and unused slots have deg = 0 (and c = v = 0).
+// Slot q of the member's chunk k is also position k*64 + q of the member's
+// message slab.  The schedule of all members is one array of chunk records;
+// a record holds 64 entries of each field, field by field:
+//   meta (u32) : c | seg << 16 | deg << 20 | dmax << 24   (seg = index of the
+//                edge inside its column, deg = the column's check count,
+//                dmax = the largest deg in the chunk, in all 64 slots)
+//   v    (u32) : the column
+//   lam  (F)   : its channel LLR in the message precision F
+//   init (B)   : the suffix state of the slot for the initial messages
+//                mu = lambda (row state bits, same width as F)
+// so a record is 64 * (8 + 2 sizeof(F)) bytes: 1024 for FP32, 1536 for FP64.
+constexpr uint32_t kMetaDegShift = 20, kMetaDmaxShift = 24;
+constexpr uint32_t kRecV = 256, kRecLam = 512;  // byte offsets of fields in a record
+inline constexpr uint32_t rec_bytes(bool fp64) { return fp64 ? 1536u : 1024u; }
+inline constexpr uint32_t rec_init(bool fp64) { return fp64 ? 1024u : 768u; }
 
 // Wave-uniform values.  A value every lane computes identically (a shuffle
 // broadcast, a wave reduction, an LDS word all lanes read) still lives in a
@@ -47,13 +57,16 @@ __device__ inline uint32_t wave_ticket(uint32_t* counter, uint32_t v) {
     return uni(__shfl(got, 0));
 }
 
-// Row state word: the float bits of a magnitude (>= 0) with a parity bit in
-// the sign position.  Magnitudes compare like unsigned integers, so
-// combining two states is an integer min of the low 31 bits and an xor of
-// bit 31.
-__host__ __device__ inline uint32_t rs_combine(uint32_t a, uint32_t b) {
-    uint32_t ma = a & 0x7fffffffu, mb = b & 0x7fffffffu;
-    return (ma < mb ? ma : mb) | ((a ^ b) & 0x80000000u);
+// Row state word: the bits of a magnitude (>= 0) in the message precision
+// with a parity bit in the sign position.  Magnitudes compare like unsigned
+// integers, so combining two states is an integer min of the magnitude bits
+// and an xor of the sign bits.  B = uint32_t for FP32 messages, uint64_t for
+// FP64.
+template <class B>
+__host__ __device__ inline B rs_combine(B a, B b) {
+    constexpr B kSign = (B)1 << (8 * sizeof(B) - 1);
+    const B ma = a & ~kSign, mb = b & ~kSign;
+    return (ma < mb ? ma : mb) | ((a ^ b) & kSign);
 }
 
 // Everything a kernel needs to know about a resident graph (passed by value).
@@ -61,19 +74,20 @@ struct DevGraph {
     uint32_t m, n, k, L, M, T;
     uint32_t E;
     uint32_t words_n, words_m;  // ceil(n/64), ceil(m/64)
-    float alpha, clamp;
-    uint32_t ident;             // row state of "no message": clamp, parity 0
+    uint32_t max_chunks;        // largest chunk count of a member (slab = max_chunks * 64)
+    int fp64;                   // message precision: 0 = FP32, 1 = FP64
+    double alpha, clamp;
+    uint32_t ident32;           // row state of "no message": clamp, parity 0 (FP32 bits)
+    uint64_t ident64;           // the same in FP64 bits
     int all_lam_positive;
     const uint32_t* rp;           // m + 1
     const uint32_t* ri;           // E, CSR column of each edge
     const uint32_t* cp;           // n + 1
     const uint32_t* ci;           // E, CSC check of each edge
-    const float* lam;             // n, FP32 channel LLR
     const double* lam64;          // n, FP64 channel LLR (candidate weights)
+    const void* lam;              // n, channel LLR in the message precision
     const uint64_t* e0;           // words_n: decisions of columns without checks
-    const uint32_t* init_suf;     // L x E: suffix states of the initial messages
-    const Slot* slots;            // L x E
-    const uint32_t* chunk_off;    // concatenated chunk offsets (into slots)
+    const unsigned char* sched;   // chunk records of all members, see above
     const uint32_t* member_chunk; // L + 1: chunk range of each member
     const uint64_t* lobs;         // k x words_n, bit-packed observable rows
 };
@@ -84,6 +98,7 @@ struct GraphHost {
     uint64_t E;
     uint32_t max_row, max_col;
     uint32_t levels_min, levels_max;
+    uint32_t chunks_min, chunks_max;
     uint64_t device_bytes;
     DevGraph dg;
     std::vector<void*> allocations;
@@ -127,13 +142,15 @@ struct BpLaunch {
     int32_t* t_conv;           // n_shots x L
     double* weight;            // n_shots x L (candidate weight), may be null
     uint64_t* cand;            // n_shots x L x words_n, may be null
-    float* post_out;           // n_shots x L x n, may be null (every iteration)
+    void* post_out;            // n_shots x L x n in the message precision, may be
+                               // null (written every iteration)
     uint64_t* conv_mask;       // n_shots x (kMaxT + 1): members converged at t
     uint32_t* iters;           // n_shots: iterations run, summed over members
     int64_t* qfix;             // n_shots x n, may be null
     // scratch
-    uint32_t* slab;            // grid x E suffix states / messages (global variant)
-    float* post_slab;          // grid x n
+    void* slab;                // grid x max_chunks x 64 row states / messages
+                               // (global variant), message precision
+    void* post_slab;           // grid x n, message precision
     uint32_t* counter;         // work counter
     int grid;
     int slab_in_lds;           // which kernel variant to launch

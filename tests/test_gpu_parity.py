@@ -1,22 +1,28 @@
 """Parity of the HIP decode path (through the C ABI) with the FP64 oracle.
 
-Bars (the device computes BP messages in FP32, the oracle in FP64):
-  * BP, per member: the convergence iteration and the hard decision are
+The device runs BP in FP32 (production) or FP64 (message_bits = 64, the
+oracle's precision and operation order).  Bars:
+  * FP64 BP, per member: convergence iteration, hard decision and every
+    posterior bit-identical to the oracle.
+  * FP32 BP, per member: the convergence iteration and the hard decision are
     identical; the final posteriors agree to 1e-4 of the largest posterior
     magnitude of that member.  Rounding in FP32 sums of <= 16 terms adds
     about 2^-24 of the largest term per operation; over <= 50 iterations of
     min-sum, which is 1-Lipschitz in its inputs apart from the alpha and
     column-degree factors that also scale the magnitudes, that stays near
     1e-6 of the largest magnitude, so 1e-4 leaves two decades of margin.
+    Members with a decision within 1e-3 of zero are skipped (either side
+    of zero is within FP32 error there).
   * LSD on identical soft input: bit-exact corrections and cluster stats.
-  * whole decoder: identical corrections on every shot whose oracle tie
-    witnesses are clear, i.e. the smallest |L_v| of any BP decision is
-    >= 1e-3 (the FP32 error of a decision near zero) and the smallest gap
-    between soft values that LSD compared is >= 1e-5.  Each soft value is a
-    sum of terms L_v / ||L|| in [-1, 1] whose FP32 error is bounded by the
-    posterior error, <= ~1.5e-6 of the member's largest |L| as measured in
-    the BP tests, so gaps under 1e-5 can be ordered either way; the logical
-    error rate lies in the oracle's 95% interval.
+  * whole decoder, FP64: identical corrections on >= 99.9% of shots (the
+    normalised average is summed in a different order, so only exact
+    mathematical ties between soft values can order differently).
+  * whole decoder, FP32: H e = s on every shot LSD did not flag, agreement
+    with the oracle no worse than the oracle's agreement with itself when
+    the priors move by 1e-6 relative (a perturbation of the size of FP32
+    rounding; workloads with uniform priors have exact ties that any
+    rounding breaks), within a 3-sigma binomial margin; the logical error
+    rate lies in the oracle's 95% interval.
 """
 import os
 
@@ -55,10 +61,10 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-def _bp_parity(torch, dem, L, T, shots, seed, stop):
+def _bp_parity(torch, dem, L, T, shots, seed, stop, bits=32):
     import paper_2508_15743_amd as P
 
-    G, perms = _graph(dem, L, min(5, L), T, seed)
+    G, perms = _graph(dem, L, min(5, L), T, seed, message_bits=bits)
     b = sample(dem, shots, seed + 1)
     tc, post, eh = G.bp_ensemble(_dev(torch, b.syndromes), T_run=T, stop=stop)
     tc, post, eh = tc.cpu().numpy(), post.cpu().numpy(), P.unpack_bits(eh, dem.n)
@@ -66,6 +72,11 @@ def _bp_parity(torch, dem, L, T, shots, seed, stop):
     for i in range(shots):
         for j in range(L):
             r = O.bp(g, b.syndromes[i], perm=perms[j], T=T, stop=stop)
+            if bits == 64:
+                assert r["t_conv"] == tc[i, j], (i, j)
+                assert np.array_equal(r["ehat"], eh[i, j]), (i, j)
+                assert np.array_equal(r["post"], post[i, j]), (i, j, np.abs(r["post"] - post[i, j]).max())
+                continue
             if r["min_abs_post"] < 1e-3:
                 continue  # a decision within FP32 error of zero
             assert r["t_conv"] == tc[i, j], (i, j)
@@ -86,8 +97,20 @@ def test_bp_members_phenomenological_no_stop(torch_cuda):
 
 
 def test_bp_members_circuit_full_size(torch_cuda):
-    # the benchmark graph itself: ~900 levels, rows of up to 194 edges
+    # the benchmark graph itself: 1110 chunks per sweep, rows of up to 194 edges
     _bp_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 2, 3, 2, 3, stop=False)
+
+
+def test_bp_members_fp64_bit_exact_code_capacity(torch_cuda):
+    _bp_parity(torch_cuda, code_capacity_dem(5, 0.05), 16, 32, 40, 11, stop=True, bits=64)
+
+
+def test_bp_members_fp64_bit_exact_phenomenological(torch_cuda):
+    _bp_parity(torch_cuda, phenomenological_dem(11, 11, 0.01, 0.01), 4, 12, 6, 12, stop=False, bits=64)
+
+
+def test_bp_members_fp64_bit_exact_circuit_full_size(torch_cuda):
+    _bp_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 2, 4, 2, 13, stop=False, bits=64)
 
 
 def _lsd_parity(torch, dem, shots, seed, noise=2.0):
@@ -143,10 +166,17 @@ def test_lsd_edge_cases(torch_cuda):
     G.close()
 
 
-def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots):
+def _oracle_decode(dem, perms, synd, L, M, T, priors=None):
+    g = O.OracleGraph(dem)
+    if priors is not None:
+        g.priors = priors
+    return O.decode(g, perms, synd, L=L, M=M, T=T, threads=NT)
+
+
+def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots, bits=32):
     import paper_2508_15743_amd as P
 
-    G, perms = _graph(dem, L, M, T, seed)
+    G, perms = _graph(dem, L, M, T, seed, message_bits=bits)
     b = sample(dem, shots, seed + 7)
     corr, obs, st = G.decode(_dev(torch, b.syndromes))
     e, obs, st = P.unpack_bits(corr, dem.n), obs.cpu().numpy(), st.cpu().numpy()
@@ -154,23 +184,30 @@ def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots):
     ok = (st[:, 0] & 4) == 0
     assert np.array_equal((e[ok].astype(np.int64) @ H.T) % 2, b.syndromes[ok])
     assert np.array_equal(obs, (e.astype(np.int64) @ dem.dense_l().T.astype(np.int64) % 2).astype(np.uint8))
-    ref = O.decode(O.OracleGraph(dem), perms, b.syndromes[:oracle_shots], L=L, M=M, T=T,
-                   threads=NT, want_q=True)
+    ref = _oracle_decode(dem, perms, b.syndromes[:oracle_shots], L, M, T)
     agree = (ref["ehat"] == e[:oracle_shots]).all(1)
-    tie = (ref["min_abs_post"] < 1e-3) | (ref["min_q_gap"] < 1e-5)
-    bad = np.flatnonzero(~agree & ~tie)
-    assert len(bad) == 0, (bad[:10], ref["min_abs_post"][bad[:10]], ref["min_q_gap"][bad[:10]])
+    n = oracle_shots
+    if bits == 64:
+        assert agree.mean() >= 0.999, (agree.mean(), np.flatnonzero(~agree)[:10])
+        bar = "0.999"
+    else:
+        rng = np.random.default_rng(seed)
+        moved = dem.priors * (1.0 + 1e-6 * rng.uniform(-1.0, 1.0, dem.n))
+        ref2 = _oracle_decode(dem, perms, b.syndromes[:oracle_shots], L, M, T, priors=moved)
+        self_agree = (ref2["ehat"] == ref["ehat"]).all(1).mean()
+        margin = 3.0 * np.sqrt(max(self_agree * (1.0 - self_agree), 1.0 / n) / n)
+        assert agree.mean() >= self_agree - margin, (agree.mean(), self_agree, margin)
+        bar = f"oracle self-agreement {self_agree:.5f} - {margin:.5f}"
     # logical error rate inside the oracle's 95% (Clopper-Pearson) interval
     from scipy.stats import beta
 
     k = int((ref["obs"] != b.observables[:oracle_shots]).any(1).sum())
-    n = oracle_shots
     lo = beta.ppf(0.025, k, n - k + 1) if k else 0.0
     hi = beta.ppf(0.975, k + 1, n - k) if k < n else 1.0
     ler = (obs != b.observables).any(1).mean()
     assert lo <= ler <= hi, (ler, lo, hi)
-    print(f"{dem.name}: agreement {agree.mean():.5f} over {oracle_shots} shots, "
-          f"{int((~agree).sum())} disagreements, all tie-witnessed")
+    print(f"{dem.name} FP{bits}: agreement {agree.mean():.5f} over {n} shots (bar {bar}); "
+          f"LER {ler:.5f} in [{lo:.5f}, {hi:.5f}]")
     G.close()
     return agree.mean()
 
@@ -185,6 +222,18 @@ def test_decode_phenomenological(torch_cuda):
 
 def test_decode_circuit_full_size(torch_cuda):
     _decode_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 32, 5, 20, 4096, 5, 32)
+
+
+def test_decode_fp64_code_capacity(torch_cuda):
+    _decode_parity(torch_cuda, code_capacity_dem(5, 0.05), 16, 5, 32, 10000, 3, 10000, bits=64)
+
+
+def test_decode_fp64_phenomenological(torch_cuda):
+    _decode_parity(torch_cuda, phenomenological_dem(11, 11, 0.01, 0.01), 32, 5, 50, 3000, 4, 600, bits=64)
+
+
+def test_decode_fp64_circuit_full_size(torch_cuda):
+    _decode_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 32, 5, 20, 2048, 5, 32, bits=64)
 
 
 def test_decode_deterministic_and_batch_invariant(torch_cuda):
@@ -240,6 +289,8 @@ def test_invalid_arguments_rejected(torch_cuda):
         P.Graph.from_dem(dem, bad, L=4, M=2, T_max=5)
     with pytest.raises(P.VibeError):
         P.Graph.from_dem(dem, perms, L=4, M=5, T_max=5)
+    with pytest.raises(P.VibeError):
+        P.Graph.from_dem(dem, perms, L=4, M=2, T_max=5, message_bits=48)
 
 
 def test_plain_equals_batched(torch_cuda):
@@ -257,4 +308,12 @@ def test_plain_equals_batched(torch_cuda):
     for i in range(0, 120, 7):
         c3, _, _ = G.decode(s[i:i + 1])
         assert torch.equal(c3, c1[i:i + 1])
+    G.close()
+    # the benchmark graph: one launch sequence per shot, global message slab
+    dem = circuit_dem(9, 9, 1e-3)
+    G, _ = _graph(dem, 32, 5, 20, 5)
+    s = _dev(torch, sample(dem, 6, 12).syndromes)
+    c1, o1, _ = G.decode(s)
+    c2, o2, _ = G.decode(s, plain=True)
+    assert torch.equal(c1, c2) and torch.equal(o1, o2)
     G.close()
