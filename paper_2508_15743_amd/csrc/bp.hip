@@ -44,7 +44,7 @@ struct Prec<float> {
     static constexpr B kSign = 0x80000000u;
     __device__ static B bits(float x) { return __float_as_uint(x); }
     __device__ static float val(B b) { return __uint_as_float(b); }
-    __device__ static float clamp(float x, float lim) { return fminf(fmaxf(x, -lim), lim); }
+    __device__ static float clamp(float x, float lim) { return __builtin_amdgcn_fmed3f(x, -lim, lim); }
     __device__ static B ident(const DevGraph& g) { return g.ident32; }
 };
 
@@ -57,6 +57,17 @@ struct Prec<double> {
     __device__ static double clamp(double x, double lim) { return fmin(fmax(x, -lim), lim); }
     __device__ static B ident(const DevGraph& g) { return g.ident64; }
 };
+
+// value of the lane whose index is byte_addr / 4 (mod 64)
+__device__ __forceinline__ float bperm(uint32_t byte_addr, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute((int)byte_addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double bperm(uint32_t byte_addr, double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute((int)byte_addr, (int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute((int)byte_addr, (int)(uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
 
 template <class F>
 __device__ inline typename Prec<F>::B rs_encode(F x) {
@@ -197,24 +208,29 @@ __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, 
     const bool neg = ((stt & P::kSign) != 0) != (((sw >> (c & 63)) & 1ull) != 0);
     const F rr = x.al * P::val(stt & ~P::kSign);
     const F r = deg ? (neg ? -rr : rr) : F(0);
-    // L_v = lambda_v + sum_c r, mu_{v->c} = lambda_v + sum_{c' != c} r, both in
-    // ascending check order over the column's consecutive lanes; the
-    // shuffles go out four at a time
-    const int b0 = x.lane - (int)seg;
-    F L = s.lam, mu = s.lam;
-    for (uint32_t j = 0; j < dmax; j += 4) {
-        F rj[4];
+    // mu_{v->c} = lambda_v + sum_{c' != c} r and L_v = lambda_v + sum_c r, in
+    // ascending check order over the column's consecutive lanes.  Position
+    // j of the column is lane b0 + j, read at a constant offset from one
+    // base address, eight positions per batch with all reads issued first;
+    // positions outside the column and the edge's own position add an exact
+    // zero (which changes no value, only possibly the sign of a zero
+    // result).  On the column's last lane the partial sums of mu are those
+    // of L, so L = mu + r there exactly, and one more read hands it to the
+    // whole column.
+    const uint32_t b0x4 = (uint32_t)(x.lane - (int)seg) << 2;
+    F mu = s.lam;
+    for (uint32_t j0 = 0; j0 < dmax; j0 += 8) {
+        F rj[8];
 #pragma unroll
-        for (int q = 0; q < 4; q++) rj[q] = __shfl(r, (b0 + (int)j + q) & (kWave - 1));
+        for (int q = 0; q < 8; q++) rj[q] = bperm(b0x4 + 4u * (j0 + (uint32_t)q), r);
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const uint32_t jj = j + q;
-            if (jj < deg) {
-                L += rj[q];
-                if (jj != seg) mu += rj[q];
-            }
+        for (int q = 0; q < 8; q++) {
+            const uint32_t j = j0 + (uint32_t)q;
+            if (j >= dmax) break;
+            mu += (j < deg && j != seg) ? rj[q] : F(0);
         }
     }
+    F L = bperm(b0x4 + 4u * (deg - 1u), mu + r);
     L = P::clamp(L, x.lim);
     mu = P::clamp(mu, x.lim);
     if constexpr (SLAB_LDS)
