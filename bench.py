@@ -9,7 +9,10 @@ circuits and data.
 
 One step = vibe_decode over one batch of B shots (all of BP ensemble,
 selection, LSD and observables), syndromes already resident in HBM.
-Prints one JSON line.  Extra legs: the per-shot-launch form
+Prints one JSON line.  Extra legs: BP+LSD-0 without ensembling (one member,
+parallel schedule) on the same batch, with LSD calls and largest-cluster
+sizes beside VibeLSD's (the comparison of the paper's Sec. IV.H); the
+per-shot-launch form
 (vibe_decode_plain, one launch sequence per shot) on the first shots of the
 batch, latency of small batches (64 shots per call, wall clock from
 submission to completion), the oracle on a bounded sample of the host cores,
@@ -74,6 +77,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--seed", type=int, default=2025)
@@ -180,6 +184,32 @@ def main():
         "logical_error_rate": ler,
         "mean_member_iterations_per_shot": member_iters / (B * args.steps),
     }
+
+    def cluster_stats(stats_np):
+        lsd = (stats_np[:, 0] & 2) != 0
+        big = stats_np[lsd, 5]
+        pct = (lambda q: float(np.percentile(big, q)) if big.size else 0.0)
+        return {"lsd_calls_per_5000": round(5000.0 * float(lsd.mean()), 1),
+                "largest_cluster_p50": pct(50), "largest_cluster_p95": pct(95),
+                "largest_cluster_max": int(big.max()) if big.size else 0}
+
+    comparison = {"vibelsd": cluster_stats(stats)}
+    if not args.no_baseline:
+        Gb = P.Graph.from_dem(dem, perms[:1], L=1, M=1, T_max=T, alpha=alpha, schedule="parallel")
+        bout = tuple(torch.empty_like(o) for o in out)
+        Gb.decode(synd, out=bout)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Gb.decode(synd, out=bout)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        bst = bout[2].cpu().numpy()
+        bler = float((bout[1].cpu().numpy() != batch.observables).any(1).mean())
+        comparison["bp_lsd0"] = dict(cluster_stats(bst), shots_per_s=round(B / dt, 1), logical_error_rate=bler)
+        Gb.close()
+        log(f"BP+LSD-0 baseline: {B / dt:.0f} shots/s, LSD calls per 5000 "
+            f"{comparison['bp_lsd0']['lsd_calls_per_5000']} vs VibeLSD {comparison['vibelsd']['lsd_calls_per_5000']}")
+    result["comparison"] = comparison
 
     result["plain"] = None
     result["batched_over_plain"] = None

@@ -63,14 +63,24 @@ typedef struct vibe_config {
                               posteriors, the production setting; 64 = FP64,
                               in the same operation order as a plain
                               column-by-column FP64 decoder, for verification */
-    uint32_t reserved;     /* set to 0 */
+    uint32_t schedule;     /* 0 = serial-V (VibeLSD: each member updates the
+                              columns one after another in its permutation
+                              order, Algorithm 1 serial branch); 1 = parallel
+                              (flooding: every message of an iteration is
+                              formed from the previous iteration's, Algorithm
+                              1 parallel branch; all members then agree, so
+                              L = 1 gives the BP+LSD-0 baseline of Sec. IV.H) */
 } vibe_config;
 
 typedef struct vibe_shot_stats {
     uint32_t flags;        /* VIBE_FLAG_* */
     int32_t winner;        /* member whose correction was taken, -1 if LSD ran */
     uint32_t t_win;        /* that member's convergence iteration, 0 if LSD ran */
-    uint32_t n_conv;       /* members seen converged before the shot finished */
+    uint32_t n_conv;       /* members seen converged before the shot finished;
+                              like member_iters it depends on timing (members
+                              past the correction limit stop as soon as that is
+                              known), unlike every other field and the
+                              correction */
     uint32_t lsd_clusters; /* final LSD clusters (0 if LSD did not run) */
     uint32_t lsd_largest;  /* columns in the largest final cluster */
     uint32_t lsd_rounds;   /* LSD growth rounds */

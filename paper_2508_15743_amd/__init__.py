@@ -30,7 +30,7 @@ class VibeError(RuntimeError):
 class vibe_config(C.Structure):
     _fields_ = [("L", C.c_uint32), ("M", C.c_uint32), ("T_max", C.c_uint32),
                 ("lsd_order", C.c_uint32), ("alpha", C.c_double), ("clamp", C.c_double),
-                ("message_bits", C.c_uint32), ("reserved", C.c_uint32)]
+                ("message_bits", C.c_uint32), ("schedule", C.c_uint32)]
 
 
 class vibe_graph_info_t(C.Structure):
@@ -169,10 +169,12 @@ class Graph:
     """A detector error model resident on the current GPU, with its member
     schedules.  `perms` is [L, n]: the serial schedules of the members.
     message_bits=64 runs BP in FP64 (verification); 32 is the production
-    setting."""
+    setting.  schedule="parallel" runs every member with the flooding
+    schedule (L=1, M=1 is the BP+LSD-0 baseline)."""
 
     def __init__(self, h_indptr, h_indices, priors, l_indptr, l_indices, perms, m=None, n=None,
-                 L=32, M=5, T_max=20, alpha=0.625, clamp=1e6, lsd_order=0, message_bits=32):
+                 L=32, M=5, T_max=20, alpha=0.625, clamp=1e6, lsd_order=0, message_bits=32,
+                 schedule="serial"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libvibelsd needs a ROCm GPU (torch.cuda is not available)")
@@ -184,7 +186,10 @@ class Graph:
         self.L, self.M, self.T_max = L, M, T_max
         self.words = (self.n + 63) // 64
         self.message_bits = message_bits
-        self.cfg = vibe_config(L, M, T_max, lsd_order, alpha, clamp, message_bits, 0)
+        if schedule not in ("serial", "parallel"):
+            raise ValueError("schedule must be 'serial' or 'parallel'")
+        self.cfg = vibe_config(L, M, T_max, lsd_order, alpha, clamp, message_bits,
+                               0 if schedule == "serial" else 1)
         self.handle = vibe_graph_create(self.m, self.n, h_indptr, h_indices, priors, self.k,
                                         l_indptr, l_indices, perms, self.cfg)
 

@@ -69,7 +69,7 @@ int carve(vibe_graph* G, uint32_t bc, bool decode, int slab_blocks, int post_blo
         decode ? 8ull * bc * g.n : 0,                      // qfix
         4ull * bc,                                         // fail_list
         64,                                                // counters
-        msg_bytes(g) * slab_blocks * std::max<size_t>((size_t)g.max_chunks * kWave, 1),  // message slabs
+        msg_bytes(g) * bp_slabs(g) * slab_blocks * std::max<size_t>((size_t)g.max_chunks * kWave, 1),  // slabs
         msg_bytes(g) * post_blocks * ((size_t)g.n + kWave),  // posterior slabs
         decode ? lsd_scratch_per_block(g) * lsd_grid : 0,  // LSD scratch
     };

@@ -140,6 +140,8 @@ struct Ctx {
     Rsrc sch;       // the member's chunk records
     Rsrc slb;       // the block's slab (global variant)
     B* lslab;       // the block's slab (LDS variant)
+    Rsrc mslb;      // parallel schedule: the block's message slab (global variant)
+    B* lmslab;      // parallel schedule: the block's message slab (LDS variant)
     B* pref;
     const uint64_t* sb;
     uint64_t* res;
@@ -157,9 +159,14 @@ struct Ctx {
 // into their own slab slot), so the compiler can count the loads still in
 // flight and wait only for the oldest stage instead of draining all of them.
 #ifndef VIBE_BP_DEPTH
-#define VIBE_BP_DEPTH 2
+#define VIBE_BP_DEPTH 3
 #endif
 constexpr int kDepth = VIBE_BP_DEPTH;  // chunks loaded ahead of the one being processed
+// occupancy the register allocator aims for (waves per SIMD) in the FP32
+// kernel: 6 keeps it within 80 VGPRs; the FP64 kernel aims for 4
+#ifndef VIBE_BP_WAVES_PER_EU
+#define VIBE_BP_WAVES_PER_EU 6
+#endif
 
 // Slot data of one chunk for the sweep, loaded ahead of use.
 template <class F>
@@ -167,11 +174,13 @@ struct Stage {
     uint32_t meta, v;
     F lam;
     typename Prec<F>::B suf;
+    F old;  // parallel schedule: the edge's message of the previous iteration
 };
 
-template <class F, bool SLAB_LDS>
+template <class F, bool SLAB_LDS, bool FLOOD>
 __device__ __forceinline__ void fetch(const Ctx<F>& x, Stage<F>& s, uint32_t k, bool first) {
-    using B = typename Prec<F>::B;
+    using P = Prec<F>;
+    using B = typename P::B;
     constexpr bool kF64 = sizeof(F) == 8;
     // chunk offset added to the lane offset (a short-lived VGPR); field
     // offsets become instruction immediates
@@ -188,11 +197,26 @@ __device__ __forceinline__ void fetch(const Ctx<F>& x, Stage<F>& s, uint32_t k, 
         const uint32_t o = first ? oF + rec_init(kF64) : x.laneF + k * kWave * (uint32_t)sizeof(B);
         s.suf = bload<B>(r, o, 0);
     }
+    if constexpr (FLOOD) {
+        // the previous message (lambda before the first iteration); the
+        // load is issued either way so that every step issues the same
+        // memory operations
+        B m;
+        if constexpr (SLAB_LDS)
+            m = x.lmslab[k * kWave + x.lane];
+        else
+            m = bload<B>(x.mslb, x.laneF + k * kWave * (uint32_t)sizeof(B), 0);
+        s.old = first ? s.lam : P::val(m);
+    }
 }
 
-// One chunk of the serial sweep: r_{c->v} = (1 - 2 s_c) alpha prod sign
-// min |mu| over N(c) \ v for each edge, then L_v and the new mu_{v->c}.
-template <class F, bool SLAB_LDS, bool WANT_POST>
+// One chunk of the sweep: r_{c->v} = (1 - 2 s_c) alpha prod sign min |mu|
+// over N(c) \ v for each edge, then L_v and the new mu_{v->c}.  Serial
+// schedule: the row's earlier edges contribute their new messages (the
+// prefix state accumulates them).  Parallel schedule (FLOOD): they
+// contribute their previous messages, so every message of the iteration
+// comes from the previous iteration's.
+template <class F, bool SLAB_LDS, bool WANT_POST, bool FLOOD>
 __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, uint32_t k) {
     using P = Prec<F>;
     using B = typename P::B;
@@ -219,28 +243,47 @@ __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, 
     // whole column.
     const uint32_t b0x4 = (uint32_t)(x.lane - (int)seg) << 2;
     F mu = s.lam;
-    for (uint32_t j0 = 0; j0 < dmax; j0 += 8) {
+    if (dmax <= 8) {
+        // one batch, offsets fixed at compile time
         F rj[8];
 #pragma unroll
-        for (int q = 0; q < 8; q++) rj[q] = bperm(b0x4 + 4u * (j0 + (uint32_t)q), r);
+        for (int q = 0; q < 8; q++) rj[q] = bperm(b0x4 + 4u * (uint32_t)q, r);
 #pragma unroll
         for (int q = 0; q < 8; q++) {
-            const uint32_t j = j0 + (uint32_t)q;
-            if (j >= dmax) break;
-            mu += (j < deg && j != seg) ? rj[q] : F(0);
+            if ((uint32_t)q >= dmax) break;
+            mu += ((uint32_t)q < deg && (uint32_t)q != seg) ? rj[q] : F(0);
+        }
+    } else {
+        for (uint32_t j0 = 0; j0 < dmax; j0 += 8) {
+            F rj[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) rj[q] = bperm(b0x4 + 4u * (j0 + (uint32_t)q), r);
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const uint32_t j = j0 + (uint32_t)q;
+                if (j >= dmax) break;
+                mu += (j < deg && j != seg) ? rj[q] : F(0);
+            }
         }
     }
     F L = bperm(b0x4 + 4u * (deg - 1u), mu + r);
     L = P::clamp(L, x.lim);
     mu = P::clamp(mu, x.lim);
-    if constexpr (SLAB_LDS)
-        x.lslab[k * kWave + x.lane] = P::bits(mu);
-    else
-        bstore<B>(P::bits(mu), x.slb, x.laneF + k * kWave * (uint32_t)sizeof(B), 0);
+    if constexpr (FLOOD) {
+        if constexpr (SLAB_LDS)
+            x.lmslab[k * kWave + x.lane] = P::bits(mu);
+        else
+            bstore<B>(P::bits(mu), x.mslb, x.laneF + k * kWave * (uint32_t)sizeof(B), 0);
+    } else {
+        if constexpr (SLAB_LDS)
+            x.lslab[k * kWave + x.lane] = P::bits(mu);
+        else
+            bstore<B>(P::bits(mu), x.slb, x.laneF + k * kWave * (uint32_t)sizeof(B), 0);
+    }
     const bool enew = L <= F(0);
     const bool eold = (ew >> (v & 63)) & 1ull;
     if (deg) {
-        x.pref[c] = rs_combine<B>(pre, rs_encode(mu));
+        x.pref[c] = rs_combine<B>(pre, rs_encode(FLOOD ? s.old : mu));
         if (enew != eold) {
             if (seg == 0) atomicXor(reinterpret_cast<unsigned long long*>(&x.eb[v >> 6]), 1ull << (v & 63));
             atomicXor(reinterpret_cast<unsigned long long*>(&x.res[c >> 6]), 1ull << (c & 63));
@@ -261,18 +304,18 @@ __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, 
 // The whole sweep: chunks 0 .. nch-1 (nch >= 1), each one's slots loaded
 // kDepth chunks ahead (the suffix states of later chunks are final for the
 // whole sweep).
-template <class F, bool SLAB_LDS, bool WANT_POST>
+template <class F, bool SLAB_LDS, bool WANT_POST, bool FLOOD>
 __device__ __forceinline__ void sweep(const Ctx<F>& x, uint32_t nch, bool first) {
     const uint32_t last = nch - 1;
     Stage<F> ring[kDepth];
 #pragma unroll
-    for (int d = 0; d < kDepth; d++) fetch<F, SLAB_LDS>(x, ring[d], min((uint32_t)d, last), first);
+    for (int d = 0; d < kDepth; d++) fetch<F, SLAB_LDS, FLOOD>(x, ring[d], min((uint32_t)d, last), first);
     for (uint32_t k = 0; k < nch; k += kDepth) {
 #pragma unroll
         for (int d = 0; d < kDepth; d++) {
             if (k + d >= nch) break;
-            sweep_chunk<F, SLAB_LDS, WANT_POST>(x, ring[d], k + d);
-            fetch<F, SLAB_LDS>(x, ring[d], min(k + d + kDepth, last), first);
+            sweep_chunk<F, SLAB_LDS, WANT_POST, FLOOD>(x, ring[d], k + d);
+            fetch<F, SLAB_LDS, FLOOD>(x, ring[d], min(k + d + kDepth, last), first);
         }
     }
 }
@@ -283,14 +326,16 @@ struct BStage {
     typename Prec<F>::B msg;
 };
 
-template <class F, bool SLAB_LDS>
+template <class F, bool SLAB_LDS, bool FLOOD>
 __device__ __forceinline__ void bfetch(const Ctx<F>& x, BStage<F>& s, uint32_t k) {
     using B = typename Prec<F>::B;
     s.meta = bload<uint32_t>(x.sch, x.lane4 + k * rec_bytes(sizeof(F) == 8), 0);
+    // the sweep's new messages: in the state slab itself (serial), or in the
+    // message slab (parallel)
     if constexpr (SLAB_LDS)
-        s.msg = x.lslab[k * kWave + x.lane];
+        s.msg = (FLOOD ? x.lmslab : x.lslab)[k * kWave + x.lane];
     else
-        s.msg = bload<B>(x.slb, x.laneF + k * kWave * (uint32_t)sizeof(B), 0);
+        s.msg = bload<B>(FLOOD ? x.mslb : x.slb, x.laneF + k * kWave * (uint32_t)sizeof(B), 0);
 }
 
 // One chunk of the backward pass: the slot receives the state of its row's
@@ -314,24 +359,24 @@ __device__ __forceinline__ void back_chunk(const Ctx<F>& x, const BStage<F>& s, 
 // Backward pass over chunks nch-1 .. 0 (nch >= 1) with loads kDepth chunks
 // ahead.  Edges of one chunk sit in distinct rows, so a chunk is one
 // parallel step.
-template <class F, bool SLAB_LDS>
+template <class F, bool SLAB_LDS, bool FLOOD>
 __device__ __forceinline__ void backward(const Ctx<F>& x, uint32_t nch, typename Prec<F>::B* running) {
     BStage<F> ring[kDepth];
     auto at = [nch](uint32_t d) { return d < nch ? nch - 1 - d : 0u; };  // d chunks from the end
 #pragma unroll
-    for (int d = 0; d < kDepth; d++) bfetch<F, SLAB_LDS>(x, ring[d], at(d));
+    for (int d = 0; d < kDepth; d++) bfetch<F, SLAB_LDS, FLOOD>(x, ring[d], at(d));
     for (uint32_t e = 0; e < nch; e += kDepth) {
 #pragma unroll
         for (int d = 0; d < kDepth; d++) {
             if (e + d >= nch) break;
             back_chunk<F, SLAB_LDS>(x, ring[d], nch - 1 - e - d, running);
-            bfetch<F, SLAB_LDS>(x, ring[d], at(e + d + kDepth));
+            bfetch<F, SLAB_LDS, FLOOD>(x, ring[d], at(e + d + kDepth));
         }
     }
 }
 
-template <class F, bool SLAB_LDS>
-__global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch a) {
+template <class F, bool SLAB_LDS, bool FLOOD>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(F) == 4 ? VIBE_BP_WAVES_PER_EU : 4))) void bp_ensemble_kernel(DevGraph g, BpLaunch a) {
     using P = Prec<F>;
     using B = typename P::B;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -339,7 +384,10 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
     uint64_t* res = sb + g.words_m;
     uint64_t* eb = res + g.words_m;
     B* pref = reinterpret_cast<B*>(eb + g.words_n);
-    B* slab = SLAB_LDS ? pref + g.m : nullptr;  // LDS variant; the global slab is a buffer resource
+    // LDS variant: the state slab, then (parallel schedule) the message slab;
+    // the global slabs are buffer resources
+    B* slab = SLAB_LDS ? pref + g.m : nullptr;
+    B* mslab = SLAB_LDS && FLOOD ? slab + (size_t)g.max_chunks * kWave : nullptr;
 
     const int lane = threadIdx.x;
     F* post = reinterpret_cast<F*>(a.post_slab) + (size_t)blockIdx.x * (g.n + kWave);
@@ -351,6 +399,10 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
     x.slb = make_rsrc(a.slab ? reinterpret_cast<B*>(a.slab) + (size_t)blockIdx.x * g.max_chunks * kWave : nullptr,
                       g.max_chunks * kWave * (uint32_t)sizeof(B));
     x.lslab = slab;
+    x.mslb = make_rsrc(FLOOD && a.slab ? reinterpret_cast<B*>(a.slab) + ((size_t)gridDim.x + blockIdx.x) * g.max_chunks * kWave
+                                      : nullptr,
+                       g.max_chunks * kWave * (uint32_t)sizeof(B));
+    x.lmslab = mslab;
     x.pref = pref;
     x.sb = sb;
     x.res = res;
@@ -442,9 +494,9 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
             __syncthreads();
             if (nch) {
                 if (want_post)
-                    sweep<F, SLAB_LDS, true>(x, nch, t == 1);
+                    sweep<F, SLAB_LDS, true, FLOOD>(x, nch, t == 1);
                 else
-                    sweep<F, SLAB_LDS, false>(x, nch, t == 1);
+                    sweep<F, SLAB_LDS, false, FLOOD>(x, nch, t == 1);
             }
             __syncthreads();  // every new message stored
             if (post_out) {
@@ -463,7 +515,7 @@ __global__ __launch_bounds__(kWave) void bp_ensemble_kernel(DevGraph g, BpLaunch
             if (t < a.T_run && nch) {
                 for (uint32_t c = lane; c < g.m; c += kWave) pref[c] = ident;
                 __syncthreads();
-                backward<F, SLAB_LDS>(x, nch, pref);
+                backward<F, SLAB_LDS, FLOOD>(x, nch, pref);
                 __syncthreads();
             }
         }
@@ -536,19 +588,28 @@ __global__ void zero_kernel(uint32_t* p, size_t words) {
         p[i] = 0u;
 }
 
-const void* kernel_for(bool fp64, bool slab_in_lds) {
-    if (fp64) return slab_in_lds ? (const void*)bp_ensemble_kernel<double, true> : (const void*)bp_ensemble_kernel<double, false>;
-    return slab_in_lds ? (const void*)bp_ensemble_kernel<float, true> : (const void*)bp_ensemble_kernel<float, false>;
+template <class F, bool FLOOD>
+const void* kernel_for_t(bool slab_in_lds) {
+    return slab_in_lds ? (const void*)bp_ensemble_kernel<F, true, FLOOD> : (const void*)bp_ensemble_kernel<F, false, FLOOD>;
+}
+
+const void* kernel_for(const DevGraph& g, bool slab_in_lds) {
+    if (g.fp64) return g.flood ? kernel_for_t<double, true>(slab_in_lds) : kernel_for_t<double, false>(slab_in_lds);
+    return g.flood ? kernel_for_t<float, true>(slab_in_lds) : kernel_for_t<float, false>(slab_in_lds);
 }
 
 }  // namespace
 
+int bp_slabs(const DevGraph& g) { return g.flood ? 2 : 1; }
+
 size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds) {
     const size_t mb = g.fp64 ? 8 : 4;
     size_t b = sizeof(uint64_t) * (2 * (size_t)g.words_m + g.words_n) + mb * g.m;
-    if (slab_in_lds) b += mb * (size_t)g.max_chunks * kWave;
+    if (slab_in_lds) b += bp_slabs(g) * mb * (size_t)g.max_chunks * kWave;
     return b;
 }
+
+
 
 bool bp_slab_fits_lds(const DevGraph& g) { return bp_lds_bytes(g, true) <= 96 * 1024; }
 
@@ -563,7 +624,7 @@ int bp_grid(const DevGraph& g, bool slab_in_lds) {
     }
     const size_t lds = bp_lds_bytes(g, slab_in_lds);
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(g.fp64, slab_in_lds), kWave, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(g, slab_in_lds), kWave, lds);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     if (per_cu > 32) per_cu = 32;
     return per_cu * cached_cus;
@@ -572,22 +633,14 @@ int bp_grid(const DevGraph& g, bool slab_in_lds) {
 int launch_bp(const DevGraph& g, const BpLaunch& a, hipStream_t st) {
     const bool in_lds = a.slab_in_lds != 0;
     const size_t lds = bp_lds_bytes(g, in_lds);
-    const void* fn = kernel_for(g.fp64, in_lds);
+    const void* fn = kernel_for(g, in_lds);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(bp)");
     }
-    if (g.fp64) {
-        if (in_lds)
-            hipLaunchKernelGGL((bp_ensemble_kernel<double, true>), dim3(a.grid), dim3(kWave), lds, st, g, a);
-        else
-            hipLaunchKernelGGL((bp_ensemble_kernel<double, false>), dim3(a.grid), dim3(kWave), lds, st, g, a);
-    } else {
-        if (in_lds)
-            hipLaunchKernelGGL((bp_ensemble_kernel<float, true>), dim3(a.grid), dim3(kWave), lds, st, g, a);
-        else
-            hipLaunchKernelGGL((bp_ensemble_kernel<float, false>), dim3(a.grid), dim3(kWave), lds, st, g, a);
-    }
+    void* args[] = {const_cast<DevGraph*>(&g), const_cast<BpLaunch*>(&a)};
+    hipError_t le = hipLaunchKernel(fn, dim3(a.grid), dim3(kWave), args, lds, st);
+    if (le != hipSuccess) return hip_fail(le, "bp_ensemble_kernel launch");
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "bp_ensemble_kernel launch");
     return VIBE_OK;

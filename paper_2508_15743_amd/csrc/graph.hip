@@ -77,6 +77,7 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     if (!(c.clamp >= 1.0) || !(c.clamp <= 1e30)) return fail(VIBE_EINVAL, "clamp must be in [1, 1e30]");
     if (c.message_bits != 0 && c.message_bits != 32 && c.message_bits != 64)
         return fail(VIBE_EINVAL, "message_bits must be 0, 32 or 64");
+    if (c.schedule > 1) return fail(VIBE_EINVAL, "schedule must be 0 (serial) or 1 (parallel)");
     if (m && (size_t)m * (c.message_bits == 64 ? 8 : 4) + 8 * (2 * (size_t)((m + 63) / 64) + (n + 63) / 64) >
                  150 * 1024)
         return fail(VIBE_EUNSUPPORTED, "per-decoder LDS state exceeds 150 KB");
@@ -377,6 +378,7 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     d.words_m = words_m;
     d.max_chunks = ch_max;
     d.fp64 = fp64 ? 1 : 0;
+    d.flood = c.schedule == 1 ? 1 : 0;
     d.alpha = c.alpha;
     d.clamp = lim;
     d.ident32 = ident32;

@@ -76,6 +76,7 @@ struct DevGraph {
     uint32_t words_n, words_m;  // ceil(n/64), ceil(m/64)
     uint32_t max_chunks;        // largest chunk count of a member (slab = max_chunks * 64)
     int fp64;                   // message precision: 0 = FP32, 1 = FP64
+    int flood;                  // schedule: 0 = serial-V, 1 = parallel (flooding)
     double alpha, clamp;
     uint32_t ident32;           // row state of "no message": clamp, parity 0 (FP32 bits)
     uint64_t ident64;           // the same in FP64 bits
@@ -148,8 +149,8 @@ struct BpLaunch {
     uint32_t* iters;           // n_shots: iterations run, summed over members
     int64_t* qfix;             // n_shots x n, may be null
     // scratch
-    void* slab;                // grid x max_chunks x 64 row states / messages
-                               // (global variant), message precision
+    void* slab;                // bp_slabs x grid x max_chunks x 64 row states /
+                               // messages (global variant), message precision
     void* post_slab;           // grid x n, message precision
     uint32_t* counter;         // work counter
     int grid;
@@ -158,6 +159,7 @@ struct BpLaunch {
 int launch_bp(const DevGraph& g, const BpLaunch& a, hipStream_t st);
 int bp_grid(const DevGraph& g, bool slab_in_lds);
 size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds);
+int bp_slabs(const DevGraph& g);  // slabs per block: 1 (serial), 2 (parallel: states and messages)
 bool bp_slab_fits_lds(const DevGraph& g);
 int launch_zero(void* p, size_t bytes, hipStream_t st);
 

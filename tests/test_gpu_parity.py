@@ -61,17 +61,17 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-def _bp_parity(torch, dem, L, T, shots, seed, stop, bits=32):
+def _bp_parity(torch, dem, L, T, shots, seed, stop, bits=32, schedule="serial"):
     import paper_2508_15743_amd as P
 
-    G, perms = _graph(dem, L, min(5, L), T, seed, message_bits=bits)
+    G, perms = _graph(dem, L, min(5, L), T, seed, message_bits=bits, schedule=schedule)
     b = sample(dem, shots, seed + 1)
     tc, post, eh = G.bp_ensemble(_dev(torch, b.syndromes), T_run=T, stop=stop)
     tc, post, eh = tc.cpu().numpy(), post.cpu().numpy(), P.unpack_bits(eh, dem.n)
     g = O.OracleGraph(dem)
     for i in range(shots):
         for j in range(L):
-            r = O.bp(g, b.syndromes[i], perm=perms[j], T=T, stop=stop)
+            r = O.bp(g, b.syndromes[i], perm=perms[j] if schedule == "serial" else None, T=T, stop=stop)
             if bits == 64:
                 assert r["t_conv"] == tc[i, j], (i, j)
                 assert np.array_equal(r["ehat"], eh[i, j]), (i, j)
@@ -111,6 +111,18 @@ def test_bp_members_fp64_bit_exact_phenomenological(torch_cuda):
 
 def test_bp_members_fp64_bit_exact_circuit_full_size(torch_cuda):
     _bp_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 2, 4, 2, 13, stop=False, bits=64)
+
+
+def test_bp_parallel_schedule_fp64_bit_exact(torch_cuda):
+    # Algorithm 1, parallel branch: every message from the previous iteration
+    _bp_parity(torch_cuda, code_capacity_dem(5, 0.05), 2, 32, 40, 14, stop=True, bits=64, schedule="parallel")
+    _bp_parity(torch_cuda, phenomenological_dem(11, 11, 0.01, 0.01), 1, 12, 6, 15, stop=False, bits=64,
+               schedule="parallel")
+    _bp_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 1, 4, 2, 16, stop=False, bits=64, schedule="parallel")
+
+
+def test_bp_parallel_schedule_fp32(torch_cuda):
+    _bp_parity(torch_cuda, phenomenological_dem(11, 11, 0.01, 0.01), 1, 20, 6, 17, stop=True, schedule="parallel")
 
 
 def _lsd_parity(torch, dem, shots, seed, noise=2.0):
@@ -166,17 +178,17 @@ def test_lsd_edge_cases(torch_cuda):
     G.close()
 
 
-def _oracle_decode(dem, perms, synd, L, M, T, priors=None):
+def _oracle_decode(dem, perms, synd, L, M, T, priors=None, schedule="serial"):
     g = O.OracleGraph(dem)
     if priors is not None:
         g.priors = priors
-    return O.decode(g, perms, synd, L=L, M=M, T=T, threads=NT)
+    return O.decode(g, perms, synd, L=L, M=M, T=T, threads=NT, schedule=schedule)
 
 
-def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots, bits=32):
+def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots, bits=32, schedule="serial"):
     import paper_2508_15743_amd as P
 
-    G, perms = _graph(dem, L, M, T, seed, message_bits=bits)
+    G, perms = _graph(dem, L, M, T, seed, message_bits=bits, schedule=schedule)
     b = sample(dem, shots, seed + 7)
     corr, obs, st = G.decode(_dev(torch, b.syndromes))
     e, obs, st = P.unpack_bits(corr, dem.n), obs.cpu().numpy(), st.cpu().numpy()
@@ -184,7 +196,7 @@ def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots, bits=32):
     ok = (st[:, 0] & 4) == 0
     assert np.array_equal((e[ok].astype(np.int64) @ H.T) % 2, b.syndromes[ok])
     assert np.array_equal(obs, (e.astype(np.int64) @ dem.dense_l().T.astype(np.int64) % 2).astype(np.uint8))
-    ref = _oracle_decode(dem, perms, b.syndromes[:oracle_shots], L, M, T)
+    ref = _oracle_decode(dem, perms, b.syndromes[:oracle_shots], L, M, T, schedule=schedule)
     agree = (ref["ehat"] == e[:oracle_shots]).all(1)
     n = oracle_shots
     if bits == 64:
@@ -193,7 +205,7 @@ def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots, bits=32):
     else:
         rng = np.random.default_rng(seed)
         moved = dem.priors * (1.0 + 1e-6 * rng.uniform(-1.0, 1.0, dem.n))
-        ref2 = _oracle_decode(dem, perms, b.syndromes[:oracle_shots], L, M, T, priors=moved)
+        ref2 = _oracle_decode(dem, perms, b.syndromes[:oracle_shots], L, M, T, priors=moved, schedule=schedule)
         self_agree = (ref2["ehat"] == ref["ehat"]).all(1).mean()
         margin = 3.0 * np.sqrt(max(self_agree * (1.0 - self_agree), 1.0 / n) / n)
         assert agree.mean() >= self_agree - margin, (agree.mean(), self_agree, margin)
@@ -206,7 +218,7 @@ def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots, bits=32):
     hi = beta.ppf(0.975, k + 1, n - k) if k < n else 1.0
     ler = (obs != b.observables).any(1).mean()
     assert lo <= ler <= hi, (ler, lo, hi)
-    print(f"{dem.name} FP{bits}: agreement {agree.mean():.5f} over {n} shots (bar {bar}); "
+    print(f"{dem.name} {schedule} FP{bits}: agreement {agree.mean():.5f} over {n} shots (bar {bar}); "
           f"LER {ler:.5f} in [{lo:.5f}, {hi:.5f}]")
     G.close()
     return agree.mean()
@@ -236,6 +248,16 @@ def test_decode_fp64_circuit_full_size(torch_cuda):
     _decode_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 32, 5, 20, 2048, 5, 32, bits=64)
 
 
+def test_decode_bp_lsd_baseline(torch_cuda):
+    # BP+LSD-0 without ensembling (Sec. IV.H): one member, parallel schedule
+    _decode_parity(torch_cuda, code_capacity_dem(5, 0.05), 1, 1, 32, 10000, 21, 10000, bits=64,
+                   schedule="parallel")
+    _decode_parity(torch_cuda, phenomenological_dem(11, 11, 0.01, 0.01), 1, 1, 50, 3000, 22, 600, bits=64,
+                   schedule="parallel")
+    _decode_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 1, 1, 20, 2048, 23, 64, bits=64, schedule="parallel")
+    _decode_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 1, 1, 20, 2048, 23, 64, bits=32, schedule="parallel")
+
+
 def test_decode_deterministic_and_batch_invariant(torch_cuda):
     """Run to run, batch split and shot order do not change any output."""
     torch = torch_cuda
@@ -245,7 +267,10 @@ def test_decode_deterministic_and_batch_invariant(torch_cuda):
     s = _dev(torch, b.syndromes)
     c1, o1, s1 = G.decode(s)
     c2, o2, s2 = G.decode(s)
-    assert torch.equal(c1, c2) and torch.equal(o1, o2) and torch.equal(s1[:, :7], s2[:, :7])
+    # every stats field but n_conv (3) and member_iters (7), which count work
+    # done before the correction limit stopped the other members
+    det = [0, 1, 2, 4, 5, 6]
+    assert torch.equal(c1, c2) and torch.equal(o1, o2) and torch.equal(s1[:, det], s2[:, det])
     ca, _, _ = G.decode(s[:1234])
     cb, _, _ = G.decode(s[1234:])
     assert torch.equal(torch.cat([ca, cb]), c1)
