@@ -9,7 +9,9 @@ circuits and data.
 
 One step = vibe_decode over one batch of B shots (all of BP ensemble,
 selection, LSD and observables), syndromes already resident in HBM.
-Prints one JSON line.  Extra legs: BP+LSD-0 without ensembling (one member,
+Prints one JSON line.  Extra legs: a ragged batch of circuit-level codes at
+d = 5..13 (rounds = d) decoded as one call against one call per code;
+BP+LSD-0 without ensembling (one member,
 parallel schedule) on the same batch, with LSD calls and largest-cluster
 sizes beside VibeLSD's (the comparison of the paper's Sec. IV.H); the
 per-shot-launch form
@@ -60,6 +62,42 @@ def measured_traffic(launch_shots):
     return float(vals["traffic_bytes_per_launch"])
 
 
+def ragged_leg(P, torch, shots, seed):
+    """Circuit-level codes d = 5, 7, 9, 11, 13 (rounds = d, p = 1e-3) in one
+    ragged call against one vibe_decode per code on the same syndromes."""
+    from synth.dem import circuit_dem
+    from synth.sample import permutations, sample
+
+    cfgs = [(5, 32, 5, 20), (7, 32, 5, 20), (9, 32, 5, 20), (11, 32, 5, 20), (13, 64, 7, 25)]
+    pairs = []
+    for d, L, M, T in cfgs:
+        dem = circuit_dem(d, d, 1e-3)
+        G = P.Graph.from_dem(dem, permutations(dem.n, L, seed + d), L=L, M=M, T_max=T, alpha=0.625)
+        pairs.append((G, torch.from_numpy(sample(dem, shots, seed + 100 + d).syndromes).to("cuda:0")))
+    rt = P.Runtime()
+    outs = [P.Runtime.outputs(G, s) for G, s in pairs]
+    rt.decode(pairs, outs=outs)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rt.decode(pairs, outs=outs)
+    torch.cuda.synchronize()
+    t_ragged = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for (G, s), o in zip(pairs, outs):
+        G.decode(s, out=o)
+    torch.cuda.synchronize()
+    t_sep = time.perf_counter() - t0
+    total = shots * len(cfgs)
+    res = {"codes": [f"circuit_d{d}_r{d}_p0.001" for d, *_ in cfgs], "shots_per_code": shots,
+           "ragged_shots_per_s": round(total / t_ragged, 1), "separate_shots_per_s": round(total / t_sep, 1),
+           "ragged_over_separate": round(t_sep / t_ragged, 3)}
+    log(f"ragged mix d=5..13: {total / t_ragged:.0f} shots/s in one call, {total / t_sep:.0f} in one call per code")
+    rt.close()
+    for G, _ in pairs:
+        G.close()
+    return res
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -78,6 +116,8 @@ def main():
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-baseline", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--ragged-shots", type=str, default="128,1024", help="shots per code in the ragged leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--seed", type=int, default=2025)
@@ -210,6 +250,9 @@ def main():
         log(f"BP+LSD-0 baseline: {B / dt:.0f} shots/s, LSD calls per 5000 "
             f"{comparison['bp_lsd0']['lsd_calls_per_5000']} vs VibeLSD {comparison['vibelsd']['lsd_calls_per_5000']}")
     result["comparison"] = comparison
+
+    if not args.no_ragged:
+        result["ragged"] = [ragged_leg(P, torch, int(k), args.seed) for k in args.ragged_shots.split(",")]
 
     result["plain"] = None
     result["batched_over_plain"] = None

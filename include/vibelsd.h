@@ -182,6 +182,54 @@ int vibe_lsd(vibe_graph* g, const uint8_t* syndromes, const float* soft, uint64_
              uint64_t* corrections, vibe_shot_stats* stats, void* stream);
 
 /*
+ * Ragged batching: several requests, possibly on graphs of different codes,
+ * decoded with one persistent BP launch over all of their (shot, member)
+ * items, then selection, LSD and observables per request.  Each request's
+ * outputs are exactly those vibe_decode produces for it alone.  All graphs
+ * of one call must share message_bits and schedule and live on the
+ * runtime's device.  A runtime owns the device workspace of its calls;
+ * calls on one runtime must not overlap in time.
+ */
+typedef struct vibe_runtime vibe_runtime;
+
+typedef struct vibe_request {
+    vibe_graph* graph;
+    const uint8_t* syndromes;   /* device, B x m uint8 */
+    uint64_t B;                 /* shots, may be 0 */
+    uint64_t* corrections;      /* device, B x ceil(n/64) uint64 */
+    uint8_t* observables;       /* device, B x k uint8 */
+    vibe_shot_stats* stats;     /* device, B records, or NULL */
+} vibe_request;
+
+int vibe_runtime_create(vibe_runtime** out); /* on the current HIP device */
+void vibe_runtime_destroy(vibe_runtime* rt); /* synchronises the device first; NULL accepted */
+int vibe_decode_ragged(vibe_runtime* rt, const vibe_request* reqs, uint32_t n_reqs, void* stream);
+
+/*
+ * A captured launch sequence: vibe_exec_create records the kernels that
+ * vibe_decode_ragged would queue for `reqs` into a HIP graph, with its own
+ * workspace, after one eager run; vibe_exec_launch replays it on `stream`.
+ * The requests' device pointers are fixed at creation: refill the syndrome
+ * buffers and replay.  A replay writes the same outputs as an eager call on
+ * the buffers' contents.  VIBE_EUNSUPPORTED if the requests need more than
+ * one round of workspace (about 4 GB of per-shot buffers).
+ */
+typedef struct vibe_exec vibe_exec;
+int vibe_exec_create(const vibe_request* reqs, uint32_t n_reqs, vibe_exec** out);
+int vibe_exec_launch(vibe_exec* ex, void* stream);
+void vibe_exec_destroy(vibe_exec* ex); /* synchronises the device first; NULL accepted */
+
+/*
+ * Autotuning of the launch settings of vibe_decode for one graph: times the
+ * decode of the given syndromes (device, B x m) with the message slab in
+ * LDS (where it fits) or in global memory, and with the BP grid at full,
+ * three-quarter and half occupancy; keeps the fastest in the handle.  The
+ * decoder's results do not depend on these settings.  Synchronises
+ * `stream`.  slab_in_lds and grid (either may be NULL) receive the choice.
+ */
+int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B, void* stream, int* slab_in_lds, int* grid);
+
+/*
  * Kernel timing, for measurement: while enabled, every launch of the BP
  * ensemble kernel, of the selection kernel and of the LSD kernel made through
  * this handle is bracketed by HIP events recorded on the launch stream.

@@ -43,6 +43,11 @@ class vibe_graph_info_t(C.Structure):
                 ("device_bytes", C.c_uint64)]
 
 
+class vibe_request(C.Structure):
+    _fields_ = [("graph", C.c_void_p), ("syndromes", C.c_void_p), ("B", C.c_uint64),
+                ("corrections", C.c_void_p), ("observables", C.c_void_p), ("stats", C.c_void_p)]
+
+
 _lib = None
 
 EXPORTS = {
@@ -61,6 +66,14 @@ EXPORTS = {
                            C.c_void_p, C.c_void_p]),
     "vibe_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "vibe_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
+    "vibe_runtime_create": (C.c_int, [C.POINTER(C.c_void_p)]),
+    "vibe_runtime_destroy": (None, [C.c_void_p]),
+    "vibe_decode_ragged": (C.c_int, [C.c_void_p, C.POINTER(vibe_request), C.c_uint32, C.c_void_p]),
+    "vibe_exec_create": (C.c_int, [C.POINTER(vibe_request), C.c_uint32, C.POINTER(C.c_void_p)]),
+    "vibe_exec_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "vibe_exec_destroy": (None, [C.c_void_p]),
+    "vibe_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(C.c_int),
+                                C.POINTER(C.c_int)]),
     "vibe_last_error": (C.c_char_p, []),
     "vibe_version": (C.c_char_p, []),
 }
@@ -143,6 +156,51 @@ def vibe_bp_ensemble(handle, syndromes, B, T_run, stop, t_conv, posteriors, ehat
 def vibe_lsd(handle, syndromes, soft, B, corrections, stats, stream):
     _check(lib().vibe_lsd(handle, _ptr(syndromes), _ptr(soft), B, _ptr(corrections), _ptr(stats),
                           stream))
+
+
+def vibe_runtime_create():
+    out = C.c_void_p()
+    _check(lib().vibe_runtime_create(C.byref(out)))
+    return out
+
+
+def vibe_runtime_destroy(rt):
+    lib().vibe_runtime_destroy(rt)
+
+
+def _requests(reqs):
+    """[(Graph, syndromes, corrections, observables, stats or None)] -> ctypes array"""
+    arr = (vibe_request * len(reqs))()
+    for i, (G, s, c, o, st) in enumerate(reqs):
+        arr[i] = vibe_request(G.handle, s.data_ptr(), s.shape[0], c.data_ptr(), o.data_ptr(),
+                              st.data_ptr() if st is not None else None)
+    return arr
+
+
+def vibe_decode_ragged(rt, reqs, stream):
+    arr = _requests(reqs)
+    _check(lib().vibe_decode_ragged(rt, arr, len(reqs), stream))
+
+
+def vibe_exec_create(reqs):
+    arr = _requests(reqs)
+    out = C.c_void_p()
+    _check(lib().vibe_exec_create(arr, len(reqs), C.byref(out)))
+    return out
+
+
+def vibe_exec_launch(ex, stream):
+    _check(lib().vibe_exec_launch(ex, stream))
+
+
+def vibe_exec_destroy(ex):
+    lib().vibe_exec_destroy(ex)
+
+
+def vibe_autotune(handle, syndromes, B, stream):
+    lds, grid = C.c_int(), C.c_int()
+    _check(lib().vibe_autotune(handle, _ptr(syndromes), B, stream, C.byref(lds), C.byref(grid)))
+    return lds.value, grid.value
 
 
 def vibe_profile_enable(handle, enable):
@@ -263,3 +321,75 @@ class Graph:
         st = torch.empty((B, 8), dtype=torch.int32, device=s.device)
         vibe_lsd(self.handle, s, soft, B, corr, st, _stream(stream))
         return corr, st
+
+
+def _graph_autotune(self, syndromes, stream=None):
+    """Time the launch settings of decode() on these syndromes and keep the
+    fastest -> (slab_in_lds, grid)."""
+    return vibe_autotune(self.handle, self._synd(syndromes), syndromes.shape[0], _stream(stream))
+
+
+Graph.autotune = _graph_autotune
+
+
+class Runtime:
+    """Device workspace for ragged calls: decode() takes requests on several
+    graphs and runs their BP ensembles as one persistent launch."""
+
+    def __init__(self):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libvibelsd needs a ROCm GPU (torch.cuda is not available)")
+        self.handle = vibe_runtime_create()
+
+    @staticmethod
+    def outputs(G, syndromes):
+        import torch
+        B, dev = syndromes.shape[0], syndromes.device
+        return (torch.empty((B, G.words), dtype=torch.int64, device=dev),
+                torch.empty((B, max(G.k, 1)), dtype=torch.uint8, device=dev),
+                torch.empty((B, 8), dtype=torch.int32, device=dev))
+
+    def decode(self, pairs, stream=None, outs=None):
+        """pairs: [(Graph, syndromes uint8 [B, m])] -> [(corrections, observables, stats)]"""
+        outs = outs or [self.outputs(G, s) for G, s in pairs]
+        reqs = [(G, G._synd(s), c, o, st) for (G, s), (c, o, st) in zip(pairs, outs)]
+        vibe_decode_ragged(self.handle, reqs, _stream(stream))
+        return outs
+
+    def close(self):
+        if getattr(self, "handle", None):
+            vibe_runtime_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Exec:
+    """A captured ragged launch sequence over fixed buffers: refill the
+    syndrome tensors, then launch()."""
+
+    def __init__(self, pairs, outs=None):
+        self.pairs = [(G, G._synd(s)) for G, s in pairs]
+        self.outs = outs or [Runtime.outputs(G, s) for G, s in self.pairs]
+        reqs = [(G, s, c, o, st) for (G, s), (c, o, st) in zip(self.pairs, self.outs)]
+        self.handle = vibe_exec_create(reqs)
+
+    def launch(self, stream=None):
+        vibe_exec_launch(self.handle, _stream(stream))
+        return self.outs
+
+    def close(self):
+        if getattr(self, "handle", None):
+            vibe_exec_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -106,7 +106,8 @@ int memset_async(void* p, size_t bytes, hipStream_t st) { return launch_zero(p, 
 
 // One chunk of the decoder: shots [shot0, shot0 + n).
 int decode_chunk(vibe_graph* G, const ChunkBufs& W, const uint8_t* synd, uint64_t shot0, uint32_t n,
-                 uint64_t* corr, vibe_shot_stats* stats, int bp_blocks, int lsd_grid, hipStream_t st) {
+                 uint64_t* corr, vibe_shot_stats* stats, int bp_blocks, int lsd_grid, hipStream_t st,
+                 bool in_lds) {
     const DevGraph& g = G->h.dg;
     int rc;
     if ((rc = memset_async(W.cmask, 8ull * n * (kMaxT + 1), st)) ||
@@ -115,7 +116,7 @@ int decode_chunk(vibe_graph* G, const ChunkBufs& W, const uint8_t* synd, uint64_
         return rc;
     BpLaunch b{};
     b.member_major = 1;
-    b.slab_in_lds = bp_slab_fits_lds(g) ? 1 : 0;
+    b.slab_in_lds = in_lds ? 1 : 0;
     b.syndromes = synd;
     b.shot0 = shot0;
     b.n_shots = n;
@@ -246,14 +247,14 @@ extern "C" int vibe_decode(vibe_graph* G, const uint8_t* syndromes, uint64_t B, 
     hipStream_t st = static_cast<hipStream_t>(stream);
     const DevGraph& g = G->h.dg;
     const uint32_t bc = chunk_for(g, B, true);
-    const bool in_lds = bp_slab_fits_lds(g);
-    const int bpg = bp_grid(g, in_lds);
+    const bool in_lds = bp_slab_fits_lds(g) && G->tune_lds != 0;
+    const int bpg = G->tune_grid > 0 ? std::min(G->tune_grid, bp_grid(g, in_lds)) : bp_grid(g, in_lds);
     const int lg = lsd_grid_for(bc);
     ChunkBufs W;
     if ((rc = carve(G, bc, true, in_lds ? 0 : bpg, bpg, lg, &W))) return rc;
     for (uint64_t s0 = 0; s0 < B; s0 += bc) {
         const uint32_t n = (uint32_t)std::min<uint64_t>(bc, B - s0);
-        if ((rc = decode_chunk(G, W, syndromes, s0, n, corrections, stats, bpg, lg, st))) return rc;
+        if ((rc = decode_chunk(G, W, syndromes, s0, n, corrections, stats, bpg, lg, st, in_lds))) return rc;
     }
     return launch_observables(g, corrections, 0, (uint32_t)std::min<uint64_t>(B, UINT32_MAX), observables, st);
 }
@@ -270,9 +271,10 @@ extern "C" int vibe_decode_plain(vibe_graph* G, const uint8_t* syndromes, uint64
     const DevGraph& g = G->h.dg;
     ChunkBufs W;
     const int blocks = (int)g.L;  // one block per member of the one shot
-    if ((rc = carve(G, 1, true, bp_slab_fits_lds(g) ? 0 : blocks, blocks, 1, &W))) return rc;
+    const bool in_lds = bp_slab_fits_lds(g);
+    if ((rc = carve(G, 1, true, in_lds ? 0 : blocks, blocks, 1, &W))) return rc;
     for (uint64_t s0 = 0; s0 < B; s0++) {
-        if ((rc = decode_chunk(G, W, syndromes, s0, 1, corrections, stats, blocks, 1, st))) return rc;
+        if ((rc = decode_chunk(G, W, syndromes, s0, 1, corrections, stats, blocks, 1, st, in_lds))) return rc;
         if ((rc = launch_observables(g, corrections, s0, 1, observables, st))) return rc;
     }
     return VIBE_OK;

@@ -162,11 +162,17 @@ struct Ctx {
 #define VIBE_BP_DEPTH 3
 #endif
 constexpr int kDepth = VIBE_BP_DEPTH;  // chunks loaded ahead of the one being processed
-// occupancy the register allocator aims for (waves per SIMD) in the FP32
-// kernel: 6 keeps it within 80 VGPRs; the FP64 kernel aims for 4
+// occupancy the register allocator aims for (waves per SIMD): 6 keeps the
+// production kernel (FP32, serial schedule, global slab, one request) within
+// 80 VGPRs without spills; the other FP32 variants need a few more
+// registers and aim for 5, the FP64 ones for 4
 #ifndef VIBE_BP_WAVES_PER_EU
 #define VIBE_BP_WAVES_PER_EU 6
 #endif
+template <class F, bool SLAB_LDS, bool FLOOD, bool RAGGED>
+constexpr int waves_target() {
+    return sizeof(F) == 8 ? 4 : (!SLAB_LDS && !FLOOD && !RAGGED ? VIBE_BP_WAVES_PER_EU : 5);
+}
 
 // Slot data of one chunk for the sweep, loaded ahead of use.
 template <class F>
@@ -375,210 +381,272 @@ __device__ __forceinline__ void backward(const Ctx<F>& x, uint32_t nch, typename
     }
 }
 
+// One work item = (shot, member) of one request: the member's BP run on the
+// shot's syndrome, its convergence record, candidate and contribution to
+// the normalised average.  `lds` is the block's dynamic LDS; the slabs and
+// posteriors are the block's own.
 template <class F, bool SLAB_LDS, bool FLOOD>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(F) == 4 ? VIBE_BP_WAVES_PER_EU : 4))) void bp_ensemble_kernel(DevGraph g, BpLaunch a) {
+__device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, uint32_t item, unsigned char* lds,
+                                         Ctx<F> x) {
     using P = Prec<F>;
     using B = typename P::B;
-    extern __shared__ __align__(16) unsigned char lds[];
     uint64_t* sb = reinterpret_cast<uint64_t*>(lds);
     uint64_t* res = sb + g.words_m;
     uint64_t* eb = res + g.words_m;
     B* pref = reinterpret_cast<B*>(eb + g.words_n);
     // LDS variant: the state slab, then (parallel schedule) the message slab;
-    // the global slabs are buffer resources
+    // the global slabs are buffer resources set up by the caller
     B* slab = SLAB_LDS ? pref + g.m : nullptr;
     B* mslab = SLAB_LDS && FLOOD ? slab + (size_t)g.max_chunks * kWave : nullptr;
-
-    const int lane = threadIdx.x;
-    F* post = reinterpret_cast<F*>(a.post_slab) + (size_t)blockIdx.x * (g.n + kWave);
+    const int lane = x.lane;
+    F* post = x.post;
     const F* lamv = reinterpret_cast<const F*>(g.lam);
-    const uint32_t n_items = a.n_shots * g.L;
     const B ident = P::ident(g);
-
-    Ctx<F> x;
-    x.slb = make_rsrc(a.slab ? reinterpret_cast<B*>(a.slab) + (size_t)blockIdx.x * g.max_chunks * kWave : nullptr,
-                      g.max_chunks * kWave * (uint32_t)sizeof(B));
+    constexpr bool kF64 = sizeof(F) == 8;
     x.lslab = slab;
-    x.mslb = make_rsrc(FLOOD && a.slab ? reinterpret_cast<B*>(a.slab) + ((size_t)gridDim.x + blockIdx.x) * g.max_chunks * kWave
-                                      : nullptr,
-                       g.max_chunks * kWave * (uint32_t)sizeof(B));
     x.lmslab = mslab;
     x.pref = pref;
     x.sb = sb;
     x.res = res;
     x.eb = eb;
-    x.post = post;
     x.trash = post + g.n;
     x.al = (F)g.alpha;
     x.lim = (F)g.clamp;
-    x.lane = lane;
-    x.lane4 = (uint32_t)lane * 4u;
-    x.laneF = (uint32_t)lane * (uint32_t)sizeof(F);
-    constexpr bool kF64 = sizeof(F) == 8;
 
+    uint32_t shot, mem;
+    if (a.member_major) {
+        mem = item / a.n_shots;
+        shot = item % a.n_shots;
+    } else {
+        shot = item / g.L;
+        mem = item % g.L;
+    }
+    const uint32_t rec = shot * g.L + mem;  // output record of this item
+    const uint8_t* s = a.syndromes + (size_t)(a.shot0 + shot) * g.m;
+    uint64_t* cmask = a.conv_mask + (size_t)shot * (kMaxT + 1);
+
+    // ---- syndrome bits; the residual s + H e starts at s (e = 0)
+    uint64_t any = 0;
+    for (uint32_t base = 0; base < g.m; base += kWave) {
+        const uint32_t c = base + lane;
+        const uint64_t mask = __ballot(c < g.m && s[c] != 0);
+        if (lane == 0) {
+            sb[base / kWave] = mask;
+            res[base / kWave] = mask;
+        }
+        any |= mask;
+    }
+    if (a.use_M && preceding_converged(cmask, 1, mem, lane) >= g.M) {
+        // M members of lower index converged at the first iteration: this
+        // one cannot be among the first M
+        if (lane == 0) a.t_conv[rec] = 0;
+        return;
+    }
+    if (!any && a.fast_zero && g.all_lam_positive) {
+        // s = 0 with every lambda > 0: the first sweep leaves every message
+        // positive, so the decision is e = 0 and it satisfies s at t = 1.
+        if (a.cand)
+            for (uint32_t w = lane; w < g.words_n; w += kWave) a.cand[(size_t)rec * g.words_n + w] = 0;
+        if (lane == 0) {
+            a.t_conv[rec] = 1;
+            if (a.weight) a.weight[rec] = 0.0;
+            atomicOr(reinterpret_cast<unsigned long long*>(&cmask[1]), 1ull << mem);
+            atomicAdd(&a.iters[shot], 1u);
+        }
+        return;
+    }
+    for (uint32_t w = lane; w < g.words_n; w += kWave) eb[w] = g.e0[w];
+
+    // The slab is only ever re-read by the lane that wrote it: a slot's
+    // position is (chunk * 64 + lane) in the sweep and in the backward
+    // pass alike.  The first sweep reads the suffix states of the initial
+    // messages from the graph itself.
+    const uint32_t c0 = uni(g.member_chunk[mem]), nch = uni(g.member_chunk[mem + 1]) - c0;
+    const unsigned char* recs = g.sched + (size_t)c0 * rec_bytes(kF64);
+    x.sch = make_rsrc(recs, nch * rec_bytes(kF64));
+    F* post_out = a.post_out ? reinterpret_cast<F*>(a.post_out) + (size_t)rec * g.n : nullptr;
+    if constexpr (SLAB_LDS) {
+        // the first sweep reads the initial suffix states from the slab
+        for (uint32_t q = 0; q < nch; q++)
+            slab[q * kWave + lane] = *reinterpret_cast<const B*>(recs + (size_t)q * rec_bytes(kF64) +
+                                                                 rec_init(kF64) + (size_t)lane * sizeof(B));
+    }
+
+    uint32_t conv_t = 0, ran = 0;
+    bool stopped = false;
+    for (uint32_t t = 1; t <= a.T_run; t++) {
+        if (a.use_M && t >= 2 && preceding_converged(cmask, t, mem, lane) >= g.M) {
+            stopped = true;  // cannot be among the first M any more
+            break;
+        }
+        const bool want_post = post_out != nullptr || (a.accumulate_q && t == a.T_run);
+        if (want_post) {
+            // columns without checks keep L_v = lambda_v
+            for (uint32_t v = lane; v < g.n; v += kWave) post[v] = lamv[v];
+        }
+        for (uint32_t c = lane; c < g.m; c += kWave) pref[c] = ident;
+        __syncthreads();
+        if (nch) {
+            if (want_post)
+                sweep<F, SLAB_LDS, true, FLOOD>(x, nch, t == 1);
+            else
+                sweep<F, SLAB_LDS, false, FLOOD>(x, nch, t == 1);
+        }
+        __syncthreads();  // every new message stored
+        if (post_out) {
+            // post[v] was written by the lane that swept v: read it past the L1
+            for (uint32_t v = lane; v < g.n; v += kWave)
+                post_out[v] = __hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        ran = t;
+        // converged iff the residual s + H e is zero
+        bool nz = false;
+        for (uint32_t w = lane; w < g.words_m; w += kWave) nz |= res[w] != 0;
+        if (__ballot(nz) == 0) {
+            if (!conv_t) conv_t = t;
+            if (a.stop_on_converge) break;
+        }
+        if (t < a.T_run && nch) {
+            for (uint32_t c = lane; c < g.m; c += kWave) pref[c] = ident;
+            __syncthreads();
+            backward<F, SLAB_LDS, FLOOD>(x, nch, pref);
+            __syncthreads();
+        }
+    }
+
+    if (lane == 0) {
+        a.t_conv[rec] = (int32_t)conv_t;
+        atomicAdd(&a.iters[shot], ran);
+    }
+    if (a.cand && (conv_t || !a.use_M))
+        for (uint32_t w = lane; w < g.words_n; w += kWave) a.cand[(size_t)rec * g.words_n + w] = eb[w];
+    if (a.weight && conv_t) {
+        // W(e) = sum_v e_v lambda_v in FP64, ascending v
+        double W = 0.0;
+        for (uint32_t base = 0; base < g.words_n; base += kWave) {
+            const uint32_t w = base + lane;
+            uint64_t nzw = __ballot(w < g.words_n && eb[w] != 0);
+            if (lane == 0) {
+                while (nzw) {
+                    const int bi = __ffsll((long long)nzw) - 1;
+                    nzw &= nzw - 1;
+                    uint64_t xw = eb[base + bi];
+                    while (xw) {
+                        const int bb = __ffsll((long long)xw) - 1;
+                        xw &= xw - 1;
+                        W += g.lam64[(size_t)(base + bi) * 64 + bb];
+                    }
+                }
+            }
+        }
+        if (lane == 0) a.weight[rec] = W;
+    }
+    if (lane == 0 && conv_t) atomicOr(reinterpret_cast<unsigned long long*>(&cmask[conv_t]), 1ull << mem);
+    if (a.accumulate_q && !conv_t && !stopped && ran == a.T_run) {
+        // normalised posterior, summed over the members of a shot with no
+        // converged member, in 2^-56 fixed point (order-independent)
+        uint32_t cnt = 0;
+        for (uint32_t tt = lane + 1; tt <= a.T_run; tt += kWave) cnt += __popcll(load_mask(&cmask[tt]));
+        if (wave_sum_u32(cnt) == 0) {
+            // ||L||^2 summed in ascending v: each lane squares one value of
+            // a block of 64 and the running sum takes them in order (every
+            // lane holds the same sum).  post[v] was written by the lane
+            // that swept v: read it past the L1.
+            double ss = 0.0;
+            for (uint32_t base = 0; base < g.n; base += kWave) {
+                const uint32_t v = base + lane;
+                double sq = 0.0;
+                if (v < g.n) {
+                    const double xv = (double)__hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    sq = xv * xv;
+                }
+                const uint32_t cnt_b = min((uint32_t)kWave, g.n - base);
+                for (uint32_t j = 0; j < cnt_b; j++) ss += readlane_f64(sq, (int)j);
+            }
+            if (uni(ss > 0.0 ? 1u : 0u)) {
+                const double scale = kQScale / sqrt(ss);
+                int64_t* q = a.qfix + (size_t)shot * g.n;
+                for (uint32_t v = lane; v < g.n; v += kWave) {
+                    const double xv = (double)__hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&q[v]), (unsigned long long)llrint(xv * scale));
+                }
+            }
+        }
+    }
+}
+
+// Pass context fields that depend only on the block: lane offsets, the
+// block's global slabs and posterior area.
+template <class F>
+__device__ __forceinline__ Ctx<F> block_ctx(typename Prec<F>::B* gslab, typename Prec<F>::B* gmslab,
+                                           uint32_t slab_elems, F* post) {
+    using B = typename Prec<F>::B;
+    Ctx<F> x;
+    x.slb = make_rsrc(gslab, slab_elems * (uint32_t)sizeof(B));
+    x.mslb = make_rsrc(gmslab, slab_elems * (uint32_t)sizeof(B));
+    x.post = post;
+    x.lane = threadIdx.x;
+    x.lane4 = (uint32_t)threadIdx.x * 4u;
+    x.laneF = (uint32_t)threadIdx.x * (uint32_t)sizeof(F);
+    return x;
+}
+
+// A read-only struct copied into registers through the constant address
+// space (scalar loads), one dword at a time.
+template <class T>
+__device__ __forceinline__ T load_const(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "dword-sized struct");
+    T v;
+    const __attribute__((address_space(4))) uint32_t* src = (const __attribute__((address_space(4))) uint32_t*)p;
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+    for (size_t i = 0; i < sizeof(T) / 4; i++) dst[i] = src[i];
+    return v;
+}
+
+// One launch over the items of one request.
+template <class F, bool SLAB_LDS, bool FLOOD>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_target<F, SLAB_LDS, FLOOD, false>()))) void bp_ensemble_kernel(DevGraph g, BpLaunch a) {
+    using B = typename Prec<F>::B;
+    extern __shared__ __align__(16) unsigned char lds[];
+    const uint32_t slab_elems = g.max_chunks * kWave;
+    B* gslab = a.slab ? reinterpret_cast<B*>(a.slab) + (size_t)blockIdx.x * slab_elems : nullptr;
+    B* gmslab = FLOOD && a.slab ? reinterpret_cast<B*>(a.slab) + ((size_t)gridDim.x + blockIdx.x) * slab_elems : nullptr;
+    F* post = reinterpret_cast<F*>(a.post_slab) + (size_t)blockIdx.x * (g.n + kWave);
+    const Ctx<F> x = block_ctx<F>(gslab, gmslab, slab_elems, post);
+    const uint32_t n_items = a.n_shots * g.L;
     for (;;) {
         const uint32_t item = wave_ticket(a.counter, 1u);
         if (item >= n_items) break;
-        uint32_t shot, mem;
-        if (a.member_major) {
-            mem = item / a.n_shots;
-            shot = item % a.n_shots;
-        } else {
-            shot = item / g.L;
-            mem = item % g.L;
-        }
-        const uint32_t rec = shot * g.L + mem;  // output record of this item
-        const uint8_t* s = a.syndromes + (size_t)(a.shot0 + shot) * g.m;
-        uint64_t* cmask = a.conv_mask + (size_t)shot * (kMaxT + 1);
+        run_item<F, SLAB_LDS, FLOOD>(g, a, item, lds, x);
+        __syncthreads();
+    }
+}
 
-        // ---- syndrome bits; the residual s + H e starts at s (e = 0)
-        uint64_t any = 0;
-        for (uint32_t base = 0; base < g.m; base += kWave) {
-            const uint32_t c = base + lane;
-            const uint64_t mask = __ballot(c < g.m && s[c] != 0);
-            if (lane == 0) {
-                sb[base / kWave] = mask;
-                res[base / kWave] = mask;
-            }
-            any |= mask;
-        }
-        if (a.use_M && preceding_converged(cmask, 1, mem, lane) >= g.M) {
-            // M members of lower index converged at the first iteration: this
-            // one cannot be among the first M
-            if (lane == 0) a.t_conv[rec] = 0;
-            continue;
-        }
-        if (!any && a.fast_zero && g.all_lam_positive) {
-            // s = 0 with every lambda > 0: the first sweep leaves every message
-            // positive, so the decision is e = 0 and it satisfies s at t = 1.
-            if (a.cand)
-                for (uint32_t w = lane; w < g.words_n; w += kWave) a.cand[(size_t)rec * g.words_n + w] = 0;
-            if (lane == 0) {
-                a.t_conv[rec] = 1;
-                if (a.weight) a.weight[rec] = 0.0;
-                atomicOr(reinterpret_cast<unsigned long long*>(&cmask[1]), 1ull << mem);
-                atomicAdd(&a.iters[shot], 1u);
-            }
-            continue;
-        }
-        for (uint32_t w = lane; w < g.words_n; w += kWave) eb[w] = g.e0[w];
-
-        // The slab is only ever re-read by the lane that wrote it: a slot's
-        // position is (chunk * 64 + lane) in the sweep and in the backward
-        // pass alike.  The first sweep reads the suffix states of the initial
-        // messages from the graph itself.
-        const uint32_t c0 = uni(g.member_chunk[mem]), nch = uni(g.member_chunk[mem + 1]) - c0;
-        const unsigned char* recs = g.sched + (size_t)c0 * rec_bytes(kF64);
-        x.sch = make_rsrc(recs, nch * rec_bytes(kF64));
-        F* post_out = a.post_out ? reinterpret_cast<F*>(a.post_out) + (size_t)rec * g.n : nullptr;
-        if constexpr (SLAB_LDS) {
-            // the first sweep reads the initial suffix states from the slab
-            for (uint32_t q = 0; q < nch; q++)
-                slab[q * kWave + lane] = *reinterpret_cast<const B*>(recs + (size_t)q * rec_bytes(kF64) +
-                                                                     rec_init(kF64) + (size_t)lane * sizeof(B));
-        }
-
-        uint32_t conv_t = 0, ran = 0;
-        bool stopped = false;
-        for (uint32_t t = 1; t <= a.T_run; t++) {
-            if (a.use_M && t >= 2 && preceding_converged(cmask, t, mem, lane) >= g.M) {
-                stopped = true;  // cannot be among the first M any more
-                break;
-            }
-            const bool want_post = post_out != nullptr || (a.accumulate_q && t == a.T_run);
-            if (want_post) {
-                // columns without checks keep L_v = lambda_v
-                for (uint32_t v = lane; v < g.n; v += kWave) post[v] = lamv[v];
-            }
-            for (uint32_t c = lane; c < g.m; c += kWave) pref[c] = ident;
-            __syncthreads();
-            if (nch) {
-                if (want_post)
-                    sweep<F, SLAB_LDS, true, FLOOD>(x, nch, t == 1);
-                else
-                    sweep<F, SLAB_LDS, false, FLOOD>(x, nch, t == 1);
-            }
-            __syncthreads();  // every new message stored
-            if (post_out) {
-                // post[v] was written by the lane that swept v: read it past the L1
-                for (uint32_t v = lane; v < g.n; v += kWave)
-                    post_out[v] = __hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            ran = t;
-            // converged iff the residual s + H e is zero
-            bool nz = false;
-            for (uint32_t w = lane; w < g.words_m; w += kWave) nz |= res[w] != 0;
-            if (__ballot(nz) == 0) {
-                if (!conv_t) conv_t = t;
-                if (a.stop_on_converge) break;
-            }
-            if (t < a.T_run && nch) {
-                for (uint32_t c = lane; c < g.m; c += kWave) pref[c] = ident;
-                __syncthreads();
-                backward<F, SLAB_LDS, FLOOD>(x, nch, pref);
-                __syncthreads();
-            }
-        }
-
-        if (lane == 0) {
-            a.t_conv[rec] = (int32_t)conv_t;
-            atomicAdd(&a.iters[shot], ran);
-        }
-        if (a.cand && (conv_t || !a.use_M))
-            for (uint32_t w = lane; w < g.words_n; w += kWave) a.cand[(size_t)rec * g.words_n + w] = eb[w];
-        if (a.weight && conv_t) {
-            // W(e) = sum_v e_v lambda_v in FP64, ascending v
-            double W = 0.0;
-            for (uint32_t base = 0; base < g.words_n; base += kWave) {
-                const uint32_t w = base + lane;
-                uint64_t nzw = __ballot(w < g.words_n && eb[w] != 0);
-                if (lane == 0) {
-                    while (nzw) {
-                        const int bi = __ffsll((long long)nzw) - 1;
-                        nzw &= nzw - 1;
-                        uint64_t xw = eb[base + bi];
-                        while (xw) {
-                            const int bb = __ffsll((long long)xw) - 1;
-                            xw &= xw - 1;
-                            W += g.lam64[(size_t)(base + bi) * 64 + bb];
-                        }
-                    }
-                }
-            }
-            if (lane == 0) a.weight[rec] = W;
-        }
-        if (lane == 0 && conv_t) atomicOr(reinterpret_cast<unsigned long long*>(&cmask[conv_t]), 1ull << mem);
-        if (a.accumulate_q && !conv_t && !stopped && ran == a.T_run) {
-            // normalised posterior, summed over the members of a shot with no
-            // converged member, in 2^-56 fixed point (order-independent)
-            uint32_t cnt = 0;
-            for (uint32_t tt = lane + 1; tt <= a.T_run; tt += kWave) cnt += __popcll(load_mask(&cmask[tt]));
-            if (wave_sum_u32(cnt) == 0) {
-                // ||L||^2 summed in ascending v: each lane squares one value of
-                // a block of 64 and the running sum takes them in order (every
-                // lane holds the same sum).  post[v] was written by the lane
-                // that swept v: read it past the L1.
-                double ss = 0.0;
-                for (uint32_t base = 0; base < g.n; base += kWave) {
-                    const uint32_t v = base + lane;
-                    double sq = 0.0;
-                    if (v < g.n) {
-                        const double xv = (double)__hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        sq = xv * xv;
-                    }
-                    const uint32_t cnt_b = min((uint32_t)kWave, g.n - base);
-                    for (uint32_t j = 0; j < cnt_b; j++) ss += readlane_f64(sq, (int)j);
-                }
-                if (uni(ss > 0.0 ? 1u : 0u)) {
-                    const double scale = kQScale / sqrt(ss);
-                    int64_t* q = a.qfix + (size_t)shot * g.n;
-                    for (uint32_t v = lane; v < g.n; v += kWave) {
-                        const double xv = (double)__hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        atomicAdd(reinterpret_cast<unsigned long long*>(&q[v]), (unsigned long long)llrint(xv * scale));
-                    }
-                }
-            }
-        }
+// One persistent launch over the items of several requests, on different
+// graphs (ragged batching).  Items are numbered request after request;
+// segs[j].item0 is request j's first.  Every block owns slabs and
+// posteriors sized for the largest graph.  The segment table is read-only
+// for the launch and read through the constant address space, so its
+// fields load as wave-uniform scalars.
+template <class F, bool SLAB_LDS, bool FLOOD>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_target<F, SLAB_LDS, FLOOD, true>()))) void bp_ragged_kernel(RaggedLaunch r) {
+    using B = typename Prec<F>::B;
+    using CSeg = const __attribute__((address_space(4))) BpSeg;
+    extern __shared__ __align__(16) unsigned char lds[];
+    CSeg* segs = (CSeg*)r.segs;
+    B* gslab = r.slab ? reinterpret_cast<B*>(r.slab) + (size_t)blockIdx.x * r.slab_elems : nullptr;
+    B* gmslab = FLOOD && r.slab ? reinterpret_cast<B*>(r.slab) + ((size_t)gridDim.x + blockIdx.x) * r.slab_elems : nullptr;
+    F* post = reinterpret_cast<F*>(r.post_slab) + (size_t)blockIdx.x * r.post_elems;
+    const Ctx<F> x = block_ctx<F>(gslab, gmslab, r.slab_elems, post);
+    for (;;) {
+        const uint32_t item = wave_ticket(r.counter, 1u);
+        if (item >= r.n_items) break;
+        uint32_t j = 0;
+        while (j + 1 < r.n_segs && segs[j + 1].item0 <= item) j++;
+        const DevGraph g = load_const(&r.segs[j].g);
+        const BpLaunch a = load_const(&r.segs[j].a);
+        run_item<F, SLAB_LDS, FLOOD>(g, a, item - segs[j].item0, lds, x);
         __syncthreads();
     }
 }
@@ -589,13 +657,27 @@ __global__ void zero_kernel(uint32_t* p, size_t words) {
 }
 
 template <class F, bool FLOOD>
-const void* kernel_for_t(bool slab_in_lds) {
+const void* kernel_for_t(bool slab_in_lds, bool ragged) {
+    if (ragged)
+        return slab_in_lds ? (const void*)bp_ragged_kernel<F, true, FLOOD> : (const void*)bp_ragged_kernel<F, false, FLOOD>;
     return slab_in_lds ? (const void*)bp_ensemble_kernel<F, true, FLOOD> : (const void*)bp_ensemble_kernel<F, false, FLOOD>;
 }
 
-const void* kernel_for(const DevGraph& g, bool slab_in_lds) {
-    if (g.fp64) return g.flood ? kernel_for_t<double, true>(slab_in_lds) : kernel_for_t<double, false>(slab_in_lds);
-    return g.flood ? kernel_for_t<float, true>(slab_in_lds) : kernel_for_t<float, false>(slab_in_lds);
+const void* kernel_for(bool fp64, bool flood, bool slab_in_lds, bool ragged) {
+    if (fp64) return flood ? kernel_for_t<double, true>(slab_in_lds, ragged) : kernel_for_t<double, false>(slab_in_lds, ragged);
+    return flood ? kernel_for_t<float, true>(slab_in_lds, ragged) : kernel_for_t<float, false>(slab_in_lds, ragged);
+}
+
+int launch_fn(const void* fn, int grid, size_t lds, void** args, hipStream_t st) {
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(bp)");
+    }
+    hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kWave), args, lds, st);
+    if (e != hipSuccess) return hip_fail(e, "bp kernel launch");
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "bp kernel launch");
+    return VIBE_OK;
 }
 
 }  // namespace
@@ -613,7 +695,7 @@ size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds) {
 
 bool bp_slab_fits_lds(const DevGraph& g) { return bp_lds_bytes(g, true) <= 96 * 1024; }
 
-int bp_grid(const DevGraph& g, bool slab_in_lds) {
+int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged) {
     static int cached_cus = 0;
     if (!cached_cus) {
         int dev = 0;
@@ -622,28 +704,27 @@ int bp_grid(const DevGraph& g, bool slab_in_lds) {
         if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
         cached_cus = prop.multiProcessorCount;
     }
-    const size_t lds = bp_lds_bytes(g, slab_in_lds);
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(g, slab_in_lds), kWave, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(fp64, flood, slab_in_lds, ragged),
+                                                                kWave, lds_bytes);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     if (per_cu > 32) per_cu = 32;
     return per_cu * cached_cus;
 }
 
+int bp_grid(const DevGraph& g, bool slab_in_lds) {
+    return bp_grid_for(g.fp64 != 0, g.flood != 0, slab_in_lds, bp_lds_bytes(g, slab_in_lds), false);
+}
+
 int launch_bp(const DevGraph& g, const BpLaunch& a, hipStream_t st) {
     const bool in_lds = a.slab_in_lds != 0;
-    const size_t lds = bp_lds_bytes(g, in_lds);
-    const void* fn = kernel_for(g, in_lds);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(bp)");
-    }
     void* args[] = {const_cast<DevGraph*>(&g), const_cast<BpLaunch*>(&a)};
-    hipError_t le = hipLaunchKernel(fn, dim3(a.grid), dim3(kWave), args, lds, st);
-    if (le != hipSuccess) return hip_fail(le, "bp_ensemble_kernel launch");
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "bp_ensemble_kernel launch");
-    return VIBE_OK;
+    return launch_fn(kernel_for(g.fp64 != 0, g.flood != 0, in_lds, false), a.grid, bp_lds_bytes(g, in_lds), args, st);
+}
+
+int launch_bp_ragged(const RaggedLaunch& r, hipStream_t st) {
+    void* args[] = {const_cast<RaggedLaunch*>(&r)};
+    return launch_fn(kernel_for(r.fp64 != 0, r.flood != 0, r.slab_in_lds != 0, true), r.grid, r.lds_bytes, args, st);
 }
 
 int launch_zero(void* p, size_t bytes, hipStream_t st) {

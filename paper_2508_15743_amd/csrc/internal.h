@@ -117,6 +117,11 @@ struct vibe_graph {
     vibe::GraphHost h;
     vibe::Workspace ws;
     int device = 0;
+    // launch settings chosen by vibe_autotune: slab in LDS (-1 = not tuned,
+    // use LDS whenever it fits; 0 = global; 1 = LDS) and BP grid (0 = full
+    // occupancy)
+    int tune_lds = -1;
+    int tune_grid = 0;
     // kernel timing (vibe_profile_enable): event pairs per kernel class
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
@@ -157,6 +162,30 @@ struct BpLaunch {
     int slab_in_lds;           // which kernel variant to launch
 };
 int launch_bp(const DevGraph& g, const BpLaunch& a, hipStream_t st);
+
+// Ragged batching: one BP launch over the items of several requests, each on
+// its own graph (all with the same message precision and schedule).
+struct BpSeg {
+    DevGraph g;
+    BpLaunch a;       // that request's inputs and outputs (slab fields unused)
+    uint32_t item0;   // its first item in the launch's numbering
+};
+struct RaggedLaunch {
+    const BpSeg* segs;     // device array, n_segs entries, item0 ascending
+    uint32_t n_segs;
+    uint32_t n_items;      // total over the segments
+    void* slab;            // bp_slabs x grid x slab_elems
+    void* post_slab;       // grid x post_elems
+    uint32_t slab_elems;   // largest max_chunks * 64 over the segments
+    uint32_t post_elems;   // largest n + 64 over the segments
+    uint32_t* counter;
+    int grid;
+    int slab_in_lds;
+    int fp64, flood;
+    size_t lds_bytes;      // largest bp_lds_bytes over the segments
+};
+int launch_bp_ragged(const RaggedLaunch& r, hipStream_t st);
+int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged);
 int bp_grid(const DevGraph& g, bool slab_in_lds);
 size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds);
 int bp_slabs(const DevGraph& g);  // slabs per block: 1 (serial), 2 (parallel: states and messages)
