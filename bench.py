@@ -9,8 +9,11 @@ circuits and data.
 
 One step = vibe_decode over one batch of B shots (all of BP ensemble,
 selection, LSD and observables), syndromes already resident in HBM.
-Prints one JSON line.  Extra legs: a ragged batch of circuit-level codes at
-d = 5..13 (rounds = d) decoded as one call against one call per code;
+Prints one JSON line.  Extra legs: serving (continuous batching of one-shot
+requests from circuit-level codes d = 9, 13, 5 mixed 50/30/20, Poisson
+arrivals at 0.5x and 0.8x the sustained rate, p50/p99 latency); a ragged
+batch of circuit-level codes at d = 5..13 (rounds = d) decoded as one call
+against one call per code;
 BP+LSD-0 without ensembling (one member,
 parallel schedule) on the same batch, with LSD calls and largest-cluster
 sizes beside VibeLSD's (the comparison of the paper's Sec. IV.H); the
@@ -98,6 +101,73 @@ def ragged_leg(P, torch, shots, seed):
     return res
 
 
+def serving_leg(P, torch, seed, seconds):
+    """One-shot requests (one window of d rounds each) from circuit-level codes
+    d = 9, 13, 5 at p = 1e-3, mixed 50/30/20, through the continuous-batching
+    server: the sustained rate of a burst, then Poisson arrivals at 0.5x and
+    0.8x that rate with p50/p99 latency from submission to completion."""
+    import threading
+
+    from synth.dem import circuit_dem
+    from synth.sample import permutations, sample
+
+    cfgs = [(9, 32, 5, 20, 0.5), (13, 64, 7, 25, 0.3), (5, 32, 5, 20, 0.2)]
+    rng = np.random.default_rng(seed)
+    graphs, pools = [], []
+    for d, L, M, T, _ in cfgs:
+        dem = circuit_dem(d, d, 1e-3)
+        graphs.append(P.Graph.from_dem(dem, permutations(dem.n, L, seed + d), L=L, M=M, T_max=T, alpha=0.625))
+        pools.append(torch.from_numpy(sample(dem, 4096, seed + 300 + d).syndromes).to("cuda:0"))
+    torch.cuda.synchronize()
+    weights = np.array([c[4] for c in cfgs])
+    srv = P.Server(graphs, slots=3, max_batch_requests=512, max_batch_shots=1024)
+
+    def run(n, rate):
+        which = rng.choice(len(cfgs), size=n, p=weights / weights.sum())
+        gaps = rng.exponential(1.0 / rate, size=n) if rate else np.zeros(n)
+        tickets = [None] * n
+        t0 = time.perf_counter()
+
+        def producer():
+            t_next = time.perf_counter()
+            for i in range(n):
+                t_next += gaps[i]
+                while rate and time.perf_counter() < t_next:
+                    pass
+                g = int(which[i])
+                tickets[i] = srv.submit(g, pools[g][i % 4096:i % 4096 + 1])[0]
+
+        th = threading.Thread(target=producer)
+        th.start()
+        lat = []
+        for i in range(n):
+            while tickets[i] is None:
+                time.sleep(1e-5)
+            lat.append(srv.wait(tickets[i]))
+        th.join()
+        return n / (time.perf_counter() - t0), np.array(lat)
+
+    run(256, 0)  # warm-up
+    sustained, lat_burst = run(3000, 0)
+    res = {"codes": [f"circuit_d{d}_r{d}_p0.001" for d, *_ in cfgs], "mix": [c[4] for c in cfgs],
+           "request": "one shot", "slots": 3, "sustained_requests_per_s": round(sustained, 1), "loads": []}
+    for rho in (0.5, 0.8):
+        rate = rho * sustained
+        n = max(200, int(rate * seconds))
+        got, lat = run(n, rate)
+        res["loads"].append({"offered": rho, "offered_requests_per_s": round(rate, 1),
+                             "achieved_requests_per_s": round(got, 1),
+                             "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                             "p99_ms": round(float(np.percentile(lat, 99)), 3)})
+        log(f"serving at {rho:.1f}x of {sustained:.0f} req/s: p50 {np.percentile(lat, 50):.2f} ms, "
+            f"p99 {np.percentile(lat, 99):.2f} ms")
+    res.update(srv.info())
+    srv.close()
+    for G in graphs:
+        G.close()
+    return res
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -117,6 +187,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=3.0, help="length of each offered-load run")
     ap.add_argument("--ragged-shots", type=str, default="128,1024", help="shots per code in the ragged leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (calibrates HBM byte counters)")
@@ -253,6 +325,8 @@ def main():
 
     if not args.no_ragged:
         result["ragged"] = [ragged_leg(P, torch, int(k), args.seed) for k in args.ragged_shots.split(",")]
+    if not args.no_serving:
+        result["serving"] = serving_leg(P, torch, args.seed, args.serving_seconds)
 
     result["plain"] = None
     result["batched_over_plain"] = None

@@ -230,6 +230,42 @@ void vibe_exec_destroy(vibe_exec* ex); /* synchronises the device first; NULL ac
 int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B, void* stream, int* slab_in_lds, int* grid);
 
 /*
+ * Serving: continuous batching over resident graphs.  vibe_server_submit
+ * queues one request (any number of shots, up to max_batch_shots) on graph
+ * graphs[graph_index] and returns at once; a server thread keeps up to
+ * `slots` batches in flight, each on its own stream, and whenever a slot is
+ * free launches the queued requests that fit it (first come, first served)
+ * as one ragged round, so requests arriving while others run are admitted as
+ * slots free up and their work overlaps on the device.  Every request's
+ * outputs are exactly those of vibe_decode on it alone.  vibe_server_wait
+ * blocks until the request is done and gives its latency from submission to
+ * completion (host clock, ms).  The server holds slots x slot_bytes of
+ * device memory from creation to destruction; creation fails with
+ * VIBE_ENOMEM when that exceeds hbm_budget (0 = no limit).  A request's
+ * syndromes must already be on the device when it is submitted (the
+ * server's streams do not wait for the caller's), and its buffers must stay
+ * valid until its wait returns.  Submit and wait may be called from any
+ * thread.
+ */
+typedef struct vibe_server vibe_server;
+
+typedef struct vibe_server_config {
+    uint32_t slots;              /* batches in flight, 1..16 */
+    uint32_t max_batch_requests; /* requests per batch */
+    uint32_t max_batch_shots;    /* shots per batch (and per request) */
+    uint32_t reserved;           /* set to 0 */
+    uint64_t hbm_budget;         /* bytes of workspace the server may hold, 0 = any */
+} vibe_server_config;
+
+int vibe_server_create(vibe_graph* const* graphs, uint32_t n_graphs, const vibe_server_config* cfg,
+                       vibe_server** out);
+int vibe_server_submit(vibe_server* s, uint32_t graph_index, const uint8_t* syndromes, uint64_t B,
+                       uint64_t* corrections, uint8_t* observables, vibe_shot_stats* stats, uint64_t* ticket);
+int vibe_server_wait(vibe_server* s, uint64_t ticket, double* latency_ms);
+int vibe_server_info(vibe_server* s, uint64_t* batches, uint64_t* requests, uint64_t* slot_bytes);
+void vibe_server_destroy(vibe_server* s); /* finishes every queued request first; NULL accepted */
+
+/*
  * Kernel timing, for measurement: while enabled, every launch of the BP
  * ensemble kernel, of the selection kernel and of the LSD kernel made through
  * this handle is bracketed by HIP events recorded on the launch stream.

@@ -48,6 +48,11 @@ class vibe_request(C.Structure):
                 ("corrections", C.c_void_p), ("observables", C.c_void_p), ("stats", C.c_void_p)]
 
 
+class vibe_server_config(C.Structure):
+    _fields_ = [("slots", C.c_uint32), ("max_batch_requests", C.c_uint32), ("max_batch_shots", C.c_uint32),
+                ("reserved", C.c_uint32), ("hbm_budget", C.c_uint64)]
+
+
 _lib = None
 
 EXPORTS = {
@@ -74,6 +79,14 @@ EXPORTS = {
     "vibe_exec_destroy": (None, [C.c_void_p]),
     "vibe_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(C.c_int),
                                 C.POINTER(C.c_int)]),
+    "vibe_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_uint32, C.POINTER(vibe_server_config),
+                                     C.POINTER(C.c_void_p)]),
+    "vibe_server_submit": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.POINTER(C.c_uint64)]),
+    "vibe_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_double)]),
+    "vibe_server_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                   C.POINTER(C.c_uint64)]),
+    "vibe_server_destroy": (None, [C.c_void_p]),
     "vibe_last_error": (C.c_char_p, []),
     "vibe_version": (C.c_char_p, []),
 }
@@ -387,6 +400,61 @@ class Exec:
         if getattr(self, "handle", None):
             vibe_exec_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous batching over resident graphs.  submit() queues a request
+    (device syndromes, ready when submitted) and returns a ticket at once;
+    wait(ticket) blocks until it is decoded and returns its latency in ms.
+    Outputs are exactly those of Graph.decode on the request alone."""
+
+    def __init__(self, graphs, slots=3, max_batch_requests=256, max_batch_shots=4096, hbm_budget=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libvibelsd needs a ROCm GPU (torch.cuda is not available)")
+        self.graphs = list(graphs)
+        arr = (C.c_void_p * len(self.graphs))(*[G.handle.value for G in self.graphs])
+        cfg = vibe_server_config(slots, max_batch_requests, max_batch_shots, 0, hbm_budget)
+        out = C.c_void_p()
+        _check(lib().vibe_server_create(arr, len(self.graphs), C.byref(cfg), C.byref(out)))
+        self.handle = out
+        self._held = {}
+
+    def submit(self, index, syndromes, out=None):
+        """-> (ticket, (corrections, observables, stats))"""
+        G = self.graphs[index]
+        s = G._synd(syndromes)
+        o = out or Runtime.outputs(G, s)
+        t = C.c_uint64()
+        _check(lib().vibe_server_submit(self.handle, index, _ptr(s), s.shape[0], _ptr(o[0]), _ptr(o[1]),
+                                        _ptr(o[2]), C.byref(t)))
+        self._held[t.value] = (s, o)
+        return t.value, o
+
+    def wait(self, ticket):
+        ms = C.c_double()
+        try:
+            _check(lib().vibe_server_wait(self.handle, ticket, C.byref(ms)))
+        finally:
+            self._held.pop(ticket, None)
+        return ms.value
+
+    def info(self):
+        b, r, sb = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check(lib().vibe_server_info(self.handle, C.byref(b), C.byref(r), C.byref(sb)))
+        return {"batches": b.value, "requests": r.value, "slot_bytes": sb.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().vibe_server_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
 
     def __del__(self):
         try:

@@ -6,7 +6,13 @@
 // results are those of vibe_decode on that request alone: every kernel's
 // output for a shot depends only on that shot's syndrome and graph.
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
@@ -14,6 +20,9 @@
 struct vibe_runtime {
     int device = 0;
     vibe::Workspace ws;
+    // host copy of the last segment table: kept until its upload has run
+    std::vector<vibe::BpSeg> table;
+    hipEvent_t table_done = nullptr;
 };
 
 struct vibe_exec {
@@ -25,7 +34,36 @@ struct vibe_exec {
 
 namespace vibe {
 
+// One device-to-device copy of a list (server gather and scatter).
+struct CopyEntry {
+    const unsigned char* src;
+    unsigned char* dst;
+    uint64_t bytes;
+};
+
 namespace {
+
+// gridDim.x entries, gridDim.y blocks per entry
+__global__ void copy_entries_kernel(const CopyEntry* tab) {
+    const CopyEntry e = tab[blockIdx.x];
+    const uint64_t step = (uint64_t)blockDim.x * gridDim.y;
+    const uint64_t start = (uint64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    const bool w8 = ((reinterpret_cast<uintptr_t>(e.src) | reinterpret_cast<uintptr_t>(e.dst) | e.bytes) & 7) == 0;
+    if (w8) {
+        const uint64_t* s8 = reinterpret_cast<const uint64_t*>(e.src);
+        uint64_t* d8 = reinterpret_cast<uint64_t*>(e.dst);
+        for (uint64_t i = start; i < e.bytes / 8; i += step) d8[i] = s8[i];
+    } else {
+        for (uint64_t i = start; i < e.bytes; i += step) e.dst[i] = e.src[i];
+    }
+}
+
+int launch_copies(const CopyEntry* dev_tab, uint32_t n, hipStream_t st) {
+    if (!n) return VIBE_OK;
+    hipLaunchKernelGGL(copy_entries_kernel, dim3(n, 8), dim3(256), 0, st, dev_tab);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? VIBE_OK : hip_fail(e, "copy_entries_kernel launch");
+}
 
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -119,6 +157,14 @@ std::vector<Round> plan(const vibe_request* reqs, uint32_t n_reqs, size_t budget
     }
     if (!cur.segs.empty()) rounds.push_back(cur);
     for (Round& r : rounds) {
+        // longest items first (edges x iteration limit), so that the long
+        // serial chains do not start last and leave the GPU idle in the
+        // round's tail; results do not depend on the order
+        std::stable_sort(r.segs.begin(), r.segs.end(), [&](const Seg& a, const Seg& b) {
+            const DevGraph& ga = reqs[a.req].graph->h.dg;
+            const DevGraph& gb = reqs[b.req].graph->h.dg;
+            return (uint64_t)ga.E * ga.T > (uint64_t)gb.E * gb.T;
+        });
         bool lds_ok = true;
         bool fp64 = false, flood = false;
         size_t lds_global = 0, lds_l = 0;
@@ -298,6 +344,7 @@ extern "C" int vibe_runtime_create(vibe_runtime** out) {
 extern "C" void vibe_runtime_destroy(vibe_runtime* rt) {
     if (!rt) return;
     (void)hipDeviceSynchronize();
+    if (rt->table_done) (void)hipEventDestroy(rt->table_done);
     if (rt->ws.base) (void)hipFree(rt->ws.base);
     delete rt;
 }
@@ -315,11 +362,20 @@ extern "C" int vibe_decode_ragged(vibe_runtime* rt, const vibe_request* reqs, ui
     if (!need) return VIBE_OK;
     if ((rc = grow(rt->ws, need))) return rc;
     unsigned char* base = static_cast<unsigned char*>(rt->ws.base);
+    if (!rt->table_done) {
+        hipError_t e = hipEventCreateWithFlags(&rt->table_done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
     for (const Round& r : rounds) {
-        std::vector<BpSeg> t = seg_table(reqs, r, base);
-        // pageable source: the call returns once the table has been taken
-        hipError_t e = hipMemcpyAsync(base + r.segs_off, t.data(), sizeof(BpSeg) * t.size(), hipMemcpyHostToDevice, st);
+        // the previous upload from the host table must have run before the
+        // table is rewritten
+        hipError_t e = hipEventSynchronize(rt->table_done);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        rt->table = seg_table(reqs, r, base);
+        e = hipMemcpyAsync(base + r.segs_off, rt->table.data(), sizeof(BpSeg) * rt->table.size(),
+                           hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(segment table)");
+        if ((e = hipEventRecord(rt->table_done, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         if ((rc = run_round(reqs, r, base, st))) return rc;
     }
     return VIBE_OK;
@@ -450,4 +506,353 @@ extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B
     if (slab_in_lds) *slab_in_lds = best_lds;
     if (grid) *grid = best_grid;
     return VIBE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Serving: continuous batching over resident graphs.
+//
+// Requests are queued by vibe_server_submit.  A server thread keeps up to
+// `slots` batches in flight, each on its own stream with its own
+// preallocated workspace: whenever a slot is free it takes the queued
+// requests (first come, first served) that fit the slot's workspace and
+// launches them as one ragged round, so requests that arrive while other
+// batches run are admitted as soon as a slot frees up and their work
+// overlaps on the device.  HBM held by the server is bounded by slots x
+// slot workspace, fixed at creation.
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct SrvReq {
+    uint64_t ticket;
+    uint32_t gi;  // graph index
+    vibe_request req;
+    Clock::time_point t_submit;
+};
+
+struct SrvSlot {
+    hipStream_t st = nullptr;
+    hipEvent_t done = nullptr;
+    vibe::Workspace ws;       // decode workspace, then staging and copy tables
+    std::vector<uint64_t> tickets;
+    bool busy = false;
+    // host tables of the batch in flight (kept until the slot retires)
+    std::vector<vibe::BpSeg> segs;
+    std::vector<vibe::CopyEntry> copies;
+};
+
+struct SrvDone {
+    bool done = false;
+    int rc = VIBE_OK;
+    double latency_ms = 0.0;
+};
+
+}  // namespace
+
+struct vibe_server {
+    std::vector<vibe_graph*> graphs;
+    vibe_server_config cfg{};
+    int device = 0;
+    std::vector<SrvSlot> slots;
+    size_t slot_bytes = 0;
+    // slot layout: decode workspace [0, dec_bytes), then per graph the staged
+    // syndromes, corrections, observables and stats of a batch, then the
+    // copy table
+    size_t dec_bytes = 0, tab_off = 0;
+    std::vector<size_t> st_synd, st_corr, st_obs, st_stats;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<SrvReq> queue;
+    std::unordered_map<uint64_t, SrvDone> status;
+    std::unordered_map<uint64_t, Clock::time_point> t_submit;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread th;
+    uint64_t batches = 0, requests = 0;
+};
+
+namespace {
+
+// Workspace of a slot: room to decode max_batch_shots shots in one round,
+// whatever the mix of graphs, then staging of those shots per graph and the
+// gather / scatter table.
+void slot_layout(vibe_server& S) {
+    size_t worst = 0;
+    for (vibe_graph* G : S.graphs) {
+        vibe_request r{};
+        r.graph = G;
+        r.syndromes = reinterpret_cast<const uint8_t*>(1);
+        r.corrections = reinterpret_cast<uint64_t*>(1);
+        r.observables = reinterpret_cast<uint8_t*>(1);
+        r.B = S.cfg.max_batch_shots;
+        std::vector<vibe::Round> rs = vibe::plan(&r, 1, vibe::kRaggedBudget);
+        size_t most = 0;
+        for (const vibe::Round& x : rs) most = std::max(most, x.bytes);
+        // a mixed round needs at most every graph's own round at full size
+        worst += most;
+    }
+    // one segment per graph in a mixed round: alignment and table slack
+    size_t off = worst + (size_t)(S.graphs.size() + 2) * (16 * 256 + sizeof(vibe::BpSeg));
+    off = vibe::al256(off);
+    S.dec_bytes = off;
+    const uint64_t B = S.cfg.max_batch_shots;
+    for (vibe_graph* G : S.graphs) {
+        const vibe::DevGraph& g = G->h.dg;
+        S.st_synd.push_back(off);
+        off += vibe::al256(B * g.m);
+        S.st_corr.push_back(off);
+        off += vibe::al256(B * 8ull * g.words_n);
+        S.st_obs.push_back(off);
+        off += vibe::al256(B * std::max<uint32_t>(g.k, 1));
+        S.st_stats.push_back(off);
+        off += vibe::al256(B * sizeof(vibe_shot_stats));
+    }
+    S.tab_off = off;
+    off += vibe::al256(sizeof(vibe::CopyEntry) * 4ull * S.cfg.max_batch_requests);
+    S.slot_bytes = off;
+}
+
+void server_loop(vibe_server* S) {
+    (void)hipSetDevice(S->device);
+    for (;;) {
+        std::vector<SrvReq> batch;
+        int slot = -1;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            // retire finished batches
+            for (SrvSlot& sl : S->slots) {
+                if (!sl.busy) continue;
+                hipError_t q = hipEventQuery(sl.done);
+                if (q == hipErrorNotReady) continue;
+                const auto now = Clock::now();
+                for (uint64_t t : sl.tickets) {
+                    SrvDone& d = S->status[t];
+                    d.done = true;
+                    d.rc = q == hipSuccess ? VIBE_OK : VIBE_EHIP;
+                    d.latency_ms = std::chrono::duration<double, std::milli>(now - S->t_submit[t]).count();
+                    S->t_submit.erase(t);
+                }
+                sl.tickets.clear();
+                sl.busy = false;
+                S->cv_done.notify_all();
+            }
+            bool any_busy = false;
+            for (size_t i = 0; i < S->slots.size(); i++) {
+                if (!S->slots[i].busy && slot < 0) slot = (int)i;
+                any_busy = any_busy || S->slots[i].busy;
+            }
+            if (S->stop && S->queue.empty() && !any_busy) return;
+            if (slot < 0 || S->queue.empty()) {
+                // wait for a submission, or poll the slots in flight
+                S->cv_work.wait_for(lk, std::chrono::microseconds(any_busy ? 20 : 2000));
+                continue;
+            }
+            // admit queued requests, first come first served, while the
+            // round fits the slot's workspace
+            uint64_t shots = 0;
+            while (!S->queue.empty() && batch.size() < S->cfg.max_batch_requests) {
+                const SrvReq& r = S->queue.front();
+                if (!batch.empty() && shots + r.req.B > S->cfg.max_batch_shots) break;
+                batch.push_back(r);
+                shots += r.req.B;
+                S->queue.pop_front();
+            }
+        }
+        // Launch outside the lock: gather the batch's syndromes into one
+        // contiguous block per graph, decode one segment per graph, scatter
+        // the outputs back to the requests' buffers.
+        SrvSlot& sl = S->slots[slot];
+        unsigned char* base = static_cast<unsigned char*>(sl.ws.base);
+        const size_t G = S->graphs.size();
+        std::vector<uint64_t> rows(G, 0);
+        std::vector<vibe_request> per(G);
+        sl.copies.clear();
+        std::vector<vibe::CopyEntry> scatter;
+        for (const SrvReq& r : batch) {
+            const vibe::DevGraph& g = r.req.graph->h.dg;
+            const uint64_t r0 = rows[r.gi];
+            rows[r.gi] += r.req.B;
+            if (!r.req.B) continue;
+            sl.copies.push_back({r.req.syndromes, base + S->st_synd[r.gi] + r0 * g.m, r.req.B * g.m});
+            const uint64_t cw = 8ull * g.words_n;
+            scatter.push_back({base + S->st_corr[r.gi] + r0 * cw, reinterpret_cast<unsigned char*>(r.req.corrections),
+                               r.req.B * cw});
+            if (g.k)
+                scatter.push_back({base + S->st_obs[r.gi] + r0 * g.k, r.req.observables, r.req.B * g.k});
+            if (r.req.stats)
+                scatter.push_back({base + S->st_stats[r.gi] + r0 * sizeof(vibe_shot_stats),
+                                   reinterpret_cast<unsigned char*>(r.req.stats), r.req.B * sizeof(vibe_shot_stats)});
+        }
+        const uint32_t n_gather = (uint32_t)sl.copies.size();
+        sl.copies.insert(sl.copies.end(), scatter.begin(), scatter.end());
+        std::vector<vibe_request> reqs;
+        for (size_t gi = 0; gi < G; gi++) {
+            if (!rows[gi]) continue;
+            vibe_request q{};
+            q.graph = S->graphs[gi];
+            q.syndromes = base + S->st_synd[gi];
+            q.B = rows[gi];
+            q.corrections = reinterpret_cast<uint64_t*>(base + S->st_corr[gi]);
+            q.observables = base + S->st_obs[gi];
+            q.stats = reinterpret_cast<vibe_shot_stats*>(base + S->st_stats[gi]);
+            reqs.push_back(q);
+        }
+        int rc = VIBE_OK;
+        vibe::CopyEntry* dtab = reinterpret_cast<vibe::CopyEntry*>(base + S->tab_off);
+        if (!reqs.empty()) {
+            std::vector<vibe::Round> rounds = vibe::plan(reqs.data(), (uint32_t)reqs.size(), vibe::kRaggedBudget);
+            if (rounds.size() != 1 || rounds[0].bytes > S->dec_bytes) {
+                rc = vibe::fail(VIBE_ENOMEM, "a batch exceeds the slot workspace");
+            } else {
+                const vibe::Round& rd = rounds[0];
+                sl.segs = vibe::seg_table(reqs.data(), rd, base);
+                hipError_t e = hipMemcpyAsync(dtab, sl.copies.data(), sizeof(vibe::CopyEntry) * sl.copies.size(),
+                                              hipMemcpyHostToDevice, sl.st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(base + rd.segs_off, sl.segs.data(), sizeof(vibe::BpSeg) * sl.segs.size(),
+                                       hipMemcpyHostToDevice, sl.st);
+                if (e != hipSuccess) rc = vibe::hip_fail(e, "hipMemcpyAsync(server tables)");
+                if (!rc) rc = vibe::launch_copies(dtab, n_gather, sl.st);
+                if (!rc) rc = vibe::run_round(reqs.data(), rd, base, sl.st);
+                if (!rc) rc = vibe::launch_copies(dtab + n_gather, (uint32_t)scatter.size(), sl.st);
+            }
+        }
+        std::unique_lock<std::mutex> lk(S->mu);
+        if (rc) {
+            for (const SrvReq& r : batch) {
+                SrvDone& d = S->status[r.ticket];
+                d.done = true;
+                d.rc = rc;
+                S->t_submit.erase(r.ticket);
+            }
+            S->cv_done.notify_all();
+            continue;
+        }
+        (void)hipEventRecord(sl.done, sl.st);
+        for (const SrvReq& r : batch) sl.tickets.push_back(r.ticket);
+        sl.busy = true;
+        S->batches++;
+        S->requests += batch.size();
+    }
+}
+
+}  // namespace
+
+extern "C" int vibe_server_create(vibe_graph* const* graphs, uint32_t n_graphs, const vibe_server_config* cfg,
+                                  vibe_server** out) {
+    set_error("");
+    if (!out || !graphs || !n_graphs || !cfg) return fail(VIBE_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (cfg->slots < 1 || cfg->slots > 16) return fail(VIBE_EINVAL, "slots must be in 1..16");
+    if (cfg->max_batch_shots < 1 || cfg->max_batch_requests < 1) return fail(VIBE_EINVAL, "batch limits must be >= 1");
+    for (uint32_t i = 0; i < n_graphs; i++) {
+        if (!graphs[i]) return fail(VIBE_EINVAL, "a graph is NULL");
+        const DevGraph& g = graphs[i]->h.dg;
+        const DevGraph& g0 = graphs[0]->h.dg;
+        if (g.fp64 != g0.fp64 || g.flood != g0.flood)
+            return fail(VIBE_EINVAL, "all graphs of a server need the same message_bits and schedule");
+    }
+    vibe_server* S = new (std::nothrow) vibe_server();
+    if (!S) return fail(VIBE_ENOMEM, "host allocation failed");
+    S->graphs.assign(graphs, graphs + n_graphs);
+    S->cfg = *cfg;
+    (void)hipGetDevice(&S->device);
+    slot_layout(*S);
+    if (cfg->hbm_budget && S->slot_bytes * cfg->slots > cfg->hbm_budget) {
+        delete S;
+        return fail(VIBE_ENOMEM, "slots x slot workspace exceed the HBM budget");
+    }
+    S->slots.resize(cfg->slots);
+    int rc = VIBE_OK;
+    for (SrvSlot& sl : S->slots) {
+        hipError_t e;
+        // default priority: streams of other priorities are avoided on purpose
+        if ((e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess) {
+            rc = hip_fail(e, "server stream or event");
+            break;
+        }
+        if ((rc = grow(sl.ws, S->slot_bytes))) break;
+    }
+    if (rc) {
+        for (SrvSlot& sl : S->slots) {
+            if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.st) (void)hipStreamDestroy(sl.st);
+            if (sl.ws.base) (void)hipFree(sl.ws.base);
+        }
+        delete S;
+        return rc;
+    }
+    S->th = std::thread(server_loop, S);
+    *out = S;
+    return VIBE_OK;
+}
+
+extern "C" int vibe_server_submit(vibe_server* S, uint32_t graph_index, const uint8_t* syndromes, uint64_t B,
+                                  uint64_t* corrections, uint8_t* observables, vibe_shot_stats* stats,
+                                  uint64_t* ticket) {
+    set_error("");
+    if (!S || !ticket) return fail(VIBE_EINVAL, "NULL argument");
+    if (graph_index >= S->graphs.size()) return fail(VIBE_EINVAL, "graph_index out of range");
+    if (B > S->cfg.max_batch_shots) return fail(VIBE_EINVAL, "a request is larger than max_batch_shots");
+    vibe_request r{};
+    r.graph = S->graphs[graph_index];
+    r.syndromes = syndromes;
+    r.B = B;
+    r.corrections = corrections;
+    r.observables = observables;
+    r.stats = stats;
+    int rc = check_requests(&r, 1);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return fail(VIBE_EINVAL, "the server is shutting down");
+    const uint64_t t = S->next_ticket++;
+    const auto now = Clock::now();
+    S->queue.push_back(SrvReq{t, graph_index, r, now});
+    S->t_submit[t] = now;
+    S->status[t] = SrvDone{};
+    *ticket = t;
+    S->cv_work.notify_one();
+    return VIBE_OK;
+}
+
+extern "C" int vibe_server_wait(vibe_server* S, uint64_t ticket, double* latency_ms) {
+    set_error("");
+    if (!S) return fail(VIBE_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->status.find(ticket);
+    if (it == S->status.end()) return fail(VIBE_EINVAL, "unknown ticket");
+    S->cv_done.wait(lk, [&] { return S->status[ticket].done; });
+    const SrvDone d = S->status[ticket];
+    S->status.erase(ticket);
+    if (latency_ms) *latency_ms = d.latency_ms;
+    if (d.rc) return fail(d.rc, "the batch of this request failed");
+    return VIBE_OK;
+}
+
+extern "C" int vibe_server_info(vibe_server* S, uint64_t* batches, uint64_t* requests, uint64_t* slot_bytes) {
+    if (!S) return fail(VIBE_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (batches) *batches = S->batches;
+    if (requests) *requests = S->requests;
+    if (slot_bytes) *slot_bytes = S->slot_bytes;
+    return VIBE_OK;
+}
+
+extern "C" void vibe_server_destroy(vibe_server* S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        S->cv_work.notify_all();
+    }
+    if (S->th.joinable()) S->th.join();
+    for (SrvSlot& sl : S->slots) {
+        if (sl.st) (void)hipStreamSynchronize(sl.st);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.st) (void)hipStreamDestroy(sl.st);
+        if (sl.ws.base) (void)hipFree(sl.ws.base);
+    }
+    delete S;
 }
