@@ -106,6 +106,53 @@ def bp(g: OracleGraph, s, perm=None, T=20, alpha=0.625, lim=1e6, stop=True, trac
             "min_abs_post": mn.value, "trace": tr}
 
 
+def bp_loss(g: OracleGraph, s, lam, alpha, K, perm=None, lim=1e6, eps=1e-7):
+    """Soft-syndrome loss after K unrolled iterations (or_bp_loss):
+    -> (loss, branch signature, final posteriors)."""
+    L = lib()
+    L.or_bp_loss.restype = C.c_double
+    s = np.ascontiguousarray(s, dtype=np.uint8)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    al = np.ascontiguousarray(np.broadcast_to(alpha, (K,)), dtype=np.float64)
+    pp = None if perm is None else np.ascontiguousarray(perm, dtype=np.uint32)
+    sig = C.c_uint64(0)
+    post = np.zeros(g.n, np.float64)
+    loss = L.or_bp_loss(*g.args(), _p(lam, F64), _p(s, U8), _p(pp, U32) if pp is not None else None,
+                        C.c_int(K), _p(al, F64), C.c_double(lim), C.c_double(eps), C.byref(sig),
+                        _p(post, F64))
+    return loss, sig.value, post
+
+
+def fd_grad(g: OracleGraph, s, lam, alpha, K, perm=None, h=1e-6, lim=1e6, eps=1e-7, idx=None):
+    """Reference gradient of bp_loss by central differences in FP64, with
+    respect to lam[v] (every v, or the v in idx; the others stay 0) and every
+    alpha[t].  Each entry comes with a flag: True where the branch signature
+    at +h and -h equals the one at the centre (the loss is smooth there, so
+    the difference quotient is the derivative to O(h^2))."""
+    lam = np.asarray(lam, dtype=np.float64)
+    al = np.asarray(np.broadcast_to(alpha, (K,)), dtype=np.float64).copy()
+    _, sig0, _ = bp_loss(g, s, lam, al, K, perm, lim, eps)
+    dl, okl = np.zeros(g.n), np.zeros(g.n, bool)
+    for v in (range(g.n) if idx is None else idx):
+        lp, lm = lam.copy(), lam.copy()
+        lp[v] += h
+        lm[v] -= h
+        fp, sp, _ = bp_loss(g, s, lp, al, K, perm, lim, eps)
+        fm, sm, _ = bp_loss(g, s, lm, al, K, perm, lim, eps)
+        dl[v] = (fp - fm) / (2 * h)
+        okl[v] = sp == sig0 and sm == sig0
+    da, oka = np.zeros(K), np.zeros(K, bool)
+    for t in range(K):
+        ap, am = al.copy(), al.copy()
+        ap[t] += h
+        am[t] -= h
+        fp, sp, _ = bp_loss(g, s, lam, ap, K, perm, lim, eps)
+        fm, sm, _ = bp_loss(g, s, lam, am, K, perm, lim, eps)
+        da[t] = (fp - fm) / (2 * h)
+        oka[t] = sp == sig0 and sm == sig0
+    return dl, okl, da, oka
+
+
 def lsd(g: OracleGraph, s, q):
     """LSD-0 on soft input q (lower = more likely flipped)."""
     L = lib()

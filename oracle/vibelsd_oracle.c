@@ -32,6 +32,8 @@ typedef struct {
     const int *rp, *ri; /* CSR: check c -> columns ri[rp[c] .. rp[c+1]) ascending */
     const int *cp, *ci; /* CSC: column v -> checks ci[cp[v] .. cp[v+1]) ascending */
     const int *ce;      /* for CSC entry j, the CSR position of the same edge */
+    uint64_t *sig;      /* if non-NULL: hash of every min-sum branch taken (argmin,
+                           sign parity, clamps); constant while the loss is smooth */
 } ograph;
 
 /* sign convention: a message is "negative" iff it is < 0, so +0 and -0 both
@@ -52,6 +54,14 @@ static int syndrome_matches(const ograph *g, const uint8_t *e, const uint8_t *s)
     return 1;
 }
 
+static void sig_mix(uint64_t *h, uint64_t x) { *h = (*h ^ x) * 0x100000001b3ull + 0x9e3779b97f4a7c15ull; }
+
+/* records in the signature that x is about to be clamped */
+static double clamp_sig(double x, double lim, uint64_t *sig) {
+    if (sig && (x > lim || x < -lim)) sig_mix(sig, 0xc1a3ull);
+    return x;
+}
+
 /* Check-to-variable message r_{c->v} from the current variable-to-check
    messages mu (indexed by CSR position), Algorithm 1's check update with the
    syndrome sign: (1 - 2 s_c) * alpha * prod sign * min |mu| over N(c)\v.
@@ -59,15 +69,19 @@ static int syndrome_matches(const ograph *g, const uint8_t *e, const uint8_t *s)
 static double check_to_var(const ograph *g, const double *mu, const uint8_t *s, int c, int v,
                            double alpha, double lim) {
     double mag = INFINITY;
-    int neg = 0, others = 0;
+    int neg = 0, others = 0, am = -1;
     for (int k = g->rp[c]; k < g->rp[c + 1]; k++) {
         if (g->ri[k] == v) continue;
         others++;
         double a = fabs(mu[k]);
-        if (a < mag) mag = a;
+        if (a < mag) {
+            mag = a;
+            am = g->ri[k];
+        }
         if (mu[k] < 0) neg ^= 1;
     }
     if (!others) mag = lim;
+    if (g->sig) sig_mix(g->sig, ((uint64_t)(uint32_t)am << 1) | (uint64_t)neg);
     double r = alpha * (neg ? -mag : mag);
     return s[c] ? -r : r;
 }
@@ -86,11 +100,11 @@ static double check_to_var(const ograph *g, const double *mu, const uint8_t *s, 
  * any decision taken), trace (if non-NULL: posteriors of every iteration,
  * [T][n], rows past the last iteration run are left untouched).
  */
-int or_bp(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci, const int *ce,
-          const double *lam, const uint8_t *s, const uint32_t *perm, int T, const double *alpha,
-          double lim, int stop_on_converge, int *t_conv, uint8_t *ehat, double *post, int *iters,
-          double *min_abs_post, double *trace) {
-    ograph g = {m, n, rp, ri, cp, ci, ce};
+static int bp_core(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci, const int *ce,
+                   const double *lam, const uint8_t *s, const uint32_t *perm, int T, const double *alpha,
+                   double lim, int stop_on_converge, int *t_conv, uint8_t *ehat, double *post, int *iters,
+                   double *min_abs_post, double *trace, uint64_t *sig) {
+    ograph g = {m, n, rp, ri, cp, ci, ce, sig};
     int E = rp[m];
     double *mu = (double *)malloc(sizeof(double) * (E ? E : 1));
     double *rv = (double *)malloc(sizeof(double) * (E ? E : 1)); /* r by CSC position */
@@ -118,12 +132,12 @@ int or_bp(int m, int n, const int *rp, const int *ri, const int *cp, const int *
                     rv[j] = check_to_var(&g, mu, s, ci[j], v, a, lim);
                 double L = lv;
                 for (int j = cp[v]; j < cp[v + 1]; j++) L += rv[j];
-                post[v] = clampd(L, lim);
+                post[v] = clampd(clamp_sig(L, lim, sig), lim);
                 for (int j = cp[v]; j < cp[v + 1]; j++) {
                     double x = lv;
                     for (int j2 = cp[v]; j2 < cp[v + 1]; j2++)
                         if (j2 != j) x += rv[j2];
-                    mu[ce[j]] = clampd(x, lim);
+                    mu[ce[j]] = clampd(clamp_sig(x, lim, sig), lim);
                 }
             }
         } else {
@@ -135,12 +149,12 @@ int or_bp(int m, int n, const int *rp, const int *ri, const int *cp, const int *
                 double lv = clampd(lam[v], lim);
                 double L = lv;
                 for (int j = cp[v]; j < cp[v + 1]; j++) L += rv[j];
-                post[v] = clampd(L, lim);
+                post[v] = clampd(clamp_sig(L, lim, sig), lim);
                 for (int j = cp[v]; j < cp[v + 1]; j++) {
                     double x = lv;
                     for (int j2 = cp[v]; j2 < cp[v + 1]; j2++)
                         if (j2 != j) x += rv[j2];
-                    mu[ce[j]] = clampd(x, lim);
+                    mu[ce[j]] = clampd(clamp_sig(x, lim, sig), lim);
                 }
             }
         }
@@ -161,6 +175,52 @@ int or_bp(int m, int n, const int *rp, const int *ri, const int *cp, const int *
     free(mu);
     free(rv);
     return 0;
+}
+
+int or_bp(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci, const int *ce,
+          const double *lam, const uint8_t *s, const uint32_t *perm, int T, const double *alpha,
+          double lim, int stop_on_converge, int *t_conv, uint8_t *ehat, double *post, int *iters,
+          double *min_abs_post, double *trace) {
+    return bp_core(m, n, rp, ri, cp, ci, ce, lam, s, perm, T, alpha, lim, stop_on_converge, t_conv, ehat,
+                   post, iters, min_abs_post, trace, NULL);
+}
+
+/*
+ * Soft-syndrome loss of K unrolled iterations (training objective of the
+ * differentiable decoder; the paper defines none).  The decoder runs exactly
+ * K iterations of Algorithm 1 (serial-V along perm, or parallel if perm is
+ * NULL) from the given channel LLRs lam[v] with scaling alpha[t-1] in
+ * iteration t.  With the final posteriors L_v, check c is violated with
+ * probability shat_c = (1 - prod_{v in N(c)} tanh(L_v / 2)) / 2 when the bits
+ * are independent with those LLRs; shat_c is clamped to [eps, 1 - eps] and
+ * the loss is the binary cross-entropy summed over the checks,
+ *   sum_c -[s_c ln shat_c + (1 - s_c) ln(1 - shat_c)].
+ * sig (nullable) receives the hash of every branch taken (argmins, sign
+ * parities, clamps); post (nullable, n) the final posteriors.
+ */
+double or_bp_loss(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci, const int *ce,
+                  const double *lam, const uint8_t *s, const uint32_t *perm, int K, const double *alpha,
+                  double lim, double eps, uint64_t *sig, double *post) {
+    double *L = (double *)malloc(sizeof(double) * (n ? n : 1));
+    uint8_t *e = (uint8_t *)malloc(n ? n : 1);
+    int tc = 0, it = 0;
+    if (sig) *sig = 0;
+    bp_core(m, n, rp, ri, cp, ci, ce, lam, s, perm, K, alpha, lim, 0, &tc, e, L, &it, NULL, NULL, sig);
+    double loss = 0.0;
+    for (int c = 0; c < m; c++) {
+        double prod = 1.0;
+        for (int k = rp[c]; k < rp[c + 1]; k++) prod *= tanh(L[ri[k]] / 2.0);
+        double sh = 0.5 * (1.0 - prod);
+        if (sh < eps || sh > 1.0 - eps) {
+            if (sig) sig_mix(sig, 0xe95ull + (uint64_t)c);
+            sh = sh < eps ? eps : 1.0 - eps;
+        }
+        loss -= s[c] ? log(sh) : log(1.0 - sh);
+    }
+    if (post) memcpy(post, L, sizeof(double) * n);
+    free(L);
+    free(e);
+    return loss;
 }
 
 /* ------------------------------------------------------------------------ */
