@@ -266,6 +266,23 @@ int vibe_server_info(vibe_server* s, uint64_t* batches, uint64_t* requests, uint
 void vibe_server_destroy(vibe_server* s); /* finishes every queued request first; NULL accepted */
 
 /*
+ * Differentiable decoder: gradient of the soft-syndrome loss of K unrolled
+ * iterations (the paper defines no training objective; this one is ours).
+ * Every member runs exactly K iterations of its schedule from the channel
+ * LLRs lam (device, n values) and scaling factors alpha (device, K values;
+ * alpha[t-1] in iteration t), both in the graph's message precision (float
+ * for message_bits 32, double for 64) instead of the graph's own.  With the
+ * final posteriors L_v, shat_c = (1 - prod_{v in N(c)} tanh(L_v / 2)) / 2 is
+ * clamped to [eps, 1 - eps] and the loss is the binary cross-entropy of s_c
+ * and shat_c summed over the checks.  Outputs (device, double): loss (1) =
+ * sum over the B x L (shot, member) items, dlam (n) and dalpha (K) = its
+ * gradient.  The gradient is exact wherever no argmin, sign or clamp changes
+ * (a piecewise-smooth function).  Deterministic.  B x L <= 2^24, K <= 64.
+ */
+int vibe_bp_grad(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint32_t K, const void* lam,
+                 const void* alpha, double eps, double* loss, double* dlam, double* dalpha, void* stream);
+
+/*
  * Kernel timing, for measurement: while enabled, every launch of the BP
  * ensemble kernel, of the selection kernel and of the LSD kernel made through
  * this handle is bracketed by HIP events recorded on the launch stream.

@@ -69,6 +69,8 @@ EXPORTS = {
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vibe_lsd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
+    "vibe_bp_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_void_p, C.c_void_p,
+                               C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vibe_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "vibe_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "vibe_runtime_create": (C.c_int, [C.POINTER(C.c_void_p)]),
@@ -169,6 +171,11 @@ def vibe_bp_ensemble(handle, syndromes, B, T_run, stop, t_conv, posteriors, ehat
 def vibe_lsd(handle, syndromes, soft, B, corrections, stats, stream):
     _check(lib().vibe_lsd(handle, _ptr(syndromes), _ptr(soft), B, _ptr(corrections), _ptr(stats),
                           stream))
+
+
+def vibe_bp_grad(handle, syndromes, B, K, lam, alpha, eps, loss, dlam, dalpha, stream):
+    _check(lib().vibe_bp_grad(handle, _ptr(syndromes), B, K, _ptr(lam), _ptr(alpha), eps, _ptr(loss),
+                              _ptr(dlam), _ptr(dalpha), stream))
 
 
 def vibe_runtime_create():
@@ -343,6 +350,65 @@ def _graph_autotune(self, syndromes, stream=None):
 
 
 Graph.autotune = _graph_autotune
+
+
+def _graph_bp_grad(self, syndromes, lam, alpha, eps=1e-7, stream=None):
+    """Soft-syndrome loss of len(alpha) unrolled iterations of every member,
+    summed over shots and members, and its gradient
+    -> (loss [1], dlam [n], dalpha [K]), float64 device tensors.  lam and
+    alpha are cast to the message precision (float32, or float64 when
+    message_bits is 64)."""
+    import torch
+    s = self._synd(syndromes)
+    dev = s.device
+    pdt = torch.float64 if self.message_bits == 64 else torch.float32
+    lam = lam.detach().to(device=dev, dtype=pdt).contiguous()
+    alpha = alpha.detach().to(device=dev, dtype=pdt).contiguous()
+    if lam.shape != (self.n,) or alpha.dim() != 1:
+        raise ValueError(f"lam must have shape [{self.n}] and alpha one dimension")
+    K = alpha.shape[0]
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    dlam = torch.empty(self.n, dtype=torch.float64, device=dev)
+    dalpha = torch.empty(K, dtype=torch.float64, device=dev)
+    vibe_bp_grad(self.handle, s, s.shape[0], K, lam, alpha, eps, loss, dlam, dalpha, _stream(stream))
+    return loss, dlam, dalpha
+
+
+Graph.bp_grad = _graph_bp_grad
+
+
+def _autograd_fn():
+    import torch
+
+    class BpLoss(torch.autograd.Function):
+        """loss = BpLoss.apply(graph, syndromes, lam, alpha, eps): the loss
+        and its gradient come from one vibe_bp_grad call; backward scales
+        the stored gradient."""
+
+        @staticmethod
+        def forward(ctx, graph, syndromes, lam, alpha, eps=1e-7):
+            loss, dlam, dalpha = graph.bp_grad(syndromes, lam, alpha, eps)
+            ctx.save_for_backward(dlam.to(lam.dtype), dalpha.to(alpha.dtype))
+            return loss[0].to(lam.dtype)
+
+        @staticmethod
+        def backward(ctx, g):
+            dlam, dalpha = ctx.saved_tensors
+            return None, None, g * dlam, g * dalpha, None
+
+    return BpLoss
+
+
+def bp_loss(graph, syndromes, lam, alpha, eps=1e-7):
+    """Differentiable soft-syndrome loss of the unrolled ensemble (see
+    Graph.bp_grad); gradients flow to lam and alpha."""
+    global _BpLoss
+    if _BpLoss is None:
+        _BpLoss = _autograd_fn()
+    return _BpLoss.apply(graph, syndromes, lam, alpha, eps)
+
+
+_BpLoss = None
 
 
 class Runtime:

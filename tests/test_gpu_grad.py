@@ -1,0 +1,174 @@
+"""The differentiable decoder (vibe_bp_grad) against the oracle.
+
+The loss is the oracle's or_bp_loss summed over shots and ensemble members;
+the gradient is checked against the oracle's central differences on every
+entry the oracle flags smooth (no argmin, sign or clamp switches within the
+step).  In FP64 the unrolled iterations follow the oracle's operation order,
+so the loss agrees to rounding and the gradient to the difference quotient's
+own error.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth.dem import circuit_dem, code_capacity_dem
+from synth.sample import permutations, sample
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_15743_amd as P
+
+    P.lib()
+    return torch
+
+
+def _inputs(dem, B, K, seed):
+    rng = np.random.default_rng(seed)
+    lam = np.log(1 / rng.uniform(0.01, 0.2, dem.n) - 1)  # distinct LLRs: no ties at the first iteration
+    alpha = rng.uniform(0.5, 1.0, K)
+    synd = sample(dem, B, seed + 1).syndromes
+    return lam, alpha, synd
+
+
+def _oracle(dem, synd, lam, alpha, K, perms, idx=None):
+    """Summed loss and FD gradient over shots x members, with the flags
+    AND-ed over every item."""
+    g = O.OracleGraph(dem)
+    loss, dl, da = 0.0, np.zeros(dem.n), np.zeros(K)
+    okl, oka = np.ones(dem.n, bool), np.ones(K, bool)
+    for s in synd:
+        for perm in (perms if perms is not None else [None]):
+            loss += O.bp_loss(g, s, lam, alpha, K, perm)[0]
+            a, b, c, d = O.fd_grad(g, s, lam, alpha, K, perm, idx=idx)
+            dl += a
+            da += c
+            okl &= b
+            oka &= d
+    if idx is not None:
+        sel = np.zeros(dem.n, bool)
+        sel[idx] = True
+        okl &= sel
+    return loss, dl, okl, da, oka
+
+
+def _graph(P, dem, L, schedule, bits, seed=3):
+    perms = permutations(dem.n, L, seed)
+    G = P.Graph.from_dem(dem, perms, L=L, M=1, T_max=8, schedule=schedule, message_bits=bits)
+    return G, (perms if schedule == "serial" else None)
+
+
+def _run(torch, G, synd, lam, alpha, bits=64):
+    dt = torch.float64 if bits == 64 else torch.float32
+    loss, dl, da = G.bp_grad(torch.from_numpy(synd).cuda(), torch.tensor(lam, dtype=dt),
+                             torch.tensor(alpha, dtype=dt))
+    return loss.item(), dl.cpu().numpy(), da.cpu().numpy()
+
+
+def _close(got, want, ok, tol):
+    assert ok.sum() > 0
+    err = np.abs(got - want)[ok] / np.maximum(1.0, np.abs(want)[ok])
+    assert err.max() <= tol, (err.max(), int(np.argmax(err)))
+
+
+@pytest.mark.parametrize("schedule,L", [("serial", 4), ("parallel", 1)])
+def test_grad_fp64_code_capacity(torch_cuda, schedule, L):
+    import paper_2508_15743_amd as P
+
+    dem = code_capacity_dem(5, 0.08)
+    K = 6
+    lam, alpha, synd = _inputs(dem, 5, K, 11)
+    G, perms = _graph(P, dem, L, schedule, 64)
+    loss, dl, da = _run(torch_cuda, G, synd, lam, alpha)
+    wl, wdl, okl, wda, oka = _oracle(dem, synd, lam, alpha, K, perms)
+    assert abs(loss - wl) <= 1e-12 * max(1.0, abs(wl))
+    assert okl.mean() >= 0.8 and oka.all()
+    _close(dl, wdl, okl, 1e-6)
+    _close(da, wda, oka, 1e-6)
+    G.close()
+
+
+@pytest.mark.parametrize("schedule,L", [("serial", 2), ("parallel", 1)])
+def test_grad_fp64_circuit(torch_cuda, schedule, L):
+    """The d = 5 circuit-level graph (several chunks per member, columns of
+    degree up to the graph's maximum): all alpha entries and a sample of 48
+    columns."""
+    import paper_2508_15743_amd as P
+
+    dem = circuit_dem(5, 5, 2e-3)
+    K = 5
+    lam, alpha, synd = _inputs(dem, 2, K, 21)
+    idx = np.random.default_rng(5).choice(dem.n, 48, replace=False)
+    G, perms = _graph(P, dem, L, schedule, 64)
+    loss, dl, da = _run(torch_cuda, G, synd, lam, alpha)
+    wl, wdl, okl, wda, oka = _oracle(dem, synd, lam, alpha, K, perms, idx)
+    assert abs(loss - wl) <= 1e-12 * max(1.0, abs(wl))
+    assert okl.sum() >= 36 and oka.sum() >= K - 2
+    _close(dl, wdl, okl, 1e-6)
+    _close(da, wda, oka, 1e-6)
+    G.close()
+
+
+def test_grad_fp32_against_oracle(torch_cuda):
+    """FP32 messages: loss to single-precision rounding, gradient to a bound
+    of the accumulated rounding over K iterations."""
+    import paper_2508_15743_amd as P
+
+    dem = code_capacity_dem(7, 0.08)
+    K = 6
+    lam, alpha, synd = _inputs(dem, 6, K, 31)
+    G, perms = _graph(P, dem, 4, "serial", 32)
+    loss, dl, da = _run(torch_cuda, G, synd, lam, alpha, bits=32)
+    wl, wdl, okl, wda, oka = _oracle(dem, synd, lam, alpha, K, perms)
+    assert abs(loss - wl) <= 1e-4 * max(1.0, abs(wl))
+    _close(dl, wdl, okl, 2e-3)
+    _close(da, wda, oka, 2e-3)
+    G.close()
+
+
+def test_grad_deterministic_and_autograd(torch_cuda):
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    dem = circuit_dem(5, 5, 2e-3)
+    K = 4
+    lam, alpha, synd = _inputs(dem, 64, K, 41)
+    G, _ = _graph(P, dem, 8, "serial", 32)
+    s = torch.from_numpy(synd).cuda()
+    r1 = G.bp_grad(s, torch.tensor(lam), torch.tensor(alpha))
+    r2 = G.bp_grad(s, torch.tensor(lam), torch.tensor(alpha))
+    for a, b in zip(r1, r2):
+        assert torch.equal(a, b)
+    lam_t = torch.tensor(lam, dtype=torch.float32, device="cuda:0", requires_grad=True)
+    al_t = torch.tensor(alpha, dtype=torch.float32, device="cuda:0", requires_grad=True)
+    loss = P.bp_loss(G, s, lam_t, al_t)
+    (2.0 * loss).backward()
+    assert torch.allclose(loss.double(), r1[0][0], rtol=1e-6)
+    assert torch.equal(lam_t.grad, (2.0 * r1[1].float()))
+    assert torch.equal(al_t.grad, (2.0 * r1[2].float()))
+    G.close()
+
+
+def test_grad_rejects_bad_arguments(torch_cuda):
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    dem = code_capacity_dem(5, 0.05)
+    G, _ = _graph(P, dem, 2, "serial", 32)
+    s = torch.zeros((3, dem.m), dtype=torch.uint8, device="cuda:0")
+    lam = torch.ones(dem.n)
+    with pytest.raises(P.VibeError):
+        G.bp_grad(s, lam, torch.ones(0))  # K = 0
+    with pytest.raises(P.VibeError):
+        G.bp_grad(s, lam, torch.ones(65))  # K > 64
+    with pytest.raises(P.VibeError):
+        G.bp_grad(s, lam, torch.ones(3), eps=0.0)
+    with pytest.raises(ValueError):
+        G.bp_grad(s, torch.ones(dem.n + 1), torch.ones(3))
+    G.close()
