@@ -14,7 +14,9 @@ requests from circuit-level codes d = 9, 13, 5 mixed 50/30/20, Poisson
 arrivals at 0.5x and 0.8x the sustained rate, p50/p99 latency); a ragged
 batch of circuit-level codes at d = 5..13 (rounds = d) decoded as one call
 against one call per code;
-BP+LSD-0 without ensembling (one member,
+the backward pass of the differentiable decoder (16 unrolled iterations of
+the d = 5 circuit-level graph, 4096 shots, L = 32, FP32) with its own
+roofline; BP+LSD-0 without ensembling (one member,
 parallel schedule) on the same batch, with LSD calls and largest-cluster
 sizes beside VibeLSD's (the comparison of the paper's Sec. IV.H); the
 per-shot-launch form
@@ -98,6 +100,51 @@ def ragged_leg(P, torch, shots, seed):
     rt.close()
     for G, _ in pairs:
         G.close()
+    return res
+
+
+# algorithmic HBM bytes of one edge-iteration of the adjoint: the forward
+# sweep reads the old message and writes the new one (8 B); the reverse
+# sweep reads the checkpointed message and reads and writes its adjoint
+# (12 B); FP32 each
+GRAD_BYTES_PER_EDGE_ITER = 20.0
+
+
+def grad_leg(P, torch, seed, batch, K):
+    """Backward pass through K unrolled iterations (the differentiable
+    decoder): d = 5 circuit-level graph (rounds 5, p = 1e-3), L = 32 serial
+    members, FP32 messages, alpha_t = 0.625 and lambda from the priors;
+    loss and gradients of a batch of syndromes, timed with HIP events on the
+    stream of the launch."""
+    from synth.dem import circuit_dem
+    from synth.sample import permutations, sample
+
+    dem = circuit_dem(5, 5, 1e-3)
+    L = 32
+    G = P.Graph.from_dem(dem, permutations(dem.n, L, seed + 5), L=L, M=5, T_max=20, alpha=0.625)
+    s = torch.from_numpy(sample(dem, batch, seed + 6).syndromes).to("cuda:0")
+    pri = np.asarray(dem.priors, dtype=np.float64)
+    lam = torch.tensor(np.log((1.0 - pri) / pri), dtype=torch.float32, device="cuda:0")
+    alpha = torch.full((K,), 0.625, dtype=torch.float32, device="cuda:0")
+    G.bp_grad(s, lam, alpha)  # warm-up (workspace)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    loss, dlam, dalpha = G.bp_grad(s, lam, alpha)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    edge_iters = batch * L * K * dem.nnz
+    achieved = GRAD_BYTES_PER_EDGE_ITER * edge_iters / sec / 1e9
+    res = {"workload": "colour666_d5_r5_circuit_uniform_p0.001", "n": dem.n, "m": dem.m, "nnz": dem.nnz,
+           "batch": batch, "L": L, "K": K, "dtype": "f32", "ms": round(1e3 * sec, 3),
+           "shots_per_s": round(batch / sec, 1), "edge_iterations_per_s": edge_iters / sec,
+           "loss": float(loss.item()), "grad_finite": bool(torch.isfinite(dlam).all() and torch.isfinite(dalpha).all()),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "bp_grad_kernel"}}
+    log(f"grad: {batch} shots x {L} members x K={K} in {1e3 * sec:.1f} ms = {batch / sec:.0f} shots/s, "
+        f"{achieved:.0f} GB/s algorithmic")
+    G.close()
     return res
 
 
@@ -188,6 +235,9 @@ def main():
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--grad-batch", type=int, default=4096)
+    ap.add_argument("--grad-K", type=int, default=16)
     ap.add_argument("--serving-seconds", type=float, default=3.0, help="length of each offered-load run")
     ap.add_argument("--ragged-shots", type=str, default="128,1024", help="shots per code in the ragged leg")
     ap.add_argument("--copy-probe", action="store_true",
@@ -327,6 +377,8 @@ def main():
         result["ragged"] = [ragged_leg(P, torch, int(k), args.seed) for k in args.ragged_shots.split(",")]
     if not args.no_serving:
         result["serving"] = serving_leg(P, torch, args.seed, args.serving_seconds)
+    if not args.no_grad:
+        result["grad"] = grad_leg(P, torch, args.seed, args.grad_batch, args.grad_K)
 
     result["plain"] = None
     result["batched_over_plain"] = None

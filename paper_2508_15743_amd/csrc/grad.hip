@@ -25,10 +25,13 @@
 // choices and clamps are piecewise constant: where they do not change, this
 // is the exact gradient of the loss.
 //
-// One wavefront per (shot, member); per-item gradients are reduced over the
-// items in a fixed order, so results are deterministic.  Adjoints that one
-// lane adds into another lane's slot go through agent-scope atomics and are
-// read back with agent-scope loads.
+// One wavefront per (shot, member) item.  Items go to blocks statically
+// (block b takes items b, b + grid, ...); a block sums its items' loss and
+// gradients in item order into a row of its own, and the rows are summed in
+// a fixed order, so the result does not depend on timing.  Adjoints that one
+// lane adds into a slot that another lane reads go through device atomics,
+// issued by one wavefront in program order, and are read back with
+// agent-scope loads.
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -146,12 +149,11 @@ struct GradLaunch {
     const void* lam;           // n, message precision
     const void* alpha;         // K
     double eps;
-    double* loss_items;        // B x L
-    double* lbar_items;        // B x L x n
-    double* abar_items;        // B x L x K
+    double* loss_rows;         // grid: per-block sums
+    double* lbar_rows;         // grid x n
+    double* abar_rows;         // grid x K
     void* scratch;
     size_t scratch_per_block;
-    uint32_t* counter;
     int grid;
 };
 
@@ -186,10 +188,11 @@ __global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a
     F* Lbar = reinterpret_cast<F*>(base + lay.Lbar);
     double* dl = reinterpret_cast<double*>(base + lay.dl);
     const uint32_t n_items = a.B * g.L;
+    double* lbar_row = a.lbar_rows + (size_t)blockIdx.x * g.n;
+    for (uint32_t v = lane; v < g.n; v += kWave) lbar_row[v] = 0.0;
+    double loss_acc = 0.0, abar_acc = 0.0;  // abar_acc: iteration lane + 1
 
-    for (;;) {
-        const uint32_t item = wave_ticket(a.counter, 1u);
-        if (item >= n_items) break;
+    for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const uint32_t shot = item / g.L, mem = item % g.L;
         const uint8_t* s = a.syndromes + (size_t)shot * g.m;
         for (uint32_t b0 = 0; b0 < g.m; b0 += kWave) {
@@ -318,7 +321,7 @@ __global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a
             loss -= sc ? log(sh) : log(1.0 - sh);
             dl[c] = d;
         }
-        loss = wave_sum(loss);
+        loss_acc += wave_sum(loss);
         __syncthreads();
         for (uint32_t v = lane; v < g.n; v += kWave) {
             const double Lv = (double)aload(&Lfin[v]);
@@ -340,8 +343,6 @@ __global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a
         __syncthreads();
 
         // ---- reverse
-        double* lbar_out = a.lbar_items + (size_t)item * g.n;
-        for (uint32_t v = lane; v < g.n; v += kWave) lbar_out[v] = 0.0;
         for (uint32_t k = 0; k < nch; k++) mbA[k * kWave + lane] = F(0);
         __syncthreads();
         F* mb_new = mbA;  // adjoint of iteration t's new messages
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a
                 if (deg) {
                     const F rbar = others + GL;
                     const F lr = lam[v];
-                    if (seg == 0 && lr <= lim && lr >= -lim) lbar_out[v] = aload(&lbar_out[v]) + (double)(all + GL);
+                    if (seg == 0 && lr <= lim && lr >= -lim) unsafeAtomicAdd(&lbar_row[v], (double)(all + GL));
                     const F q = rq[i];
                     abar += (double)(rbar * q);
                     const uint32_t u = rarg[i] & 0x7fffffffu;
@@ -386,14 +387,14 @@ __global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a
                         // serial: an earlier slot holds this iteration's new
                         // message; parallel: every slot its previous one
                         F* tgt = (!FLOOD && u < i) ? mb_new : mb_old;
-                        atomicAdd(&tgt[u], d);
+                        unsafeAtomicAdd(&tgt[u], d);
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
             }
             abar = wave_sum(abar);
-            if (lane == 0) a.abar_items[(size_t)item * a.K + (t - 1)] = abar;
+            if (lane == t - 1) abar_acc += abar;
             __syncthreads();
             F* tmp = mb_new;
             mb_new = mb_old;
@@ -414,21 +415,32 @@ __global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a
                 const F gj = shfl_f(gm, (b0 + (int)jj) & (kWave - 1));
                 if (jj < deg) all += gj;
             }
-            if (deg && seg == 0) lbar_out[v] = aload(&lbar_out[v]) + (double)all;
+            if (deg && seg == 0) unsafeAtomicAdd(&lbar_row[v], (double)all);
         }
         // (a column without checks is in no check's product: its gradient is 0)
-        if (lane == 0) a.loss_items[item] = loss;
         __syncthreads();
     }
+    if (lane == 0) a.loss_rows[blockIdx.x] = loss_acc;
+    if (lane < a.K) a.abar_rows[(size_t)blockIdx.x * a.K + lane] = abar_acc;
 }
 
-// out[j] = sum over items of in[item * width + j], items in ascending order
-__global__ void reduce_items_kernel(const double* in, uint32_t items, uint32_t width, double* out) {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= width) return;
+// out[j] = sum over rows r of in[r * width + j]: eight partial sums over the
+// rows r = p (mod 8), each in ascending r, then the eight in order of p
+__global__ __launch_bounds__(256) void reduce_rows_kernel(const double* in, uint32_t rows, uint32_t width,
+                                                          double* out) {
+    __shared__ double part[8][32];
+    const uint32_t jl = threadIdx.x & 31u, p = threadIdx.x >> 5;
+    const uint32_t j = blockIdx.x * 32u + jl;
     double acc = 0.0;
-    for (uint32_t i = 0; i < items; i++) acc += in[(size_t)i * width + j];
-    out[j] = acc;
+    if (j < width)
+        for (uint32_t r = p; r < rows; r += 8) acc += in[(size_t)r * width + j];
+    part[p][jl] = acc;
+    __syncthreads();
+    if (p == 0 && j < width) {
+        double sum = part[0][jl];
+        for (int q = 1; q < 8; q++) sum += part[q][jl];
+        out[j] = sum;
+    }
 }
 
 template <class F, bool FLOOD>
@@ -437,6 +449,10 @@ const void* grad_fn() {
 }
 
 }  // namespace
+
+// grad launch limits: blocks (one wavefront each) and their scratch in total
+constexpr uint64_t kGradMaxGrid = 8192;
+constexpr uint64_t kGradScratchBudget = 16ull << 30;
 
 size_t grad_scratch_per_block(const DevGraph& g, uint32_t K) {
     return grad_layout((size_t)g.max_chunks * kWave, g.n, g.m, K, g.fp64 ? 8 : 4).bytes;
@@ -461,11 +477,11 @@ int launch_grad(const DevGraph& g, const GradLaunch& a, hipStream_t st) {
     return VIBE_OK;
 }
 
-int launch_reduce_items(const double* in, uint32_t items, uint32_t width, double* out, hipStream_t st) {
+int launch_reduce_rows(const double* in, uint32_t rows, uint32_t width, double* out, hipStream_t st) {
     if (!width) return VIBE_OK;
-    hipLaunchKernelGGL(reduce_items_kernel, dim3((width + 255) / 256), dim3(256), 0, st, in, items, width, out);
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3((width + 31) / 32), dim3(256), 0, st, in, rows, width, out);
     hipError_t e = hipGetLastError();
-    return e == hipSuccess ? VIBE_OK : hip_fail(e, "reduce_items_kernel launch");
+    return e == hipSuccess ? VIBE_OK : hip_fail(e, "reduce_rows_kernel launch");
 }
 
 }  // namespace vibe
@@ -487,15 +503,18 @@ extern "C" int vibe_bp_grad(vibe_graph* G, const uint8_t* syndromes, uint64_t B,
     const uint32_t items = (uint32_t)items64;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t per = grad_scratch_per_block(g, K);
-    const int grid = (int)std::min<uint64_t>(items, std::max<uint64_t>(1, std::min<uint64_t>(2048, (8ull << 30) / per)));
-    // workspace: counter | per-item loss, lambda-bar, alpha-bar | scratch
-    size_t off = 256;
+    // one block per resident wavefront slot at most, within the scratch budget
+    const uint64_t fit = std::max<uint64_t>(1, kGradScratchBudget / std::max<size_t>(per, 1));
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(items, std::min<uint64_t>(kGradMaxGrid, fit));
+    // workspace: per-block loss, lambda-bar and alpha-bar rows | scratch
+    auto round256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = 0;
     const size_t o_loss = off;
-    off += ((8ull * items) + 255) & ~(size_t)255;
+    off += round256(8ull * grid);
     const size_t o_lbar = off;
-    off += ((8ull * items * g.n) + 255) & ~(size_t)255;
+    off += round256(8ull * grid * g.n);
     const size_t o_abar = off;
-    off += ((8ull * items * K) + 255) & ~(size_t)255;
+    off += round256(8ull * grid * K);
     const size_t o_scr = off;
     off += per * grid;
     if (G->ws.bytes < off) {
@@ -510,8 +529,6 @@ extern "C" int vibe_bp_grad(vibe_graph* G, const uint8_t* syndromes, uint64_t B,
         G->ws.bytes = off;
     }
     unsigned char* base = static_cast<unsigned char*>(G->ws.base);
-    int rc = launch_zero(base, 256, st);
-    if (rc) return rc;
     GradLaunch a{};
     a.syndromes = syndromes;
     a.B = (uint32_t)B;
@@ -519,15 +536,15 @@ extern "C" int vibe_bp_grad(vibe_graph* G, const uint8_t* syndromes, uint64_t B,
     a.lam = lam;
     a.alpha = alpha;
     a.eps = eps;
-    a.loss_items = reinterpret_cast<double*>(base + o_loss);
-    a.lbar_items = reinterpret_cast<double*>(base + o_lbar);
-    a.abar_items = reinterpret_cast<double*>(base + o_abar);
+    a.loss_rows = reinterpret_cast<double*>(base + o_loss);
+    a.lbar_rows = reinterpret_cast<double*>(base + o_lbar);
+    a.abar_rows = reinterpret_cast<double*>(base + o_abar);
     a.scratch = base + o_scr;
     a.scratch_per_block = per;
-    a.counter = reinterpret_cast<uint32_t*>(base);
-    a.grid = grid;
-    if ((rc = launch_grad(g, a, st))) return rc;
-    if ((rc = launch_reduce_items(a.loss_items, items, 1, loss, st))) return rc;
-    if ((rc = launch_reduce_items(a.lbar_items, items, g.n, dlam, st))) return rc;
-    return launch_reduce_items(a.abar_items, items, K, dalpha, st);
+    a.grid = (int)grid;
+    int rc = launch_grad(g, a, st);
+    if (rc) return rc;
+    if ((rc = launch_reduce_rows(a.loss_rows, grid, 1, loss, st))) return rc;
+    if ((rc = launch_reduce_rows(a.lbar_rows, grid, g.n, dlam, st))) return rc;
+    return launch_reduce_rows(a.abar_rows, grid, K, dalpha, st);
 }

@@ -172,3 +172,36 @@ def test_grad_rejects_bad_arguments(torch_cuda):
     with pytest.raises(ValueError):
         G.bp_grad(s, torch.ones(dem.n + 1), torch.ones(3))
     G.close()
+
+
+def test_grad_full_size_additive_and_sampled(torch_cuda):
+    """The configuration the benchmark times: d = 5 circuit-level graph,
+    L = 32 serial members, K = 16, FP32, 4096 shots, alpha_t = 0.625 and
+    lambda from the priors.  Every per-item result is independent of the
+    launch, so the batch equals the sum of its four quarters up to the order
+    of the FP64 sums; two sampled shots alone match the oracle's loss."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    dem = circuit_dem(5, 5, 1e-3)
+    K, L, B = 16, 32, 4096
+    perms = permutations(dem.n, L, 7)
+    G = P.Graph.from_dem(dem, perms, L=L, M=5, T_max=20)
+    synd = sample(dem, B, 8).syndromes
+    s = torch.from_numpy(synd).cuda()
+    lam = np.log((1 - dem.priors) / dem.priors)
+    lam_t = torch.tensor(lam, dtype=torch.float32)
+    al_t = torch.full((K,), 0.625)
+    loss, dl, da = G.bp_grad(s, lam_t, al_t)
+    assert torch.isfinite(dl).all() and torch.isfinite(da).all()
+    parts = [G.bp_grad(s[q * 1024:(q + 1) * 1024], lam_t, al_t) for q in range(4)]
+    for i, full in enumerate((loss, dl, da)):
+        summed = sum(p[i] for p in parts)
+        scale = float(torch.abs(torch.stack([p[i] for p in parts])).sum(0).max())
+        assert float(torch.abs(full - summed).max()) <= 1e-12 * max(scale, 1.0)
+    rows = np.random.default_rng(9).choice(B, 2, replace=False)
+    got = G.bp_grad(s[rows], lam_t, al_t)[0].item()
+    g = O.OracleGraph(dem)
+    want = sum(O.bp_loss(g, synd[r], lam, np.full(K, 0.625), K, perm)[0] for r in rows for perm in perms)
+    assert abs(got - want) <= 1e-4 * max(1.0, abs(want))
+    G.close()
