@@ -3,35 +3,45 @@
 // scaling factors alpha_t (the differentiable decoder; Algorithm 1 unrolled).
 //
 // Forward: K iterations of the serial (or parallel) schedule without early
-// stop, from lambda and alpha given as inputs, keeping the messages at the
-// start of every iteration (checkpoints).  Loss: with the final posteriors
-// L_v, shat_c = (1 - prod_{v in N(c)} tanh(L_v / 2)) / 2 clamped to
-// [eps, 1 - eps], loss = sum_c BCE(s_c, shat_c).
+// stop, from lambda and alpha given as inputs.  Every iteration records, per
+// edge e = (c, v), its check message q_e (r_e = alpha_t q_e), the edge u*
+// attaining the minimum with the sign factor of dq_e / dmu_{u*}, and whether
+// the new message was clamped (these records are the checkpoints: the
+// reverse pass needs nothing else).  Loss: with the final posteriors L_v,
+// shat_c = (1 - prod_{v in N(c)} tanh(L_v / 2)) / 2 clamped to [eps, 1 - eps],
+// loss = sum_c BCE(s_c, shat_c), in FP64.
 //
-// Reverse, iteration t = K .. 1: the iteration is recomputed from its
-// checkpoint, recording for every edge e = (c, v) its check message
-// r_e = alpha_t q_e, the edge u* that attains the minimum (with its sign) and
-// whether the new message was clamped.  Then the chunks are visited in
-// reverse order.  Edge e's new message feeds the other edges' messages of
-// its column (and L_v after the last iteration), so
+// Reverse, iteration t = K .. 1, chunks in reverse order.  Edge e's new
+// message feeds the other messages of its column (and L_v after the last
+// iteration), so
 //   rbar_e = sum_{e' in column, e' != e} mubar_e' + Lbar_v,
 //   lambdabar_v += sum_{e' in column} mubar_e' + Lbar_v,
 //   alphabar_t += rbar_e q_e,
 //   mubar_{u*} += rbar_e alpha_t (1 - 2 s_c) prod sign * sign(mu_{u*}),
 // where mu_{u*} is u*'s new message of iteration t if u* comes earlier in
-// the sweep (its adjoint is completed later in the reverse order) and its
-// message of iteration t - 1 otherwise (the adjoint passed on to iteration
-// t - 1).  At t = 1 the messages are lambda itself.  Sign products, argmin
-// choices and clamps are piecewise constant: where they do not change, this
-// is the exact gradient of the loss.
+// the sweep and its message of iteration t - 1 otherwise.  At t = 1 the old
+// messages are lambda itself.  Sign products, argmin choices and clamps are
+// piecewise constant: where they do not change this is the exact gradient.
+//
+// The argmin adjoints of one row are summed in LDS, not in memory.  In the
+// serial schedule, the prefix argmin of the row's edges, visited in reverse,
+// only moves to earlier edges, and every edge before the current prefix
+// argmin is still to come: one accumulator per row collects the adjoint of
+// that argmin and hands it over when the reverse pass reaches it.  The
+// suffix argmin (an old message) also only moves to earlier edges as the
+// pass goes on, so a second accumulator is written out once, when its
+// target changes or the pass ends.  In the parallel schedule the argmin
+// over a row without the edge itself is the row's first minimum for every
+// edge but that one, and the next minimum for it: two accumulators.
 //
 // One wavefront per (shot, member) item.  Items go to blocks statically
 // (block b takes items b, b + grid, ...); a block sums its items' loss and
 // gradients in item order into a row of its own, and the rows are summed in
-// a fixed order, so the result does not depend on timing.  Adjoints that one
-// lane adds into a slot that another lane reads go through device atomics,
-// issued by one wavefront in program order, and are read back with
-// agent-scope loads.
+// a fixed order, so the result does not depend on timing.  Slot arrays are
+// private to their lane except for the argmin adjoints written out by
+// another lane and the per-column values of the loss stage; those are read
+// with agent-scope loads after a barrier.  Every pass loads the next chunk's
+// slot data while it works on the current one.
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -61,8 +71,15 @@ struct GP<double> {
 
 // A row state with its argmin: magnitude bits with the parity of the signs
 // in the sign position, and the slot of the edge attaining the minimum with
-// that edge's own sign in bit 31 (kNoArg: none).
+// that edge's own sign in bit 31 (kNoArg: none).  On equal magnitudes the
+// earlier operand's slot is kept.
 constexpr uint32_t kNoArg = 0x7fffffffu;
+
+// Per-edge record word: argmin slot (kSlotMask: none) and flags.
+constexpr uint32_t kSlotMask = 0x00ffffffu;
+constexpr uint32_t kSneg = 1u << 24;  // dq_e / dmu_{u*} is negative
+constexpr uint32_t kNcm = 1u << 25;   // the new message was not clamped
+constexpr uint32_t kLnc = 1u << 26;   // lambda_v was not clamped
 
 template <class F>
 struct RS {
@@ -95,11 +112,6 @@ __device__ inline F clampv(F x, F lim) {
     return x > lim ? lim : (x < -lim ? -lim : x);
 }
 
-template <class F>
-__device__ inline F shfl_f(F v, int src) {
-    return __shfl(v, src);
-}
-
 __device__ inline double aload(const double* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 __device__ inline float aload(const float* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
@@ -109,33 +121,41 @@ __device__ inline F wave_sum(F x) {
     return x;
 }
 
-struct GradItemBufs {
-    size_t ckpt, mu_new, sufst, sufarg, rq, rarg, flags, mubar_a, mubar_b, Lfin, Lbar, dl;
+__device__ inline uint32_t deg_of(uint32_t meta) { return (meta >> kMetaDegShift) & 15u; }
+
+// keeps the compiler from moving LDS traffic of one chunk past the next's
+__device__ inline void chunk_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+struct GradBufs {
+    size_t lamS, msgA, msgB, sufst, sufarg, rq, rw, mbA, mbB, Lfin, Lbar, dl;
     size_t bytes;
 };
 
 // Per-block scratch layout, for S slots (max_chunks * 64), n columns, m checks
-// and K iterations, element size fb.
-__host__ __device__ inline GradItemBufs grad_layout(size_t S, size_t n, size_t m, uint32_t K, size_t fb) {
-    GradItemBufs b;
+// and K iterations, message size fb.
+__host__ __device__ inline GradBufs grad_layout(size_t S, size_t n, size_t m, uint32_t K, size_t fb) {
+    GradBufs b;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
         off += (bytes + 255) & ~(size_t)255;
         return o;
     };
-    b.ckpt = take(fb * S * K);   // messages at the start of iterations 1..K
-    b.mu_new = take(fb * S);     // this iteration's new messages (recompute)
-    b.sufst = take(fb * S);      // suffix states of the recompute
+    b.lamS = take(fb * S);       // lambda_v of the slot's column (unclamped)
+    b.msgA = take(fb * S);       // messages, double-buffered over iterations
+    b.msgB = take(fb * S);
+    b.sufst = take(fb * S);      // suffix row states of this iteration's sweep
     b.sufarg = take(4 * S);
-    b.rq = take(fb * S);         // q_e, r_e = alpha_t q_e
-    b.rarg = take(4 * S);        // argmin slot | its sign, or kNoArg
-    b.flags = take(4 * S);       // bit 0: new message not clamped; bit 1: sign factor negative
-    b.mubar_a = take(fb * S);
-    b.mubar_b = take(fb * S);
-    b.Lfin = take(fb * n);
-    b.Lbar = take(fb * n);
-    b.dl = take(8 * m);          // d loss / d shat_c (the loss stage runs in FP64)
+    b.rq = take(fb * S * K);     // records: q_e per iteration
+    b.rw = take(4 * S * K);      // records: argmin slot and flags per iteration
+    b.mbA = take(fb * S);        // message adjoints, double-buffered
+    b.mbB = take(fb * S);
+    b.Lfin = take(fb * n);       // final posteriors (unclamped)
+    b.Lbar = take(fb * n);       // d loss / d L_v (0 where L_v was clamped)
+    b.dl = take(8 * m);          // d loss / d shat_c
     b.bytes = off;
     return b;
 }
@@ -165,29 +185,35 @@ __global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a
     using B = typename P::B;
     extern __shared__ __align__(16) unsigned char lds[];
     uint64_t* sb = reinterpret_cast<uint64_t*>(lds);
-    B* pst = reinterpret_cast<B*>(sb + g.words_m);  // prefix states, m
-    uint32_t* parg = reinterpret_cast<uint32_t*>(pst + g.m);
-    const int lane = threadIdx.x;
+    B* pst = reinterpret_cast<B*>(sb + g.words_m);     // running row states, m
+    F* pacc = reinterpret_cast<F*>(pst + g.m);         // row accumulators (reverse), m
+    F* sacc = pacc + g.m;
+    uint32_t* parg = reinterpret_cast<uint32_t*>(sacc + g.m);
+    uint32_t* ptgt = parg + g.m;
+    uint32_t* stgt = ptgt + g.m;
+    const uint32_t lane = threadIdx.x;
     const F* lam = reinterpret_cast<const F*>(a.lam);
     const F* alpha = reinterpret_cast<const F*>(a.alpha);
     const F lim = (F)g.clamp;
     const B ident = P::ident(g);
     const uint32_t S = g.max_chunks * kWave;
-    const GradItemBufs lay = grad_layout(S, g.n, g.m, a.K, sizeof(F));
+    const GradBufs lay = grad_layout(S, g.n, g.m, a.K, sizeof(F));
     unsigned char* base = static_cast<unsigned char*>(a.scratch) + (size_t)blockIdx.x * a.scratch_per_block;
-    F* ckpt = reinterpret_cast<F*>(base + lay.ckpt);
-    F* mu_new = reinterpret_cast<F*>(base + lay.mu_new);
+    F* lamS = reinterpret_cast<F*>(base + lay.lamS);
+    F* msgA = reinterpret_cast<F*>(base + lay.msgA);
+    F* msgB = reinterpret_cast<F*>(base + lay.msgB);
     B* sufst = reinterpret_cast<B*>(base + lay.sufst);
     uint32_t* sufarg = reinterpret_cast<uint32_t*>(base + lay.sufarg);
     F* rq = reinterpret_cast<F*>(base + lay.rq);
-    uint32_t* rarg = reinterpret_cast<uint32_t*>(base + lay.rarg);
-    uint32_t* flags = reinterpret_cast<uint32_t*>(base + lay.flags);
-    F* mbA = reinterpret_cast<F*>(base + lay.mubar_a);
-    F* mbB = reinterpret_cast<F*>(base + lay.mubar_b);
+    uint32_t* rw = reinterpret_cast<uint32_t*>(base + lay.rw);
+    F* mbA = reinterpret_cast<F*>(base + lay.mbA);
+    F* mbB = reinterpret_cast<F*>(base + lay.mbB);
     F* Lfin = reinterpret_cast<F*>(base + lay.Lfin);
     F* Lbar = reinterpret_cast<F*>(base + lay.Lbar);
     double* dl = reinterpret_cast<double*>(base + lay.dl);
     const uint32_t n_items = a.B * g.L;
+    const uint32_t K = a.K;
+    const uint32_t rb = rec_bytes(sizeof(F) == 8);
     double* lbar_row = a.lbar_rows + (size_t)blockIdx.x * g.n;
     for (uint32_t v = lane; v < g.n; v += kWave) lbar_row[v] = 0.0;
     double loss_acc = 0.0, abar_acc = 0.0;  // abar_acc: iteration lane + 1
@@ -201,110 +227,141 @@ __global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a
             if (lane == 0) sb[b0 / kWave] = mk;
         }
         const uint32_t c0 = uni(g.member_chunk[mem]), nch = uni(g.member_chunk[mem + 1]) - c0;
-        const uint32_t rb = rec_bytes(sizeof(F) == 8);
         const unsigned char* recs = g.sched + (size_t)c0 * rb;
         auto meta_of = [&](uint32_t k) { return *reinterpret_cast<const uint32_t*>(recs + (size_t)k * rb + 4u * lane); };
         auto v_of = [&](uint32_t k) { return *reinterpret_cast<const uint32_t*>(recs + (size_t)k * rb + kRecV + 4u * lane); };
-        __syncthreads();
+        auto synd_bit = [&](uint32_t c) { return ((sb[c >> 6] >> (c & 63)) & 1ull) != 0; };
 
-        // the iteration from messages `old` (slot order): records q, argmin,
-        // flags and the new messages; at the last iteration also L
-        auto iterate = [&](const F* old, uint32_t t, bool last) {
-            const F al = alpha[t - 1];
-            // suffix states (with argmin) of the old messages
-            for (uint32_t c = lane; c < g.m; c += kWave) {
-                pst[c] = ident;
-                parg[c] = kNoArg;
-            }
-            __syncthreads();
-            for (uint32_t k = nch; k-- > 0;) {
-                const uint32_t meta = meta_of(k);
-                const uint32_t i = k * kWave + lane;
-                if ((meta >> kMetaDegShift) & 15u) {
-                    const uint32_t c = meta & 0xffffu;
-                    RS<F> run{pst[c], parg[c]};
-                    sufst[i] = run.st;
-                    sufarg[i] = run.arg;
-                    run = rs_join(rs_of(old[i], i), run);
-                    pst[c] = run.st;
-                    parg[c] = run.arg;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-            }
-            for (uint32_t c = lane; c < g.m; c += kWave) {
-                pst[c] = ident;
-                parg[c] = kNoArg;
-            }
-            __syncthreads();
-            // the sweep
-            for (uint32_t k = 0; k < nch; k++) {
-                const uint32_t meta = meta_of(k), v = v_of(k);
-                const uint32_t deg = (meta >> kMetaDegShift) & 15u, dmax = uni((meta >> kMetaDmaxShift) & 15u);
-                const uint32_t c = meta & 0xffffu, seg = (meta >> 16) & 15u;
-                const uint32_t i = k * kWave + lane;
-                F q = F(0);
-                RS<F> pre{pst[c], parg[c]};
-                if (deg) {
-                    const RS<F> j = rs_join(pre, RS<F>{sufst[i], sufarg[i]});
-                    const bool neg = ((j.st & P::kSign) != 0) != (((sb[c >> 6] >> (c & 63)) & 1ull) != 0);
-                    const F mag = P::val(j.st & ~P::kSign);
-                    q = neg ? -mag : mag;
-                    rq[i] = q;
-                    rarg[i] = j.arg;
-                    // sign factor of dr/dmu_{u*}: (1 - 2 s_c) prod sign * sign(mu_{u*})
-                    const bool sneg = neg != ((j.arg & 0x80000000u) != 0);
-                    flags[i] = sneg ? 2u : 0u;
-                }
-                const F r = al * q;
-                const F lv = deg ? clampv(lam[v], lim) : F(0);
-                F L = lv, mu = lv;
-                const int b0 = lane - (int)seg;
-                for (uint32_t jj = 0; jj < dmax; jj++) {
-                    const F rj = shfl_f(r, (b0 + (int)jj) & (kWave - 1));
-                    if (jj < deg) {
-                        L += rj;
-                        if (jj != seg) mu += rj;
-                    }
-                }
-                if (deg) {
-                    const bool ncm = mu <= lim && mu >= -lim;
-                    mu = clampv(mu, lim);
-                    mu_new[i] = mu;
-                    flags[i] |= ncm ? 1u : 0u;
-                    // serial: the row's later edges see the new message
-                    // parallel: they see the previous one
-                    const RS<F> mine = FLOOD ? rs_of(old[i], i) : rs_of(mu, i);
-                    const RS<F> np = rs_join(pre, mine);
-                    pst[c] = np.st;
-                    parg[c] = np.arg;
-                    if (last && seg == 0) Lfin[v] = L;  // unclamped (flags of L in Lbar)
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-            }
-            __syncthreads();
-        };
-
-        // ---- forward with checkpoints
+        // lambda per slot and the messages before iteration 1
         for (uint32_t k = 0; k < nch; k++) {
-            const uint32_t i = k * kWave + lane;
             const uint32_t meta = meta_of(k);
-            ckpt[i] = ((meta >> kMetaDegShift) & 15u) ? clampv(lam[v_of(k)], lim) : F(0);
+            if (deg_of(meta)) {
+                const F lr = lam[v_of(k)];
+                lamS[k * kWave + lane] = lr;
+                msgA[k * kWave + lane] = clampv(lr, lim);
+            }
         }
-        for (uint32_t v = lane; v < g.n; v += kWave) Lfin[v] = clampv(lam[v], lim);  // columns without checks
         __syncthreads();
-        for (uint32_t t = 1; t <= a.K; t++) {
-            iterate(ckpt + (size_t)(t - 1) * S, t, t == a.K);
-            if (t < a.K)
-                for (uint32_t k = 0; k < nch; k++) {
-                    const uint32_t i = k * kWave + lane;
-                    ckpt[(size_t)t * S + i] = mu_new[i];
+
+        // ---- forward, recording every iteration
+        for (uint32_t t = 1; t <= K; t++) {
+            const F* old = (t & 1) ? msgA : msgB;
+            F* nw = (t & 1) ? msgB : msgA;
+            F* rqt = rq + (size_t)(t - 1) * S;
+            uint32_t* rwt = rw + (size_t)(t - 1) * S;
+            const F al = alpha[t - 1];
+
+            // suffix states of the old messages: chunks in reverse
+            for (uint32_t c = lane; c < g.m; c += kWave) {
+                pst[c] = ident;
+                parg[c] = kNoArg;
+            }
+            __syncthreads();
+            {
+                uint32_t mA = nch ? meta_of(nch - 1) : 0u;
+                F xA = (nch && deg_of(mA)) ? old[(nch - 1) * kWave + lane] : F(0);
+                uint32_t mB = nch > 1 ? meta_of(nch - 2) : 0u;
+                for (uint32_t k = nch; k-- > 0;) {
+                    const uint32_t meta = mA;
+                    const F x = xA;
+                    mA = mB;
+                    xA = (k > 0 && deg_of(mA)) ? old[(k - 1) * kWave + lane] : F(0);
+                    mB = k > 1 ? meta_of(k - 2) : 0u;
+                    if (deg_of(meta)) {
+                        const uint32_t c = meta & 0xffffu, i = k * kWave + lane;
+                        RS<F> run{pst[c], parg[c]};
+                        sufst[i] = run.st;
+                        sufarg[i] = run.arg;
+                        run = rs_join(rs_of(x, i), run);
+                        pst[c] = run.st;
+                        parg[c] = run.arg;
+                    }
+                    chunk_fence();
                 }
+            }
+            for (uint32_t c = lane; c < g.m; c += kWave) {
+                pst[c] = ident;
+                parg[c] = kNoArg;
+            }
+            __syncthreads();
+
+            // the sweep
+            {
+                uint32_t mA = nch ? meta_of(0) : 0u, vA = nch ? v_of(0) : 0u;
+                B sA = ident;
+                uint32_t aA = kNoArg;
+                F lA = F(0), oA = F(0);
+                if (nch && deg_of(mA)) {
+                    sA = sufst[lane];
+                    aA = sufarg[lane];
+                    lA = lamS[lane];
+                    if (FLOOD) oA = old[lane];
+                }
+                uint32_t mB = nch > 1 ? meta_of(1) : 0u, vB = nch > 1 ? v_of(1) : 0u;
+                for (uint32_t k = 0; k < nch; k++) {
+                    const uint32_t meta = mA, v = vA;
+                    const B sst = sA;
+                    const uint32_t sarg = aA;
+                    const F lr = lA, xo = oA;
+                    mA = mB;
+                    vA = vB;
+                    if (k + 1 < nch && deg_of(mA)) {
+                        const uint32_t i1 = (k + 1) * kWave + lane;
+                        sA = sufst[i1];
+                        aA = sufarg[i1];
+                        lA = lamS[i1];
+                        if (FLOOD) oA = old[i1];
+                    }
+                    if (k + 2 < nch) {
+                        mB = meta_of(k + 2);
+                        vB = v_of(k + 2);
+                    }
+                    const uint32_t deg = deg_of(meta), dmax = uni((meta >> kMetaDmaxShift) & 15u);
+                    const uint32_t c = meta & 0xffffu, seg = (meta >> 16) & 15u;
+                    const uint32_t i = k * kWave + lane;
+                    F q = F(0);
+                    uint32_t w = 0;
+                    const RS<F> pre{pst[c], parg[c]};
+                    if (deg) {
+                        const RS<F> j = rs_join(pre, RS<F>{sst, sarg});
+                        const bool neg = ((j.st & P::kSign) != 0) != synd_bit(c);
+                        const F mag = P::val(j.st & ~P::kSign);
+                        q = neg ? -mag : mag;
+                        const uint32_t u = j.arg & 0x7fffffffu;
+                        w = (u == kNoArg ? kSlotMask : u) | ((neg != ((j.arg >> 31) != 0)) ? kSneg : 0u);
+                    }
+                    const F r = al * q;
+                    const F lv = clampv(lr, lim);
+                    F L = lv, mu = lv;
+                    const int b0 = (int)lane - (int)seg;
+                    for (uint32_t jj = 0; jj < dmax; jj++) {
+                        const F rj = __shfl(r, (b0 + (int)jj) & (kWave - 1));
+                        if (jj < deg) {
+                            L += rj;
+                            if (jj != seg) mu += rj;
+                        }
+                    }
+                    if (deg) {
+                        w |= (mu <= lim && mu >= -lim) ? kNcm : 0u;
+                        w |= (lr <= lim && lr >= -lim) ? kLnc : 0u;
+                        mu = clampv(mu, lim);
+                        rqt[i] = q;
+                        rwt[i] = w;
+                        if (t < K) nw[i] = mu;
+                        // serial: the row's later edges see the new message;
+                        // parallel: the previous one
+                        const RS<F> np = rs_join(pre, FLOOD ? rs_of(xo, i) : rs_of(mu, i));
+                        pst[c] = np.st;
+                        parg[c] = np.arg;
+                        if (t == K && seg == 0) Lfin[v] = L;
+                    }
+                    chunk_fence();
+                }
+            }
             __syncthreads();
         }
+
         // ---- loss and d loss / d L, in FP64 whatever the message precision
-        // (Lfin was written by other lanes)
         double loss = 0.0;
         const double dlim = g.clamp;
         for (uint32_t c = lane; c < g.m; c += kWave) {
@@ -326,7 +383,7 @@ __global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a
         for (uint32_t v = lane; v < g.n; v += kWave) {
             const double Lv = (double)aload(&Lfin[v]);
             double gsum = 0.0;
-            if (Lv <= dlim && Lv >= -dlim) {
+            if (g.cp[v + 1] > g.cp[v] && Lv <= dlim && Lv >= -dlim) {
                 const double tv = tanh(Lv / 2.0);
                 for (uint32_t j = g.cp[v]; j < g.cp[v + 1]; j++) {
                     const uint32_t c = g.ci[j];
@@ -343,76 +400,125 @@ __global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a
         __syncthreads();
 
         // ---- reverse
-        for (uint32_t k = 0; k < nch; k++) mbA[k * kWave + lane] = F(0);
-        __syncthreads();
-        F* mb_new = mbA;  // adjoint of iteration t's new messages
-        F* mb_old = mbB;  // adjoint of its old messages (iteration t - 1's)
-        for (uint32_t t = a.K; t >= 1; t--) {
-            iterate(ckpt + (size_t)(t - 1) * S, t, t == a.K);
+        const F* mbp = mbA;  // adjoint of iteration t's new messages from iteration t + 1
+        F* mbn = mbB;        // adjoint of iteration t's old messages, written out here
+        for (uint32_t t = K; t >= 1; t--) {
+            const F* rqt = rq + (size_t)(t - 1) * S;
+            const uint32_t* rwt = rw + (size_t)(t - 1) * S;
             const F al = alpha[t - 1];
-            for (uint32_t k = 0; k < nch; k++) mb_old[k * kWave + lane] = F(0);
+            const bool last = t == K;  // no later iteration; L enters the loss
+            for (uint32_t c = lane; c < g.m; c += kWave) {
+                ptgt[c] = kSlotMask;
+                stgt[c] = kSlotMask;
+                pacc[c] = F(0);
+                sacc[c] = F(0);
+            }
             __syncthreads();
             double abar = 0.0;
-            for (uint32_t k = nch; k-- > 0;) {
-                const uint32_t meta = meta_of(k), v = v_of(k);
-                const uint32_t deg = (meta >> kMetaDegShift) & 15u, dmax = uni((meta >> kMetaDmaxShift) & 15u);
-                const uint32_t seg = (meta >> 16) & 15u;
-                const uint32_t i = k * kWave + lane;
-                const uint32_t fl = deg ? flags[i] : 0u;
-                const F gm = deg && (fl & 1u) ? aload(&mb_new[i]) : F(0);
-                F GL = F(0);
-                if (deg && t == a.K) {
-                    const F Lv = aload(&Lfin[v]);
-                    GL = (Lv <= lim && Lv >= -lim) ? aload(&Lbar[v]) : F(0);
+            {
+                uint32_t mA = nch ? meta_of(nch - 1) : 0u, vA = nch ? v_of(nch - 1) : 0u;
+                F qA = F(0), gA = F(0), glA = F(0);
+                uint32_t wA = 0;
+                if (nch && deg_of(mA)) {
+                    const uint32_t i1 = (nch - 1) * kWave + lane;
+                    qA = rqt[i1];
+                    wA = rwt[i1];
+                    if (!last) gA = aload(&mbp[i1]);
+                    if (last) glA = aload(&Lbar[vA]);
                 }
-                // column sums of the message adjoints
-                F all = F(0), others = F(0);
-                const int b0 = lane - (int)seg;
-                for (uint32_t jj = 0; jj < dmax; jj++) {
-                    const F gj = shfl_f(gm, (b0 + (int)jj) & (kWave - 1));
-                    if (jj < deg) {
-                        all += gj;
-                        if (jj != seg) others += gj;
+                uint32_t mB = nch > 1 ? meta_of(nch - 2) : 0u, vB = nch > 1 ? v_of(nch - 2) : 0u;
+                for (uint32_t k = nch; k-- > 0;) {
+                    const uint32_t meta = mA, v = vA, w = wA;
+                    const F q = qA, gprev = gA, GLv = glA;
+                    mA = mB;
+                    vA = vB;
+                    if (k > 0 && deg_of(mA)) {
+                        const uint32_t i1 = (k - 1) * kWave + lane;
+                        qA = rqt[i1];
+                        wA = rwt[i1];
+                        if (!last) gA = aload(&mbp[i1]);
+                        if (last) glA = aload(&Lbar[vA]);
                     }
-                }
-                if (deg) {
-                    const F rbar = others + GL;
-                    const F lr = lam[v];
-                    if (seg == 0 && lr <= lim && lr >= -lim) unsafeAtomicAdd(&lbar_row[v], (double)(all + GL));
-                    const F q = rq[i];
-                    abar += (double)(rbar * q);
-                    const uint32_t u = rarg[i] & 0x7fffffffu;
-                    if (u != kNoArg) {
-                        const F d = rbar * al * ((fl & 2u) ? F(-1) : F(1));
-                        // serial: an earlier slot holds this iteration's new
-                        // message; parallel: every slot its previous one
-                        F* tgt = (!FLOOD && u < i) ? mb_new : mb_old;
-                        unsafeAtomicAdd(&tgt[u], d);
+                    if (k > 1) {
+                        mB = meta_of(k - 2);
+                        vB = v_of(k - 2);
                     }
+                    const uint32_t deg = deg_of(meta), dmax = uni((meta >> kMetaDmaxShift) & 15u);
+                    const uint32_t c = meta & 0xffffu, seg = (meta >> 16) & 15u;
+                    const uint32_t i = k * kWave + lane;
+                    F gin = last ? F(0) : gprev;
+                    if (deg) {
+                        if (!FLOOD && ptgt[c] == i) {  // the prefix argmin reached: take its adjoint
+                            gin += pacc[c];
+                            ptgt[c] = kSlotMask;
+                        }
+                        mbn[i] = F(0);  // written out later if this edge is a suffix argmin
+                    }
+                    const F gm = (deg && (w & kNcm)) ? gin : F(0);
+                    const F GL = (deg && last) ? GLv : F(0);
+                    F all = F(0), others = F(0);
+                    const int b0 = (int)lane - (int)seg;
+                    for (uint32_t jj = 0; jj < dmax; jj++) {
+                        const F gj = __shfl(gm, (b0 + (int)jj) & (kWave - 1));
+                        if (jj < deg) {
+                            all += gj;
+                            if (jj != seg) others += gj;
+                        }
+                    }
+                    if (deg) {
+                        const F rbar = others + GL;
+                        if (seg == 0 && (w & kLnc)) unsafeAtomicAdd(&lbar_row[v], (double)(all + GL));
+                        abar += (double)(rbar * q);
+                        const uint32_t u = w & kSlotMask;
+                        if (u != kSlotMask) {
+                            const F d = (w & kSneg) ? -(rbar * al) : rbar * al;
+                            if (FLOOD) {
+                                if (ptgt[c] == u || ptgt[c] == kSlotMask) {
+                                    ptgt[c] = u;
+                                    pacc[c] += d;
+                                } else {
+                                    stgt[c] = u;
+                                    sacc[c] += d;
+                                }
+                            } else if (u < i) {
+                                pacc[c] = ptgt[c] == kSlotMask ? d : pacc[c] + d;
+                                ptgt[c] = u;
+                            } else if (stgt[c] != u) {
+                                if (stgt[c] != kSlotMask) mbn[stgt[c]] = sacc[c];
+                                stgt[c] = u;
+                                sacc[c] = d;
+                            } else {
+                                sacc[c] += d;
+                            }
+                        }
+                    }
+                    chunk_fence();
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
+            }
+            __syncthreads();
+            for (uint32_t c = lane; c < g.m; c += kWave) {
+                if (stgt[c] != kSlotMask) mbn[stgt[c]] = sacc[c];
+                if (FLOOD && ptgt[c] != kSlotMask) mbn[ptgt[c]] = pacc[c];
             }
             abar = wave_sum(abar);
             if (lane == t - 1) abar_acc += abar;
             __syncthreads();
-            F* tmp = mb_new;
-            mb_new = mb_old;
-            mb_old = tmp;
+            F* tmp = const_cast<F*>(mbp);
+            mbp = mbn;
+            mbn = tmp;
         }
-        // the messages before iteration 1 are lambda itself
+        // the old messages of iteration 1 are lambda itself
         for (uint32_t k = 0; k < nch; k++) {
             const uint32_t meta = meta_of(k), v = v_of(k);
-            const uint32_t deg = (meta >> kMetaDegShift) & 15u, dmax = uni((meta >> kMetaDmaxShift) & 15u);
+            const uint32_t deg = deg_of(meta), dmax = uni((meta >> kMetaDmaxShift) & 15u);
             const uint32_t seg = (meta >> 16) & 15u;
             const uint32_t i = k * kWave + lane;
-            const F x = deg ? aload(&mb_new[i]) : F(0);
-            const F lv = deg ? lam[v] : F(0);
-            const F gm = (lv <= lim && lv >= -lim) ? x : F(0);
+            const F x = deg ? aload(&mbp[i]) : F(0);
+            const F gm = (deg && (rw[i] & kLnc)) ? x : F(0);
             F all = F(0);
-            const int b0 = lane - (int)seg;
+            const int b0 = (int)lane - (int)seg;
             for (uint32_t jj = 0; jj < dmax; jj++) {
-                const F gj = shfl_f(gm, (b0 + (int)jj) & (kWave - 1));
+                const F gj = __shfl(gm, (b0 + (int)jj) & (kWave - 1));
                 if (jj < deg) all += gj;
             }
             if (deg && seg == 0) unsafeAtomicAdd(&lbar_row[v], (double)all);
@@ -421,7 +527,7 @@ __global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a
         __syncthreads();
     }
     if (lane == 0) a.loss_rows[blockIdx.x] = loss_acc;
-    if (lane < a.K) a.abar_rows[(size_t)blockIdx.x * a.K + lane] = abar_acc;
+    if (lane < K) a.abar_rows[(size_t)blockIdx.x * K + lane] = abar_acc;
 }
 
 // out[j] = sum over rows r of in[r * width + j]: eight partial sums over the
@@ -452,7 +558,7 @@ const void* grad_fn() {
 
 // grad launch limits: blocks (one wavefront each) and their scratch in total
 constexpr uint64_t kGradMaxGrid = 8192;
-constexpr uint64_t kGradScratchBudget = 16ull << 30;
+constexpr uint64_t kGradScratchBudget = 40ull << 30;
 
 size_t grad_scratch_per_block(const DevGraph& g, uint32_t K) {
     return grad_layout((size_t)g.max_chunks * kWave, g.n, g.m, K, g.fp64 ? 8 : 4).bytes;
@@ -460,12 +566,28 @@ size_t grad_scratch_per_block(const DevGraph& g, uint32_t K) {
 
 size_t grad_lds_bytes(const DevGraph& g) {
     const size_t fb = g.fp64 ? 8 : 4;
-    return 8ull * g.words_m + (fb + 4) * g.m + 16;
+    return 8ull * g.words_m + (3 * fb + 12) * g.m + 16;
+}
+
+const void* grad_kernel_for(const DevGraph& g) {
+    return g.fp64 ? (g.flood ? grad_fn<double, true>() : grad_fn<double, false>())
+                  : (g.flood ? grad_fn<float, true>() : grad_fn<float, false>());
+}
+
+// blocks of the gradient kernel resident on the whole device at once
+int grad_resident_blocks(const DevGraph& g) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return 1024;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, grad_kernel_for(g), kWave, grad_lds_bytes(g)) !=
+            hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return per_cu * cus;
 }
 
 int launch_grad(const DevGraph& g, const GradLaunch& a, hipStream_t st) {
-    const void* fn = g.fp64 ? (g.flood ? grad_fn<double, true>() : grad_fn<double, false>())
-                            : (g.flood ? grad_fn<float, true>() : grad_fn<float, false>());
+    const void* fn = grad_kernel_for(g);
     const size_t lds = grad_lds_bytes(g);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -498,14 +620,18 @@ extern "C" int vibe_bp_grad(vibe_graph* G, const uint8_t* syndromes, uint64_t B,
     if (!syndromes || !lam || !alpha || !loss || !dlam || !dalpha) return fail(VIBE_EINVAL, "NULL argument");
     if (!(eps > 0.0 && eps < 0.5)) return fail(VIBE_EINVAL, "eps must be in (0, 0.5)");
     const DevGraph& g = G->h.dg;
+    if ((uint64_t)g.max_chunks * kWave >= kSlotMask)
+        return fail(VIBE_EUNSUPPORTED, "graph too large for the gradient (slots per member >= 2^24 - 1)");
     const uint64_t items64 = B * g.L;
     if (items64 > (1u << 24)) return fail(VIBE_EINVAL, "B x L must be at most 2^24");
     const uint32_t items = (uint32_t)items64;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t per = grad_scratch_per_block(g, K);
-    // one block per resident wavefront slot at most, within the scratch budget
+    // as many blocks as can be resident at once (items are assigned
+    // statically, so more would only queue), within the scratch budget
     const uint64_t fit = std::max<uint64_t>(1, kGradScratchBudget / std::max<size_t>(per, 1));
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(items, std::min<uint64_t>(kGradMaxGrid, fit));
+    const uint64_t resident = std::max<uint64_t>(1, (uint64_t)grad_resident_blocks(g));
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(items, std::min<uint64_t>(std::min(kGradMaxGrid, resident), fit));
     // workspace: per-block loss, lambda-bar and alpha-bar rows | scratch
     auto round256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off = 0;
