@@ -114,6 +114,7 @@ __device__ inline F clampv(F x, F lim) {
 
 __device__ inline double aload(const double* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 __device__ inline float aload(const float* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline uint32_t aload(const uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
 template <class F>
 __device__ inline F wave_sum(F x) {
@@ -130,7 +131,7 @@ __device__ inline void chunk_fence() {
 }
 
 struct GradBufs {
-    size_t lamS, msgA, msgB, sufst, sufarg, rq, rw, mbA, mbB, Lfin, Lbar, dl;
+    size_t lamS, msgA, msgB, sufst, sufarg, rq, rw, mbA, mbB, Lfin, Lbar, colA, colB, cS, csg, dl;
     size_t bytes;
 };
 
@@ -155,6 +156,10 @@ __host__ __device__ inline GradBufs grad_layout(size_t S, size_t n, size_t m, ui
     b.mbB = take(fb * S);
     b.Lfin = take(fb * n);       // final posteriors (unclamped)
     b.Lbar = take(fb * n);       // d loss / d L_v (0 where L_v was clamped)
+    b.colA = take(fb * n);       // per-column terms of the loss stage
+    b.colB = take(fb * n);
+    b.cS = take(fb * m);         // per-check terms of the loss stage
+    b.csg = take(4 * m);
     b.dl = take(8 * m);          // d loss / d shat_c
     b.bytes = off;
     return b;
@@ -179,8 +184,113 @@ struct GradLaunch {
 
 namespace {
 
+// The loss of one item from its final posteriors L (unclamped, n) and its
+// gradient Lbar = d loss / d L_v (0 where L_v was clamped); returns the
+// loss (every lane).  shat_c = (1 - prod_v t_v) / 2 with t_v = tanh(L_v / 2).
+// FP64 messages: the product in the row's column order, as the definition
+// reads.  FP32 messages: in the log domain, which keeps shat_c accurate when
+// it is tiny: with a_v = |L_v| and e_v = exp(-a_v),
+//   log tanh(a_v / 2) = log1p(-e_v) - log1p(e_v) = l_v,  |prod| = exp(S_c),
+//   S_c = sum_v l_v, shat_c = -expm1(S_c) / 2 if the sign product is +1,
+// and dt_v / dL_v = (1 - t_v^2) / 2 = 2 e_v / (1 + e_v)^2.  l_v is bounded
+// below by -80 so that exp(S_c - l_v), the product without v, stays finite.
+template <class F>
+__device__ double loss_stage(const DevGraph& g, const uint8_t* s, double eps, const F* Lfin, F* Lbar, F* colA,
+                             F* colB, F* cS, uint32_t* csg, double* dl) {
+    const uint32_t lane = threadIdx.x;
+    const F lim = (F)g.clamp;
+    double loss = 0.0;
+    // per column: FP64 t_v; FP32 l_v and e_v
+    for (uint32_t v = lane; v < g.n; v += kWave) {
+        if (g.cp[v + 1] == g.cp[v]) continue;  // in no check
+        const F L = clampv(aload(&Lfin[v]), lim);
+        if constexpr (sizeof(F) == 8) {
+            colA[v] = tanh(L / 2.0);
+        } else {
+            const float e = expf(-fabsf(L));
+            colA[v] = fmaxf(log1pf(-e) - log1pf(e), -80.0f);
+            colB[v] = e;
+        }
+    }
+    __syncthreads();
+    for (uint32_t c = lane; c < g.m; c += kWave) {
+        const bool sc = s[c] != 0;
+        double sh, sh1;  // shat_c and 1 - shat_c
+        if constexpr (sizeof(F) == 8) {
+            double prod = 1.0;
+            for (uint32_t kk = g.rp[c]; kk < g.rp[c + 1]; kk++) prod *= aload(&colA[g.ri[kk]]);
+            sh = 0.5 * (1.0 - prod);
+            sh1 = 1.0 - sh;
+        } else {
+            float S = 0.0f;
+            uint32_t neg = 0;
+            for (uint32_t kk = g.rp[c]; kk < g.rp[c + 1]; kk++) {
+                const uint32_t u = g.ri[kk];
+                S += aload(&colA[u]);
+                neg ^= aload(&Lfin[u]) < 0.0f ? 1u : 0u;
+            }
+            cS[c] = S;
+            csg[c] = neg;
+            const float small = -0.5f * expm1f(S), big = 0.5f * (1.0f + expf(S));
+            sh = neg ? big : small;
+            sh1 = neg ? small : big;
+        }
+        double d = 0.0;
+        if (sh < eps || sh1 < eps) {
+            if (sh < eps) {
+                sh = eps;
+                sh1 = 1.0 - eps;
+            } else {
+                sh1 = eps;
+                sh = 1.0 - eps;
+            }
+        } else {
+            d = sc ? -1.0 / sh : 1.0 / sh1;
+        }
+        if constexpr (sizeof(F) == 8)
+            loss -= sc ? log(sh) : log(sh1);
+        else
+            loss -= (double)logf((float)(sc ? sh : sh1));
+        dl[c] = d;
+    }
+    __syncthreads();
+    for (uint32_t v = lane; v < g.n; v += kWave) {
+        const F Lv = aload(&Lfin[v]);
+        double gsum = 0.0;
+        if (g.cp[v + 1] > g.cp[v] && Lv <= lim && Lv >= -lim) {
+            for (uint32_t j = g.cp[v]; j < g.cp[v + 1]; j++) {
+                const uint32_t c = g.ci[j];
+                if constexpr (sizeof(F) == 8) {
+                    const double tv = aload(&colA[v]);
+                    double ex = 1.0;
+                    for (uint32_t kk = g.rp[c]; kk < g.rp[c + 1]; kk++) {
+                        const uint32_t u = g.ri[kk];
+                        if (u != v) ex *= aload(&colA[u]);
+                    }
+                    gsum += aload(&dl[c]) * (-0.25 * ex * (1.0 - tv * tv));
+                } else {
+                    const float e = aload(&colB[v]);
+                    const float sech2_half = 2.0f * e / ((1.0f + e) * (1.0f + e));  // dt_v / dL_v
+                    const bool neg = (aload(&csg[c]) != 0) != (Lv < 0.0f);
+                    const float ex = expf(aload(&cS[c]) - aload(&colA[v]));  // |prod without v|
+                    gsum += aload(&dl[c]) * (-0.5 * (double)sech2_half * (double)(neg ? -ex : ex));
+                }
+            }
+        }
+        Lbar[v] = (F)gsum;
+    }
+    return wave_sum(loss);
+}
+
+// waves per SIMD the register allocation aims at (FP32: 6 fit without spills)
+template <class F>
+constexpr int grad_waves() {
+    return sizeof(F) == 4 ? 6 : 3;
+}
+
 template <class F, bool FLOOD>
-__global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_waves<F>()))) void bp_grad_kernel(
+    DevGraph g, GradLaunch a) {
     using P = GP<F>;
     using B = typename P::B;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -210,6 +320,10 @@ __global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a
     F* mbB = reinterpret_cast<F*>(base + lay.mbB);
     F* Lfin = reinterpret_cast<F*>(base + lay.Lfin);
     F* Lbar = reinterpret_cast<F*>(base + lay.Lbar);
+    F* colA = reinterpret_cast<F*>(base + lay.colA);
+    F* colB = reinterpret_cast<F*>(base + lay.colB);
+    F* cS = reinterpret_cast<F*>(base + lay.cS);
+    uint32_t* csg = reinterpret_cast<uint32_t*>(base + lay.csg);
     double* dl = reinterpret_cast<double*>(base + lay.dl);
     const uint32_t n_items = a.B * g.L;
     const uint32_t K = a.K;
@@ -361,42 +475,8 @@ __global__ __launch_bounds__(kWave) void bp_grad_kernel(DevGraph g, GradLaunch a
             __syncthreads();
         }
 
-        // ---- loss and d loss / d L, in FP64 whatever the message precision
-        double loss = 0.0;
-        const double dlim = g.clamp;
-        for (uint32_t c = lane; c < g.m; c += kWave) {
-            double prod = 1.0;
-            for (uint32_t kk = g.rp[c]; kk < g.rp[c + 1]; kk++)
-                prod *= tanh(clampv((double)aload(&Lfin[g.ri[kk]]), dlim) / 2.0);
-            double sh = 0.5 * (1.0 - prod), d = 0.0;
-            const bool sc = s[c] != 0;
-            if (sh < a.eps || sh > 1.0 - a.eps) {
-                sh = sh < a.eps ? a.eps : 1.0 - a.eps;
-            } else {
-                d = sc ? -1.0 / sh : 1.0 / (1.0 - sh);
-            }
-            loss -= sc ? log(sh) : log(1.0 - sh);
-            dl[c] = d;
-        }
-        loss_acc += wave_sum(loss);
-        __syncthreads();
-        for (uint32_t v = lane; v < g.n; v += kWave) {
-            const double Lv = (double)aload(&Lfin[v]);
-            double gsum = 0.0;
-            if (g.cp[v + 1] > g.cp[v] && Lv <= dlim && Lv >= -dlim) {
-                const double tv = tanh(Lv / 2.0);
-                for (uint32_t j = g.cp[v]; j < g.cp[v + 1]; j++) {
-                    const uint32_t c = g.ci[j];
-                    double ex = 1.0;
-                    for (uint32_t kk = g.rp[c]; kk < g.rp[c + 1]; kk++) {
-                        const uint32_t u = g.ri[kk];
-                        if (u != v) ex *= tanh(clampv((double)aload(&Lfin[u]), dlim) / 2.0);
-                    }
-                    gsum += aload(&dl[c]) * (-0.25 * ex * (1.0 - tv * tv));
-                }
-            }
-            Lbar[v] = (F)gsum;
-        }
+        // ---- loss and d loss / d L (Lfin was written by other lanes)
+        loss_acc += loss_stage<F>(g, s, a.eps, Lfin, Lbar, colA, colB, cS, csg, dl);
         __syncthreads();
 
         // ---- reverse
