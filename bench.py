@@ -49,20 +49,23 @@ BYTES_PER_EDGE_UPDATE = 8.0
 
 PROFILE = os.path.join(ROOT, "profiles", "bp_ensemble_kernel_circuit_d9_r9_p1e-3.txt")
 KERNEL_SOURCES = ("bp.hip", "internal.h", "graph.hip")
+GRAD_PROFILE = os.path.join(ROOT, "profiles", "bp_grad_kernel_circuit_d5_r5_p1e-3.txt")
+GRAD_SOURCES = ("grad.hip", "internal.h", "graph.hip")
 
 
-def measured_traffic(launch_shots):
-    """HBM bytes per BP launch from the committed counter summary, if it was
-    taken on this kernel source at this launch size; else None."""
+def measured_traffic(launch_shots, profile=PROFILE, sources=KERNEL_SOURCES, key="traffic_launch_shots"):
+    """HBM bytes per launch of a kernel from its committed counter summary, if
+    the counters were taken on the same kernel sources at the same launch
+    size; else None."""
     try:
-        lines = open(PROFILE).read().splitlines()
+        lines = open(profile).read().splitlines()
     except OSError:
         return None
-    src = "".join(open(os.path.join(ROOT, "paper_2508_15743_amd", "csrc", f)).read() for f in KERNEL_SOURCES)
+    src = "".join(open(os.path.join(ROOT, "paper_2508_15743_amd", "csrc", f)).read() for f in sources)
     sha = hashlib.sha256(src.encode()).hexdigest()[:16]
-    vals = dict(l.split()[:2] for l in lines if l.startswith(("source_sha256_16 ", "traffic_launch_shots ",
+    vals = dict(l.split()[:2] for l in lines if l.startswith(("source_sha256_16 ", key + " ",
                                                                 "traffic_bytes_per_launch ")))
-    if vals.get("source_sha256_16") != sha or vals.get("traffic_launch_shots") != str(launch_shots):
+    if vals.get("source_sha256_16") != sha or vals.get(key) != str(launch_shots):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -141,7 +144,9 @@ def grad_leg(P, torch, seed, batch, K):
            "shots_per_s": round(batch / sec, 1), "edge_iterations_per_s": edge_iters / sec,
            "loss": float(loss.item()), "grad_finite": bool(torch.isfinite(dlam).all() and torch.isfinite(dalpha).all()),
            "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "bp_grad_kernel"}}
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic(batch, GRAD_PROFILE, GRAD_SOURCES, "traffic_launch_batch"),
+                        "kernel": "bp_grad_kernel"}}
     log(f"grad: {batch} shots x {L} members x K={K} in {1e3 * sec:.1f} ms = {batch / sec:.0f} shots/s, "
         f"{achieved:.0f} GB/s algorithmic")
     G.close()
@@ -238,6 +243,7 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--grad-batch", type=int, default=4096)
     ap.add_argument("--grad-K", type=int, default=16)
+    ap.add_argument("--grad-only", action="store_true", help="run only the gradient leg (for profiling)")
     ap.add_argument("--serving-seconds", type=float, default=3.0, help="length of each offered-load run")
     ap.add_argument("--ragged-shots", type=str, default="128,1024", help="shots per code in the ragged leg")
     ap.add_argument("--copy-probe", action="store_true",
@@ -264,6 +270,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log("copy probe: 3 copies of 1 GiB")
+        return
+
+    if args.grad_only:
+        print(json.dumps({"grad": grad_leg(P, torch, args.seed, args.grad_batch, args.grad_K)}), flush=True)
         return
 
     d, rounds, p = 9, 9, 1e-3

@@ -124,6 +124,12 @@ __device__ inline F wave_sum(F x) {
 
 __device__ inline uint32_t deg_of(uint32_t meta) { return (meta >> kMetaDegShift) & 15u; }
 
+// edges in a chunk (its first lanes), from every lane's meta word
+__device__ inline uint32_t edges_of(uint32_t meta) { return uni((uint32_t)__popcll(__ballot(deg_of(meta) != 0))); }
+
+// XCDs of the device: workgroups are dispatched to them round-robin
+constexpr uint32_t kXcds = 8;
+
 // keeps the compiler from moving LDS traffic of one chunk past the next's
 __device__ inline void chunk_fence() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -135,8 +141,10 @@ struct GradBufs {
     size_t bytes;
 };
 
-// Per-block scratch layout, for S slots (max_chunks * 64), n columns, m checks
-// and K iterations, message size fb.
+// Per-block scratch layout, for E edges (slot arrays are compact: a chunk's
+// edges sit on its first lanes, so the edge of lane l in chunk k has index
+// base_k + l, base_k = edges in the member's earlier chunks), n columns,
+// m checks and K iterations, message size fb.
 __host__ __device__ inline GradBufs grad_layout(size_t S, size_t n, size_t m, uint32_t K, size_t fb) {
     GradBufs b;
     size_t off = 0;
@@ -306,7 +314,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
     const F* alpha = reinterpret_cast<const F*>(a.alpha);
     const F lim = (F)g.clamp;
     const B ident = P::ident(g);
-    const uint32_t S = g.max_chunks * kWave;
+    const uint32_t S = g.E;  // edges of every member
     const GradBufs lay = grad_layout(S, g.n, g.m, a.K, sizeof(F));
     unsigned char* base = static_cast<unsigned char*>(a.scratch) + (size_t)blockIdx.x * a.scratch_per_block;
     F* lamS = reinterpret_cast<F*>(base + lay.lamS);
@@ -325,15 +333,25 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
     F* cS = reinterpret_cast<F*>(base + lay.cS);
     uint32_t* csg = reinterpret_cast<uint32_t*>(base + lay.csg);
     double* dl = reinterpret_cast<double*>(base + lay.dl);
-    const uint32_t n_items = a.B * g.L;
     const uint32_t K = a.K;
+    // items (shot, member): with at least one member per XCD, the blocks of
+    // one XCD (dispatched round-robin, block b to XCD b mod 8) take the
+    // members of one eighth of the ensemble, so the chunk records they read
+    // stay in that XCD's L2
+    const bool grouped = g.L >= kXcds && gridDim.x >= kXcds;
+    const uint32_t xcd = blockIdx.x % kXcds;
+    const uint32_t mlo = grouped ? xcd * g.L / kXcds : 0u;
+    const uint32_t gsz = grouped ? (xcd + 1) * g.L / kXcds - mlo : g.L;
+    const uint32_t z0 = grouped ? blockIdx.x / kXcds : blockIdx.x;
+    const uint32_t zstep = grouped ? (gridDim.x - xcd + kXcds - 1) / kXcds : gridDim.x;
+    const uint32_t n_z = a.B * gsz;
     const uint32_t rb = rec_bytes(sizeof(F) == 8);
     double* lbar_row = a.lbar_rows + (size_t)blockIdx.x * g.n;
     for (uint32_t v = lane; v < g.n; v += kWave) lbar_row[v] = 0.0;
     double loss_acc = 0.0, abar_acc = 0.0;  // abar_acc: iteration lane + 1
 
-    for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const uint32_t shot = item / g.L, mem = item % g.L;
+    for (uint32_t z = z0; z < n_z; z += zstep) {
+        const uint32_t shot = z / gsz, mem = mlo + z % gsz;
         const uint8_t* s = a.syndromes + (size_t)shot * g.m;
         for (uint32_t b0 = 0; b0 < g.m; b0 += kWave) {
             const uint32_t c = b0 + lane;
@@ -346,14 +364,15 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
         auto v_of = [&](uint32_t k) { return *reinterpret_cast<const uint32_t*>(recs + (size_t)k * rb + kRecV + 4u * lane); };
         auto synd_bit = [&](uint32_t c) { return ((sb[c >> 6] >> (c & 63)) & 1ull) != 0; };
 
-        // lambda per slot and the messages before iteration 1
-        for (uint32_t k = 0; k < nch; k++) {
+        // lambda per edge and the messages before iteration 1
+        for (uint32_t k = 0, base0 = 0; k < nch; k++) {
             const uint32_t meta = meta_of(k);
             if (deg_of(meta)) {
                 const F lr = lam[v_of(k)];
-                lamS[k * kWave + lane] = lr;
-                msgA[k * kWave + lane] = clampv(lr, lim);
+                lamS[base0 + lane] = lr;
+                msgA[base0 + lane] = clampv(lr, lim);
             }
+            base0 += edges_of(meta);
         }
         __syncthreads();
 
@@ -373,16 +392,18 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
             __syncthreads();
             {
                 uint32_t mA = nch ? meta_of(nch - 1) : 0u;
-                F xA = (nch && deg_of(mA)) ? old[(nch - 1) * kWave + lane] : F(0);
+                uint32_t bA = nch ? S - edges_of(mA) : 0u;
+                F xA = (nch && deg_of(mA)) ? old[bA + lane] : F(0);
                 uint32_t mB = nch > 1 ? meta_of(nch - 2) : 0u;
                 for (uint32_t k = nch; k-- > 0;) {
-                    const uint32_t meta = mA;
+                    const uint32_t meta = mA, base_k = bA;
                     const F x = xA;
                     mA = mB;
-                    xA = (k > 0 && deg_of(mA)) ? old[(k - 1) * kWave + lane] : F(0);
+                    if (k > 0) bA = base_k - edges_of(mA);
+                    xA = (k > 0 && deg_of(mA)) ? old[bA + lane] : F(0);
                     mB = k > 1 ? meta_of(k - 2) : 0u;
                     if (deg_of(meta)) {
-                        const uint32_t c = meta & 0xffffu, i = k * kWave + lane;
+                        const uint32_t c = meta & 0xffffu, i = base_k + lane;
                         RS<F> run{pst[c], parg[c]};
                         sufst[i] = run.st;
                         sufarg[i] = run.arg;
@@ -401,7 +422,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
 
             // the sweep
             {
-                uint32_t mA = nch ? meta_of(0) : 0u, vA = nch ? v_of(0) : 0u;
+                uint32_t mA = nch ? meta_of(0) : 0u, vA = nch ? v_of(0) : 0u, bA = 0;
                 B sA = ident;
                 uint32_t aA = kNoArg;
                 F lA = F(0), oA = F(0);
@@ -413,14 +434,15 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                 }
                 uint32_t mB = nch > 1 ? meta_of(1) : 0u, vB = nch > 1 ? v_of(1) : 0u;
                 for (uint32_t k = 0; k < nch; k++) {
-                    const uint32_t meta = mA, v = vA;
+                    const uint32_t meta = mA, v = vA, base_k = bA;
                     const B sst = sA;
                     const uint32_t sarg = aA;
                     const F lr = lA, xo = oA;
+                    bA = base_k + edges_of(meta);
                     mA = mB;
                     vA = vB;
                     if (k + 1 < nch && deg_of(mA)) {
-                        const uint32_t i1 = (k + 1) * kWave + lane;
+                        const uint32_t i1 = bA + lane;
                         sA = sufst[i1];
                         aA = sufarg[i1];
                         lA = lamS[i1];
@@ -432,7 +454,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                     }
                     const uint32_t deg = deg_of(meta), dmax = uni((meta >> kMetaDmaxShift) & 15u);
                     const uint32_t c = meta & 0xffffu, seg = (meta >> 16) & 15u;
-                    const uint32_t i = k * kWave + lane;
+                    const uint32_t i = base_k + lane;
                     F q = F(0);
                     uint32_t w = 0;
                     const RS<F> pre{pst[c], parg[c]};
@@ -497,10 +519,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
             double abar = 0.0;
             {
                 uint32_t mA = nch ? meta_of(nch - 1) : 0u, vA = nch ? v_of(nch - 1) : 0u;
+                uint32_t bA = nch ? S - edges_of(mA) : 0u;
                 F qA = F(0), gA = F(0), glA = F(0);
                 uint32_t wA = 0;
                 if (nch && deg_of(mA)) {
-                    const uint32_t i1 = (nch - 1) * kWave + lane;
+                    const uint32_t i1 = bA + lane;
                     qA = rqt[i1];
                     wA = rwt[i1];
                     if (!last) gA = aload(&mbp[i1]);
@@ -508,12 +531,13 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                 }
                 uint32_t mB = nch > 1 ? meta_of(nch - 2) : 0u, vB = nch > 1 ? v_of(nch - 2) : 0u;
                 for (uint32_t k = nch; k-- > 0;) {
-                    const uint32_t meta = mA, v = vA, w = wA;
+                    const uint32_t meta = mA, v = vA, w = wA, base_k = bA;
                     const F q = qA, gprev = gA, GLv = glA;
                     mA = mB;
                     vA = vB;
+                    if (k > 0) bA = base_k - edges_of(mA);
                     if (k > 0 && deg_of(mA)) {
-                        const uint32_t i1 = (k - 1) * kWave + lane;
+                        const uint32_t i1 = bA + lane;
                         qA = rqt[i1];
                         wA = rwt[i1];
                         if (!last) gA = aload(&mbp[i1]);
@@ -525,7 +549,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                     }
                     const uint32_t deg = deg_of(meta), dmax = uni((meta >> kMetaDmaxShift) & 15u);
                     const uint32_t c = meta & 0xffffu, seg = (meta >> 16) & 15u;
-                    const uint32_t i = k * kWave + lane;
+                    const uint32_t i = base_k + lane;
                     F gin = last ? F(0) : gprev;
                     if (deg) {
                         if (!FLOOD && ptgt[c] == i) {  // the prefix argmin reached: take its adjoint
@@ -588,11 +612,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
             mbn = tmp;
         }
         // the old messages of iteration 1 are lambda itself
-        for (uint32_t k = 0; k < nch; k++) {
+        for (uint32_t k = 0, base0 = 0; k < nch; k++) {
             const uint32_t meta = meta_of(k), v = v_of(k);
             const uint32_t deg = deg_of(meta), dmax = uni((meta >> kMetaDmaxShift) & 15u);
             const uint32_t seg = (meta >> 16) & 15u;
-            const uint32_t i = k * kWave + lane;
+            const uint32_t i = base0 + lane;
+            base0 += edges_of(meta);
             const F x = deg ? aload(&mbp[i]) : F(0);
             const F gm = (deg && (rw[i] & kLnc)) ? x : F(0);
             F all = F(0);
@@ -641,7 +666,7 @@ constexpr uint64_t kGradMaxGrid = 8192;
 constexpr uint64_t kGradScratchBudget = 40ull << 30;
 
 size_t grad_scratch_per_block(const DevGraph& g, uint32_t K) {
-    return grad_layout((size_t)g.max_chunks * kWave, g.n, g.m, K, g.fp64 ? 8 : 4).bytes;
+    return grad_layout(g.E, g.n, g.m, K, g.fp64 ? 8 : 4).bytes;
 }
 
 size_t grad_lds_bytes(const DevGraph& g) {
@@ -700,8 +725,7 @@ extern "C" int vibe_bp_grad(vibe_graph* G, const uint8_t* syndromes, uint64_t B,
     if (!syndromes || !lam || !alpha || !loss || !dlam || !dalpha) return fail(VIBE_EINVAL, "NULL argument");
     if (!(eps > 0.0 && eps < 0.5)) return fail(VIBE_EINVAL, "eps must be in (0, 0.5)");
     const DevGraph& g = G->h.dg;
-    if ((uint64_t)g.max_chunks * kWave >= kSlotMask)
-        return fail(VIBE_EUNSUPPORTED, "graph too large for the gradient (slots per member >= 2^24 - 1)");
+    if ((uint64_t)g.E >= kSlotMask) return fail(VIBE_EUNSUPPORTED, "graph too large for the gradient (E >= 2^24 - 1)");
     const uint64_t items64 = B * g.L;
     if (items64 > (1u << 24)) return fail(VIBE_EINVAL, "B x L must be at most 2^24");
     const uint32_t items = (uint32_t)items64;
