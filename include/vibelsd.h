@@ -277,7 +277,13 @@ void vibe_server_destroy(vibe_server* s); /* finishes every queued request first
  * and shat_c summed over the checks.  Outputs (device, double): loss (1) =
  * sum over the B x L (shot, member) items, dlam (n) and dalpha (K) = its
  * gradient.  The gradient is exact wherever no argmin, sign or clamp changes
- * (a piecewise-smooth function).  Deterministic.  B x L <= 2^24, K <= 64.
+ * (a piecewise-smooth function).  Deterministic: the same inputs give the
+ * same bits.  syndromes: device, B x m bytes, row-major.
+ * Limits: 1 <= K <= 64, B >= 1, B x L <= 2^24, 0 < eps < 0.5, fewer than
+ * 2^24 - 1 edges; VIBE_EINVAL / VIBE_EUNSUPPORTED otherwise.  The first call
+ * on a graph builds its gradient schedule (device memory freed with the
+ * graph); every call may grow the graph's workspace, like vibe_decode.
+ * Calls on one graph must not overlap.
  */
 int vibe_bp_grad(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint32_t K, const void* lam,
                  const void* alpha, double eps, double* loss, double* dlam, double* dalpha, void* stream);

@@ -176,15 +176,17 @@ __host__ __device__ inline GradBufs grad_layout(size_t S, size_t n, size_t m, ui
 }  // namespace
 
 struct GradLaunch {
-    const uint8_t* syndromes;  // B x m
-    uint32_t B;                // shots
+    const uint8_t* syndromes;       // B x m
+    uint32_t B;                     // shots
     uint32_t K;
-    const void* lam;           // n, message precision
-    const void* alpha;         // K
+    const void* lam;                // n, message precision
+    const void* alpha;              // K
     double eps;
-    double* loss_rows;         // grid: per-block sums
-    double* lbar_rows;         // grid x n
-    double* abar_rows;         // grid x K
+    const unsigned char* recs;      // gradient schedule: per chunk meta[W] then v[W]
+    const uint32_t* member_chunk;   // L + 1
+    double* loss_rows;              // grid: per-block sums
+    double* lbar_rows;              // grid x n
+    double* abar_rows;              // grid x K
     void* scratch;
     size_t scratch_per_block;
     int grid;
@@ -192,53 +194,57 @@ struct GradLaunch {
 
 namespace {
 
-// The loss of one item from its final posteriors L (unclamped, n) and its
-// gradient Lbar = d loss / d L_v (0 where L_v was clamped); returns the
-// loss (every lane).  shat_c = (1 - prod_v t_v) / 2 with t_v = tanh(L_v / 2).
-// FP64 messages: the product in the row's column order, as the definition
-// reads.  FP32 messages: in the log domain, which keeps shat_c accurate when
-// it is tiny: with a_v = |L_v| and e_v = exp(-a_v),
+// The loss of the P items of a wavefront (item p of column v at v * P + p,
+// of check c at c * P + p; items p >= nact are idle) from their final
+// posteriors L (unclamped) and the gradient Lbar = d loss / d L_v (0 where
+// L_v was clamped); returns the summed loss (every lane).
+// shat_c = (1 - prod_v t_v) / 2 with t_v = tanh(L_v / 2).  FP64 messages:
+// the product in the row's column order, as the definition reads.  FP32
+// messages: in the log domain, which keeps shat_c accurate when it is tiny:
+// with a_v = |L_v| and e_v = exp(-a_v),
 //   log tanh(a_v / 2) = log1p(-e_v) - log1p(e_v) = l_v,  |prod| = exp(S_c),
 //   S_c = sum_v l_v, shat_c = -expm1(S_c) / 2 if the sign product is +1,
 // and dt_v / dL_v = (1 - t_v^2) / 2 = 2 e_v / (1 + e_v)^2.  l_v is bounded
 // below by -80 so that exp(S_c - l_v), the product without v, stays finite.
-template <class F>
-__device__ double loss_stage(const DevGraph& g, const uint8_t* s, double eps, const F* Lfin, F* Lbar, F* colA,
-                             F* colB, F* cS, uint32_t* csg, double* dl) {
+template <class F, int P>
+__device__ double loss_stage(const DevGraph& g, const uint64_t* sb, uint32_t nact, double eps, const F* Lfin,
+                             F* Lbar, F* colA, F* colB, F* cS, uint32_t* csg, double* dl) {
     const uint32_t lane = threadIdx.x;
     const F lim = (F)g.clamp;
     double loss = 0.0;
     // per column: FP64 t_v; FP32 l_v and e_v
-    for (uint32_t v = lane; v < g.n; v += kWave) {
+    for (uint32_t x = lane; x < g.n * P; x += kWave) {
+        const uint32_t v = x / P;
         if (g.cp[v + 1] == g.cp[v]) continue;  // in no check
-        const F L = clampv(aload(&Lfin[v]), lim);
+        const F L = clampv(aload(&Lfin[x]), lim);
         if constexpr (sizeof(F) == 8) {
-            colA[v] = tanh(L / 2.0);
+            colA[x] = tanh(L / 2.0);
         } else {
             const float e = expf(-fabsf(L));
-            colA[v] = fmaxf(log1pf(-e) - log1pf(e), -80.0f);
-            colB[v] = e;
+            colA[x] = fmaxf(log1pf(-e) - log1pf(e), -80.0f);
+            colB[x] = e;
         }
     }
     __syncthreads();
-    for (uint32_t c = lane; c < g.m; c += kWave) {
-        const bool sc = s[c] != 0;
+    for (uint32_t x = lane; x < g.m * P; x += kWave) {
+        const uint32_t c = x / P, p = x % P;
+        const bool sc = ((sb[(c >> 6) * P + p] >> (c & 63)) & 1ull) != 0;
         double sh, sh1;  // shat_c and 1 - shat_c
         if constexpr (sizeof(F) == 8) {
             double prod = 1.0;
-            for (uint32_t kk = g.rp[c]; kk < g.rp[c + 1]; kk++) prod *= aload(&colA[g.ri[kk]]);
+            for (uint32_t kk = g.rp[c]; kk < g.rp[c + 1]; kk++) prod *= aload(&colA[g.ri[kk] * P + p]);
             sh = 0.5 * (1.0 - prod);
             sh1 = 1.0 - sh;
         } else {
             float S = 0.0f;
             uint32_t neg = 0;
             for (uint32_t kk = g.rp[c]; kk < g.rp[c + 1]; kk++) {
-                const uint32_t u = g.ri[kk];
+                const uint32_t u = g.ri[kk] * P + p;
                 S += aload(&colA[u]);
                 neg ^= aload(&Lfin[u]) < 0.0f ? 1u : 0u;
             }
-            cS[c] = S;
-            csg[c] = neg;
+            cS[x] = S;
+            csg[x] = neg;
             const float small = -0.5f * expm1f(S), big = 0.5f * (1.0f + expf(S));
             sh = neg ? big : small;
             sh1 = neg ? small : big;
@@ -255,37 +261,40 @@ __device__ double loss_stage(const DevGraph& g, const uint8_t* s, double eps, co
         } else {
             d = sc ? -1.0 / sh : 1.0 / sh1;
         }
+        double term;
         if constexpr (sizeof(F) == 8)
-            loss -= sc ? log(sh) : log(sh1);
+            term = sc ? log(sh) : log(sh1);
         else
-            loss -= (double)logf((float)(sc ? sh : sh1));
-        dl[c] = d;
+            term = (double)logf((float)(sc ? sh : sh1));
+        if (p < nact) loss -= term;
+        dl[x] = d;
     }
     __syncthreads();
-    for (uint32_t v = lane; v < g.n; v += kWave) {
-        const F Lv = aload(&Lfin[v]);
+    for (uint32_t x = lane; x < g.n * P; x += kWave) {
+        const uint32_t v = x / P, p = x % P;
+        const F Lv = aload(&Lfin[x]);
         double gsum = 0.0;
         if (g.cp[v + 1] > g.cp[v] && Lv <= lim && Lv >= -lim) {
             for (uint32_t j = g.cp[v]; j < g.cp[v + 1]; j++) {
                 const uint32_t c = g.ci[j];
                 if constexpr (sizeof(F) == 8) {
-                    const double tv = aload(&colA[v]);
+                    const double tv = aload(&colA[x]);
                     double ex = 1.0;
                     for (uint32_t kk = g.rp[c]; kk < g.rp[c + 1]; kk++) {
                         const uint32_t u = g.ri[kk];
-                        if (u != v) ex *= aload(&colA[u]);
+                        if (u != v) ex *= aload(&colA[u * P + p]);
                     }
-                    gsum += aload(&dl[c]) * (-0.25 * ex * (1.0 - tv * tv));
+                    gsum += aload(&dl[c * P + p]) * (-0.25 * ex * (1.0 - tv * tv));
                 } else {
-                    const float e = aload(&colB[v]);
+                    const float e = aload(&colB[x]);
                     const float sech2_half = 2.0f * e / ((1.0f + e) * (1.0f + e));  // dt_v / dL_v
-                    const bool neg = (aload(&csg[c]) != 0) != (Lv < 0.0f);
-                    const float ex = expf(aload(&cS[c]) - aload(&colA[v]));  // |prod without v|
-                    gsum += aload(&dl[c]) * (-0.5 * (double)sech2_half * (double)(neg ? -ex : ex));
+                    const bool neg = (aload(&csg[c * P + p]) != 0) != (Lv < 0.0f);
+                    const float ex = expf(aload(&cS[c * P + p]) - aload(&colA[x]));  // |prod without v|
+                    gsum += aload(&dl[c * P + p]) * (-0.5 * (double)sech2_half * (double)(neg ? -ex : ex));
                 }
             }
         }
-        Lbar[v] = (F)gsum;
+        Lbar[x] = (F)gsum;
     }
     return wave_sum(loss);
 }
@@ -296,26 +305,33 @@ constexpr int grad_waves() {
     return sizeof(F) == 4 ? 6 : 3;
 }
 
-template <class F, bool FLOOD>
+// One wavefront runs P items: P consecutive shots of one member, on the
+// gradient schedule whose chunks hold at most W = 64 / P edges.  Lane l
+// serves item p = l mod P at chunk position l / P, so every per-edge array
+// is indexed base_k * P + l (base_k: edges in the member's earlier chunks)
+// and a chunk's data for all P items is one contiguous run.
+template <class F, bool FLOOD, int P>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_waves<F>()))) void bp_grad_kernel(
     DevGraph g, GradLaunch a) {
-    using P = GP<F>;
-    using B = typename P::B;
+    using Pr = GP<F>;
+    using B = typename Pr::B;
+    constexpr uint32_t W = kWave / P;
     extern __shared__ __align__(16) unsigned char lds[];
-    uint64_t* sb = reinterpret_cast<uint64_t*>(lds);
-    B* pst = reinterpret_cast<B*>(sb + g.words_m);     // running row states, m
-    F* pacc = reinterpret_cast<F*>(pst + g.m);         // row accumulators (reverse), m
-    F* sacc = pacc + g.m;
-    uint32_t* parg = reinterpret_cast<uint32_t*>(sacc + g.m);
-    uint32_t* ptgt = parg + g.m;
-    uint32_t* stgt = ptgt + g.m;
-    const uint32_t lane = threadIdx.x;
+    const uint32_t mP = g.m * P;
+    uint64_t* sb = reinterpret_cast<uint64_t*>(lds);      // syndrome bits, word w of item p at w * P + p
+    B* pst = reinterpret_cast<B*>(sb + g.words_m * P);    // running row states, m * P
+    F* pacc = reinterpret_cast<F*>(pst + mP);             // row accumulators (reverse)
+    F* sacc = pacc + mP;
+    uint32_t* parg = reinterpret_cast<uint32_t*>(sacc + mP);
+    uint32_t* ptgt = parg + mP;
+    uint32_t* stgt = ptgt + mP;
+    const uint32_t lane = threadIdx.x, p = lane % P, sl = lane / P;
     const F* lam = reinterpret_cast<const F*>(a.lam);
     const F* alpha = reinterpret_cast<const F*>(a.alpha);
     const F lim = (F)g.clamp;
-    const B ident = P::ident(g);
-    const uint32_t S = g.E;  // edges of every member
-    const GradBufs lay = grad_layout(S, g.n, g.m, a.K, sizeof(F));
+    const B ident = Pr::ident(g);
+    const uint32_t S = g.E * P;  // per-edge slots of the P items
+    const GradBufs lay = grad_layout(S, g.n * P, mP, a.K, sizeof(F));
     unsigned char* base = static_cast<unsigned char*>(a.scratch) + (size_t)blockIdx.x * a.scratch_per_block;
     F* lamS = reinterpret_cast<F*>(base + lay.lamS);
     F* msgA = reinterpret_cast<F*>(base + lay.msgA);
@@ -334,45 +350,52 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
     uint32_t* csg = reinterpret_cast<uint32_t*>(base + lay.csg);
     double* dl = reinterpret_cast<double*>(base + lay.dl);
     const uint32_t K = a.K;
-    // items (shot, member): with at least one member per XCD, the blocks of
-    // one XCD (dispatched round-robin, block b to XCD b mod 8) take the
-    // members of one eighth of the ensemble, so the chunk records they read
-    // stay in that XCD's L2
+    constexpr uint32_t rb = 8 * W;  // gradient chunk record: meta[W], v[W]
+    // work units (group of P shots, member): with at least one member per
+    // XCD, the blocks of one XCD (dispatched round-robin, block b to XCD
+    // b mod 8) take the members of one eighth of the ensemble, so the chunk
+    // records they read stay in that XCD's L2
+    const uint32_t n_groups = (a.B + P - 1) / P;
     const bool grouped = g.L >= kXcds && gridDim.x >= kXcds;
     const uint32_t xcd = blockIdx.x % kXcds;
     const uint32_t mlo = grouped ? xcd * g.L / kXcds : 0u;
     const uint32_t gsz = grouped ? (xcd + 1) * g.L / kXcds - mlo : g.L;
     const uint32_t z0 = grouped ? blockIdx.x / kXcds : blockIdx.x;
     const uint32_t zstep = grouped ? (gridDim.x - xcd + kXcds - 1) / kXcds : gridDim.x;
-    const uint32_t n_z = a.B * gsz;
-    const uint32_t rb = rec_bytes(sizeof(F) == 8);
+    const uint32_t n_z = n_groups * gsz;
     double* lbar_row = a.lbar_rows + (size_t)blockIdx.x * g.n;
     for (uint32_t v = lane; v < g.n; v += kWave) lbar_row[v] = 0.0;
     double loss_acc = 0.0, abar_acc = 0.0;  // abar_acc: iteration lane + 1
 
     for (uint32_t z = z0; z < n_z; z += zstep) {
-        const uint32_t shot = z / gsz, mem = mlo + z % gsz;
-        const uint8_t* s = a.syndromes + (size_t)shot * g.m;
-        for (uint32_t b0 = 0; b0 < g.m; b0 += kWave) {
-            const uint32_t c = b0 + lane;
-            const uint64_t mk = __ballot(c < g.m && s[c] != 0);
-            if (lane == 0) sb[b0 / kWave] = mk;
+        const uint32_t grp = z / gsz, mem = mlo + z % gsz;
+        const uint32_t shot0 = grp * P, nact = min((uint32_t)P, a.B - shot0);
+        const bool act = p < nact;  // idle items repeat shot0 and contribute nothing
+        for (uint32_t q = 0; q < P; q++) {
+            const uint8_t* sq = a.syndromes + (size_t)(shot0 + (q < nact ? q : 0u)) * g.m;
+            for (uint32_t b0 = 0; b0 < g.m; b0 += kWave) {
+                const uint32_t c = b0 + lane;
+                const uint64_t mk = __ballot(c < g.m && sq[c] != 0);
+                if (lane == 0) sb[(b0 / kWave) * P + q] = mk;
+            }
         }
-        const uint32_t c0 = uni(g.member_chunk[mem]), nch = uni(g.member_chunk[mem + 1]) - c0;
-        const unsigned char* recs = g.sched + (size_t)c0 * rb;
-        auto meta_of = [&](uint32_t k) { return *reinterpret_cast<const uint32_t*>(recs + (size_t)k * rb + 4u * lane); };
-        auto v_of = [&](uint32_t k) { return *reinterpret_cast<const uint32_t*>(recs + (size_t)k * rb + kRecV + 4u * lane); };
-        auto synd_bit = [&](uint32_t c) { return ((sb[c >> 6] >> (c & 63)) & 1ull) != 0; };
+        const uint32_t c0 = uni(a.member_chunk[mem]), nch = uni(a.member_chunk[mem + 1]) - c0;
+        const unsigned char* recs = a.recs + (size_t)c0 * rb;
+        auto meta_of = [&](uint32_t k) { return *reinterpret_cast<const uint32_t*>(recs + (size_t)k * rb + 4u * sl); };
+        auto v_of = [&](uint32_t k) { return *reinterpret_cast<const uint32_t*>(recs + (size_t)k * rb + 4u * W + 4u * sl); };
+        auto synd_bit = [&](uint32_t c) { return ((sb[(c >> 6) * P + p] >> (c & 63)) & 1ull) != 0; };
+        auto edges = [&](uint32_t meta) { return edges_of(meta) / P; };  // per item
+        __syncthreads();
 
         // lambda per edge and the messages before iteration 1
         for (uint32_t k = 0, base0 = 0; k < nch; k++) {
             const uint32_t meta = meta_of(k);
             if (deg_of(meta)) {
                 const F lr = lam[v_of(k)];
-                lamS[base0 + lane] = lr;
-                msgA[base0 + lane] = clampv(lr, lim);
+                lamS[base0 * P + lane] = lr;
+                msgA[base0 * P + lane] = clampv(lr, lim);
             }
-            base0 += edges_of(meta);
+            base0 += edges(meta);
         }
         __syncthreads();
 
@@ -385,38 +408,38 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
             const F al = alpha[t - 1];
 
             // suffix states of the old messages: chunks in reverse
-            for (uint32_t c = lane; c < g.m; c += kWave) {
-                pst[c] = ident;
-                parg[c] = kNoArg;
+            for (uint32_t x = lane; x < mP; x += kWave) {
+                pst[x] = ident;
+                parg[x] = kNoArg;
             }
             __syncthreads();
             {
                 uint32_t mA = nch ? meta_of(nch - 1) : 0u;
-                uint32_t bA = nch ? S - edges_of(mA) : 0u;
-                F xA = (nch && deg_of(mA)) ? old[bA + lane] : F(0);
+                uint32_t bA = nch ? g.E - edges(mA) : 0u;
+                F xA = (nch && deg_of(mA)) ? old[bA * P + lane] : F(0);
                 uint32_t mB = nch > 1 ? meta_of(nch - 2) : 0u;
                 for (uint32_t k = nch; k-- > 0;) {
                     const uint32_t meta = mA, base_k = bA;
                     const F x = xA;
                     mA = mB;
-                    if (k > 0) bA = base_k - edges_of(mA);
-                    xA = (k > 0 && deg_of(mA)) ? old[bA + lane] : F(0);
+                    if (k > 0) bA = base_k - edges(mA);
+                    xA = (k > 0 && deg_of(mA)) ? old[bA * P + lane] : F(0);
                     mB = k > 1 ? meta_of(k - 2) : 0u;
                     if (deg_of(meta)) {
-                        const uint32_t c = meta & 0xffffu, i = base_k + lane;
-                        RS<F> run{pst[c], parg[c]};
+                        const uint32_t r = (meta & 0xffffu) * P + p, i = base_k * P + lane;
+                        RS<F> run{pst[r], parg[r]};
                         sufst[i] = run.st;
                         sufarg[i] = run.arg;
                         run = rs_join(rs_of(x, i), run);
-                        pst[c] = run.st;
-                        parg[c] = run.arg;
+                        pst[r] = run.st;
+                        parg[r] = run.arg;
                     }
                     chunk_fence();
                 }
             }
-            for (uint32_t c = lane; c < g.m; c += kWave) {
-                pst[c] = ident;
-                parg[c] = kNoArg;
+            for (uint32_t x = lane; x < mP; x += kWave) {
+                pst[x] = ident;
+                parg[x] = kNoArg;
             }
             __syncthreads();
 
@@ -438,11 +461,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                     const B sst = sA;
                     const uint32_t sarg = aA;
                     const F lr = lA, xo = oA;
-                    bA = base_k + edges_of(meta);
+                    bA = base_k + edges(meta);
                     mA = mB;
                     vA = vB;
                     if (k + 1 < nch && deg_of(mA)) {
-                        const uint32_t i1 = bA + lane;
+                        const uint32_t i1 = bA * P + lane;
                         sA = sufst[i1];
                         aA = sufarg[i1];
                         lA = lamS[i1];
@@ -454,24 +477,24 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                     }
                     const uint32_t deg = deg_of(meta), dmax = uni((meta >> kMetaDmaxShift) & 15u);
                     const uint32_t c = meta & 0xffffu, seg = (meta >> 16) & 15u;
-                    const uint32_t i = base_k + lane;
+                    const uint32_t r = c * P + p, i = base_k * P + lane;
                     F q = F(0);
                     uint32_t w = 0;
-                    const RS<F> pre{pst[c], parg[c]};
+                    const RS<F> pre{pst[r], parg[r]};
                     if (deg) {
                         const RS<F> j = rs_join(pre, RS<F>{sst, sarg});
-                        const bool neg = ((j.st & P::kSign) != 0) != synd_bit(c);
-                        const F mag = P::val(j.st & ~P::kSign);
+                        const bool neg = ((j.st & Pr::kSign) != 0) != synd_bit(c);
+                        const F mag = Pr::val(j.st & ~Pr::kSign);
                         q = neg ? -mag : mag;
                         const uint32_t u = j.arg & 0x7fffffffu;
                         w = (u == kNoArg ? kSlotMask : u) | ((neg != ((j.arg >> 31) != 0)) ? kSneg : 0u);
                     }
-                    const F r = al * q;
+                    const F rr = al * q;
                     const F lv = clampv(lr, lim);
                     F L = lv, mu = lv;
-                    const int b0 = (int)lane - (int)seg;
+                    const int b0 = (int)lane - (int)(seg * P);
                     for (uint32_t jj = 0; jj < dmax; jj++) {
-                        const F rj = __shfl(r, (b0 + (int)jj) & (kWave - 1));
+                        const F rj = __shfl(rr, (b0 + (int)(jj * P)) & (kWave - 1));
                         if (jj < deg) {
                             L += rj;
                             if (jj != seg) mu += rj;
@@ -487,9 +510,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                         // serial: the row's later edges see the new message;
                         // parallel: the previous one
                         const RS<F> np = rs_join(pre, FLOOD ? rs_of(xo, i) : rs_of(mu, i));
-                        pst[c] = np.st;
-                        parg[c] = np.arg;
-                        if (t == K && seg == 0) Lfin[v] = L;
+                        pst[r] = np.st;
+                        parg[r] = np.arg;
+                        if (t == K && seg == 0) Lfin[v * P + p] = L;
                     }
                     chunk_fence();
                 }
@@ -498,7 +521,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
         }
 
         // ---- loss and d loss / d L (Lfin was written by other lanes)
-        loss_acc += loss_stage<F>(g, s, a.eps, Lfin, Lbar, colA, colB, cS, csg, dl);
+        loss_acc += loss_stage<F, P>(g, sb, nact, a.eps, Lfin, Lbar, colA, colB, cS, csg, dl);
         __syncthreads();
 
         // ---- reverse
@@ -509,25 +532,25 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
             const uint32_t* rwt = rw + (size_t)(t - 1) * S;
             const F al = alpha[t - 1];
             const bool last = t == K;  // no later iteration; L enters the loss
-            for (uint32_t c = lane; c < g.m; c += kWave) {
-                ptgt[c] = kSlotMask;
-                stgt[c] = kSlotMask;
-                pacc[c] = F(0);
-                sacc[c] = F(0);
+            for (uint32_t x = lane; x < mP; x += kWave) {
+                ptgt[x] = kSlotMask;
+                stgt[x] = kSlotMask;
+                pacc[x] = F(0);
+                sacc[x] = F(0);
             }
             __syncthreads();
             double abar = 0.0;
             {
                 uint32_t mA = nch ? meta_of(nch - 1) : 0u, vA = nch ? v_of(nch - 1) : 0u;
-                uint32_t bA = nch ? S - edges_of(mA) : 0u;
+                uint32_t bA = nch ? g.E - edges(mA) : 0u;
                 F qA = F(0), gA = F(0), glA = F(0);
                 uint32_t wA = 0;
                 if (nch && deg_of(mA)) {
-                    const uint32_t i1 = bA + lane;
+                    const uint32_t i1 = bA * P + lane;
                     qA = rqt[i1];
                     wA = rwt[i1];
                     if (!last) gA = aload(&mbp[i1]);
-                    if (last) glA = aload(&Lbar[vA]);
+                    if (last) glA = aload(&Lbar[vA * P + p]);
                 }
                 uint32_t mB = nch > 1 ? meta_of(nch - 2) : 0u, vB = nch > 1 ? v_of(nch - 2) : 0u;
                 for (uint32_t k = nch; k-- > 0;) {
@@ -535,13 +558,13 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                     const F q = qA, gprev = gA, GLv = glA;
                     mA = mB;
                     vA = vB;
-                    if (k > 0) bA = base_k - edges_of(mA);
+                    if (k > 0) bA = base_k - edges(mA);
                     if (k > 0 && deg_of(mA)) {
-                        const uint32_t i1 = bA + lane;
+                        const uint32_t i1 = bA * P + lane;
                         qA = rqt[i1];
                         wA = rwt[i1];
                         if (!last) gA = aload(&mbp[i1]);
-                        if (last) glA = aload(&Lbar[vA]);
+                        if (last) glA = aload(&Lbar[vA * P + p]);
                     }
                     if (k > 1) {
                         mB = meta_of(k - 2);
@@ -549,21 +572,21 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                     }
                     const uint32_t deg = deg_of(meta), dmax = uni((meta >> kMetaDmaxShift) & 15u);
                     const uint32_t c = meta & 0xffffu, seg = (meta >> 16) & 15u;
-                    const uint32_t i = base_k + lane;
+                    const uint32_t r = c * P + p, i = base_k * P + lane;
                     F gin = last ? F(0) : gprev;
                     if (deg) {
-                        if (!FLOOD && ptgt[c] == i) {  // the prefix argmin reached: take its adjoint
-                            gin += pacc[c];
-                            ptgt[c] = kSlotMask;
+                        if (!FLOOD && ptgt[r] == i) {  // the prefix argmin reached: take its adjoint
+                            gin += pacc[r];
+                            ptgt[r] = kSlotMask;
                         }
                         mbn[i] = F(0);  // written out later if this edge is a suffix argmin
                     }
                     const F gm = (deg && (w & kNcm)) ? gin : F(0);
                     const F GL = (deg && last) ? GLv : F(0);
                     F all = F(0), others = F(0);
-                    const int b0 = (int)lane - (int)seg;
+                    const int b0 = (int)lane - (int)(seg * P);
                     for (uint32_t jj = 0; jj < dmax; jj++) {
-                        const F gj = __shfl(gm, (b0 + (int)jj) & (kWave - 1));
+                        const F gj = __shfl(gm, (b0 + (int)(jj * P)) & (kWave - 1));
                         if (jj < deg) {
                             all += gj;
                             if (jj != seg) others += gj;
@@ -571,28 +594,28 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                     }
                     if (deg) {
                         const F rbar = others + GL;
-                        if (seg == 0 && (w & kLnc)) unsafeAtomicAdd(&lbar_row[v], (double)(all + GL));
-                        abar += (double)(rbar * q);
+                        if (act && seg == 0 && (w & kLnc)) unsafeAtomicAdd(&lbar_row[v], (double)(all + GL));
+                        if (act) abar += (double)(rbar * q);
                         const uint32_t u = w & kSlotMask;
                         if (u != kSlotMask) {
                             const F d = (w & kSneg) ? -(rbar * al) : rbar * al;
                             if (FLOOD) {
-                                if (ptgt[c] == u || ptgt[c] == kSlotMask) {
-                                    ptgt[c] = u;
-                                    pacc[c] += d;
+                                if (ptgt[r] == u || ptgt[r] == kSlotMask) {
+                                    ptgt[r] = u;
+                                    pacc[r] += d;
                                 } else {
-                                    stgt[c] = u;
-                                    sacc[c] += d;
+                                    stgt[r] = u;
+                                    sacc[r] += d;
                                 }
                             } else if (u < i) {
-                                pacc[c] = ptgt[c] == kSlotMask ? d : pacc[c] + d;
-                                ptgt[c] = u;
-                            } else if (stgt[c] != u) {
-                                if (stgt[c] != kSlotMask) mbn[stgt[c]] = sacc[c];
-                                stgt[c] = u;
-                                sacc[c] = d;
+                                pacc[r] = ptgt[r] == kSlotMask ? d : pacc[r] + d;
+                                ptgt[r] = u;
+                            } else if (stgt[r] != u) {
+                                if (stgt[r] != kSlotMask) mbn[stgt[r]] = sacc[r];
+                                stgt[r] = u;
+                                sacc[r] = d;
                             } else {
-                                sacc[c] += d;
+                                sacc[r] += d;
                             }
                         }
                     }
@@ -600,9 +623,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                 }
             }
             __syncthreads();
-            for (uint32_t c = lane; c < g.m; c += kWave) {
-                if (stgt[c] != kSlotMask) mbn[stgt[c]] = sacc[c];
-                if (FLOOD && ptgt[c] != kSlotMask) mbn[ptgt[c]] = pacc[c];
+            for (uint32_t x = lane; x < mP; x += kWave) {
+                if (stgt[x] != kSlotMask) mbn[stgt[x]] = sacc[x];
+                if (FLOOD && ptgt[x] != kSlotMask) mbn[ptgt[x]] = pacc[x];
             }
             abar = wave_sum(abar);
             if (lane == t - 1) abar_acc += abar;
@@ -616,17 +639,17 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
             const uint32_t meta = meta_of(k), v = v_of(k);
             const uint32_t deg = deg_of(meta), dmax = uni((meta >> kMetaDmaxShift) & 15u);
             const uint32_t seg = (meta >> 16) & 15u;
-            const uint32_t i = base0 + lane;
-            base0 += edges_of(meta);
+            const uint32_t i = base0 * P + lane;
+            base0 += edges(meta);
             const F x = deg ? aload(&mbp[i]) : F(0);
             const F gm = (deg && (rw[i] & kLnc)) ? x : F(0);
             F all = F(0);
-            const int b0 = (int)lane - (int)seg;
+            const int b0 = (int)lane - (int)(seg * P);
             for (uint32_t jj = 0; jj < dmax; jj++) {
-                const F gj = __shfl(gm, (b0 + (int)jj) & (kWave - 1));
+                const F gj = __shfl(gm, (b0 + (int)(jj * P)) & (kWave - 1));
                 if (jj < deg) all += gj;
             }
-            if (deg && seg == 0) unsafeAtomicAdd(&lbar_row[v], (double)all);
+            if (act && deg && seg == 0) unsafeAtomicAdd(&lbar_row[v], (double)all);
         }
         // (a column without checks is in no check's product: its gradient is 0)
         __syncthreads();
@@ -655,8 +678,9 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const double* in, uint
 }
 
 template <class F, bool FLOOD>
-const void* grad_fn() {
-    return (const void*)bp_grad_kernel<F, FLOOD>;
+const void* grad_fn(uint32_t P) {
+    return P == 4 ? (const void*)bp_grad_kernel<F, FLOOD, 4>
+                  : P == 2 ? (const void*)bp_grad_kernel<F, FLOOD, 2> : (const void*)bp_grad_kernel<F, FLOOD, 1>;
 }
 
 }  // namespace
@@ -665,35 +689,35 @@ const void* grad_fn() {
 constexpr uint64_t kGradMaxGrid = 8192;
 constexpr uint64_t kGradScratchBudget = 40ull << 30;
 
-size_t grad_scratch_per_block(const DevGraph& g, uint32_t K) {
-    return grad_layout(g.E, g.n, g.m, K, g.fp64 ? 8 : 4).bytes;
+size_t grad_scratch_per_block(const DevGraph& g, uint32_t K, uint32_t P) {
+    return grad_layout((size_t)g.E * P, (size_t)g.n * P, (size_t)g.m * P, K, g.fp64 ? 8 : 4).bytes;
 }
 
-size_t grad_lds_bytes(const DevGraph& g) {
+size_t grad_lds_bytes(const DevGraph& g, uint32_t P) {
     const size_t fb = g.fp64 ? 8 : 4;
-    return 8ull * g.words_m + (3 * fb + 12) * g.m + 16;
+    return (8ull * g.words_m + (3 * fb + 12) * g.m) * P + 16;
 }
 
-const void* grad_kernel_for(const DevGraph& g) {
-    return g.fp64 ? (g.flood ? grad_fn<double, true>() : grad_fn<double, false>())
-                  : (g.flood ? grad_fn<float, true>() : grad_fn<float, false>());
+const void* grad_kernel_for(const DevGraph& g, uint32_t P) {
+    return g.fp64 ? (g.flood ? grad_fn<double, true>(P) : grad_fn<double, false>(P))
+                  : (g.flood ? grad_fn<float, true>(P) : grad_fn<float, false>(P));
 }
 
 // blocks of the gradient kernel resident on the whole device at once
-int grad_resident_blocks(const DevGraph& g) {
+int grad_resident_blocks(const DevGraph& g, uint32_t P) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         return 1024;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, grad_kernel_for(g), kWave, grad_lds_bytes(g)) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, grad_kernel_for(g, P), kWave, grad_lds_bytes(g, P)) !=
             hipSuccess || per_cu < 1)
         per_cu = 1;
     return per_cu * cus;
 }
 
-int launch_grad(const DevGraph& g, const GradLaunch& a, hipStream_t st) {
-    const void* fn = grad_kernel_for(g);
-    const size_t lds = grad_lds_bytes(g);
+int launch_grad(const DevGraph& g, uint32_t P, const GradLaunch& a, hipStream_t st) {
+    const void* fn = grad_kernel_for(g, P);
+    const size_t lds = grad_lds_bytes(g, P);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(grad)");
@@ -701,6 +725,119 @@ int launch_grad(const DevGraph& g, const GradLaunch& a, hipStream_t st) {
     void* args[] = {const_cast<DevGraph*>(&g), const_cast<GradLaunch*>(&a)};
     hipError_t e = hipLaunchKernel(fn, dim3(a.grid), dim3(kWave), args, lds, st);
     if (e != hipSuccess) return hip_fail(e, "bp_grad_kernel launch");
+    return VIBE_OK;
+}
+
+// The gradient schedule.  The decode schedule's chunks (at most 64 edges,
+// whole columns, no two columns sharing a check) are recut into chunks of
+// at most W edges, columns kept whole and in lane order: a part of an
+// independent set is independent, so the sweep is unchanged.  W = 64 / P
+// lets one wavefront run P shots side by side; W is the one of 64, 32, 16
+// that gives the fewest chunks per shot (on graphs whose chunks are far
+// from full, most of a 64-lane chunk is idle).  Built once per graph.
+int build_grad_schedule(vibe_graph* G) {
+    if (G->grad_width) return VIBE_OK;
+    const DevGraph& d = G->h.dg;
+    const uint32_t L = d.L;
+    std::vector<uint32_t> mc(L + 1);
+    hipError_t e = hipMemcpy(mc.data(), d.member_chunk, 4ull * (L + 1), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(member_chunk)");
+    const size_t nrec = mc[L];
+    const uint32_t rb = rec_bytes(d.fp64 != 0);
+    std::vector<unsigned char> recs(std::max<size_t>(nrec, 1) * rb);
+    if (nrec) {
+        e = hipMemcpy(recs.data(), d.sched, nrec * rb, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(schedule)");
+    }
+    auto meta_at = [&](size_t k, uint32_t q) { return reinterpret_cast<const uint32_t*>(recs.data() + k * rb)[q]; };
+    auto v_at = [&](size_t k, uint32_t q) { return reinterpret_cast<const uint32_t*>(recs.data() + k * rb + kRecV)[q]; };
+    // the columns of chunk k as (first lane, degree)
+    auto columns = [&](size_t k, std::vector<std::pair<uint32_t, uint32_t>>& out) {
+        out.clear();
+        for (uint32_t q = 0; q < (uint32_t)kWave;) {
+            const uint32_t deg = (meta_at(k, q) >> kMetaDegShift) & 15u;
+            if (!deg) break;
+            out.push_back({q, deg});
+            q += deg;
+        }
+    };
+    std::vector<std::pair<uint32_t, uint32_t>> cols;
+    uint32_t bestW = kWave;
+    double best = -1.0;
+    for (uint32_t W : {64u, 32u, 16u}) {
+        size_t cnt = 0, worst = 0;
+        for (uint32_t i = 0; i < L; i++) {
+            size_t ci = 0;
+            for (size_t k = mc[i]; k < mc[i + 1]; k++) {
+                columns(k, cols);
+                uint32_t fill = W + 1;
+                for (auto& cd : cols) {
+                    if (fill + cd.second > W) {
+                        ci++;
+                        fill = 0;
+                    }
+                    fill += cd.second;
+                }
+            }
+            cnt += ci;
+            worst = std::max(worst, ci);
+        }
+        const double cost = (double)cnt / (kWave / W);
+        if (best < 0 || cost < best) {
+            best = cost;
+            bestW = W;
+        }
+        (void)worst;
+    }
+    const uint32_t W = bestW;
+    std::vector<uint32_t> out;  // per chunk: meta[W], v[W]
+    std::vector<uint32_t> gmc(L + 1, 0);
+    uint32_t maxc = 0;
+    for (uint32_t i = 0; i < L; i++) {
+        gmc[i] = (uint32_t)(out.size() / (2 * W));
+        for (size_t k = mc[i]; k < mc[i + 1]; k++) {
+            columns(k, cols);
+            size_t a = 0;
+            while (a < cols.size()) {
+                size_t b = a;
+                uint32_t fill = 0, dmax = 0;
+                while (b < cols.size() && fill + cols[b].second <= W) {
+                    fill += cols[b].second;
+                    dmax = std::max(dmax, cols[b].second);
+                    b++;
+                }
+                const size_t at = out.size();
+                out.resize(at + 2 * W, 0);
+                uint32_t lane = 0;
+                for (size_t cc = a; cc < b; cc++)
+                    for (uint32_t j = 0; j < cols[cc].second; j++, lane++) {
+                        const uint32_t q = cols[cc].first + j;
+                        out[at + lane] = (meta_at(k, q) & ~(15u << kMetaDmaxShift)) | (dmax << kMetaDmaxShift);
+                        out[at + W + lane] = v_at(k, q);
+                    }
+                for (; lane < W; lane++) out[at + lane] = dmax << kMetaDmaxShift;  // unused slots
+                a = b;
+            }
+        }
+        maxc = std::max(maxc, (uint32_t)(out.size() / (2 * W)) - gmc[i]);
+    }
+    gmc[L] = (uint32_t)(out.size() / (2 * W));
+    if (out.empty()) out.assign(2 * W, 0);
+    void* pr = nullptr;
+    void* pm = nullptr;
+    if (hipMalloc(&pr, 4 * out.size()) != hipSuccess) return fail(VIBE_ENOMEM, "gradient schedule allocation failed");
+    G->h.allocations.push_back(pr);
+    if (hipMalloc(&pm, 4 * gmc.size()) != hipSuccess) return fail(VIBE_ENOMEM, "gradient schedule allocation failed");
+    G->h.allocations.push_back(pm);
+    G->h.device_bytes += 4 * (out.size() + gmc.size());
+    if ((e = hipMemcpy(pr, out.data(), 4 * out.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(pm, gmc.data(), 4 * gmc.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(gradient schedule)");
+    G->grad_recs = static_cast<const unsigned char*>(pr);
+    G->grad_member_chunk = static_cast<const uint32_t*>(pm);
+    G->grad_P = kWave / W;
+    G->grad_max_chunks = maxc;
+    G->grad_width = W;
     return VIBE_OK;
 }
 
@@ -728,14 +865,17 @@ extern "C" int vibe_bp_grad(vibe_graph* G, const uint8_t* syndromes, uint64_t B,
     if ((uint64_t)g.E >= kSlotMask) return fail(VIBE_EUNSUPPORTED, "graph too large for the gradient (E >= 2^24 - 1)");
     const uint64_t items64 = B * g.L;
     if (items64 > (1u << 24)) return fail(VIBE_EINVAL, "B x L must be at most 2^24");
-    const uint32_t items = (uint32_t)items64;
+    int rc = build_grad_schedule(G);
+    if (rc) return rc;
+    const uint32_t P = G->grad_P;
+    const uint64_t units = (B + P - 1) / P * g.L;  // (group of P shots, member)
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const size_t per = grad_scratch_per_block(g, K);
-    // as many blocks as can be resident at once (items are assigned
+    const size_t per = grad_scratch_per_block(g, K, P);
+    // as many blocks as can be resident at once (work is assigned
     // statically, so more would only queue), within the scratch budget
     const uint64_t fit = std::max<uint64_t>(1, kGradScratchBudget / std::max<size_t>(per, 1));
-    const uint64_t resident = std::max<uint64_t>(1, (uint64_t)grad_resident_blocks(g));
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(items, std::min<uint64_t>(std::min(kGradMaxGrid, resident), fit));
+    const uint64_t resident = std::max<uint64_t>(1, (uint64_t)grad_resident_blocks(g, P));
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(units, std::min<uint64_t>(std::min(kGradMaxGrid, resident), fit));
     // workspace: per-block loss, lambda-bar and alpha-bar rows | scratch
     auto round256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off = 0;
@@ -766,14 +906,15 @@ extern "C" int vibe_bp_grad(vibe_graph* G, const uint8_t* syndromes, uint64_t B,
     a.lam = lam;
     a.alpha = alpha;
     a.eps = eps;
+    a.recs = G->grad_recs;
+    a.member_chunk = G->grad_member_chunk;
     a.loss_rows = reinterpret_cast<double*>(base + o_loss);
     a.lbar_rows = reinterpret_cast<double*>(base + o_lbar);
     a.abar_rows = reinterpret_cast<double*>(base + o_abar);
     a.scratch = base + o_scr;
     a.scratch_per_block = per;
     a.grid = (int)grid;
-    int rc = launch_grad(g, a, st);
-    if (rc) return rc;
+    if ((rc = launch_grad(g, P, a, st))) return rc;
     if ((rc = launch_reduce_rows(a.loss_rows, grid, 1, loss, st))) return rc;
     if ((rc = launch_reduce_rows(a.lbar_rows, grid, g.n, dlam, st))) return rc;
     return launch_reduce_rows(a.abar_rows, grid, K, dalpha, st);

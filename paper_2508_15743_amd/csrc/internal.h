@@ -122,6 +122,12 @@ struct vibe_graph {
     // occupancy)
     int tune_lds = -1;
     int tune_grid = 0;
+    // gradient schedule, built by the first vibe_bp_grad call: the member
+    // sweeps recut into chunks of at most grad_width edges, so that one
+    // wavefront runs grad_P = 64 / grad_width shots of a member side by side
+    uint32_t grad_width = 0, grad_P = 1, grad_max_chunks = 0;
+    const unsigned char* grad_recs = nullptr;
+    const uint32_t* grad_member_chunk = nullptr;
     // kernel timing (vibe_profile_enable): event pairs per kernel class
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
