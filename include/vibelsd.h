@@ -94,7 +94,9 @@ typedef struct vibe_graph_info {
     uint32_t levels_min, levels_max; /* dependency levels per member schedule */
     uint32_t chunks_min, chunks_max; /* parallel steps of one sweep per member */
     uint32_t message_bits;           /* 32 or 64 */
-    uint32_t reserved;
+    uint32_t grad_width;             /* chunk width of the gradient schedule
+                                        (16, 32 or 64; 0 before the first
+                                        vibe_bp_grad call on the graph) */
     uint64_t device_bytes; /* graph + schedules resident on the device */
 } vibe_graph_info_t;
 
@@ -285,6 +287,16 @@ void vibe_server_destroy(vibe_server* s); /* finishes every queued request first
  * graph); every call may grow the graph's workspace, like vibe_decode.
  * Calls on one graph must not overlap.
  */
+/*
+ * Chunk width of the gradient schedule: 16, 32 or 64 edges (64 / width
+ * shots per wavefront), or 0 to let the library choose per graph (the
+ * default).  Results per (shot, member) do not depend on it; only the
+ * order of the final sums does.  Takes effect at the next vibe_bp_grad
+ * call; waits for the device if a schedule must be dropped.
+ * VIBE_EINVAL for other widths.  For measurements and tests.
+ */
+int vibe_grad_set_width(vibe_graph* g, uint32_t width);
+
 int vibe_bp_grad(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint32_t K, const void* lam,
                  const void* alpha, double eps, double* loss, double* dlam, double* dalpha, void* stream);
 

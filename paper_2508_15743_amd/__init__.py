@@ -39,7 +39,7 @@ class vibe_graph_info_t(C.Structure):
                 ("max_row_degree", C.c_uint32), ("max_col_degree", C.c_uint32),
                 ("levels_min", C.c_uint32), ("levels_max", C.c_uint32),
                 ("chunks_min", C.c_uint32), ("chunks_max", C.c_uint32),
-                ("message_bits", C.c_uint32), ("reserved", C.c_uint32),
+                ("message_bits", C.c_uint32), ("grad_width", C.c_uint32),
                 ("device_bytes", C.c_uint64)]
 
 
@@ -71,6 +71,7 @@ EXPORTS = {
                            C.c_void_p, C.c_void_p]),
     "vibe_bp_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_void_p, C.c_void_p,
                                C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vibe_grad_set_width": (C.c_int, [C.c_void_p, C.c_uint32]),
     "vibe_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "vibe_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "vibe_runtime_create": (C.c_int, [C.POINTER(C.c_void_p)]),
@@ -375,6 +376,14 @@ def _graph_bp_grad(self, syndromes, lam, alpha, eps=1e-7, stream=None):
 
 
 Graph.bp_grad = _graph_bp_grad
+
+
+def _graph_set_grad_width(self, width):
+    """Chunk width of the gradient schedule (16, 32, 64; 0 = chosen per graph)."""
+    _check(lib().vibe_grad_set_width(self.handle, width))
+
+
+Graph.set_grad_width = _graph_set_grad_width
 
 
 def _autograd_fn():

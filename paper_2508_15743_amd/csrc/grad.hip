@@ -733,8 +733,8 @@ int launch_grad(const DevGraph& g, uint32_t P, const GradLaunch& a, hipStream_t 
 // at most W edges, columns kept whole and in lane order: a part of an
 // independent set is independent, so the sweep is unchanged.  W = 64 / P
 // lets one wavefront run P shots side by side; W is the one of 64, 32, 16
-// that gives the fewest chunks per shot (on graphs whose chunks are far
-// from full, most of a 64-lane chunk is idle).  Built once per graph.
+// that gives the least estimated time per shot (on graphs whose chunks are
+// far from full, most of a 64-lane chunk is idle).  Built once per graph.
 int build_grad_schedule(vibe_graph* G) {
     if (G->grad_width) return VIBE_OK;
     const DevGraph& d = G->h.dg;
@@ -782,13 +782,23 @@ int build_grad_schedule(vibe_graph* G) {
             cnt += ci;
             worst = std::max(worst, ci);
         }
-        const double cost = (double)cnt / (kWave / W);
+        // chunk steps per shot, weighted by the cost of a step with P shots
+        // side by side (measured on the d = 5 and d = 7 circuit graphs: a
+        // step takes 1.2-1.7x as long with P = 2 and 1.6-2.0x with P = 4;
+        // the larger factors are used)
+        const uint32_t P = kWave / W;
+        const double step = P == 1 ? 1.0 : P == 2 ? 1.7 : 2.0;
+        const double cost = (double)cnt * step / P;
         if (best < 0 || cost < best) {
             best = cost;
             bestW = W;
         }
         (void)worst;
     }
+#ifdef VIBE_GRAD_WIDTH
+    bestW = VIBE_GRAD_WIDTH;  // build-time override, for measurements
+#endif
+    if (G->grad_force) bestW = G->grad_force;
     const uint32_t W = bestW;
     std::vector<uint32_t> out;  // per chunk: meta[W], v[W]
     std::vector<uint32_t> gmc(L + 1, 0);
@@ -851,6 +861,31 @@ int launch_reduce_rows(const double* in, uint32_t rows, uint32_t width, double* 
 }  // namespace vibe
 
 using namespace vibe;
+
+extern "C" int vibe_grad_set_width(vibe_graph* G, uint32_t width) {
+    set_error("");
+    if (!G) return fail(VIBE_EINVAL, "graph handle is NULL");
+    if (width != 0 && width != 16 && width != 32 && width != 64)
+        return fail(VIBE_EINVAL, "width must be 0 (automatic), 16, 32 or 64");
+    if (width == G->grad_force) return VIBE_OK;
+    if (G->grad_width) {  // drop the schedule built for the previous setting
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        auto& al = G->h.allocations;
+        for (const void* p : {static_cast<const void*>(G->grad_recs), static_cast<const void*>(G->grad_member_chunk)})
+            for (size_t i = 0; i < al.size(); i++)
+                if (al[i] == p) {
+                    (void)hipFree(al[i]);
+                    al.erase(al.begin() + (long)i);
+                    break;
+                }
+        G->grad_recs = nullptr;
+        G->grad_member_chunk = nullptr;
+        G->grad_width = 0;
+    }
+    G->grad_force = width;
+    return VIBE_OK;
+}
 
 extern "C" int vibe_bp_grad(vibe_graph* G, const uint8_t* syndromes, uint64_t B, uint32_t K, const void* lam,
                             const void* alpha, double eps, double* loss, double* dlam, double* dalpha,

@@ -457,6 +457,7 @@ extern "C" int vibe_graph_info(const vibe_graph* g, vibe_graph_info_t* info) {
     info->chunks_min = h.chunks_min;
     info->chunks_max = h.chunks_max;
     info->message_bits = h.dg.fp64 ? 64 : 32;
+    info->grad_width = g->grad_width;
     info->device_bytes = h.device_bytes;
     return VIBE_OK;
 }

@@ -126,6 +126,7 @@ struct vibe_graph {
     // sweeps recut into chunks of at most grad_width edges, so that one
     // wavefront runs grad_P = 64 / grad_width shots of a member side by side
     uint32_t grad_width = 0, grad_P = 1, grad_max_chunks = 0;
+    uint32_t grad_force = 0;  // width set by vibe_grad_set_width (0: chosen per graph)
     const unsigned char* grad_recs = nullptr;
     const uint32_t* grad_member_chunk = nullptr;
     // kernel timing (vibe_profile_enable): event pairs per kernel class

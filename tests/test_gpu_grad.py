@@ -205,3 +205,33 @@ def test_grad_full_size_additive_and_sampled(torch_cuda):
     want = sum(O.bp_loss(g, synd[r], lam, np.full(K, 0.625), K, perm)[0] for r in rows for perm in perms)
     assert abs(got - want) <= 1e-4 * max(1.0, abs(want))
     G.close()
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+def test_grad_same_at_every_chunk_width(torch_cuda, bits):
+    """The gradient schedule may run 1, 2 or 4 shots per wavefront (chunk
+    widths 64, 32, 16).  Per-item arithmetic is the same at every width, so
+    the sums agree up to their order; the d = 5 circuit graph with an odd
+    number of shots also leaves idle items in the last wavefront."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    dem = circuit_dem(5, 5, 2e-3)
+    K = 6
+    lam, alpha, synd = _inputs(dem, 37, K, 51)
+    G, _ = _graph(P, dem, 8, "serial", bits)
+    dt = torch.float64 if bits == 64 else torch.float32
+    s = torch.from_numpy(synd).cuda()
+    res = {}
+    for w in (64, 32, 16):
+        G.set_grad_width(w)
+        res[w] = [x.cpu().numpy() for x in G.bp_grad(s, torch.tensor(lam, dtype=dt), torch.tensor(alpha, dtype=dt))]
+        assert G.info()["grad_width"] == w
+    for w in (32, 16):
+        for got, want in zip(res[w], res[64]):
+            scale = max(1.0, float(np.abs(want).max()))
+            assert np.abs(got - want).max() <= 1e-9 * scale
+    G.set_grad_width(0)
+    with pytest.raises(P.VibeError):
+        G.set_grad_width(24)
+    G.close()
