@@ -137,7 +137,7 @@ __device__ inline void chunk_fence() {
 }
 
 struct GradBufs {
-    size_t lamS, msgA, msgB, sufst, sufarg, rq, rw, mbA, mbB, Lfin, Lbar, colA, colB, cS, csg, dl;
+    size_t msgA, msgB, sufst, sufarg, rq, rw, mbA, mbB, Lfin, Lbar, colA, colB, cS, csg, dl;
     size_t bytes;
 };
 
@@ -153,7 +153,6 @@ __host__ __device__ inline GradBufs grad_layout(size_t S, size_t n, size_t m, ui
         off += (bytes + 255) & ~(size_t)255;
         return o;
     };
-    b.lamS = take(fb * S);       // lambda_v of the slot's column (unclamped)
     b.msgA = take(fb * S);       // messages, double-buffered over iterations
     b.msgB = take(fb * S);
     b.sufst = take(fb * S);      // suffix row states of this iteration's sweep
@@ -333,7 +332,6 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
     const uint32_t S = g.E * P;  // per-edge slots of the P items
     const GradBufs lay = grad_layout(S, g.n * P, mP, a.K, sizeof(F));
     unsigned char* base = static_cast<unsigned char*>(a.scratch) + (size_t)blockIdx.x * a.scratch_per_block;
-    F* lamS = reinterpret_cast<F*>(base + lay.lamS);
     F* msgA = reinterpret_cast<F*>(base + lay.msgA);
     F* msgB = reinterpret_cast<F*>(base + lay.msgB);
     B* sufst = reinterpret_cast<B*>(base + lay.sufst);
@@ -387,14 +385,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
         auto edges = [&](uint32_t meta) { return edges_of(meta) / P; };  // per item
         __syncthreads();
 
-        // lambda per edge and the messages before iteration 1
+        // the messages before iteration 1
         for (uint32_t k = 0, base0 = 0; k < nch; k++) {
             const uint32_t meta = meta_of(k);
-            if (deg_of(meta)) {
-                const F lr = lam[v_of(k)];
-                lamS[base0 * P + lane] = lr;
-                msgA[base0 * P + lane] = clampv(lr, lim);
-            }
+            if (deg_of(meta)) msgA[base0 * P + lane] = clampv(lam[v_of(k)], lim);
             base0 += edges(meta);
         }
         __syncthreads();
@@ -452,7 +446,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                 if (nch && deg_of(mA)) {
                     sA = sufst[lane];
                     aA = sufarg[lane];
-                    lA = lamS[lane];
+                    lA = lam[vA];  // lambda is small and stays in the caches
                     if (FLOOD) oA = old[lane];
                 }
                 uint32_t mB = nch > 1 ? meta_of(1) : 0u, vB = nch > 1 ? v_of(1) : 0u;
@@ -468,7 +462,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                         const uint32_t i1 = bA * P + lane;
                         sA = sufst[i1];
                         aA = sufarg[i1];
-                        lA = lamS[i1];
+                        lA = lam[vA];
                         if (FLOOD) oA = old[i1];
                     }
                     if (k + 2 < nch) {

@@ -207,8 +207,8 @@ def test_grad_full_size_additive_and_sampled(torch_cuda):
     G.close()
 
 
-@pytest.mark.parametrize("bits", [64, 32])
-def test_grad_same_at_every_chunk_width(torch_cuda, bits):
+@pytest.mark.parametrize("bits,schedule", [(64, "serial"), (32, "serial"), (64, "parallel"), (32, "parallel")])
+def test_grad_same_at_every_chunk_width(torch_cuda, bits, schedule):
     """The gradient schedule may run 1, 2 or 4 shots per wavefront (chunk
     widths 64, 32, 16).  Per-item arithmetic is the same at every width, so
     the sums agree up to their order; the d = 5 circuit graph with an odd
@@ -219,7 +219,7 @@ def test_grad_same_at_every_chunk_width(torch_cuda, bits):
     dem = circuit_dem(5, 5, 2e-3)
     K = 6
     lam, alpha, synd = _inputs(dem, 37, K, 51)
-    G, _ = _graph(P, dem, 8, "serial", bits)
+    G, _ = _graph(P, dem, 8 if schedule == "serial" else 1, schedule, bits)
     dt = torch.float64 if bits == 64 else torch.float32
     s = torch.from_numpy(synd).cuda()
     res = {}
