@@ -112,9 +112,33 @@ __device__ inline F clampv(F x, F lim) {
     return x > lim ? lim : (x < -lim ? -lim : x);
 }
 
-__device__ inline double aload(const double* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-__device__ inline float aload(const float* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-__device__ inline uint32_t aload(const uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+// Reads of words that another lane of the wavefront wrote to the block's
+// scratch.  A buffer load with the first cache-policy bit set misses the
+// vector L1 and reads the L2, which this CU's stores write through to (an
+// agent-scope atomic load would also leave this XCD's L2 behind).  The
+// scratch of one block is addressed as a wave-uniform descriptor plus a byte
+// offset.
+struct Scr {
+    __amdgpu_buffer_rsrc_t r;
+    const unsigned char* base;
+};
+constexpr int kBufFlags = 0x00020000;  // 32-bit data format: plain dword access
+
+__device__ __forceinline__ Scr make_scr(const void* base, uint32_t bytes) {
+    return Scr{__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufFlags),
+               static_cast<const unsigned char*>(base)};
+}
+
+template <class T>
+__device__ __forceinline__ T xload(const Scr& sc, const T* p) {
+    const int off = (int)(reinterpret_cast<const unsigned char*>(p) - sc.base);
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(sc.r, off, 0, 1));
+    } else {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(sc.r, off, 0, 1);
+        return __builtin_bit_cast(T, u);
+    }
+}
 
 template <class F>
 __device__ inline F wave_sum(F x) {
@@ -130,10 +154,54 @@ __device__ inline uint32_t edges_of(uint32_t meta) { return uni((uint32_t)__popc
 // XCDs of the device: workgroups are dispatched to them round-robin
 constexpr uint32_t kXcds = 8;
 
-// keeps the compiler from moving LDS traffic of one chunk past the next's
+// keeps the compiler from moving LDS traffic of one chunk past the next's,
+// or scheduling a later chunk's work into this one
 __device__ inline void chunk_fence() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// v of the lane at byte address addr (lane * 4, taken mod 256)
+__device__ __forceinline__ float perm(uint32_t addr, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute((int)addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double perm(uint32_t addr, double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr, (int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr, (int)(uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// acc + the sum of v over the column's other positions, in position order.
+// Position j of the column is the lane at byte address b0x4 + 4 P j; the
+// reads go eight at a time at constant offsets from that base, and
+// positions past the column and the edge's own add an exact zero.
+template <class F, int P>
+__device__ __forceinline__ F column_others(F acc, F v, uint32_t b0x4, uint32_t deg, uint32_t seg, uint32_t dmax) {
+    if (dmax <= 8) {
+        F vj[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) vj[q] = perm(b0x4 + 4u * P * (uint32_t)q, v);
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            if ((uint32_t)q >= dmax) break;
+            acc += ((uint32_t)q < deg && (uint32_t)q != seg) ? vj[q] : F(0);
+        }
+    } else {
+        for (uint32_t j0 = 0; j0 < dmax; j0 += 8) {
+            F vj[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) vj[q] = perm(b0x4 + 4u * P * (j0 + (uint32_t)q), v);
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const uint32_t j = j0 + (uint32_t)q;
+                if (j >= dmax) break;
+                acc += (j < deg && j != seg) ? vj[q] : F(0);
+            }
+        }
+    }
+    return acc;
 }
 
 struct GradBufs {
@@ -206,8 +274,8 @@ namespace {
 // and dt_v / dL_v = (1 - t_v^2) / 2 = 2 e_v / (1 + e_v)^2.  l_v is bounded
 // below by -80 so that exp(S_c - l_v), the product without v, stays finite.
 template <class F, int P>
-__device__ double loss_stage(const DevGraph& g, const uint64_t* sb, uint32_t nact, double eps, const F* Lfin,
-                             F* Lbar, F* colA, F* colB, F* cS, uint32_t* csg, double* dl) {
+__device__ double loss_stage(const DevGraph& g, const Scr& sc, const uint64_t* sb, uint32_t nact, double eps,
+                             const F* Lfin, F* Lbar, F* colA, F* colB, F* cS, uint32_t* csg, double* dl) {
     const uint32_t lane = threadIdx.x;
     const F lim = (F)g.clamp;
     double loss = 0.0;
@@ -215,7 +283,7 @@ __device__ double loss_stage(const DevGraph& g, const uint64_t* sb, uint32_t nac
     for (uint32_t x = lane; x < g.n * P; x += kWave) {
         const uint32_t v = x / P;
         if (g.cp[v + 1] == g.cp[v]) continue;  // in no check
-        const F L = clampv(aload(&Lfin[x]), lim);
+        const F L = clampv(xload(sc, &Lfin[x]), lim);
         if constexpr (sizeof(F) == 8) {
             colA[x] = tanh(L / 2.0);
         } else {
@@ -227,11 +295,11 @@ __device__ double loss_stage(const DevGraph& g, const uint64_t* sb, uint32_t nac
     __syncthreads();
     for (uint32_t x = lane; x < g.m * P; x += kWave) {
         const uint32_t c = x / P, p = x % P;
-        const bool sc = ((sb[(c >> 6) * P + p] >> (c & 63)) & 1ull) != 0;
+        const bool sbit = ((sb[(c >> 6) * P + p] >> (c & 63)) & 1ull) != 0;
         double sh, sh1;  // shat_c and 1 - shat_c
         if constexpr (sizeof(F) == 8) {
             double prod = 1.0;
-            for (uint32_t kk = g.rp[c]; kk < g.rp[c + 1]; kk++) prod *= aload(&colA[g.ri[kk] * P + p]);
+            for (uint32_t kk = g.rp[c]; kk < g.rp[c + 1]; kk++) prod *= xload(sc, &colA[g.ri[kk] * P + p]);
             sh = 0.5 * (1.0 - prod);
             sh1 = 1.0 - sh;
         } else {
@@ -239,8 +307,8 @@ __device__ double loss_stage(const DevGraph& g, const uint64_t* sb, uint32_t nac
             uint32_t neg = 0;
             for (uint32_t kk = g.rp[c]; kk < g.rp[c + 1]; kk++) {
                 const uint32_t u = g.ri[kk] * P + p;
-                S += aload(&colA[u]);
-                neg ^= aload(&Lfin[u]) < 0.0f ? 1u : 0u;
+                S += xload(sc, &colA[u]);
+                neg ^= xload(sc, &Lfin[u]) < 0.0f ? 1u : 0u;
             }
             cS[x] = S;
             csg[x] = neg;
@@ -258,38 +326,38 @@ __device__ double loss_stage(const DevGraph& g, const uint64_t* sb, uint32_t nac
                 sh = 1.0 - eps;
             }
         } else {
-            d = sc ? -1.0 / sh : 1.0 / sh1;
+            d = sbit ? -1.0 / sh : 1.0 / sh1;
         }
         double term;
         if constexpr (sizeof(F) == 8)
-            term = sc ? log(sh) : log(sh1);
+            term = sbit ? log(sh) : log(sh1);
         else
-            term = (double)logf((float)(sc ? sh : sh1));
+            term = (double)logf((float)(sbit ? sh : sh1));
         if (p < nact) loss -= term;
         dl[x] = d;
     }
     __syncthreads();
     for (uint32_t x = lane; x < g.n * P; x += kWave) {
         const uint32_t v = x / P, p = x % P;
-        const F Lv = aload(&Lfin[x]);
+        const F Lv = xload(sc, &Lfin[x]);
         double gsum = 0.0;
         if (g.cp[v + 1] > g.cp[v] && Lv <= lim && Lv >= -lim) {
             for (uint32_t j = g.cp[v]; j < g.cp[v + 1]; j++) {
                 const uint32_t c = g.ci[j];
                 if constexpr (sizeof(F) == 8) {
-                    const double tv = aload(&colA[x]);
+                    const double tv = xload(sc, &colA[x]);
                     double ex = 1.0;
                     for (uint32_t kk = g.rp[c]; kk < g.rp[c + 1]; kk++) {
                         const uint32_t u = g.ri[kk];
-                        if (u != v) ex *= aload(&colA[u * P + p]);
+                        if (u != v) ex *= xload(sc, &colA[u * P + p]);
                     }
-                    gsum += aload(&dl[c * P + p]) * (-0.25 * ex * (1.0 - tv * tv));
+                    gsum += xload(sc, &dl[c * P + p]) * (-0.25 * ex * (1.0 - tv * tv));
                 } else {
-                    const float e = aload(&colB[x]);
+                    const float e = xload(sc, &colB[x]);
                     const float sech2_half = 2.0f * e / ((1.0f + e) * (1.0f + e));  // dt_v / dL_v
-                    const bool neg = (aload(&csg[c * P + p]) != 0) != (Lv < 0.0f);
-                    const float ex = expf(aload(&cS[c * P + p]) - aload(&colA[x]));  // |prod without v|
-                    gsum += aload(&dl[c * P + p]) * (-0.5 * (double)sech2_half * (double)(neg ? -ex : ex));
+                    const bool neg = (xload(sc, &csg[c * P + p]) != 0) != (Lv < 0.0f);
+                    const float ex = expf(xload(sc, &cS[c * P + p]) - xload(sc, &colA[x]));  // |prod without v|
+                    gsum += xload(sc, &dl[c * P + p]) * (-0.5 * (double)sech2_half * (double)(neg ? -ex : ex));
                 }
             }
         }
@@ -329,9 +397,14 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
     const F* alpha = reinterpret_cast<const F*>(a.alpha);
     const F lim = (F)g.clamp;
     const B ident = Pr::ident(g);
-    const uint32_t S = g.E * P;  // per-edge slots of the P items
+    // per-edge slots of the P items, plus one wavefront of padding: the
+    // loads of the next chunk are issued whatever its size (a conditional
+    // load makes the compiler wait for every load in flight at each use),
+    // and the last chunk's unused lanes read past the end
+    const uint32_t S = g.E * P + kWave;
     const GradBufs lay = grad_layout(S, g.n * P, mP, a.K, sizeof(F));
     unsigned char* base = static_cast<unsigned char*>(a.scratch) + (size_t)blockIdx.x * a.scratch_per_block;
+    const Scr sc = make_scr(base, (uint32_t)a.scratch_per_block);
     F* msgA = reinterpret_cast<F*>(base + lay.msgA);
     F* msgB = reinterpret_cast<F*>(base + lay.msgB);
     B* sufst = reinterpret_cast<B*>(base + lay.sufst);
@@ -407,18 +480,18 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                 parg[x] = kNoArg;
             }
             __syncthreads();
-            {
-                uint32_t mA = nch ? meta_of(nch - 1) : 0u;
-                uint32_t bA = nch ? g.E - edges(mA) : 0u;
-                F xA = (nch && deg_of(mA)) ? old[bA * P + lane] : F(0);
-                uint32_t mB = nch > 1 ? meta_of(nch - 2) : 0u;
+            if (nch) {
+                uint32_t mA = meta_of(nch - 1);
+                uint32_t bA = g.E - edges(mA);
+                F xA = old[bA * P + lane];
+                uint32_t mB = meta_of(nch > 1 ? nch - 2 : 0u);
                 for (uint32_t k = nch; k-- > 0;) {
                     const uint32_t meta = mA, base_k = bA;
                     const F x = xA;
-                    mA = mB;
+                    mA = mB;  // chunk k - 1 (chunk 0 again at the end)
                     if (k > 0) bA = base_k - edges(mA);
-                    xA = (k > 0 && deg_of(mA)) ? old[bA * P + lane] : F(0);
-                    mB = k > 1 ? meta_of(k - 2) : 0u;
+                    xA = old[bA * P + lane];
+                    mB = meta_of(k > 1 ? k - 2 : 0u);
                     if (deg_of(meta)) {
                         const uint32_t r = (meta & 0xffffu) * P + p, i = base_k * P + lane;
                         RS<F> run{pst[r], parg[r]};
@@ -438,37 +511,32 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
             __syncthreads();
 
             // the sweep
-            {
-                uint32_t mA = nch ? meta_of(0) : 0u, vA = nch ? v_of(0) : 0u, bA = 0;
-                B sA = ident;
-                uint32_t aA = kNoArg;
-                F lA = F(0), oA = F(0);
-                if (nch && deg_of(mA)) {
-                    sA = sufst[lane];
-                    aA = sufarg[lane];
-                    lA = lam[vA];  // lambda is small and stays in the caches
-                    if (FLOOD) oA = old[lane];
-                }
-                uint32_t mB = nch > 1 ? meta_of(1) : 0u, vB = nch > 1 ? v_of(1) : 0u;
+            if (nch) {
+                uint32_t mA = meta_of(0), vA = v_of(0), bA = 0;
+                B sA = sufst[lane];
+                uint32_t aA = sufarg[lane];
+                F lA = lam[vA];  // lambda is small and stays in the caches
+                F oA = FLOOD ? old[lane] : F(0);
+                const uint32_t k1 = nch > 1 ? 1u : 0u;
+                uint32_t mB = meta_of(k1), vB = v_of(k1);
                 for (uint32_t k = 0; k < nch; k++) {
                     const uint32_t meta = mA, v = vA, base_k = bA;
                     const B sst = sA;
                     const uint32_t sarg = aA;
                     const F lr = lA, xo = oA;
-                    bA = base_k + edges(meta);
+                    bA = base_k + edges(meta);  // chunk k + 1 (past the end after the last)
                     mA = mB;
                     vA = vB;
-                    if (k + 1 < nch && deg_of(mA)) {
+                    {
                         const uint32_t i1 = bA * P + lane;
                         sA = sufst[i1];
                         aA = sufarg[i1];
                         lA = lam[vA];
                         if (FLOOD) oA = old[i1];
                     }
-                    if (k + 2 < nch) {
-                        mB = meta_of(k + 2);
-                        vB = v_of(k + 2);
-                    }
+                    const uint32_t k2 = min(k + 2, nch - 1);
+                    mB = meta_of(k2);
+                    vB = v_of(k2);
                     const uint32_t deg = deg_of(meta), dmax = uni((meta >> kMetaDmaxShift) & 15u);
                     const uint32_t c = meta & 0xffffu, seg = (meta >> 16) & 15u;
                     const uint32_t r = c * P + p, i = base_k * P + lane;
@@ -485,15 +553,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                     }
                     const F rr = al * q;
                     const F lv = clampv(lr, lim);
-                    F L = lv, mu = lv;
-                    const int b0 = (int)lane - (int)(seg * P);
-                    for (uint32_t jj = 0; jj < dmax; jj++) {
-                        const F rj = __shfl(rr, (b0 + (int)(jj * P)) & (kWave - 1));
-                        if (jj < deg) {
-                            L += rj;
-                            if (jj != seg) mu += rj;
-                        }
-                    }
+                    // mu = lambda + the column's other r in check order; on
+                    // the column's last position that is L without its own r
+                    const uint32_t b0x4 = (uint32_t)((int)lane - (int)(seg * P)) << 2;
+                    F mu = column_others<F, P>(lv, rr, b0x4, deg, seg, dmax);
+                    const F L = perm(b0x4 + 4u * P * (deg - 1u), mu + rr);
                     if (deg) {
                         w |= (mu <= lim && mu >= -lim) ? kNcm : 0u;
                         w |= (lr <= lim && lr >= -lim) ? kLnc : 0u;
@@ -515,7 +579,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
         }
 
         // ---- loss and d loss / d L (Lfin was written by other lanes)
-        loss_acc += loss_stage<F, P>(g, sb, nact, a.eps, Lfin, Lbar, colA, colB, cS, csg, dl);
+        loss_acc += loss_stage<F, P>(g, sc, sb, nact, a.eps, Lfin, Lbar, colA, colB, cS, csg, dl);
         __syncthreads();
 
         // ---- reverse
@@ -534,36 +598,32 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
             }
             __syncthreads();
             double abar = 0.0;
-            {
-                uint32_t mA = nch ? meta_of(nch - 1) : 0u, vA = nch ? v_of(nch - 1) : 0u;
-                uint32_t bA = nch ? g.E - edges(mA) : 0u;
-                F qA = F(0), gA = F(0), glA = F(0);
-                uint32_t wA = 0;
-                if (nch && deg_of(mA)) {
-                    const uint32_t i1 = bA * P + lane;
-                    qA = rqt[i1];
-                    wA = rwt[i1];
-                    if (!last) gA = aload(&mbp[i1]);
-                    if (last) glA = aload(&Lbar[vA * P + p]);
-                }
-                uint32_t mB = nch > 1 ? meta_of(nch - 2) : 0u, vB = nch > 1 ? v_of(nch - 2) : 0u;
+            if (nch) {
+                // mbp is not read at the last iteration (no adjoint comes
+                // from later) and Lbar only there, but both loads are issued
+                // every step (in bounds either way)
+                uint32_t mA = meta_of(nch - 1), vA = v_of(nch - 1);
+                uint32_t bA = g.E - edges(mA);
+                F qA = rqt[bA * P + lane], gA = xload(sc, &mbp[bA * P + lane]), glA = xload(sc, &Lbar[vA * P + p]);
+                uint32_t wA = rwt[bA * P + lane];
+                const uint32_t km = nch > 1 ? nch - 2 : 0u;
+                uint32_t mB = meta_of(km), vB = v_of(km);
                 for (uint32_t k = nch; k-- > 0;) {
                     const uint32_t meta = mA, v = vA, w = wA, base_k = bA;
                     const F q = qA, gprev = gA, GLv = glA;
-                    mA = mB;
+                    mA = mB;  // chunk k - 1 (chunk 0 again at the end)
                     vA = vB;
                     if (k > 0) bA = base_k - edges(mA);
-                    if (k > 0 && deg_of(mA)) {
+                    {
                         const uint32_t i1 = bA * P + lane;
                         qA = rqt[i1];
                         wA = rwt[i1];
-                        if (!last) gA = aload(&mbp[i1]);
-                        if (last) glA = aload(&Lbar[vA * P + p]);
+                        gA = xload(sc, &mbp[i1]);
+                        glA = xload(sc, &Lbar[vA * P + p]);
                     }
-                    if (k > 1) {
-                        mB = meta_of(k - 2);
-                        vB = v_of(k - 2);
-                    }
+                    const uint32_t k2 = k > 1 ? k - 2 : 0u;
+                    mB = meta_of(k2);
+                    vB = v_of(k2);
                     const uint32_t deg = deg_of(meta), dmax = uni((meta >> kMetaDmaxShift) & 15u);
                     const uint32_t c = meta & 0xffffu, seg = (meta >> 16) & 15u;
                     const uint32_t r = c * P + p, i = base_k * P + lane;
@@ -577,18 +637,13 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
                     }
                     const F gm = (deg && (w & kNcm)) ? gin : F(0);
                     const F GL = (deg && last) ? GLv : F(0);
-                    F all = F(0), others = F(0);
-                    const int b0 = (int)lane - (int)(seg * P);
-                    for (uint32_t jj = 0; jj < dmax; jj++) {
-                        const F gj = __shfl(gm, (b0 + (int)(jj * P)) & (kWave - 1));
-                        if (jj < deg) {
-                            all += gj;
-                            if (jj != seg) others += gj;
-                        }
-                    }
+                    const uint32_t b0x4 = (uint32_t)((int)lane - (int)(seg * P)) << 2;
+                    const F others = column_others<F, P>(F(0), gm, b0x4, deg, seg, dmax);
                     if (deg) {
                         const F rbar = others + GL;
-                        if (act && seg == 0 && (w & kLnc)) unsafeAtomicAdd(&lbar_row[v], (double)(all + GL));
+                        // the column's last position adds its own term last:
+                        // the sum over the column in check order
+                        if (act && seg + 1 == deg && (w & kLnc)) unsafeAtomicAdd(&lbar_row[v], (double)((others + gm) + GL));
                         if (act) abar += (double)(rbar * q);
                         const uint32_t u = w & kSlotMask;
                         if (u != kSlotMask) {
@@ -635,15 +690,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(grad_wave
             const uint32_t seg = (meta >> 16) & 15u;
             const uint32_t i = base0 * P + lane;
             base0 += edges(meta);
-            const F x = deg ? aload(&mbp[i]) : F(0);
+            const F x = deg ? xload(sc, &mbp[i]) : F(0);
             const F gm = (deg && (rw[i] & kLnc)) ? x : F(0);
-            F all = F(0);
-            const int b0 = (int)lane - (int)(seg * P);
-            for (uint32_t jj = 0; jj < dmax; jj++) {
-                const F gj = __shfl(gm, (b0 + (int)(jj * P)) & (kWave - 1));
-                if (jj < deg) all += gj;
-            }
-            if (act && deg && seg == 0) unsafeAtomicAdd(&lbar_row[v], (double)all);
+            const uint32_t b0x4 = (uint32_t)((int)lane - (int)(seg * P)) << 2;
+            const F others = column_others<F, P>(F(0), gm, b0x4, deg, seg, dmax);
+            if (act && deg && seg + 1 == deg) unsafeAtomicAdd(&lbar_row[v], (double)(others + gm));
         }
         // (a column without checks is in no check's product: its gradient is 0)
         __syncthreads();
@@ -684,7 +735,7 @@ constexpr uint64_t kGradMaxGrid = 8192;
 constexpr uint64_t kGradScratchBudget = 40ull << 30;
 
 size_t grad_scratch_per_block(const DevGraph& g, uint32_t K, uint32_t P) {
-    return grad_layout((size_t)g.E * P, (size_t)g.n * P, (size_t)g.m * P, K, g.fp64 ? 8 : 4).bytes;
+    return grad_layout((size_t)g.E * P + kWave, (size_t)g.n * P, (size_t)g.m * P, K, g.fp64 ? 8 : 4).bytes;
 }
 
 size_t grad_lds_bytes(const DevGraph& g, uint32_t P) {
@@ -900,6 +951,7 @@ extern "C" int vibe_bp_grad(vibe_graph* G, const uint8_t* syndromes, uint64_t B,
     const uint64_t units = (B + P - 1) / P * g.L;  // (group of P shots, member)
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t per = grad_scratch_per_block(g, K, P);
+    if (per >= (1ull << 31)) return fail(VIBE_EUNSUPPORTED, "gradient scratch per wavefront exceeds 2 GB (graph x K too large)");
     // as many blocks as can be resident at once (work is assigned
     // statically, so more would only queue), within the scratch budget
     const uint64_t fit = std::max<uint64_t>(1, kGradScratchBudget / std::max<size_t>(per, 1));
