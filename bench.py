@@ -365,22 +365,42 @@ def main():
                 "largest_cluster_p50": pct(50), "largest_cluster_p95": pct(95),
                 "largest_cluster_max": int(big.max()) if big.size else 0}
 
-    comparison = {"vibelsd": cluster_stats(stats)}
-    if not args.no_baseline:
-        Gb = P.Graph.from_dem(dem, perms[:1], L=1, M=1, T_max=T, alpha=alpha, schedule="parallel")
-        bout = tuple(torch.empty_like(o) for o in out)
-        Gb.decode(synd, out=bout)
+    def baseline(dem_b, perms_b, synd_b, obs_b):
+        """BP+LSD-0 without ensembling: one member, parallel schedule."""
+        Gb = P.Graph.from_dem(dem_b, perms_b[:1], L=1, M=1, T_max=T, alpha=alpha, schedule="parallel")
+        Gb.decode(synd_b)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        Gb.decode(synd, out=bout)
+        _, bobs, bst = Gb.decode(synd_b)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
-        bst = bout[2].cpu().numpy()
-        bler = float((bout[1].cpu().numpy() != batch.observables).any(1).mean())
-        comparison["bp_lsd0"] = dict(cluster_stats(bst), shots_per_s=round(B / dt, 1), logical_error_rate=bler)
+        bler = float((bobs.cpu().numpy() != obs_b).any(1).mean())
         Gb.close()
-        log(f"BP+LSD-0 baseline: {B / dt:.0f} shots/s, LSD calls per 5000 "
+        return dict(cluster_stats(bst.cpu().numpy()), shots_per_s=round(synd_b.shape[0] / dt, 1),
+                    logical_error_rate=bler)
+
+    comparison = {"vibelsd": cluster_stats(stats)}
+    if not args.no_baseline:
+        comparison["bp_lsd0"] = baseline(dem, perms, synd, batch.observables)
+        log(f"BP+LSD-0 baseline: {comparison['bp_lsd0']['shots_per_s']:.0f} shots/s, LSD calls per 5000 "
             f"{comparison['bp_lsd0']['lsd_calls_per_5000']} vs VibeLSD {comparison['vibelsd']['lsd_calls_per_5000']}")
+        # the same comparison under the Si1000 rates (the paper's Sec. IV.H
+        # setting uses them), on 8192 shots
+        dem_s = circuit_dem(d, rounds, p, noise="si1000")
+        perms_s = permutations(dem_s.n, L, args.seed + 2)
+        bs = sample(dem_s, 8192, args.seed + 3)
+        synd_s = torch.from_numpy(bs.syndromes).to(dev)
+        Gs = P.Graph.from_dem(dem_s, perms_s, L=L, M=M, T_max=T, alpha=alpha)
+        _, sobs, sst = Gs.decode(synd_s)
+        torch.cuda.synchronize()
+        Gs.close()
+        comparison["si1000"] = {"workload": dem_s.name, "shots": 8192,
+                                "vibelsd": dict(cluster_stats(sst.cpu().numpy()),
+                                                logical_error_rate=float((sobs.cpu().numpy() != bs.observables)
+                                                                         .any(1).mean())),
+                                "bp_lsd0": baseline(dem_s, perms_s, synd_s, bs.observables)}
+        log(f"Si1000: LSD calls per 5000 {comparison['si1000']['bp_lsd0']['lsd_calls_per_5000']} (BP+LSD-0) "
+            f"vs {comparison['si1000']['vibelsd']['lsd_calls_per_5000']} (VibeLSD)")
     result["comparison"] = comparison
 
     if not args.no_ragged:

@@ -191,8 +191,17 @@ def _combine(p_old: float, p_new: float) -> float:
     return p_old * (1.0 - p_new) + p_new * (1.0 - p_old)
 
 
-def circuit_dem(d: int, rounds: int, p: float, return_stats: bool = False):
-    """X-memory circuit-level DEM with the Uniform noise model at rate p.
+def circuit_dem(d: int, rounds: int, p: float, return_stats: bool = False, noise: str = "uniform"):
+    """X-memory circuit-level DEM at rate p.
+
+    noise="uniform": every two-qubit gate is followed by two-qubit
+    depolarising noise p, every idle qubit of a layer by one-qubit
+    depolarising p, resets and readouts flip with probability p.
+    noise="si1000" (Sec. IV.A's superconducting-inspired table): two-qubit
+    gates p; idling in a gate layer p/10; idling in a readout or reset layer
+    2p; resets flip with 2p and readouts with 5p.  The CNOT of this circuit is
+    taken as the native two-qubit gate (the table's CZ), so no single-qubit
+    Cliffords are added around it.
 
     Qubits: data 0..n-1, X ancillas n..n+P-1, Z ancillas n+P..n+2P-1.
     One round: reset the X ancillas in |+>; six CNOT layers ancilla->data
@@ -209,6 +218,12 @@ def circuit_dem(d: int, rounds: int, p: float, return_stats: bool = False):
     through the circuit: sx[q] / sz[q] is the set of detectors (bit mask,
     bit `m` = observable) flipped by an X / Z on qubit q at the current time.
     """
+    if noise == "uniform":
+        p_gate, p_idle_gate, p_idle_mr, p_reset, p_meas = p, p, p, p, p
+    elif noise == "si1000":
+        p_gate, p_idle_gate, p_idle_mr, p_reset, p_meas = p, p / 10, 2 * p, 2 * p, 5 * p
+    else:
+        raise ValueError(f"unknown noise model {noise!r}")
     code = triangular_666(d)
     n, P = code.n, code.num_plaquettes
     R = rounds
@@ -278,26 +293,26 @@ def circuit_dem(d: int, rounds: int, p: float, return_stats: bool = False):
         old = sigs.get(effect)
         sigs[effect] = prob if old is None else _combine(old, prob)
 
-    def depol1(q):
+    def depol1(q, pr):
         a, b = sx[q], sz[q]
-        add(a, p / 3)
-        add(a ^ b, p / 3)
-        add(b, p / 3)
+        add(a, pr / 3)
+        add(a ^ b, pr / 3)
+        add(b, pr / 3)
 
-    def depol2(q1, q2):
+    def depol2(q1, q2, pr):
         e1 = (0, sx[q1], sx[q1] ^ sz[q1], sz[q1])
         e2 = (0, sx[q2], sx[q2] ^ sz[q2], sz[q2])
         for i in range(4):
             for j in range(4):
                 if i or j:
-                    add(e1[i] ^ e2[j], p / 15)
+                    add(e1[i] ^ e2[j], pr / 15)
 
     # --- final data readout (X basis): Z flip before it, then the readout
     for qb in range(n):
         sz[qb] = dets_mfinal(qb)
         sx[qb] = 0
     for qb in range(n):
-        add(sz[qb], p)  # readout flip
+        add(sz[qb], p_meas)  # readout flip
 
     all_q = list(range(nq))
 
@@ -305,12 +320,12 @@ def circuit_dem(d: int, rounds: int, p: float, return_stats: bool = False):
         for layer in reversed(layers):
             busy = set()
             for (ctl, tgt) in layer:
-                depol2(ctl, tgt)
+                depol2(ctl, tgt, p_gate)
                 busy.add(ctl)
                 busy.add(tgt)
             for q in all_q:
                 if q not in busy:
-                    depol1(q)  # idle in this layer
+                    depol1(q, p_idle_gate)  # idle in this layer
             for (ctl, tgt) in layer:
                 # backward through CNOT: X_ctl -> X_ctl X_tgt, Z_tgt -> Z_ctl Z_tgt
                 sx[ctl] ^= sx[tgt]
@@ -322,35 +337,35 @@ def circuit_dem(d: int, rounds: int, p: float, return_stats: bool = False):
             sx[za[c]] = dets_mz(c, r)
             sz[za[c]] = 0
         for c in range(P):
-            add(sx[za[c]], p)
+            add(sx[za[c]], p_meas)
         for qb in range(n):
-            depol1(qb)
+            depol1(qb, p_idle_mr)
         cnot_layers_backward(z_layers)
         # layer: X-ancilla readout (flip before it) and Z-ancilla reset (flip
         # after it); data idle
         for c in range(P):
-            add(sx[za[c]], p)
+            add(sx[za[c]], p_reset)
             sx[za[c]] = sz[za[c]] = 0
         for c in range(P):
             sz[xa[c]] = dets_mx(c, r)
             sx[xa[c]] = 0
         for c in range(P):
-            add(sz[xa[c]], p)
+            add(sz[xa[c]], p_meas)
         for qb in range(n):
-            depol1(qb)
+            depol1(qb, p_idle_mr)
         cnot_layers_backward(x_layers)
         # layer: X-ancilla reset (flip after it); data reset in round 1,
         # otherwise idle
         for c in range(P):
-            add(sz[xa[c]], p)
+            add(sz[xa[c]], p_reset)
             sx[xa[c]] = sz[xa[c]] = 0
         if r == 1:
             for qb in range(n):
-                add(sz[qb], p)  # data prepared in |+> with a phase flip
+                add(sz[qb], p_reset)  # data prepared in |+> with a phase flip
                 sx[qb] = sz[qb] = 0
         else:
             for qb in range(n):
-                depol1(qb)
+                depol1(qb, p_idle_mr)
 
     det_mask = obs_bit - 1
     undetectable = [s for s in sigs if (s & det_mask) == 0]
@@ -367,9 +382,10 @@ def circuit_dem(d: int, rounds: int, p: float, return_stats: bool = False):
         col_dets.append(dets)
         col_obs.append([0] if s & obs_bit else [])
         pri.append(sigs[s])
+    suffix = "" if noise == "uniform" else f"_{noise}"
     dem = dem_from_columns(m, 1, col_dets, col_obs, pri,
-                           name=f"circuit_d{d}_r{R}_p{p:g}",
-                           meta={"d": d, "rounds": R, "p": p, "family": "circuit_uniform",
+                           name=f"circuit_d{d}_r{R}_p{p:g}{suffix}",
+                           meta={"d": d, "rounds": R, "p": p, "family": f"circuit_{noise}",
                                  "elementary_faults": n_faults})
     if return_stats:
         return dem, {"elementary_faults": n_faults, "signatures": len(sigs)}

@@ -113,6 +113,11 @@ def test_bp_members_fp64_bit_exact_circuit_full_size(torch_cuda):
     _bp_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 2, 4, 2, 13, stop=False, bits=64)
 
 
+def test_bp_members_fp64_bit_exact_circuit_si1000(torch_cuda):
+    # Si1000 rates (Sec. IV.A): same circuit, readout flips at 5p
+    _bp_parity(torch_cuda, circuit_dem(5, 5, 2e-3, noise="si1000"), 4, 8, 4, 16, stop=False, bits=64)
+
+
 def test_bp_parallel_schedule_fp64_bit_exact(torch_cuda):
     # Algorithm 1, parallel branch: every message from the previous iteration
     _bp_parity(torch_cuda, code_capacity_dem(5, 0.05), 2, 32, 40, 14, stop=True, bits=64, schedule="parallel")
@@ -246,6 +251,10 @@ def test_decode_fp64_phenomenological(torch_cuda):
 
 def test_decode_fp64_circuit_full_size(torch_cuda):
     _decode_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 32, 5, 20, 2048, 5, 32, bits=64)
+
+
+def test_decode_fp64_circuit_si1000(torch_cuda):
+    _decode_parity(torch_cuda, circuit_dem(5, 5, 2e-3, noise="si1000"), 32, 5, 20, 1024, 8, 64, bits=64)
 
 
 def test_decode_bp_lsd_baseline(torch_cuda):

@@ -101,3 +101,24 @@ def test_permutations():
     for row in p:
         assert sorted(row.tolist()) == list(range(100))
     assert np.array_equal(p, permutations(100, 8, 1))
+
+
+def test_circuit_dem_si1000_same_faults_table_rates():
+    """Si1000 (Sec. IV.A table) changes the rates, not the circuit: the same
+    elementary fault locations and the same merged columns as Uniform.  To
+    first order a column's prior is the sum of its faults' rates, and each
+    Si1000 rate is between 1/10 (idling in a gate layer) and 5 (readout
+    flips) times the Uniform one, so every column's ratio lies in that range;
+    columns made only of two-qubit gate faults keep their prior (ratio 1),
+    and columns holding readout flips rise well above it."""
+    u, su = circuit_dem(5, 5, 1e-4, return_stats=True)
+    s, ss = circuit_dem(5, 5, 1e-4, return_stats=True, noise="si1000")
+    assert su["elementary_faults"] == ss["elementary_faults"]
+    assert u.m == s.m and u.n == s.n
+    assert np.array_equal(u.dense_h(), s.dense_h()) and np.array_equal(u.dense_l(), s.dense_l())
+    ratio = s.priors / u.priors
+    assert ratio.min() >= 0.1 * (1 - 1e-3) and ratio.max() <= 5.0 * (1 + 1e-3)
+    assert np.isclose(np.median(ratio), 1.0, rtol=1e-3)
+    assert ratio.max() > 2.5 and ratio.min() < 0.5
+    with pytest.raises(ValueError):
+        circuit_dem(3, 3, 1e-3, noise="nope")
