@@ -106,6 +106,30 @@ def bp(g: OracleGraph, s, perm=None, T=20, alpha=0.625, lim=1e6, stop=True, trac
             "min_abs_post": mn.value, "trace": tr}
 
 
+def bp_layered(g: OracleGraph, s, cperm, T=20, alpha=0.625, lim=1e6, stop=True, trace=False, lam=None):
+    """One min-sum decoder with the layered (check-serial) schedule: the
+    checks in the order cperm (or_bp_layered).  Same outputs as bp()."""
+    L = lib()
+    s = np.ascontiguousarray(s, dtype=np.uint8)
+    lam = prior_llr(g.priors, lim) if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
+    al = np.full(T, alpha, dtype=np.float64) if np.ndim(alpha) == 0 else \
+        np.ascontiguousarray(alpha, dtype=np.float64)
+    tconv, iters, mn = C.c_int(0), C.c_int(0), C.c_double(0)
+    ehat = np.zeros(g.n, np.uint8)
+    post = np.zeros(g.n, np.float64)
+    tr = np.full((T, g.n), np.nan) if trace else None
+    cp = np.ascontiguousarray(cperm, dtype=np.uint32)
+    if cp.shape != (g.m,):
+        raise ValueError("cperm must be a permutation of the m checks")
+    rc = L.or_bp_layered(*g.args(), _p(lam, F64), _p(s, U8), _p(cp, U32), C.c_int(T), _p(al, F64),
+                         C.c_double(lim), C.c_int(1 if stop else 0), C.byref(tconv), _p(ehat, U8),
+                         _p(post, F64), C.byref(iters), C.byref(mn), _p(tr, F64) if trace else None)
+    if rc:
+        raise MemoryError("oracle bp failed")
+    return {"t_conv": tconv.value, "ehat": ehat, "post": post, "iters": iters.value,
+            "min_abs_post": mn.value, "trace": tr}
+
+
 def bp_loss(g: OracleGraph, s, lam, alpha, K, perm=None, lim=1e6, eps=1e-7):
     """Soft-syndrome loss after K unrolled iterations (or_bp_loss):
     -> (loss, branch signature, final posteriors)."""
@@ -182,6 +206,9 @@ def decode(g: OracleGraph, perms, synd, L=32, M=5, T=20, alpha=0.625, lim=1e6,
     perms = np.ascontiguousarray(perms, dtype=np.uint32)
     if schedule == "serial" and perms.shape != (L, g.n):
         raise ValueError("perms must be [L, n]")
+    if schedule == "layered" and perms.shape != (L, g.m):
+        raise ValueError("layered schedules take check permutations [L, m]")
+    sched = {"serial": 0, "parallel": 1, "layered": 2}[schedule]
     lam = prior_llr(g.priors, lim)
     al = np.full(T, alpha, dtype=np.float64) if np.ndim(alpha) == 0 else \
         np.ascontiguousarray(alpha, dtype=np.float64)
@@ -194,7 +221,7 @@ def decode(g: OracleGraph, perms, synd, L=32, M=5, T=20, alpha=0.625, lim=1e6,
     lb.or_decode_batch(g.m, g.n, g.k, _p(g.rp, I32), _p(g.ri, I32), _p(g.cp, I32),
                        _p(g.ci, I32), _p(g.ce, I32), _p(g.lp, I32), _p(g.li, I32),
                        _p(lam, F64), _p(perms, U32), C.c_int(L), C.c_int(M), C.c_int(T),
-                       _p(al, F64), C.c_double(lim), C.c_int(0 if schedule == "serial" else 1),
+                       _p(al, F64), C.c_double(lim), C.c_int(sched),
                        _p(synd, U8), C.c_int64(B), C.c_int(threads), _p(ehat, U8), _p(obs, U8),
                        _p(rec, F64), _p(tm, I32) if tm is not None else None,
                        _p(qo, F64) if qo is not None else None)

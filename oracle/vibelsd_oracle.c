@@ -12,7 +12,8 @@
  * What it follows (paper = arXiv 2508.15743):
  *   - min-sum BP, parallel and serial-V schedules: Appendix A, Algorithm 1,
  *     with the syndrome sign (1 - 2 s_c) of syndrome-based decoding and a
- *     constant or per-iteration scaling factor alpha_t;
+ *     constant or per-iteration scaling factor alpha_t; the layered
+ *     (check-serial) schedule that Sec. V names as future work;
  *   - the ensemble, correction limit M, candidate ranking by prior weight
  *     and the normalised LLR average: Sec. III.D.1-2 (offline / online);
  *   - LSD-0 post-processing: Sec. III.C (cluster growth guided by soft
@@ -183,6 +184,82 @@ int or_bp(int m, int n, const int *rp, const int *ri, const int *cp, const int *
           double *min_abs_post, double *trace) {
     return bp_core(m, n, rp, ri, cp, ci, ce, lam, s, perm, T, alpha, lim, stop_on_converge, t_conv, ehat,
                    post, iters, min_abs_post, trace, NULL);
+}
+
+/*
+ * Min-sum BP with the layered (check-serial) schedule: the checks are visited
+ * one at a time in the order cperm (a permutation of the m checks, one per
+ * member), and each check works from the latest posteriors.  The paper names
+ * layered schedules only as future work (Sec. V); the update is the usual
+ * layered form of the same min-sum message passing:
+ *   L_v starts at lambda_v (clamped), every check message r_{c->v} at 0;
+ *   at check c, for each v in N(c): mu_{v->c} = L_v - r_{c->v} (the variable
+ *   message without this check's own contribution), clamped;
+ *   r_{c->v} = (1 - 2 s_c) alpha_t prod sign min |mu| over N(c) \ v;
+ *   L_v = (L_v - r_old) + r_{c->v}, with the unclamped difference.
+ * After all m checks, the posteriors are L_v clamped; the decision, the
+ * convergence test and the outputs are those of or_bp.
+ */
+int or_bp_layered(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci, const int *ce,
+                  const double *lam, const uint8_t *s, const uint32_t *cperm, int T, const double *alpha,
+                  double lim, int stop_on_converge, int *t_conv, uint8_t *ehat, double *post, int *iters,
+                  double *min_abs_post, double *trace) {
+    ograph g = {m, n, rp, ri, cp, ci, ce, NULL};
+    int E = rp[m];
+    double *r = (double *)calloc((size_t)(E ? E : 1), sizeof(double));    /* by CSR position */
+    double *mu = (double *)malloc(sizeof(double) * (E ? E : 1));          /* this check's mu, clamped */
+    double *mraw = (double *)malloc(sizeof(double) * (E ? E : 1));        /* unclamped */
+    double *rn = (double *)malloc(sizeof(double) * (E ? E : 1));
+    double *Lv = (double *)malloc(sizeof(double) * (n ? n : 1));
+    if (!r || !mu || !mraw || !rn || !Lv) {
+        free(r);
+        free(mu);
+        free(mraw);
+        free(rn);
+        free(Lv);
+        return -2;
+    }
+    for (int v = 0; v < n; v++) Lv[v] = clampd(lam[v], lim);
+    memset(ehat, 0, (size_t)n);
+    for (int v = 0; v < n; v++) post[v] = Lv[v];
+    *t_conv = 0;
+    *iters = 0;
+    double minabs = INFINITY;
+    for (int t = 1; t <= T; t++) {
+        double a = alpha[t - 1];
+        for (int idx = 0; idx < m; idx++) {
+            int c = (int)cperm[idx];
+            for (int k = rp[c]; k < rp[c + 1]; k++) {
+                mraw[k] = Lv[ri[k]] - r[k];
+                mu[k] = clampd(mraw[k], lim);
+            }
+            /* every message of the row from the same mu (check_to_var reads mu by CSR position) */
+            for (int k = rp[c]; k < rp[c + 1]; k++) rn[k] = check_to_var(&g, mu, s, c, ri[k], a, lim);
+            for (int k = rp[c]; k < rp[c + 1]; k++) {
+                r[k] = rn[k];
+                Lv[ri[k]] = mraw[k] + r[k];
+            }
+        }
+        for (int v = 0; v < n; v++) {
+            post[v] = clampd(Lv[v], lim);
+            ehat[v] = post[v] <= 0.0;
+            double aa = fabs(post[v]);
+            if (aa < minabs) minabs = aa;
+        }
+        if (trace) memcpy(trace + (size_t)(t - 1) * n, post, sizeof(double) * n);
+        *iters = t;
+        if (syndrome_matches(&g, ehat, s)) {
+            if (!*t_conv) *t_conv = t;
+            if (stop_on_converge) break;
+        }
+    }
+    if (min_abs_post) *min_abs_post = minabs;
+    free(r);
+    free(mu);
+    free(mraw);
+    free(rn);
+    free(Lv);
+    return 0;
 }
 
 /*
@@ -557,11 +634,11 @@ typedef struct {
     int m, n, k;
     const int *rp, *ri, *cp, *ci, *ce, *lp, *li;
     const double *lam;
-    const uint32_t *perms; /* L x n */
+    const uint32_t *perms; /* L x n (serial-V) or L x m (layered) */
     int L, M, T;
     const double *alpha; /* T */
     double lim;
-    int schedule; /* 0 serial-V, 1 parallel (members ignore perms) */
+    int schedule; /* 0 serial-V, 1 parallel (members ignore perms), 2 layered */
 } odec;
 
 static void decode_one(const odec *D, const uint8_t *s, uint8_t *ehat, uint8_t *obs, double *rec,
@@ -578,9 +655,14 @@ static void decode_one(const odec *D, const uint8_t *s, uint8_t *ehat, uint8_t *
     for (int i = 0; i < L; i++) {
         int iters = 0;
         double mn = INFINITY;
-        or_bp(D->m, n, D->rp, D->ri, D->cp, D->ci, D->ce, D->lam, s,
-              D->schedule == 0 ? D->perms + (size_t)i * n : NULL, D->T, D->alpha, D->lim, 1,
-              &tc[i], e + (size_t)i * n, post + (size_t)i * n, &iters, &mn, NULL);
+        if (D->schedule == 2)
+            or_bp_layered(D->m, n, D->rp, D->ri, D->cp, D->ci, D->ce, D->lam, s, D->perms + (size_t)i * D->m,
+                          D->T, D->alpha, D->lim, 1, &tc[i], e + (size_t)i * n, post + (size_t)i * n, &iters, &mn,
+                          NULL);
+        else
+            or_bp(D->m, n, D->rp, D->ri, D->cp, D->ci, D->ce, D->lam, s,
+                  D->schedule == 0 ? D->perms + (size_t)i * n : NULL, D->T, D->alpha, D->lim, 1,
+                  &tc[i], e + (size_t)i * n, post + (size_t)i * n, &iters, &mn, NULL);
         if (mn < minabs_all) minabs_all = mn;
         if (t_members) t_members[i] = tc[i];
     }
