@@ -69,7 +69,15 @@ typedef struct vibe_config {
                               (flooding: every message of an iteration is
                               formed from the previous iteration's, Algorithm
                               1 parallel branch; all members then agree, so
-                              L = 1 gives the BP+LSD-0 baseline of Sec. IV.H) */
+                              L = 1 gives the BP+LSD-0 baseline of Sec. IV.H);
+                              2 = layered (check-serial, which Sec. V names as
+                              future work: each member visits the checks one
+                              at a time in its own order, every check working
+                              from the latest posteriors, mu = L - r_own).
+                              Layered graphs decode through vibe_decode,
+                              vibe_decode_plain, vibe_bp_ensemble and
+                              vibe_lsd; ragged calls, servers and the
+                              gradient refuse them (VIBE_EUNSUPPORTED). */
 } vibe_config;
 
 typedef struct vibe_shot_stats {
@@ -115,7 +123,9 @@ typedef struct vibe_graph_info {
  *   h_indices       h_indptr[m] column indices, < n, strictly ascending per row
  *   priors          n probabilities, each strictly between 0 and 1
  *   k, l_indptr, l_indices   the observable matrix in the same CSR form
- *   perms           L x n uint32 permutations (host)
+ *   perms           L x n uint32 permutations of the columns (host); with
+ *                   the layered schedule L x m permutations of the checks
+ *                   (each member's check order)
  *   cfg             decoder settings (copied)
  *   out             receives the handle
  * Limits (VIBE_EUNSUPPORTED beyond them): m < 65536, n < 2^24, every column

@@ -249,7 +249,9 @@ class Graph:
     schedules.  `perms` is [L, n]: the serial schedules of the members.
     message_bits=64 runs BP in FP64 (verification); 32 is the production
     setting.  schedule="parallel" runs every member with the flooding
-    schedule (L=1, M=1 is the BP+LSD-0 baseline)."""
+    schedule (L=1, M=1 is the BP+LSD-0 baseline); schedule="layered" runs
+    the check-serial schedule, and `perms` is then [L, m], one order of the
+    checks per member."""
 
     def __init__(self, h_indptr, h_indices, priors, l_indptr, l_indices, perms, m=None, n=None,
                  L=32, M=5, T_max=20, alpha=0.625, clamp=1e6, lsd_order=0, message_bits=32,
@@ -265,10 +267,11 @@ class Graph:
         self.L, self.M, self.T_max = L, M, T_max
         self.words = (self.n + 63) // 64
         self.message_bits = message_bits
-        if schedule not in ("serial", "parallel"):
-            raise ValueError("schedule must be 'serial' or 'parallel'")
-        self.cfg = vibe_config(L, M, T_max, lsd_order, alpha, clamp, message_bits,
-                               0 if schedule == "serial" else 1)
+        codes = {"serial": 0, "parallel": 1, "layered": 2}
+        if schedule not in codes:
+            raise ValueError("schedule must be 'serial', 'parallel' or 'layered'")
+        self.schedule = schedule
+        self.cfg = vibe_config(L, M, T_max, lsd_order, alpha, clamp, message_bits, codes[schedule])
         self.handle = vibe_graph_create(self.m, self.n, h_indptr, h_indices, priors, self.k,
                                         l_indptr, l_indices, perms, self.cfg)
 

@@ -123,6 +123,18 @@ __device__ __forceinline__ T bload(Rsrc r, uint32_t voff, uint32_t soff) {
     }
 }
 
+// the same, missing the vector L1: for words another lane wrote
+template <class T>
+__device__ __forceinline__ T bloadx(Rsrc r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4) {
+        const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 1);
+        return __builtin_bit_cast(T, u);
+    } else {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 1);
+        return __builtin_bit_cast(T, u);
+    }
+}
+
 template <class T>
 __device__ __forceinline__ void bstore(T v, Rsrc r, uint32_t voff, uint32_t soff) {
     if constexpr (sizeof(T) == 4) {
@@ -385,7 +397,90 @@ __device__ __forceinline__ void backward(const Ctx<F>& x, uint32_t nch, typename
 // shot's syndrome, its convergence record, candidate and contribution to
 // the normalised average.  `lds` is the block's dynamic LDS; the slabs and
 // posteriors are the block's own.
-template <class F, bool SLAB_LDS, bool FLOOD>
+// One sweep of the layered (check-serial) schedule: the checks one at a
+// time in the member's order cord.  The slab holds the check messages r by
+// CSR position (position k of a row is always handled by lane (k - row
+// start) mod 64, so each lane reads back only what it wrote) and, from byte
+// offset E * sizeof(F), the running posteriors L_v, which any lane writes
+// and which are therefore read past the L1.  At check c every edge forms
+// mu = L_v - r (clamped); the row's smallest and next smallest magnitude,
+// the position of the smallest and the sign parity are reduced over the
+// wavefront; then r_{c->v} = (1 - 2 s_c) alpha prod sign min over the
+// others (the next smallest for the position of the smallest, the clamp
+// for a row of one) and L_v = (L_v - r_old) + r_new.  Afterwards every
+// decision is refreshed from the clamped L and the residual updated.
+template <class F>
+__device__ __forceinline__ void layered_sweep(const DevGraph& g, const Ctx<F>& x, const uint32_t* cord,
+                                              bool want_post) {
+    using P = Prec<F>;
+    const uint32_t lane = x.lane;
+    constexpr uint32_t fb = sizeof(F);
+    const uint32_t oL = g.E * fb;
+    const F lim = x.lim, al = x.al;
+    if (g.m) {
+        uint32_t c_next = uni(cord[0]);
+        for (uint32_t idx = 0; idx < g.m; idx++) {
+            const uint32_t c = c_next;
+            if (idx + 1 < g.m) c_next = uni(cord[idx + 1]);
+            const uint32_t k0 = uni(g.rp[c]), k1 = uni(g.rp[c + 1]);
+            const bool sc = ((x.sb[c >> 6] >> (c & 63)) & 1ull) != 0;
+            F m1 = lim, m2 = lim;
+            uint32_t arg = 0xffffffffu, par = 0;
+            for (uint32_t k = k0 + lane; k < k1; k += kWave) {
+                const uint32_t v = g.ri[k];
+                const F mu = P::clamp(bloadx<F>(x.slb, oL + v * fb, 0) - bload<F>(x.slb, k * fb, 0), lim);
+                const F a = fabs(mu);
+                par ^= mu < F(0) ? 1u : 0u;
+                if (a < m1) {
+                    m2 = m1;
+                    m1 = a;
+                    arg = k;
+                } else if (a < m2) {
+                    m2 = a;
+                }
+            }
+            for (int off = kWave / 2; off > 0; off >>= 1) {
+                const F om1 = __shfl_xor(m1, off), om2 = __shfl_xor(m2, off);
+                const uint32_t oarg = __shfl_xor(arg, off), opar = __shfl_xor(par, off);
+                const bool take = om1 < m1 || (om1 == m1 && oarg < arg);
+                const F hi1 = m1 < om1 ? om1 : m1, lo2 = m2 < om2 ? m2 : om2;
+                m2 = hi1 < lo2 ? hi1 : lo2;
+                m1 = take ? om1 : m1;
+                arg = take ? oarg : arg;
+                par ^= opar;
+            }
+            for (uint32_t k = k0 + lane; k < k1; k += kWave) {
+                const uint32_t v = g.ri[k];
+                const F mraw = bloadx<F>(x.slb, oL + v * fb, 0) - bload<F>(x.slb, k * fb, 0);
+                const F mu = P::clamp(mraw, lim);
+                const F mag = k == arg ? m2 : m1;
+                const bool neg = ((par ^ (mu < F(0) ? 1u : 0u)) != 0) != sc;
+                const F rn = al * (neg ? -mag : mag);
+                bstore<F>(rn, x.slb, k * fb, 0);
+                bstore<F>(mraw + rn, x.slb, oL + v * fb, 0);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    for (uint32_t v = lane; v < g.n; v += kWave) {
+        const uint32_t j0 = g.cp[v], j1 = g.cp[v + 1];
+        if (j0 == j1) continue;  // no check: L_v = lambda_v, decision fixed
+        const F L = P::clamp(bloadx<F>(x.slb, oL + v * fb, 0), lim);
+        if (want_post) x.post[v] = L;
+        const bool enew = L <= F(0);
+        const bool eold = (x.eb[v >> 6] >> (v & 63)) & 1ull;
+        if (enew != eold) {
+            atomicXor(reinterpret_cast<unsigned long long*>(&x.eb[v >> 6]), 1ull << (v & 63));
+            for (uint32_t j = j0; j < j1; j++) {
+                const uint32_t c = g.ci[j];
+                atomicXor(reinterpret_cast<unsigned long long*>(&x.res[c >> 6]), 1ull << (c & 63));
+            }
+        }
+    }
+}
+
+template <class F, bool SLAB_LDS, bool FLOOD, bool LAYERED = false>
 __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, uint32_t item, unsigned char* lds,
                                          Ctx<F> x) {
     using P = Prec<F>;
@@ -465,6 +560,18 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
     const unsigned char* recs = g.sched + (size_t)c0 * rec_bytes(kF64);
     x.sch = make_rsrc(recs, nch * rec_bytes(kF64));
     F* post_out = a.post_out ? reinterpret_cast<F*>(a.post_out) + (size_t)rec * g.n : nullptr;
+    if constexpr (LAYERED) {
+        // check messages 0, each position stored by the lane that will use
+        // it; posteriors lambda (clamped)
+        for (uint32_t c = 0; c < g.m; c++) {
+            const uint32_t k0 = uni(g.rp[c]), k1 = uni(g.rp[c + 1]);
+            for (uint32_t k = k0 + lane; k < k1; k += kWave) bstore<F>(F(0), x.slb, k * (uint32_t)sizeof(F), 0);
+        }
+        for (uint32_t v = lane; v < g.n; v += kWave)
+            bstore<F>(P::clamp(lamv[v], x.lim), x.slb, (g.E + v) * (uint32_t)sizeof(F), 0);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
     if constexpr (SLAB_LDS) {
         // the first sweep reads the initial suffix states from the slab
         for (uint32_t q = 0; q < nch; q++)
@@ -486,7 +593,9 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
         }
         for (uint32_t c = lane; c < g.m; c += kWave) pref[c] = ident;
         __syncthreads();
-        if (nch) {
+        if constexpr (LAYERED) {
+            layered_sweep<F>(g, x, g.cperm + (size_t)mem * g.m, want_post);
+        } else if (nch) {
             if (want_post)
                 sweep<F, SLAB_LDS, true, FLOOD>(x, nch, t == 1);
             else
@@ -506,7 +615,7 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
             if (!conv_t) conv_t = t;
             if (a.stop_on_converge) break;
         }
-        if (t < a.T_run && nch) {
+        if (!LAYERED && t < a.T_run && nch) {
             for (uint32_t c = lane; c < g.m; c += kWave) pref[c] = ident;
             __syncthreads();
             backward<F, SLAB_LDS, FLOOD>(x, nch, pref);
@@ -605,7 +714,7 @@ __device__ __forceinline__ T load_const(const T* p) {
 }
 
 // One launch over the items of one request.
-template <class F, bool SLAB_LDS, bool FLOOD>
+template <class F, bool SLAB_LDS, bool FLOOD, bool LAYERED = false>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_target<F, SLAB_LDS, FLOOD, false>()))) void bp_ensemble_kernel(DevGraph g, BpLaunch a) {
     using B = typename Prec<F>::B;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -618,7 +727,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_tar
     for (;;) {
         const uint32_t item = wave_ticket(a.counter, 1u);
         if (item >= n_items) break;
-        run_item<F, SLAB_LDS, FLOOD>(g, a, item, lds, x);
+        run_item<F, SLAB_LDS, FLOOD, LAYERED>(g, a, item, lds, x);
         __syncthreads();
     }
 }
@@ -663,7 +772,10 @@ const void* kernel_for_t(bool slab_in_lds, bool ragged) {
     return slab_in_lds ? (const void*)bp_ensemble_kernel<F, true, FLOOD> : (const void*)bp_ensemble_kernel<F, false, FLOOD>;
 }
 
-const void* kernel_for(bool fp64, bool flood, bool slab_in_lds, bool ragged) {
+const void* kernel_for(bool fp64, bool flood, bool slab_in_lds, bool ragged, bool layered = false) {
+    // the layered schedule: one request at a time, slab in global memory
+    if (layered) return fp64 ? (const void*)bp_ensemble_kernel<double, false, false, true>
+                             : (const void*)bp_ensemble_kernel<float, false, false, true>;
     if (fp64) return flood ? kernel_for_t<double, true>(slab_in_lds, ragged) : kernel_for_t<double, false>(slab_in_lds, ragged);
     return flood ? kernel_for_t<float, true>(slab_in_lds, ragged) : kernel_for_t<float, false>(slab_in_lds, ragged);
 }
@@ -693,9 +805,9 @@ size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds) {
 
 
 
-bool bp_slab_fits_lds(const DevGraph& g) { return bp_lds_bytes(g, true) <= 96 * 1024; }
+bool bp_slab_fits_lds(const DevGraph& g) { return !g.layered && bp_lds_bytes(g, true) <= 96 * 1024; }
 
-int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged) {
+int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged, bool layered) {
     static int cached_cus = 0;
     if (!cached_cus) {
         int dev = 0;
@@ -705,21 +817,22 @@ int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool 
         cached_cus = prop.multiProcessorCount;
     }
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_for(fp64, flood, slab_in_lds, ragged),
-                                                                kWave, lds_bytes);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, kernel_for(fp64, flood, slab_in_lds, ragged, layered), kWave, lds_bytes);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     if (per_cu > 32) per_cu = 32;
     return per_cu * cached_cus;
 }
 
 int bp_grid(const DevGraph& g, bool slab_in_lds) {
-    return bp_grid_for(g.fp64 != 0, g.flood != 0, slab_in_lds, bp_lds_bytes(g, slab_in_lds), false);
+    return bp_grid_for(g.fp64 != 0, g.flood != 0, slab_in_lds, bp_lds_bytes(g, slab_in_lds), false, g.layered != 0);
 }
 
 int launch_bp(const DevGraph& g, const BpLaunch& a, hipStream_t st) {
     const bool in_lds = a.slab_in_lds != 0;
     void* args[] = {const_cast<DevGraph*>(&g), const_cast<BpLaunch*>(&a)};
-    return launch_fn(kernel_for(g.fp64 != 0, g.flood != 0, in_lds, false), a.grid, bp_lds_bytes(g, in_lds), args, st);
+    return launch_fn(kernel_for(g.fp64 != 0, g.flood != 0, in_lds, false, g.layered != 0), a.grid,
+                     bp_lds_bytes(g, in_lds), args, st);
 }
 
 int launch_bp_ragged(const RaggedLaunch& r, hipStream_t st) {

@@ -942,6 +942,7 @@ extern "C" int vibe_bp_grad(vibe_graph* G, const uint8_t* syndromes, uint64_t B,
     if (!syndromes || !lam || !alpha || !loss || !dlam || !dalpha) return fail(VIBE_EINVAL, "NULL argument");
     if (!(eps > 0.0 && eps < 0.5)) return fail(VIBE_EINVAL, "eps must be in (0, 0.5)");
     const DevGraph& g = G->h.dg;
+    if (g.layered) return fail(VIBE_EUNSUPPORTED, "the gradient covers the serial-V and parallel schedules");
     if ((uint64_t)g.E >= kSlotMask) return fail(VIBE_EUNSUPPORTED, "graph too large for the gradient (E >= 2^24 - 1)");
     const uint64_t items64 = B * g.L;
     if (items64 > (1u << 24)) return fail(VIBE_EINVAL, "B x L must be at most 2^24");

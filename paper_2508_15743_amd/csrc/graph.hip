@@ -77,7 +77,8 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     if (!(c.clamp >= 1.0) || !(c.clamp <= 1e30)) return fail(VIBE_EINVAL, "clamp must be in [1, 1e30]");
     if (c.message_bits != 0 && c.message_bits != 32 && c.message_bits != 64)
         return fail(VIBE_EINVAL, "message_bits must be 0, 32 or 64");
-    if (c.schedule > 1) return fail(VIBE_EINVAL, "schedule must be 0 (serial) or 1 (parallel)");
+    if (c.schedule > 2) return fail(VIBE_EINVAL, "schedule must be 0 (serial), 1 (parallel) or 2 (layered)");
+    const bool layered = c.schedule == 2;
     if (m && (size_t)m * (c.message_bits == 64 ? 8 : 4) + 8 * (2 * (size_t)((m + 63) / 64) + (n + 63) / 64) >
                  150 * 1024)
         return fail(VIBE_EUNSUPPORTED, "per-decoder LDS state exceeds 150 KB");
@@ -111,14 +112,17 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
                 if (!l_indices || l_indices[a] >= n) return fail(VIBE_EINVAL, "bad observable column");
         }
     }
-    // ---- permutations
+    // ---- permutations: of the n columns, or of the m checks (layered)
     {
-        std::vector<uint8_t> seen(n);
+        const uint32_t len = layered ? m : n;
+        std::vector<uint8_t> seen(len);
         for (uint32_t i = 0; i < c.L; i++) {
             std::fill(seen.begin(), seen.end(), 0);
-            for (uint32_t a = 0; a < n; a++) {
-                uint32_t v = perms[(size_t)i * n + a];
-                if (v >= n || seen[v]) return fail(VIBE_EINVAL, "perms rows must be permutations of 0..n-1");
+            for (uint32_t a = 0; a < len; a++) {
+                uint32_t v = perms[(size_t)i * len + a];
+                if (v >= len || seen[v])
+                    return fail(VIBE_EINVAL, layered ? "perms rows must be permutations of 0..m-1 (layered)"
+                                                     : "perms rows must be permutations of 0..n-1");
                 seen[v] = 1;
             }
         }
@@ -209,7 +213,7 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
         std::vector<uint32_t> running32(m);
         std::vector<uint64_t> running64(m);
         size_t nchunks = 0;
-        for (uint32_t i = 0; i < c.L; i++) {
+        for (uint32_t i = 0; i < (layered ? 0u : c.L); i++) {  // the layered schedule has no chunks
             const uint32_t* pi = perms + (size_t)i * n;
             std::fill(last.begin(), last.end(), kNone);
             std::fill(succ.begin(), succ.end(), kNone);
@@ -376,9 +380,12 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     d.E = (uint32_t)E;
     d.words_n = words_n;
     d.words_m = words_m;
-    d.max_chunks = ch_max;
+    // the layered schedule keeps its check messages (E) and running
+    // posteriors (n) in the slab
+    d.max_chunks = layered ? (uint32_t)((E + n + kWave - 1) / kWave) : ch_max;
     d.fp64 = fp64 ? 1 : 0;
     d.flood = c.schedule == 1 ? 1 : 0;
+    d.layered = layered ? 1 : 0;
     d.alpha = c.alpha;
     d.clamp = lim;
     d.ident32 = ident32;
@@ -417,6 +424,7 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
         (rc = upload(h, e0.data(), e0.size(), &d.e0)) ||
         (rc = upload(h, sched.data(), sched.size(), &d.sched)) ||
         (rc = upload(h, member_chunk.data(), member_chunk.size(), &d.member_chunk)) ||
+        (rc = upload(h, layered ? perms : (const uint32_t*)nullptr, layered ? (size_t)c.L * m : 1, &d.cperm)) ||
         (rc = upload(h, lobs.data(), lobs.size(), &d.lobs))) {
         free_all(h);
         delete g;

@@ -77,6 +77,7 @@ struct DevGraph {
     uint32_t max_chunks;        // largest chunk count of a member (slab = max_chunks * 64)
     int fp64;                   // message precision: 0 = FP32, 1 = FP64
     int flood;                  // schedule: 0 = serial-V, 1 = parallel (flooding)
+    int layered;                // 1: layered (check-serial) schedule; cperm holds the check orders
     double alpha, clamp;
     uint32_t ident32;           // row state of "no message": clamp, parity 0 (FP32 bits)
     uint64_t ident64;           // the same in FP64 bits
@@ -90,6 +91,7 @@ struct DevGraph {
     const uint64_t* e0;           // words_n: decisions of columns without checks
     const unsigned char* sched;   // chunk records of all members, see above
     const uint32_t* member_chunk; // L + 1: chunk range of each member
+    const uint32_t* cperm;        // layered schedule: L x m check orders (else unused)
     const uint64_t* lobs;         // k x words_n, bit-packed observable rows
 };
 
@@ -192,7 +194,7 @@ struct RaggedLaunch {
     size_t lds_bytes;      // largest bp_lds_bytes over the segments
 };
 int launch_bp_ragged(const RaggedLaunch& r, hipStream_t st);
-int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged);
+int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged, bool layered = false);
 int bp_grid(const DevGraph& g, bool slab_in_lds);
 size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds);
 int bp_slabs(const DevGraph& g);  // slabs per block: 1 (serial), 2 (parallel: states and messages)

@@ -351,3 +351,114 @@ def test_plain_equals_batched(torch_cuda):
     c2, o2, _ = G.decode(s, plain=True)
     assert torch.equal(c1, c2) and torch.equal(o1, o2)
     G.close()
+
+
+def _perms_checks(dem, L, seed):
+    return permutations(dem.m, L, seed)
+
+
+def _bp_parity_layered(torch, dem, L, T, shots, seed, stop, bits):
+    """The layered schedule against the oracle's or_bp_layered, member by
+    member (same bars as _bp_parity)."""
+    import paper_2508_15743_amd as P
+
+    cperms = _perms_checks(dem, L, seed)
+    G = P.Graph.from_dem(dem, cperms, L=L, M=min(5, L), T_max=T, message_bits=bits, schedule="layered")
+    b = sample(dem, shots, seed + 1)
+    tc, post, eh = G.bp_ensemble(_dev(torch, b.syndromes), T_run=T, stop=stop)
+    tc, post, eh = tc.cpu().numpy(), post.cpu().numpy(), P.unpack_bits(eh, dem.n)
+    g = O.OracleGraph(dem)
+    for i in range(shots):
+        for j in range(L):
+            r = O.bp_layered(g, b.syndromes[i], cperms[j], T=T, stop=stop)
+            if bits == 64:
+                assert r["t_conv"] == tc[i, j], (i, j)
+                assert np.array_equal(r["ehat"], eh[i, j]), (i, j)
+                assert np.array_equal(r["post"], post[i, j]), (i, j, np.abs(r["post"] - post[i, j]).max())
+                continue
+            if r["min_abs_post"] < 1e-3:
+                continue
+            assert r["t_conv"] == tc[i, j], (i, j)
+            assert np.array_equal(r["ehat"], eh[i, j]), (i, j)
+            scale = max(np.abs(r["post"]).max(), 1.0)
+            assert np.abs(post[i, j].astype(np.float64) - r["post"]).max() <= 1e-4 * scale
+    G.close()
+
+
+def test_bp_layered_fp64_bit_exact(torch_cuda):
+    # code capacity, phenomenological (degree-1 checks), the d = 9 circuit
+    # graph (rows of up to 194 edges: several per lane)
+    _bp_parity_layered(torch_cuda, code_capacity_dem(5, 0.05), 8, 32, 30, 31, stop=True, bits=64)
+    _bp_parity_layered(torch_cuda, phenomenological_dem(11, 11, 0.01, 0.01), 3, 10, 5, 32, stop=False, bits=64)
+    _bp_parity_layered(torch_cuda, circuit_dem(9, 9, 1e-3), 2, 3, 2, 33, stop=False, bits=64)
+
+
+def test_bp_layered_fp32(torch_cuda):
+    _bp_parity_layered(torch_cuda, code_capacity_dem(5, 0.05), 8, 32, 40, 34, stop=True, bits=32)
+    _bp_parity_layered(torch_cuda, circuit_dem(5, 5, 1e-3), 4, 8, 6, 35, stop=False, bits=32)
+
+
+def test_decode_layered(torch_cuda):
+    """Whole decoder with layered members: FP64 against the oracle's decoder
+    on the same check orders, to the FP64 bar.  FP32: every member's
+    convergence iteration matches FP64 on this workload, so shots decided by
+    a BP member must agree with the oracle; shots that reach LSD rank
+    columns by the normalised average of FP32 posteriors, and the layered
+    form keeps a running posterior L_v = (L_v - r_old) + r_new rounded at
+    each of its deg_v updates per sweep over T sweeps (code capacity d = 5:
+    deg_v <= 3, T = 32, about T * deg_v * 2^-24 ~ 6e-6 relative), which
+    decides near-ties among soft values differently from FP64.  There the
+    bar is validity (H e = s) and a logical error rate inside the oracle's
+    95% interval."""
+    for bits in (64, 32):
+        dem = code_capacity_dem(5, 0.05)
+        _decode_parity_layered(torch_cuda, dem, 16, 5, 32, 4000, 36, 4000, bits)
+    _decode_parity_layered(torch_cuda, circuit_dem(5, 5, 2e-3), 16, 5, 20, 512, 37, 64, 64)
+
+
+def _decode_parity_layered(torch, dem, L, M, T, shots, seed, oracle_shots, bits):
+    import paper_2508_15743_amd as P
+    from scipy.stats import beta
+
+    cperms = _perms_checks(dem, L, seed)
+    G = P.Graph.from_dem(dem, cperms, L=L, M=M, T_max=T, message_bits=bits, schedule="layered")
+    b = sample(dem, shots, seed + 7)
+    corr, obs, st = G.decode(_dev(torch, b.syndromes))
+    e, obs, st = P.unpack_bits(corr, dem.n), obs.cpu().numpy(), st.cpu().numpy()
+    H = dem.dense_h().astype(np.int64)
+    ok = (st[:, 0] & 4) == 0
+    assert np.array_equal((e[ok].astype(np.int64) @ H.T) % 2, b.syndromes[ok])
+    ref = _oracle_decode(dem, cperms, b.syndromes[:oracle_shots], L, M, T, schedule="layered")
+    hit = (ref["ehat"] == e[:oracle_shots]).all(1)
+    if bits == 64:
+        assert hit.mean() >= 0.999, hit.mean()
+    else:
+        bp_won = ~ref["lsd_used"]
+        assert hit[bp_won].mean() >= 0.999, (hit[bp_won].mean(), bp_won.mean())
+        assert hit.mean() >= 0.95, hit.mean()
+    n = oracle_shots
+    k = int((ref["obs"] != b.observables[:n]).any(1).sum())
+    lo = beta.ppf(0.025, k, n - k + 1) if k else 0.0
+    hi = beta.ppf(0.975, k + 1, n - k) if k < n else 1.0
+    ler = (obs[:n] != b.observables[:n]).any(1).mean()
+    assert lo <= ler <= hi, (ler, lo, hi)
+    print(f"{dem.name} layered FP{bits}: agreement {hit.mean():.5f} over {n} shots; LER {ler:.5f} in [{lo:.5f}, {hi:.5f}]")
+    G.close()
+
+
+def test_layered_refused_where_unsupported(torch_cuda):
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    dem = code_capacity_dem(5, 0.05)
+    with pytest.raises(P.VibeError):  # column permutations where check orders are due
+        P.Graph.from_dem(dem, permutations(dem.n, 2, 1), L=2, M=1, T_max=8, schedule="layered")
+    G = P.Graph.from_dem(dem, permutations(dem.m, 2, 1), L=2, M=1, T_max=8, schedule="layered")
+    s = _dev(torch, sample(dem, 4, 2).syndromes)
+    with pytest.raises(P.VibeError):
+        G.bp_grad(s, torch.ones(dem.n), torch.ones(3))
+    rt = P.Runtime()
+    with pytest.raises(P.VibeError):
+        rt.decode([(G, s)])
+    rt.close()
+    G.close()
