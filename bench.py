@@ -16,7 +16,8 @@ batch of circuit-level codes at d = 5..13 (rounds = d) decoded as one call
 against one call per code;
 the backward pass of the differentiable decoder (16 unrolled iterations of
 the d = 5 circuit-level graph, 4096 shots, L = 32, FP32) with its own
-roofline; BP+LSD-0 without ensembling (one member,
+roofline; the layered (check-serial) schedule on 8192 of the shots; BP+LSD-0
+without ensembling (one member,
 parallel schedule) on the same batch, with LSD calls and largest-cluster
 sizes beside VibeLSD's (the comparison of the paper's Sec. IV.H); the
 per-shot-launch form
@@ -401,6 +402,25 @@ def main():
                                 "bp_lsd0": baseline(dem_s, perms_s, synd_s, bs.observables)}
         log(f"Si1000: LSD calls per 5000 {comparison['si1000']['bp_lsd0']['lsd_calls_per_5000']} (BP+LSD-0) "
             f"vs {comparison['si1000']['vibelsd']['lsd_calls_per_5000']} (VibeLSD)")
+        # the layered (check-serial) schedule: the same ensemble size and
+        # limits, members ordering the checks instead of the columns
+        nl = min(B, 8192)
+        Gl = P.Graph.from_dem(dem, permutations(dem.m, L, args.seed + 4), L=L, M=M, T_max=T, alpha=alpha,
+                              schedule="layered")
+        Gl.decode(synd[:256])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, lobs, lst = Gl.decode(synd[:nl])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        lst = lst.cpu().numpy()
+        comparison["layered"] = dict(cluster_stats(lst), shots=nl, shots_per_s=round(nl / dt, 1),
+                                     logical_error_rate=float((lobs.cpu().numpy() != batch.observables[:nl])
+                                                              .any(1).mean()),
+                                     mean_member_iterations_per_shot=float(lst[:, 7].mean()))
+        Gl.close()
+        log(f"layered schedule: {nl / dt:.0f} shots/s, LSD calls per 5000 "
+            f"{comparison['layered']['lsd_calls_per_5000']}")
     result["comparison"] = comparison
 
     if not args.no_ragged:

@@ -409,6 +409,65 @@ __device__ __forceinline__ void backward(const Ctx<F>& x, uint32_t nch, typename
 // others (the next smallest for the position of the smallest, the clamp
 // for a row of one) and L_v = (L_v - r_old) + r_new.  Afterwards every
 // decision is refreshed from the clamped L and the residual updated.
+// A row of the layered sweep as held in registers: up to kRowRegs edges per
+// lane (rows of up to 64 * kRowRegs edges); longer rows take a slower path
+// that reloads.
+constexpr int kRowRegs = 4;
+template <class F>
+struct LRow {
+    uint32_t c, k0, k1;
+    uint32_t v[kRowRegs];
+    F r[kRowRegs];
+};
+
+template <class F>
+__device__ __forceinline__ void layered_load_row(const DevGraph& g, const Ctx<F>& x, const uint32_t* cord,
+                                                 uint32_t idx, LRow<F>& row) {
+    row.c = uni(cord[idx]);
+    row.k0 = uni(g.rp[row.c]);
+    row.k1 = uni(g.rp[row.c + 1]);
+    // every load is issued, at a clamped position, so that the compiler
+    // counts them instead of waiting for all loads at each use
+    const uint32_t kmax = g.E ? g.E - 1 : 0;
+#pragma unroll
+    for (int q = 0; q < kRowRegs; q++) {
+        const uint32_t k = min(row.k0 + x.lane + (uint32_t)q * kWave, kmax);
+        row.v[q] = g.ri[k];
+        row.r[q] = bload<F>(x.slb, k * (uint32_t)sizeof(F), 0);
+    }
+}
+
+// the smallest and next smallest magnitude, position of the smallest and
+// sign parity over the wavefront
+template <class F>
+__device__ __forceinline__ void row_reduce(F& m1, F& m2, uint32_t& arg, uint32_t& par) {
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const F om1 = __shfl_xor(m1, off), om2 = __shfl_xor(m2, off);
+        const uint32_t oarg = __shfl_xor(arg, off), opar = __shfl_xor(par, off);
+        const bool take = om1 < m1 || (om1 == m1 && oarg < arg);
+        const F hi1 = m1 < om1 ? om1 : m1, lo2 = m2 < om2 ? m2 : om2;
+        m2 = hi1 < lo2 ? hi1 : lo2;
+        m1 = take ? om1 : m1;
+        arg = take ? oarg : arg;
+        par ^= opar;
+    }
+}
+
+// One sweep of the layered (check-serial) schedule: the checks one at a
+// time in the member's order cord.  The slab holds the check messages r by
+// CSR position (position k of a row is always handled by lane (k - row
+// start) mod 64, so each lane reads back only what it wrote) and, from byte
+// offset E * sizeof(F), the running posteriors L_v, which any lane writes
+// and which are therefore read past the L1.  At check c every edge forms
+// mu = L_v - r (clamped); the row's smallest and next smallest magnitude,
+// the position of the smallest and the sign parity are reduced over the
+// wavefront; then r_{c->v} = (1 - 2 s_c) alpha prod sign min over the
+// others (the next smallest for the position of the smallest, the clamp
+// for a row of one) and L_v = (L_v - r_old) + r_new.  The next check's
+// columns and messages are loaded while the current one is worked on (no
+// other check touches them); its posteriors are not, since the current
+// check may update them.  Afterwards every decision is refreshed from the
+// clamped L and the residual updated.
 template <class F>
 __device__ __forceinline__ void layered_sweep(const DevGraph& g, const Ctx<F>& x, const uint32_t* cord,
                                               bool want_post) {
@@ -418,47 +477,74 @@ __device__ __forceinline__ void layered_sweep(const DevGraph& g, const Ctx<F>& x
     const uint32_t oL = g.E * fb;
     const F lim = x.lim, al = x.al;
     if (g.m) {
-        uint32_t c_next = uni(cord[0]);
+        LRow<F> cur, nxt;
+        layered_load_row<F>(g, x, cord, 0, cur);
         for (uint32_t idx = 0; idx < g.m; idx++) {
-            const uint32_t c = c_next;
-            if (idx + 1 < g.m) c_next = uni(cord[idx + 1]);
-            const uint32_t k0 = uni(g.rp[c]), k1 = uni(g.rp[c + 1]);
+            layered_load_row<F>(g, x, cord, idx + 1 < g.m ? idx + 1 : idx, nxt);
+            const uint32_t c = cur.c, k0 = cur.k0, k1 = cur.k1;
             const bool sc = ((x.sb[c >> 6] >> (c & 63)) & 1ull) != 0;
             F m1 = lim, m2 = lim;
             uint32_t arg = 0xffffffffu, par = 0;
-            for (uint32_t k = k0 + lane; k < k1; k += kWave) {
-                const uint32_t v = g.ri[k];
-                const F mu = P::clamp(bloadx<F>(x.slb, oL + v * fb, 0) - bload<F>(x.slb, k * fb, 0), lim);
-                const F a = fabs(mu);
-                par ^= mu < F(0) ? 1u : 0u;
-                if (a < m1) {
-                    m2 = m1;
-                    m1 = a;
-                    arg = k;
-                } else if (a < m2) {
-                    m2 = a;
+            if (k1 - k0 <= (uint32_t)(kRowRegs * kWave)) {
+                F mraw[kRowRegs];
+#pragma unroll
+                for (int q = 0; q < kRowRegs; q++) {
+                    const uint32_t k = k0 + lane + (uint32_t)q * kWave;
+                    mraw[q] = bloadx<F>(x.slb, oL + cur.v[q] * fb, 0) - cur.r[q];
+                    if (k < k1) {
+                        const F mu = P::clamp(mraw[q], lim);
+                        const F aa = fabs(mu);
+                        par ^= mu < F(0) ? 1u : 0u;
+                        if (aa < m1) {
+                            m2 = m1;
+                            m1 = aa;
+                            arg = k;
+                        } else if (aa < m2) {
+                            m2 = aa;
+                        }
+                    }
+                }
+                row_reduce<F>(m1, m2, arg, par);
+#pragma unroll
+                for (int q = 0; q < kRowRegs; q++) {
+                    const uint32_t k = k0 + lane + (uint32_t)q * kWave;
+                    if (k < k1) {
+                        const F mu = P::clamp(mraw[q], lim);
+                        const F mag = k == arg ? m2 : m1;
+                        const bool neg = ((par ^ (mu < F(0) ? 1u : 0u)) != 0) != sc;
+                        const F rn = al * (neg ? -mag : mag);
+                        bstore<F>(rn, x.slb, k * fb, 0);
+                        bstore<F>(mraw[q] + rn, x.slb, oL + cur.v[q] * fb, 0);
+                    }
+                }
+            } else {
+                // a long row: reload in the second pass
+                for (uint32_t k = k0 + lane; k < k1; k += kWave) {
+                    const uint32_t v = g.ri[k];
+                    const F mu = P::clamp(bloadx<F>(x.slb, oL + v * fb, 0) - bload<F>(x.slb, k * fb, 0), lim);
+                    const F aa = fabs(mu);
+                    par ^= mu < F(0) ? 1u : 0u;
+                    if (aa < m1) {
+                        m2 = m1;
+                        m1 = aa;
+                        arg = k;
+                    } else if (aa < m2) {
+                        m2 = aa;
+                    }
+                }
+                row_reduce<F>(m1, m2, arg, par);
+                for (uint32_t k = k0 + lane; k < k1; k += kWave) {
+                    const uint32_t v = g.ri[k];
+                    const F mraw = bloadx<F>(x.slb, oL + v * fb, 0) - bload<F>(x.slb, k * fb, 0);
+                    const F mu = P::clamp(mraw, lim);
+                    const F mag = k == arg ? m2 : m1;
+                    const bool neg = ((par ^ (mu < F(0) ? 1u : 0u)) != 0) != sc;
+                    const F rn = al * (neg ? -mag : mag);
+                    bstore<F>(rn, x.slb, k * fb, 0);
+                    bstore<F>(mraw + rn, x.slb, oL + v * fb, 0);
                 }
             }
-            for (int off = kWave / 2; off > 0; off >>= 1) {
-                const F om1 = __shfl_xor(m1, off), om2 = __shfl_xor(m2, off);
-                const uint32_t oarg = __shfl_xor(arg, off), opar = __shfl_xor(par, off);
-                const bool take = om1 < m1 || (om1 == m1 && oarg < arg);
-                const F hi1 = m1 < om1 ? om1 : m1, lo2 = m2 < om2 ? m2 : om2;
-                m2 = hi1 < lo2 ? hi1 : lo2;
-                m1 = take ? om1 : m1;
-                arg = take ? oarg : arg;
-                par ^= opar;
-            }
-            for (uint32_t k = k0 + lane; k < k1; k += kWave) {
-                const uint32_t v = g.ri[k];
-                const F mraw = bloadx<F>(x.slb, oL + v * fb, 0) - bload<F>(x.slb, k * fb, 0);
-                const F mu = P::clamp(mraw, lim);
-                const F mag = k == arg ? m2 : m1;
-                const bool neg = ((par ^ (mu < F(0) ? 1u : 0u)) != 0) != sc;
-                const F rn = al * (neg ? -mag : mag);
-                bstore<F>(rn, x.slb, k * fb, 0);
-                bstore<F>(mraw + rn, x.slb, oL + v * fb, 0);
-            }
+            cur = nxt;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
