@@ -177,8 +177,10 @@ def fd_grad(g: OracleGraph, s, lam, alpha, K, perm=None, h=1e-6, lim=1e6, eps=1e
     return dl, okl, da, oka
 
 
-def lsd(g: OracleGraph, s, q):
-    """LSD-0 on soft input q (lower = more likely flipped)."""
+def lsd(g: OracleGraph, s, q, order=0, lim=1e6):
+    """LSD on soft input q (lower = more likely flipped): LSD-0, or with
+    order > 0 the combination sweep over each cluster's non-pivot columns,
+    weighted by the prior LLRs."""
     L = lib()
     s = np.ascontiguousarray(s, dtype=np.uint8)
     q = np.ascontiguousarray(q, dtype=np.float64)
@@ -187,8 +189,9 @@ def lsd(g: OracleGraph, s, q):
     gap = C.c_double(0)
     cl = np.zeros(g.m, np.int32)
     bl = np.zeros(g.n, np.int32)
+    lam = prior_llr(g.priors, lim)
     rc = L.or_lsd(g.m, g.n, _p(g.rp, I32), _p(g.ri, I32), _p(g.cp, I32), _p(g.ci, I32),
-                  _p(s, U8), _p(q, F64), _p(ehat, U8), _p(st, I32), C.byref(gap),
+                  _p(s, U8), _p(q, F64), C.c_int(order), _p(lam, F64), _p(ehat, U8), _p(st, I32), C.byref(gap),
                   _p(cl, I32), _p(bl, I32))
     return {"ehat": ehat, "failed": bool(rc), "clusters": int(st[0]), "largest": int(st[1]),
             "rounds": int(st[2]), "total_bits": int(st[4]), "min_gap": gap.value,
@@ -196,7 +199,7 @@ def lsd(g: OracleGraph, s, q):
 
 
 def decode(g: OracleGraph, perms, synd, L=32, M=5, T=20, alpha=0.625, lim=1e6,
-           schedule="serial", threads=None, want_members=False, want_q=False):
+           schedule="serial", threads=None, want_members=False, want_q=False, lsd_order=0):
     """The full VibeLSD decoder over a batch of syndromes [B, m]."""
     lb = lib()
     synd = np.ascontiguousarray(synd, dtype=np.uint8)
@@ -221,7 +224,7 @@ def decode(g: OracleGraph, perms, synd, L=32, M=5, T=20, alpha=0.625, lim=1e6,
     lb.or_decode_batch(g.m, g.n, g.k, _p(g.rp, I32), _p(g.ri, I32), _p(g.cp, I32),
                        _p(g.ci, I32), _p(g.ce, I32), _p(g.lp, I32), _p(g.li, I32),
                        _p(lam, F64), _p(perms, U32), C.c_int(L), C.c_int(M), C.c_int(T),
-                       _p(al, F64), C.c_double(lim), C.c_int(sched),
+                       _p(al, F64), C.c_double(lim), C.c_int(sched), C.c_int(lsd_order),
                        _p(synd, U8), C.c_int64(B), C.c_int(threads), _p(ehat, U8), _p(obs, U8),
                        _p(rec, F64), _p(tm, I32) if tm is not None else None,
                        _p(qo, F64) if qo is not None else None)

@@ -19,6 +19,8 @@
  *   - LSD-0 post-processing: Sec. III.C (cluster growth guided by soft
  *     information, merging, per-cluster GF(2) solve), with the growth rule
  *     made precise as the synchronous one-column-per-invalid-cluster rule;
+ *     higher LSD orders as the combination sweep of ordered statistics
+ *     decoding on every cluster (osd_cs);
  *   - observables L_obs * e mod 2: Sec. II.B.
  * Readings of points the paper leaves open are listed in the design notes.
  */
@@ -421,14 +423,88 @@ static double soft_val(const osoft *S, int v) {
     return S->k ? (double)S->k[v] * (1.0 / 72057594037927936.0) : S->q[v];
 }
 
+/* LSD-lambda for one valid cluster (its columns ord[0..cols) in rank order,
+   H restricted to its checks in A0, s restricted to them in b0, pivots of
+   the rank-order elimination in piv): the combination sweep of ordered
+   statistics decoding over the non-pivot columns F (in rank order).  The
+   candidates, in this order, set to 1 no column of F; each single column
+   of F; each pair among the first min(order, |F|) columns of F, pairs in
+   lexicographic order.  Every candidate's pivot values are solved afresh
+   from s plus the chosen columns.  The candidate of least prior weight
+   W(e) = sum_v e_v lam_v (summed in ascending v) replaces x; ties keep the
+   earlier candidate.  The paper runs LSD-0 only and names higher orders as
+   an option of the method it builds on (Sec. III.C). */
+static void osd_cs(const ograph *g, const uint8_t *bit, const int *ord, int rows, int cols,
+                   const uint8_t *A0, const uint8_t *b0, const uint8_t *piv, int order, const double *lam,
+                   uint8_t *x) {
+    int nf = 0;
+    int *F = (int *)malloc(sizeof(int) * (cols ? cols : 1));
+    for (int j = 0; j < cols; j++)
+        if (!piv[j]) F[nf++] = j;
+    if (nf == 0) {
+        free(F);
+        return;
+    }
+    const int lo = nf < order ? nf : order;
+    const int ncand = 1 + nf + lo * (lo - 1) / 2;
+    int *ca = (int *)malloc(sizeof(int) * ncand), *cb = (int *)malloc(sizeof(int) * ncand);
+    int t = 0;
+    ca[t] = cb[t] = -1;
+    t++;
+    for (int a = 0; a < nf; a++, t++) {
+        ca[t] = F[a];
+        cb[t] = -1;
+    }
+    for (int a = 0; a < lo; a++)
+        for (int b = a + 1; b < lo; b++, t++) {
+            ca[t] = F[a];
+            cb[t] = F[b];
+        }
+    int *pos = (int *)malloc(sizeof(int) * (g->n ? g->n : 1));
+    for (int v = 0; v < g->n; v++) pos[v] = -1;
+    for (int j = 0; j < cols; j++) pos[ord[j]] = j;
+    uint8_t *A = (uint8_t *)malloc((size_t)rows * cols), *b = (uint8_t *)malloc(rows ? rows : 1);
+    uint8_t *pv = (uint8_t *)malloc(cols), *xc = (uint8_t *)malloc(cols), *best = (uint8_t *)malloc(cols);
+    double bw = 0.0;
+    for (t = 0; t < ncand; t++) {
+        memcpy(A, A0, (size_t)rows * cols);
+        memcpy(b, b0, (size_t)rows);
+        for (int r = 0; r < rows; r++) {
+            if (ca[t] >= 0) b[r] ^= A0[(size_t)r * cols + ca[t]];
+            if (cb[t] >= 0) b[r] ^= A0[(size_t)r * cols + cb[t]];
+        }
+        int ok = 0;
+        gf2_eliminate(A, rows, cols, b, pv, &ok, xc);
+        if (ca[t] >= 0) xc[ca[t]] = 1;
+        if (cb[t] >= 0) xc[cb[t]] = 1;
+        double w = 0.0;
+        for (int v = 0; v < g->n; v++)
+            if (bit[v] && xc[pos[v]]) w += lam[v];
+        if (t == 0 || w < bw) {
+            bw = w;
+            memcpy(best, xc, cols);
+        }
+    }
+    memcpy(x, best, cols);
+    free(F);
+    free(ca);
+    free(cb);
+    free(pos);
+    free(A);
+    free(b);
+    free(pv);
+    free(xc);
+    free(best);
+}
+
 /* stats layout (int[6]): clusters at the end, largest cluster (columns),
    growth rounds, failed (0/1), columns over all clusters, reserved.
    min_gap (if non-NULL): smallest q gap of any rank decision taken.
    chk_label / bit_label (if non-NULL, lengths m / n): final cluster of every
    check / column, numbered in order of the clusters' first check, or -1. */
 static int lsd_impl(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci,
-                    const uint8_t *s, const osoft *S, uint8_t *ehat, int *stats, double *min_gap,
-                    int *chk_label, int *bit_label) {
+                    const uint8_t *s, const osoft *S, int order, const double *lam, uint8_t *ehat,
+                    int *stats, double *min_gap, int *chk_label, int *bit_label) {
     ograph g = {m, n, rp, ri, cp, ci, NULL};
     memset(ehat, 0, (size_t)n);
     double gap = INFINITY;
@@ -558,10 +634,17 @@ static int lsd_impl(int m, int n, const int *rp, const int *ri, const int *cp, c
         }
         for (int c = 0; c < m; c++)
             if (rix[c] >= 0) b[rix[c]] = s[c];
+        uint8_t *A0 = (uint8_t *)malloc((size_t)rows * (cols ? cols : 1));
+        uint8_t *b0 = (uint8_t *)malloc(rows ? rows : 1);
+        memcpy(A0, A, (size_t)rows * cols);
+        memcpy(b0, b, (size_t)rows);
         int ok = 0;
         gf2_eliminate(A, rows, cols, b, piv, &ok, x);
+        if (order > 0) osd_cs(&g, K[i].bit, ord, rows, cols, A0, b0, piv, order, lam, x);
         for (int j = 0; j < cols; j++)
             if (x[j]) ehat[ord[j]] = 1;
+        free(A0);
+        free(b0);
         free(ord);
         free(rix);
         free(A);
@@ -603,20 +686,21 @@ static int lsd_impl(int m, int n, const int *rp, const int *ri, const int *cp, c
 /* ------------------------------------------------------------------------ */
 /* The full decoder for one shot.                                             */
 
-/* LSD-0 on double soft values (rank by (q, index) ascending). */
+/* LSD on double soft values (rank by (q, index) ascending); order 0 is
+   LSD-0, order > 0 adds the combination sweep (osd_cs) with weights lam. */
 int or_lsd(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci,
-           const uint8_t *s, const double *q, uint8_t *ehat, int *stats, double *min_gap,
-           int *chk_label, int *bit_label) {
+           const uint8_t *s, const double *q, int order, const double *lam, uint8_t *ehat, int *stats,
+           double *min_gap, int *chk_label, int *bit_label) {
     osoft S = {q, NULL};
-    return lsd_impl(m, n, rp, ri, cp, ci, s, &S, ehat, stats, min_gap, chk_label, bit_label);
+    return lsd_impl(m, n, rp, ri, cp, ci, s, &S, order, lam, ehat, stats, min_gap, chk_label, bit_label);
 }
 
-/* LSD-0 on int64 fixed-point soft values. */
+/* The same on int64 fixed-point soft values. */
 int or_lsd_key(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci,
-               const uint8_t *s, const int64_t *qk, uint8_t *ehat, int *stats, double *min_gap,
-               int *chk_label, int *bit_label) {
+               const uint8_t *s, const int64_t *qk, int order, const double *lam, uint8_t *ehat,
+               int *stats, double *min_gap, int *chk_label, int *bit_label) {
     osoft S = {NULL, qk};
-    return lsd_impl(m, n, rp, ri, cp, ci, s, &S, ehat, stats, min_gap, chk_label, bit_label);
+    return lsd_impl(m, n, rp, ri, cp, ci, s, &S, order, lam, ehat, stats, min_gap, chk_label, bit_label);
 }
 
 /* per-shot record written by or_decode_batch, 16 doubles:
@@ -639,6 +723,7 @@ typedef struct {
     const double *alpha; /* T */
     double lim;
     int schedule; /* 0 serial-V, 1 parallel (members ignore perms), 2 layered */
+    int lsd_order; /* 0 = LSD-0; > 0 adds the combination sweep */
 } odec;
 
 static void decode_one(const odec *D, const uint8_t *s, uint8_t *ehat, uint8_t *obs, double *rec,
@@ -721,7 +806,8 @@ static void decode_one(const odec *D, const uint8_t *s, uint8_t *ehat, uint8_t *
             for (int v = 0; v < n; v++) q_out[v] = (double)qk[v] * (1.0 / 72057594037927936.0) / L;
         int st[6];
         double gap = INFINITY;
-        int f = or_lsd_key(D->m, n, D->rp, D->ri, D->cp, D->ci, s, qk, ehat, st, &gap, NULL, NULL);
+        int f = or_lsd_key(D->m, n, D->rp, D->ri, D->cp, D->ci, s, qk, D->lsd_order, D->lam, ehat, st, &gap,
+                           NULL, NULL);
         rec[0] = 2 | (f ? 4 : 0);
         rec[4] = st[0];
         rec[5] = st[1];
@@ -772,9 +858,9 @@ static void *worker_main(void *arg) {
 int or_decode_batch(int m, int n, int k, const int *rp, const int *ri, const int *cp, const int *ci,
                     const int *ce, const int *lp, const int *li, const double *lam,
                     const uint32_t *perms, int L, int M, int T, const double *alpha, double lim,
-                    int schedule, const uint8_t *synd, int64_t B, int threads, uint8_t *ehat,
-                    uint8_t *obs, double *rec, int *t_members, double *q_out) {
-    odec D = {m, n, k, rp, ri, cp, ci, ce, lp, li, lam, perms, L, M, T, alpha, lim, schedule};
+                    int schedule, int lsd_order, const uint8_t *synd, int64_t B, int threads,
+                    uint8_t *ehat, uint8_t *obs, double *rec, int *t_members, double *q_out) {
+    odec D = {m, n, k, rp, ri, cp, ci, ce, lp, li, lam, perms, L, M, T, alpha, lim, schedule, lsd_order};
     pthread_mutex_t lock;
     pthread_mutex_init(&lock, NULL);
     oworker w = {&D, synd, ehat, obs, rec, t_members, q_out, 0, B, &lock};
