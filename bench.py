@@ -14,7 +14,8 @@ requests from circuit-level codes d = 9, 13, 5 mixed 50/30/20, Poisson
 arrivals at 0.5x and 0.8x the sustained rate, p50/p99 latency); a ragged
 batch of circuit-level codes at d = 5..13 (rounds = d) decoded as one call
 against one call per code;
-the backward pass of the differentiable decoder (16 unrolled iterations of
+the phenomenological workload (d = 11, 11 rounds, L = 32, T = 50) with
+LSD-0 and with LSD order 10; the backward pass of the differentiable decoder (16 unrolled iterations of
 the d = 5 circuit-level graph, 4096 shots, L = 32, FP32) with its own
 roofline; the layered (check-serial) schedule on 8192 of the shots; BP+LSD-0
 without ensembling (one member,
@@ -112,6 +113,42 @@ def ragged_leg(P, torch, shots, seed):
 # sweep reads the checkpointed message and reads and writes its adjoint
 # (12 B); FP32 each
 GRAD_BYTES_PER_EDGE_ITER = 20.0
+
+
+def phenom_leg(P, torch, seed, shots):
+    """The phenomenological workload as configured (colour code d = 11, 11
+    noisy rounds and a perfect one, p = q = 0.01; L = 32, M = 5, T = 50,
+    FP32): LSD-0 against LSD order 10 on the same seeded shots."""
+    from synth.dem import phenomenological_dem
+    from synth.sample import permutations, sample
+
+    dem = phenomenological_dem(11, 11, 0.01, 0.01)
+    perms = permutations(dem.n, 32, seed + 5)
+    b = sample(dem, shots, seed + 6)
+    synd = torch.from_numpy(b.syndromes).to("cuda:0")
+    out = {"workload": dem.name, "m": dem.m, "n": dem.n, "shots": shots}
+    corr = {}
+    for order in (0, 10):
+        G = P.Graph.from_dem(dem, perms, L=32, M=5, T_max=50, lsd_order=order)
+        G.decode(synd[:256])
+        torch.cuda.synchronize()
+        P.vibe_profile_enable(G.handle, True)
+        P.vibe_profile_read(G.handle)
+        t1 = time.perf_counter()
+        c, obs, st = G.decode(synd)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        prof = P.vibe_profile_read(G.handle)
+        G.close()
+        st = st.cpu().numpy()
+        corr[order] = c.cpu().numpy()
+        out[f"lsd{order}"] = {"shots_per_s": round(shots / dt, 1),
+                              "lsd_fraction": round(float(((st[:, 0] & 2) != 0).mean()), 5),
+                              "lsd_kernel_ms": round(prof["lsd"][0], 3),
+                              "logical_error_rate": float((obs.cpu().numpy() != b.observables).any(1).mean())}
+        log(f"phenomenological LSD-{order}: {shots / dt:.0f} shots/s, LSD kernel {prof['lsd'][0]:.1f} ms")
+    out["corrections_changed_by_order10"] = int((corr[0] != corr[10]).any(1).sum())
+    return out
 
 
 def grad_leg(P, torch, seed, batch, K):
@@ -242,6 +279,8 @@ def main():
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-phenom", action="store_true", help="skip the phenomenological LSD-0 / LSD-10 leg")
+    ap.add_argument("--phenom-shots", type=int, default=16384)
     ap.add_argument("--grad-batch", type=int, default=4096)
     ap.add_argument("--grad-K", type=int, default=16)
     ap.add_argument("--grad-only", action="store_true", help="run only the gradient leg (for profiling)")
@@ -429,6 +468,8 @@ def main():
         result["serving"] = serving_leg(P, torch, args.seed, args.serving_seconds)
     if not args.no_grad:
         result["grad"] = grad_leg(P, torch, args.seed, args.grad_batch, args.grad_K)
+    if not args.no_phenom:
+        result["phenomenological"] = phenom_leg(P, torch, args.seed, args.phenom_shots)
 
     result["plain"] = None
     result["batched_over_plain"] = None

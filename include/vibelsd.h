@@ -54,7 +54,14 @@ typedef struct vibe_config {
     uint32_t L;         /* ensemble size, 1..64 (Sec. III.D.1 step 1) */
     uint32_t M;         /* correction limit, 1..L (step 2) */
     uint32_t T_max;     /* iteration limit of every member, 1..64 */
-    uint32_t lsd_order; /* 0 = LSD-0 (the only order implemented) */
+    uint32_t lsd_order; /* 0 = LSD-0, the paper's setting (Sec. III.D.1 step
+                           5); 1..64 adds, on every valid cluster, the
+                           combination sweep of ordered statistics decoding
+                           (Sec. III.C names higher orders): no non-pivot
+                           column, each single one, each pair among the first
+                           lsd_order in rank order; the candidate of least
+                           prior weight wins, ties to the earlier.  Larger
+                           values are VIBE_EINVAL. */
     double alpha;       /* min-sum scaling factor applied to every check message */
     double clamp;       /* bound on |messages|, |posteriors| and |lambda|; also
                            the magnitude sent by a check with no other

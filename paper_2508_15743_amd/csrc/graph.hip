@@ -72,7 +72,7 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     if (c.L < 1 || c.L > (uint32_t)kMaxL) return fail(VIBE_EINVAL, "L must be in 1..64");
     if (c.M < 1 || c.M > c.L) return fail(VIBE_EINVAL, "M must be in 1..L");
     if (c.T_max < 1 || c.T_max > (uint32_t)kMaxT) return fail(VIBE_EINVAL, "T_max must be in 1..64");
-    if (c.lsd_order != 0) return fail(VIBE_EUNSUPPORTED, "only LSD order 0 is implemented");
+    if (c.lsd_order > kMaxLsdOrder) return fail(VIBE_EINVAL, "lsd_order must be in 0..64");
     if (!(c.alpha > 0.0) || !(c.alpha <= 1e6)) return fail(VIBE_EINVAL, "alpha must be in (0, 1e6]");
     if (!(c.clamp >= 1.0) || !(c.clamp <= 1e30)) return fail(VIBE_EINVAL, "clamp must be in [1, 1e30]");
     if (c.message_bits != 0 && c.message_bits != 32 && c.message_bits != 64)
@@ -386,6 +386,7 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     d.fp64 = fp64 ? 1 : 0;
     d.flood = c.schedule == 1 ? 1 : 0;
     d.layered = layered ? 1 : 0;
+    d.lsd_order = c.lsd_order;
     d.alpha = c.alpha;
     d.clamp = lim;
     d.ident32 = ident32;

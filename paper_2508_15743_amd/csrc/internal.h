@@ -15,6 +15,7 @@ constexpr int kWave = 64;
 constexpr int kMaxColDeg = 15;
 constexpr int kMaxL = 64;
 constexpr int kMaxT = 64;
+constexpr uint32_t kMaxLsdOrder = 64;  // pairs among the first 64 non-pivot columns: 2016
 constexpr double kQScale = 72057594037927936.0;  // 2^56: fixed point of the LLR average
 
 // Member schedules.  Member i's serial sweep (its permutation of the columns)
@@ -78,6 +79,7 @@ struct DevGraph {
     int fp64;                   // message precision: 0 = FP32, 1 = FP64
     int flood;                  // schedule: 0 = serial-V, 1 = parallel (flooding)
     int layered;                // 1: layered (check-serial) schedule; cperm holds the check orders
+    uint32_t lsd_order;         // 0 = LSD-0; > 0: combination sweep over the first lsd_order non-pivots
     double alpha, clamp;
     uint32_t ident32;           // row state of "no message": clamp, parity 0 (FP32 bits)
     uint64_t ident64;           // the same in FP64 bits

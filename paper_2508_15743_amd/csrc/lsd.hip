@@ -12,6 +12,16 @@
 // ranked and eliminated in rank order; a column is a pivot iff it is
 // independent of the earlier ones, and every basis vector carries its
 // combination of pivot columns, so reducing s yields the solution.
+//
+// Higher orders (lsd_order > 0) add the combination sweep of ordered
+// statistics decoding on every valid cluster.  Its non-pivot columns F, in
+// rank order, give the candidates: none of F, each single column of F, each
+// pair among the first lsd_order columns of F (lexicographic).  Setting the
+// columns J of F moves the pivot solution by the xor of their pivot
+// combinations, which the elimination leaves in the combination words of a
+// non-pivot column.  The candidate of least prior weight (FP64, summed in
+// ascending column index) replaces the cluster's OSD-0 solution; ties keep
+// the earlier candidate.
 #include "internal.h"
 
 namespace vibe {
@@ -43,12 +53,20 @@ struct LsdMem {
     uint64_t* ebits;    // words_n
     uint64_t* xbuf;     // words_m
     uint64_t* cbuf;     // words_m
+    uint64_t* dbuf;     // words_m: a candidate's change of the pivot solution
     // global
     int32_t* cols;      // n
     int32_t* sorted;    // n
     int64_t* ckey;      // n
     uint64_t* pool;     // m x words_m
     uint64_t* basis2;   // m x 2 words_m (vector, combination)
+    // global, lsd_order > 0 only
+    int32_t* npc;       // n: non-pivot columns in rank order
+    int32_t* nproot;    // n: their clusters
+    int32_t* pidx;      // n: pivot index of a column, -1 if none (lane 0 only)
+    int32_t* ck;        // n: one cluster's columns, ascending (lane 0 only)
+    int32_t* fl;        // n: one cluster's non-pivot ordinals, rank order (lane 0 only)
+    uint64_t* reps;     // n x words_m: pivot combination of each non-pivot column
 };
 
 __host__ __device__ inline size_t al8(size_t x) { return (x + 7) & ~(size_t)7; }
@@ -75,6 +93,7 @@ __host__ __device__ inline void lsd_layout(const DevGraph& g, unsigned char* lds
     M.ebits = (uint64_t*)tl(8 * wn);
     M.xbuf = (uint64_t*)tl(8 * wm);
     M.cbuf = (uint64_t*)tl(8 * wm);
+    M.dbuf = (uint64_t*)tl(8 * wm);
     M.chk_cl = (int32_t*)tl(4 * m);
     M.parent = (int32_t*)tl(4 * m);
     M.cstate = (uint32_t*)tl(4 * m);
@@ -90,6 +109,13 @@ __host__ __device__ inline void lsd_layout(const DevGraph& g, unsigned char* lds
     M.basis2 = (uint64_t*)tg(16 * wm * m);
     M.cols = (int32_t*)tg(4 * n);
     M.sorted = (int32_t*)tg(4 * n);
+    const size_t nh = g.lsd_order ? n : 0;
+    M.npc = (int32_t*)tg(4 * nh);
+    M.nproot = (int32_t*)tg(4 * nh);
+    M.pidx = (int32_t*)tg(4 * nh);
+    M.ck = (int32_t*)tg(4 * nh);
+    M.fl = (int32_t*)tg(4 * nh);
+    M.reps = (uint64_t*)tg(8 * wm * nh);
     if (out) *out = M;
     if (lds_bytes) *lds_bytes = lo;
     if (glob_bytes) *glob_bytes = go;
@@ -159,6 +185,106 @@ __device__ void column_vector(const DevGraph& g, uint64_t* x, uint32_t v, int la
             x[c >> 6] |= 1ull << (c & 63);
         }
     __syncthreads();
+}
+
+// dbuf = pivot combination of non-pivot ordinals oa and ob (-1 = none)
+__device__ void candidate_delta(const LsdMem& S, int32_t oa, int32_t ob, uint32_t wm, int lane) {
+    for (uint32_t w = lane; w < wm; w += kWave) {
+        uint64_t d = 0;
+        if (oa >= 0) d ^= S.reps[(size_t)oa * wm + w];
+        if (ob >= 0) d ^= S.reps[(size_t)ob * wm + w];
+        S.dbuf[w] = d;
+    }
+    __syncthreads();
+}
+
+// Is column v set in the cluster's solution for the candidate whose pivot
+// change is in dbuf and whose non-pivot columns are va, vb?  (lane 0)
+__device__ inline bool cand_bit(const LsdMem& S, int32_t v, int32_t va, int32_t vb) {
+    bool b = (S.ebits[v >> 6] >> (v & 63)) & 1ull;
+    const int32_t k = S.pidx[v];
+    if (k >= 0) b ^= (S.dbuf[k >> 6] >> (k & 63)) & 1ull;
+    return b ^ (v == va) ^ (v == vb);
+}
+
+// The combination sweep on every valid cluster that has non-pivot columns.
+// ebits holds the OSD-0 solution on entry and the chosen one on return.
+__device__ void combination_sweep(const DevGraph& g, const LsdMem& S, int nk, int ncol, int nnp, uint32_t wm,
+                                  int lane) {
+    for (int K = 0; K < nk; K++) {
+        if (uni(S.parent[K]) != K || !(uni(S.cstate[K]) & kValid)) continue;
+        int nf = 0, nck = 0;
+        if (lane == 0) {
+            for (int f = 0; f < nnp; f++)
+                if (S.nproot[f] == K) S.fl[nf++] = f;
+            if (nf)
+                for (int i = 0; i < ncol; i++) {
+                    const int32_t v = S.cols[i];
+                    if (find_root(S.parent, S.chk_cl[g.ci[g.cp[v]]]) == K) S.ck[nck++] = v;
+                }
+        }
+        nf = uni(__shfl(nf, 0));
+        nck = uni(__shfl(nck, 0));
+        __syncthreads();
+        if (!nf) continue;
+        const int lo = min(nf, (int)g.lsd_order);
+        const int ncand = 1 + nf + lo * (lo - 1) / 2;
+        double bw = 0.0;
+        int bt = 0;
+        int pa = 0, pb = 1;  // the next pair among the first lo columns of F
+        int32_t best_oa = -1, best_ob = -1;
+        for (int t = 0; t < ncand; t++) {
+            int fa = -1, fb = -1;  // positions in F
+            if (t >= 1 && t <= nf) {
+                fa = t - 1;
+            } else if (t > nf) {
+                fa = pa;
+                fb = pb;
+                if (++pb == lo) {
+                    pa++;
+                    pb = pa + 1;
+                }
+            }
+            int32_t oa = -1, ob = -1;
+            if (lane == 0) {
+                oa = fa >= 0 ? S.fl[fa] : -1;
+                ob = fb >= 0 ? S.fl[fb] : -1;
+            }
+            oa = uni(__shfl(oa, 0));
+            ob = uni(__shfl(ob, 0));
+            candidate_delta(S, oa, ob, wm, lane);
+            if (lane == 0) {
+                const int32_t va = oa >= 0 ? S.npc[oa] : -1, vb = ob >= 0 ? S.npc[ob] : -1;
+                double w = 0.0;
+                for (int i = 0; i < nck; i++) {
+                    const int32_t v = S.ck[i];
+                    if (cand_bit(S, v, va, vb)) w += g.lam64[v];
+                }
+                if (t == 0 || w < bw) {
+                    bw = w;
+                    bt = t;
+                    best_oa = oa;
+                    best_ob = ob;
+                }
+            }
+            __syncthreads();
+        }
+        bt = uni(__shfl(bt, 0));
+        best_oa = uni(__shfl(best_oa, 0));
+        best_ob = uni(__shfl(best_ob, 0));
+        if (bt == 0) continue;
+        candidate_delta(S, best_oa, best_ob, wm, lane);
+        if (lane == 0) {
+            const int32_t va = best_oa >= 0 ? S.npc[best_oa] : -1, vb = best_ob >= 0 ? S.npc[best_ob] : -1;
+            for (int i = 0; i < nck; i++) {
+                const int32_t v = S.ck[i];
+                const bool b = cand_bit(S, v, va, vb);
+                const uint64_t bit = 1ull << (v & 63);
+                S.ebits[v >> 6] = b ? (S.ebits[v >> 6] | bit) : (S.ebits[v >> 6] & ~bit);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
@@ -333,7 +459,10 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                     const uint32_t v = w * 64 + b;
                     const int32_t R = find_root(S.parent, S.chk_cl[g.ci[g.cp[v]]]);
                     S.ccount[R]++;
-                    if (S.cstate[R] & kValid) S.cols[ncol++] = (int32_t)v;
+                    if (S.cstate[R] & kValid) {
+                        S.cols[ncol++] = (int32_t)v;
+                        if (g.lsd_order) S.pidx[v] = -1;
+                    }
                 }
             }
         }
@@ -350,7 +479,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
             S.sorted[r] = vi;
         }
         __syncthreads();
-        int nb = 0;
+        int nb = 0, nnp = 0;
         for (int i = 0; i < ncol; i++) {
             const uint32_t v = (uint32_t)uni(ald32(&S.sorted[i]));
             column_vector(g, S.xbuf, v, lane);
@@ -368,8 +497,17 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                 if (lane == 0) {
                     S.piv2[nb] = p;
                     S.pivcol[nb] = (int32_t)v;
+                    if (g.lsd_order) S.pidx[v] = nb;
                 }
                 nb++;
+            } else if (g.lsd_order) {
+                // a non-pivot column: cbuf holds its combination of pivots
+                for (uint32_t w = lane; w < wm; w += kWave) S.reps[(size_t)nnp * wm + w] = S.cbuf[w];
+                if (lane == 0) {
+                    S.npc[nnp] = (int32_t)v;
+                    S.nproot[nnp] = find_root(S.parent, S.chk_cl[g.ci[g.cp[v]]]);
+                }
+                nnp++;
             }
             __syncthreads();
         }
@@ -394,6 +532,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                     S.ebits[v >> 6] |= 1ull << (v & 63);
                 }
         __syncthreads();
+        if (g.lsd_order && nnp) combination_sweep(g, S, nk, ncol, nnp, wm, lane);
         uint64_t* out = a.corrections + gshot * g.words_n;
         for (uint32_t w = lane; w < g.words_n; w += kWave) out[w] = S.ebits[w];
         int nclus = 0, largest = 0;

@@ -133,10 +133,10 @@ def test_bp_parallel_schedule_fp32(torch_cuda):
     _bp_parity(torch_cuda, phenomenological_dem(11, 11, 0.01, 0.01), 1, 20, 6, 17, stop=True, schedule="parallel")
 
 
-def _lsd_parity(torch, dem, shots, seed, noise=2.0):
+def _lsd_parity(torch, dem, shots, seed, noise=2.0, order=0):
     import paper_2508_15743_amd as P
 
-    G, _ = _graph(dem, 2, 1, 5, seed)
+    G, _ = _graph(dem, 2, 1, 5, seed, lsd_order=order)
     b = sample(dem, shots, seed)
     lam = np.log((1 - dem.priors) / dem.priors)
     e = b.errors_dense(dem.n)
@@ -146,12 +146,16 @@ def _lsd_parity(torch, dem, shots, seed, noise=2.0):
     corr, st = G.lsd(_dev(torch, b.syndromes), _dev(torch, soft))
     got, st = P.unpack_bits(corr, dem.n), st.cpu().numpy()
     g = O.OracleGraph(dem)
+    moved = 0
     for i in range(shots):
-        r = O.lsd(g, b.syndromes[i], soft[i].astype(np.float64))
+        r = O.lsd(g, b.syndromes[i], soft[i].astype(np.float64), order=order)
         assert np.array_equal(r["ehat"], got[i]), i
         assert (r["clusters"], r["largest"], r["rounds"]) == tuple(st[i, 4:7]), i
         assert bool(st[i, 0] & 4) == r["failed"], i
+        if order:
+            moved += not np.array_equal(O.lsd(g, b.syndromes[i], soft[i].astype(np.float64))["ehat"], got[i])
     G.close()
+    return moved
 
 
 def test_lsd_bit_exact_code_capacity(torch_cuda):
@@ -164,6 +168,23 @@ def test_lsd_bit_exact_phenomenological(torch_cuda):
 
 def test_lsd_bit_exact_circuit_full_size(torch_cuda):
     _lsd_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 40, 7)
+
+
+def test_lsd_order10_bit_exact(torch_cuda):
+    """Higher-order LSD (order 10, the phenomenological workload's setting)
+    on identical soft input: bit-exact corrections and cluster stats on all
+    three workloads.  Soft values with noise of scale 8 grow clusters with
+    several non-pivot columns, so the sweep changes most corrections
+    relative to LSD-0 (counted, and required to happen)."""
+    moved = _lsd_parity(torch_cuda, code_capacity_dem(5, 0.08), 400, 5, noise=8.0, order=10)
+    assert moved >= 5, moved
+    moved = _lsd_parity(torch_cuda, phenomenological_dem(11, 11, 0.01, 0.01), 120, 6, noise=8.0, order=10)
+    assert moved >= 60, moved
+    moved = _lsd_parity(torch_cuda, circuit_dem(9, 9, 1e-3), 40, 7, noise=8.0, order=10)
+    assert moved >= 20, moved
+    # order 1 (singles only) and 2 (one pair) on the phenomenological graph
+    for order in (1, 2):
+        _lsd_parity(torch_cuda, phenomenological_dem(11, 11, 0.01, 0.01), 60, 9, noise=8.0, order=order)
 
 
 def test_lsd_edge_cases(torch_cuda):
@@ -186,11 +207,11 @@ def test_lsd_edge_cases(torch_cuda):
     G.close()
 
 
-def _oracle_decode(dem, perms, synd, L, M, T, priors=None, schedule="serial"):
+def _oracle_decode(dem, perms, synd, L, M, T, priors=None, schedule="serial", lsd_order=0):
     g = O.OracleGraph(dem)
     if priors is not None:
         g.priors = priors
-    return O.decode(g, perms, synd, L=L, M=M, T=T, threads=NT, schedule=schedule)
+    return O.decode(g, perms, synd, L=L, M=M, T=T, threads=NT, schedule=schedule, lsd_order=lsd_order)
 
 
 def _tie_witness(ref, e, st, dem, L):
@@ -215,10 +236,10 @@ def _tie_witness(ref, e, st, dem, L):
             f"{ref['min_q_gap'][rest].max() if rest.any() else 0.0:.3g} < {dq:.3g}")
 
 
-def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots, bits=32, schedule="serial"):
+def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots, bits=32, schedule="serial", lsd_order=0):
     import paper_2508_15743_amd as P
 
-    G, perms = _graph(dem, L, M, T, seed, message_bits=bits, schedule=schedule)
+    G, perms = _graph(dem, L, M, T, seed, message_bits=bits, schedule=schedule, lsd_order=lsd_order)
     b = sample(dem, shots, seed + 7)
     corr, obs, st = G.decode(_dev(torch, b.syndromes))
     e, obs, st = P.unpack_bits(corr, dem.n), obs.cpu().numpy(), st.cpu().numpy()
@@ -226,7 +247,7 @@ def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots, bits=32, sche
     ok = (st[:, 0] & 4) == 0
     assert np.array_equal((e[ok].astype(np.int64) @ H.T) % 2, b.syndromes[ok])
     assert np.array_equal(obs, (e.astype(np.int64) @ dem.dense_l().T.astype(np.int64) % 2).astype(np.uint8))
-    ref = _oracle_decode(dem, perms, b.syndromes[:oracle_shots], L, M, T, schedule=schedule)
+    ref = _oracle_decode(dem, perms, b.syndromes[:oracle_shots], L, M, T, schedule=schedule, lsd_order=lsd_order)
     agree = (ref["ehat"] == e[:oracle_shots]).all(1)
     n = oracle_shots
     if bits == 64:
@@ -235,7 +256,8 @@ def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots, bits=32, sche
     else:
         rng = np.random.default_rng(seed)
         moved = dem.priors * (1.0 + 1e-6 * rng.uniform(-1.0, 1.0, dem.n))
-        ref2 = _oracle_decode(dem, perms, b.syndromes[:oracle_shots], L, M, T, priors=moved, schedule=schedule)
+        ref2 = _oracle_decode(dem, perms, b.syndromes[:oracle_shots], L, M, T, priors=moved, schedule=schedule,
+                              lsd_order=lsd_order)
         self_agree = (ref2["ehat"] == ref["ehat"]).all(1).mean()
         margin = 3.0 * np.sqrt(max(self_agree * (1.0 - self_agree), 1.0 / n) / n)
         assert agree.mean() >= self_agree - margin, (agree.mean(), self_agree, margin)
@@ -248,10 +270,18 @@ def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots, bits=32, sche
     hi = beta.ppf(0.975, k + 1, n - k) if k < n else 1.0
     ler = (obs != b.observables).any(1).mean()
     assert lo <= ler <= hi, (ler, lo, hi)
-    print(f"{dem.name} {schedule} FP{bits}: agreement {agree.mean():.5f} over {n} shots (bar {bar}); "
+    print(f"{dem.name} {schedule} FP{bits} LSD-{lsd_order}: agreement {agree.mean():.5f} over {n} shots (bar {bar}); "
           f"LER {ler:.5f} in [{lo:.5f}, {hi:.5f}]")
     G.close()
     return agree.mean()
+
+
+def test_decode_phenomenological_lsd10(torch_cuda):
+    """The phenomenological workload as configured: 32 members, T = 50, FP32
+    messages and LSD order 10; and the same in FP64 to the FP64 bar."""
+    dem = phenomenological_dem(11, 11, 0.01, 0.01)
+    _decode_parity(torch_cuda, dem, 32, 5, 50, 6000, 4, 600, lsd_order=10)
+    _decode_parity(torch_cuda, dem, 32, 5, 50, 3000, 4, 600, bits=64, lsd_order=10)
 
 
 def test_decode_code_capacity(torch_cuda):
@@ -350,6 +380,9 @@ def test_invalid_arguments_rejected(torch_cuda):
         P.Graph.from_dem(dem, perms, L=4, M=5, T_max=5)
     with pytest.raises(P.VibeError):
         P.Graph.from_dem(dem, perms, L=4, M=2, T_max=5, message_bits=48)
+    with pytest.raises(P.VibeError) as ei:
+        P.Graph.from_dem(dem, perms, L=4, M=2, T_max=5, lsd_order=65)
+    assert ei.value.code == P.VIBE_EINVAL
 
 
 def test_plain_equals_batched(torch_cuda):
