@@ -57,7 +57,8 @@ typedef struct vibe_config {
     uint32_t lsd_order; /* 0 = LSD-0, the paper's setting (Sec. III.D.1 step
                            5); 1..64 adds, on every valid cluster, the
                            combination sweep of ordered statistics decoding
-                           (Sec. III.C names higher orders): no non-pivot
+                           (the higher-order search that LSD-0 leaves out,
+                           Sec. III.D.1 step 5): no non-pivot
                            column, each single one, each pair among the first
                            lsd_order in rank order; the candidate of least
                            prior weight wins, ties to the earlier.  Larger

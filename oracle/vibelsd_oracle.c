@@ -432,8 +432,9 @@ static double soft_val(const osoft *S, int v) {
    lexicographic order.  Every candidate's pivot values are solved afresh
    from s plus the chosen columns.  The candidate of least prior weight
    W(e) = sum_v e_v lam_v (summed in ascending v) replaces x; ties keep the
-   earlier candidate.  The paper runs LSD-0 only and names higher orders as
-   an option of the method it builds on (Sec. III.C). */
+   earlier candidate.  The paper runs LSD-0, the variant without the
+   higher-order search around the first solution (Sec. III.D.1 step 5); the
+   sweep is the one of the OSD post-processor it cites (Sec. III.C). */
 static void osd_cs(const ograph *g, const uint8_t *bit, const int *ord, int rows, int cols,
                    const uint8_t *A0, const uint8_t *b0, const uint8_t *piv, int order, const double *lam,
                    uint8_t *x) {

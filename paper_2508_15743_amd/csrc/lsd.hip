@@ -13,7 +13,8 @@
 // independent of the earlier ones, and every basis vector carries its
 // combination of pivot columns, so reducing s yields the solution.
 //
-// Higher orders (lsd_order > 0) add the combination sweep of ordered
+// Higher orders (lsd_order > 0) add the higher-order search that LSD-0
+// leaves out (Sec. III.D.1 step 5), read as the combination sweep of ordered
 // statistics decoding on every valid cluster.  Its non-pivot columns F, in
 // rank order, give the candidates: none of F, each single column of F, each
 // pair among the first lsd_order columns of F (lexicographic).  Setting the

@@ -1,8 +1,9 @@
 """Pins of the oracle's higher-order LSD (the combination sweep over each
 cluster's non-pivot columns, weighted by the prior LLRs).
 
-The paper runs LSD-0 only (Sec. III.D.1 step 5) and mentions higher orders
-as an option of the LSD method it builds on (Sec. III.C); the workload list
+The paper runs LSD-0, the variant that leaves out the higher-order search
+around the first solution (Sec. III.D.1 step 5), and cites OSD, whose
+combination sweep that search is (Sec. III.C); the workload list
 asks for order 10 on the phenomenological workload.  The sweep is the
 ordered-statistics combination sweep: no non-pivot column, each single
 non-pivot column, each pair among the first `order` of them (rank order);
