@@ -151,6 +151,12 @@ void vibe_graph_destroy(vibe_graph* g);
 /* Sizes and footprint of a graph. */
 int vibe_graph_info(const vibe_graph* g, vibe_graph_info_t* info);
 
+/* Copies the member schedules the graph holds into perms (host, L x n
+   uint32 column permutations, or L x m check orders for the layered
+   schedule), so that a reference decoder can run the same members
+   (Sec. III.D.1 step 1 draws them offline). */
+int vibe_graph_get_schedules(const vibe_graph* g, uint32_t* perms);
+
 /*
  * Online stage, batched (Sec. III.D.2): decode B syndromes in one launch
  * sequence on `stream`.
@@ -164,6 +170,20 @@ int vibe_graph_info(const vibe_graph* g, vibe_graph_info_t* info);
  */
 int vibe_decode(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint64_t* corrections,
                 uint8_t* observables, vibe_shot_stats* stats, void* stream);
+
+/*
+ * vibe_decode with bit-packed syndromes (the a1 ingest variant).
+ *   syndromes    device, B x ceil(m/64) uint64 words, row-major: check c of a
+ *                shot is bit (c mod 64) of its word c / 64; bits past m in the
+ *                last word are ignored
+ * Outputs, results and errors are those of vibe_decode on the same
+ * syndromes.  The words are expanded, one chunk of shots at a time, into a
+ * buffer the handle keeps (one byte per check, grown on demand and freed by
+ * vibe_graph_destroy); like vibe_decode's workspace it is shared by the
+ * handle's calls, so calls on one handle must not overlap.
+ */
+int vibe_decode_packed(vibe_graph* g, const uint64_t* syndromes, uint64_t B, uint64_t* corrections,
+                       uint8_t* observables, vibe_shot_stats* stats, void* stream);
 
 /*
  * The same decoder with one launch sequence per shot: every shot is decoded
@@ -192,7 +212,8 @@ int vibe_bp_ensemble(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint32
                      void* stream);
 
 /*
- * LSD-0 alone (Sec. III.C) on caller-given soft information.
+ * LSD alone (Sec. III.C), at the graph's lsd_order, on caller-given soft
+ * information.
  *   soft         device, B x n float: lower = more likely flipped; columns are
  *                ranked by (soft, index) ascending
  *   corrections  device, B x ceil(n/64) uint64 (bit-packed e-hat)

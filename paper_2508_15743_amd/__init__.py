@@ -63,6 +63,9 @@ EXPORTS = {
     "vibe_graph_info": (C.c_int, [C.c_void_p, C.POINTER(vibe_graph_info_t)]),
     "vibe_decode": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_void_p]),
+    "vibe_decode_packed": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
+    "vibe_graph_get_schedules": (C.c_int, [C.c_void_p, C.c_void_p]),
     "vibe_decode_plain": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p]),
     "vibe_bp_ensemble": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_int,
@@ -157,6 +160,17 @@ def vibe_graph_info(handle) -> dict:
 def vibe_decode(handle, syndromes, B, corrections, observables, stats, stream):
     _check(lib().vibe_decode(handle, _ptr(syndromes), B, _ptr(corrections), _ptr(observables),
                              _ptr(stats), stream))
+
+
+def vibe_decode_packed(handle, words, B, corrections, observables, stats, stream):
+    _check(lib().vibe_decode_packed(handle, _ptr(words), B, _ptr(corrections), _ptr(observables),
+                                    _ptr(stats), stream))
+
+
+def vibe_graph_get_schedules(handle, L, length) -> np.ndarray:
+    out = np.zeros((L, length), dtype=np.uint32)
+    _check(lib().vibe_graph_get_schedules(handle, out.ctypes.data))
+    return out
 
 
 def vibe_decode_plain(handle, syndromes, B, corrections, observables, stats, stream):
@@ -317,6 +331,25 @@ class Graph:
         fn = vibe_decode_plain if plain else vibe_decode
         fn(self.handle, s, B, corr, obs, st, _stream(stream))
         return corr, obs, st
+
+    def decode_packed(self, words, with_stats=True, stream=None):
+        """Bit-packed syndromes int64 [B, ceil(m/64)] (check c in bit c % 64 of
+        word c // 64) -> the results of decode()"""
+        import torch
+        wm = (self.m + 63) // 64
+        if words.dtype != torch.int64 or words.dim() != 2 or words.shape[1] != wm or not words.is_cuda:
+            raise ValueError(f"words must be an int64 device tensor [B, {wm}]")
+        w = words.contiguous()
+        B = w.shape[0]
+        corr = torch.empty((B, self.words), dtype=torch.int64, device=w.device)
+        obs = torch.empty((B, max(self.k, 1)), dtype=torch.uint8, device=w.device)
+        st = torch.empty((B, 8), dtype=torch.int32, device=w.device) if with_stats else None
+        vibe_decode_packed(self.handle, w, B, corr, obs, st, _stream(stream))
+        return corr, obs, st
+
+    def schedules(self) -> np.ndarray:
+        """The member schedules the graph holds: [L, n] (or [L, m] layered)."""
+        return vibe_graph_get_schedules(self.handle, self.L, self.m if self.schedule == "layered" else self.n)
 
     def bp_ensemble(self, syndromes, T_run=None, stop=True, posteriors=True, ehat=True, stream=None):
         """-> (t_conv int32 [B, L], posteriors [B, L, n] (float32, or float64 when

@@ -370,6 +370,7 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     h.chunks_min = ch_min;
     h.chunks_max = ch_max;
     h.device_bytes = 0;
+    h.perms.assign(perms, perms + (size_t)c.L * (layered ? m : n));
     DevGraph& d = h.dg;
     d.m = m;
     d.n = n;
@@ -446,7 +447,14 @@ extern "C" void vibe_graph_destroy(vibe_graph* g) {
         }
     free_all(g->h);
     if (g->ws.base) (void)hipFree(g->ws.base);
+    if (g->ws_in.base) (void)hipFree(g->ws_in.base);
     delete g;
+}
+
+extern "C" int vibe_graph_get_schedules(const vibe_graph* g, uint32_t* perms) {
+    if (!g || !perms) return fail(VIBE_EINVAL, "NULL argument");
+    std::memcpy(perms, g->h.perms.data(), 4 * g->h.perms.size());
+    return VIBE_OK;
 }
 
 extern "C" int vibe_graph_info(const vibe_graph* g, vibe_graph_info_t* info) {

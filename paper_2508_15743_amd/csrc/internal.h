@@ -107,6 +107,7 @@ struct GraphHost {
     uint64_t device_bytes;
     DevGraph dg;
     std::vector<void*> allocations;
+    std::vector<uint32_t> perms;  // the member schedules as given (L x n, or L x m layered)
 };
 
 // Per-handle workspace, grown on demand and reused across calls.
@@ -120,6 +121,7 @@ struct Workspace {
 struct vibe_graph {
     vibe::GraphHost h;
     vibe::Workspace ws;
+    vibe::Workspace ws_in;  // unpacked syndromes of vibe_decode_packed
     int device = 0;
     // launch settings chosen by vibe_autotune: slab in LDS (-1 = not tuned,
     // use LDS whenever it fits; 0 = global; 1 = LDS) and BP grid (0 = full

@@ -385,6 +385,46 @@ def test_invalid_arguments_rejected(torch_cuda):
     assert ei.value.code == P.VIBE_EINVAL
 
 
+def _pack_rows(bits, junk_seed=None):
+    """uint8 [B, m] -> int64 [B, ceil(m/64)] words, bit c % 64 of word c // 64;
+    with junk_seed, random bits fill the unused tail of the last word."""
+    B, m = bits.shape
+    wm = (m + 63) // 64
+    padded = np.zeros((B, 64 * wm), np.uint8)
+    padded[:, :m] = bits
+    if junk_seed is not None and m % 64:
+        padded[:, m:] = np.random.default_rng(junk_seed).integers(0, 2, (B, 64 * wm - m))
+    return np.packbits(padded, axis=1, bitorder="little").view(np.int64)
+
+
+def test_decode_packed_equals_decode(torch_cuda):
+    """Bit-packed syndrome ingest gives the byte-per-check results: on the
+    code-capacity graph (m = 9, one partial word) and the phenomenological
+    graph (m = 540, eight full words and a partial one), with the unused
+    bits of the last word set at random; B = 0 does nothing.  The graph
+    also hands back the schedules it was created with."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    for dem, L, T, shots, seed in ((code_capacity_dem(5, 0.05), 16, 32, 3000, 41),
+                                   (phenomenological_dem(11, 11, 0.01, 0.01), 32, 50, 2000, 42)):
+        G, perms = _graph(dem, L, 5, T, seed)
+        assert np.array_equal(G.schedules(), perms)
+        b = sample(dem, shots, seed)
+        c1, o1, s1 = G.decode(_dev(torch, b.syndromes))
+        c2, o2, s2 = G.decode_packed(_dev(torch, _pack_rows(b.syndromes, junk_seed=seed)))
+        assert torch.equal(c1, c2) and torch.equal(o1, o2)
+        keep = [0, 1, 2, 4, 5, 6]  # every stats field but the timing-dependent n_conv and member_iters
+        assert torch.equal(s1[:, keep], s2[:, keep])
+        z = G.decode_packed(_dev(torch, np.zeros((0, (dem.m + 63) // 64), np.int64)))
+        assert z[0].shape[0] == 0
+        G.close()
+    cperms = _perms_checks(code_capacity_dem(5, 0.05), 4, 3)
+    Gl = P.Graph.from_dem(code_capacity_dem(5, 0.05), cperms, L=4, M=2, T_max=8, schedule="layered")
+    assert np.array_equal(Gl.schedules(), cperms)
+    Gl.close()
+
+
 def test_plain_equals_batched(torch_cuda):
     """One launch sequence per shot gives the batched results, including on
     shots that go to LSD alone on the device (a lone LSD block)."""
