@@ -526,11 +526,25 @@ def main():
                      threads=threads)
             done += chunk
         dt = time.perf_counter() - t1
+        # one thread on the next shots, for the per-core rate
+        one, t2 = 0, time.perf_counter()
+        while time.perf_counter() - t2 < args.cpu_seconds / 3 and done + one < B:
+            O.decode(g, perms, batch.syndromes[done + one:done + one + 1], L=L, M=M, T=T, alpha=alpha, threads=1)
+            one += 1
+        dt1 = time.perf_counter() - t2
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
         result["cpu_baseline"] = {"value": round(done / dt, 3), "unit": "shots/s", "cores": threads,
                                   "kind": "oracle",
                                   "sample": f"first {done} shots of the batch, {dt:.1f}s, "
-                                            f"{threads} threads, FP64 oracle"}
-        log(f"cpu oracle: {done / dt:.2f} shots/s on {threads} threads")
+                                            f"{threads} threads, FP64 oracle",
+                                  "single_thread_value": round(one / dt1, 4) if one else None,
+                                  "nproc": os.cpu_count(), "cpu_model": model}
+        log(f"cpu oracle: {done / dt:.2f} shots/s on {threads} threads, {one / dt1:.3f} on one")
 
     print(json.dumps(result), flush=True)
     G.close()
