@@ -10,7 +10,7 @@ circuits and data.
 One step = vibe_decode over one batch of B shots (all of BP ensemble,
 selection, LSD and observables), syndromes already resident in HBM.
 Prints one JSON line.  Extra legs: serving (continuous batching of one-shot
-requests from circuit-level codes d = 9, 13, 5 mixed 50/30/20, Poisson
+requests from circuit-level codes d = 9, 13, 17 mixed 50/30/20 at p = 5e-4 and 1e-3, Poisson
 arrivals at 0.5x and 0.8x the sustained rate, p50/p99 latency); a ragged
 batch of circuit-level codes at d = 5..13 (rounds = d) decoded as one call
 against one call per code;
@@ -193,23 +193,26 @@ def grad_leg(P, torch, seed, batch, K):
 
 def serving_leg(P, torch, seed, seconds):
     """One-shot requests (one window of d rounds each) from circuit-level codes
-    d = 9, 13, 5 at p = 1e-3, mixed 50/30/20, through the continuous-batching
-    server: the sustained rate of a burst, then Poisson arrivals at 0.5x and
-    0.8x that rate with p50/p99 latency from submission to completion."""
+    d = 9, 13, 17 mixed 50/30/20, each at p = 5e-4 or 1e-3 with equal odds
+    (six resident graphs; L/M/T = 32/5/20 at d = 9, 64/7/25 above), through
+    the continuous-batching server: the sustained rate of a burst, then
+    Poisson arrivals at 0.5x and 0.8x that rate with p50/p99 latency from
+    submission to completion."""
     import threading
 
     from synth.dem import circuit_dem
     from synth.sample import permutations, sample
 
-    cfgs = [(9, 32, 5, 20, 0.5), (13, 64, 7, 25, 0.3), (5, 32, 5, 20, 0.2)]
+    cfgs = [(d, p, L, M, T, w / 2) for d, L, M, T, w in ((9, 32, 5, 20, 0.5), (13, 64, 7, 25, 0.3),
+                                                         (17, 64, 7, 25, 0.2)) for p in (5e-4, 1e-3)]
     rng = np.random.default_rng(seed)
     graphs, pools = [], []
-    for d, L, M, T, _ in cfgs:
-        dem = circuit_dem(d, d, 1e-3)
+    for d, p, L, M, T, _ in cfgs:
+        dem = circuit_dem(d, d, p)
         graphs.append(P.Graph.from_dem(dem, permutations(dem.n, L, seed + d), L=L, M=M, T_max=T, alpha=0.625))
-        pools.append(torch.from_numpy(sample(dem, 4096, seed + 300 + d).syndromes).to("cuda:0"))
+        pools.append(torch.from_numpy(sample(dem, 4096, seed + 300 + d + int(p * 1e4)).syndromes).to("cuda:0"))
     torch.cuda.synchronize()
-    weights = np.array([c[4] for c in cfgs])
+    weights = np.array([c[5] for c in cfgs])
     srv = P.Server(graphs, slots=3, max_batch_requests=512, max_batch_shots=1024)
 
     def run(n, rate):
@@ -239,7 +242,7 @@ def serving_leg(P, torch, seed, seconds):
 
     run(256, 0)  # warm-up
     sustained, lat_burst = run(3000, 0)
-    res = {"codes": [f"circuit_d{d}_r{d}_p0.001" for d, *_ in cfgs], "mix": [c[4] for c in cfgs],
+    res = {"codes": [f"circuit_d{d}_r{d}_p{p:g}" for d, p, *_ in cfgs], "mix": [c[5] for c in cfgs],
            "request": "one shot", "slots": 3, "sustained_requests_per_s": round(sustained, 1), "loads": []}
     for rho in (0.5, 0.8):
         rate = rho * sustained

@@ -30,6 +30,7 @@ namespace vibe {
 namespace {
 
 constexpr uint32_t kValid = 1u, kFailed = 2u;
+constexpr size_t kLsdLds = 150 * 1024;  // LDS budget of one LSD wavefront
 
 // Per-shot state.  Everything one lane writes and another reads lives in
 // LDS.  The global part holds the large arrays: the basis vectors, which
@@ -88,8 +89,16 @@ __host__ __device__ inline void lsd_layout(const DevGraph& g, unsigned char* lds
         go += al8(bytes);
         return p;
     };
+    // The arrays only lane 0 touches (best_q, best_v, ccount, picks, added,
+    // pivcol: 32 bytes per check) move to global memory when everything
+    // would not fit in kLsdLds bytes of LDS (graphs with several thousand
+    // checks).  Reads and writes by one lane need no cross-lane visibility.
+    const size_t all_lds = al8(8 * m) + 2 * al8(8 * wn) + 3 * al8(8 * wm) + 5 * al8(4 * m) + al8(8 * m) +
+                           4 * al8(4 * m);
+    const bool priv_glob = all_lds > kLsdLds;
+    auto tp = [&](size_t bytes) { return priv_glob ? tg(bytes) : tl(bytes); };
     LsdMem M;
-    M.best_q = (int64_t*)tl(8 * m);
+    M.best_q = (int64_t*)tp(8 * m);
     M.in_bits = (uint64_t*)tl(8 * wn);
     M.ebits = (uint64_t*)tl(8 * wn);
     M.xbuf = (uint64_t*)tl(8 * wm);
@@ -98,13 +107,13 @@ __host__ __device__ inline void lsd_layout(const DevGraph& g, unsigned char* lds
     M.chk_cl = (int32_t*)tl(4 * m);
     M.parent = (int32_t*)tl(4 * m);
     M.cstate = (uint32_t*)tl(4 * m);
-    M.best_v = (int32_t*)tl(4 * m);
-    M.ccount = (int32_t*)tl(4 * m);
-    M.picks = (int32_t*)tl(8 * m);
-    M.added = (int32_t*)tl(4 * m);
+    M.best_v = (int32_t*)tp(4 * m);
+    M.ccount = (int32_t*)tp(4 * m);
+    M.picks = (int32_t*)tp(8 * m);
+    M.added = (int32_t*)tp(4 * m);
     M.pool_piv = (int32_t*)tl(4 * m);
     M.piv2 = (int32_t*)tl(4 * m);
-    M.pivcol = (int32_t*)tl(4 * m);
+    M.pivcol = (int32_t*)tp(4 * m);
     M.ckey = (int64_t*)tg(8 * n);
     M.pool = (uint64_t*)tg(8 * wm * m);
     M.basis2 = (uint64_t*)tg(16 * wm * m);
@@ -317,7 +326,6 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                     S.chk_cl[c] = slot;
                     S.parent[slot] = slot;
                     S.cstate[slot] = 0;
-                    S.ccount[slot] = 0;
                 } else {
                     S.chk_cl[c] = -1;
                 }
@@ -333,10 +341,11 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
 
         for (;;) {
             // 1. best boundary column of every invalid, growing cluster
-            for (int K = lane; K < nk; K += kWave) {
-                S.best_q[K] = INT64_MAX;
-                S.best_v[K] = -1;
-            }
+            if (lane == 0)
+                for (int K = 0; K < nk; K++) {
+                    S.best_q[K] = INT64_MAX;
+                    S.best_v[K] = -1;
+                }
             __syncthreads();
             for (uint32_t c = 0; c < g.m; c++) {
                 const int32_t cl = uni(S.chk_cl[c]);
@@ -417,7 +426,9 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
             __syncthreads();
             // 4. extend the basis pool with the new columns
             for (int i = 0; i < nadd; i++) {
-                column_vector(g, S.xbuf, (uint32_t)uni(S.added[i]), lane);
+                int32_t col = 0;
+                if (lane == 0) col = S.added[i];
+                column_vector(g, S.xbuf, (uint32_t)uni(__shfl(col, 0)), lane);
                 reduce_by(S.xbuf, nullptr, S.pool, wm, S.pool_piv, pool_n, wm, lane);
                 const int p = lowest_bit(S.xbuf, wm, lane);
                 if (p >= 0) {
@@ -452,6 +463,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
         int ncol = 0;
         bool failed = false;
         if (lane == 0) {
+            for (int K = 0; K < nk; K++) S.ccount[K] = 0;
             for (uint32_t w = 0; w < g.words_n; w++) {
                 uint64_t x = S.in_bits[w];
                 while (x) {

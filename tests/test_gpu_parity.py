@@ -187,6 +187,45 @@ def test_lsd_order10_bit_exact(torch_cuda):
         _lsd_parity(torch_cuda, phenomenological_dem(11, 11, 0.01, 0.01), 60, 9, noise=8.0, order=order)
 
 
+def test_largest_serving_graph_d17(torch_cuda):
+    """The circuit-level d = 17 graph of the serving mix (17 rounds, m = 3672,
+    n = 130426, 582135 edges): its LSD state no longer fits the LDS budget
+    whole, so the per-cluster arrays only lane 0 touches live in global
+    memory.  FP64 BP members bit-identical to the oracle (two members, two
+    iterations); LSD bit-exact on identical soft input at orders 0 and 10
+    (soft values with noise of scale 2: noisier ones grow clusters of
+    thousands of columns, which the dense oracle takes minutes to solve);
+    a full FP32 decode (L = 64, M = 7, T = 25) satisfies H e = s on every
+    shot LSD did not flag and gives the same rows in a smaller batch."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    dem = circuit_dem(17, 17, 1e-3)
+    print(f"d17: m={dem.m} n={dem.n} nnz={dem.nnz}", flush=True)
+    _bp_parity(torch, dem, 2, 2, 1, 61, stop=False, bits=64)
+    print("d17: BP members bit-exact", flush=True)
+    _lsd_parity(torch, dem, 6, 62, noise=2.0)
+    _lsd_parity(torch, dem, 4, 63, noise=2.0, order=10)
+    print("d17: LSD bit-exact at orders 0 and 10", flush=True)
+    G, _ = _graph(dem, 64, 7, 25, 64)
+    print("d17: L = 64 graph created", flush=True)
+    b = sample(dem, 256, 65)
+    s = _dev(torch, b.syndromes)
+    corr, obs, st = G.decode(s)
+    e, st = P.unpack_bits(corr, dem.n), st.cpu().numpy()
+    ok = (st[:, 0] & 4) == 0
+    assert ok.mean() > 0.9
+    rows = np.repeat(np.arange(dem.m), np.diff(dem.h_indptr))
+    for i in np.flatnonzero(ok):
+        syn = np.zeros(dem.m, np.int64)
+        np.add.at(syn, rows, e[i][dem.h_indices].astype(np.int64))
+        assert np.array_equal(syn % 2, b.syndromes[i]), i
+    c2, o2, s2 = G.decode(s[64:128])
+    assert torch.equal(c2, corr[64:128]) and torch.equal(o2, obs[64:128])
+    print(f"d17: decoded 256 shots, {int(((st[:, 0] & 2) != 0).sum())} through LSD", flush=True)
+    G.close()
+
+
 def test_lsd_edge_cases(torch_cuda):
     """Zero syndrome: nothing to do.  A flipped check with no columns: the
     cluster cannot grow, LSD reports failure and leaves it unexplained."""
