@@ -29,7 +29,9 @@ namespace vibe {
 
 namespace {
 
-constexpr uint32_t kValid = 1u, kFailed = 2u;
+// cluster state bits; kDirty: the cluster took a column or merged this round,
+// so its validity must be computed again (an unchanged cluster keeps it)
+constexpr uint32_t kValid = 1u, kFailed = 2u, kDirty = 4u;
 constexpr size_t kLsdLds = 150 * 1024;  // LDS budget of one LSD wavefront
 
 // Per-shot state.  Everything one lane writes and another reads lives in
@@ -416,10 +418,11 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                             if (ra != rb) {
                                 const int32_t lo = min(ra, rb), hi = max(ra, rb);
                                 S.parent[hi] = lo;
-                                S.cstate[lo] |= S.cstate[hi] & kFailed;
+                                S.cstate[lo] |= (S.cstate[hi] & kFailed) | kDirty;
                             }
                         }
                     }
+                    S.cstate[find_root(S.parent, K)] |= kDirty;
                 }
             }
             nadd = uni(__shfl(nadd, 0));
@@ -438,9 +441,9 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                 }
                 __syncthreads();
             }
-            // 5. validity of every live cluster that has not failed
+            // 5. validity of every live cluster that changed and has not failed
             for (int K = 0; K < nk; K++) {
-                if (uni(S.parent[K]) != K || (uni(S.cstate[K]) & kFailed)) continue;
+                if (uni(S.parent[K]) != K || (uni(S.cstate[K]) & (kFailed | kDirty)) != kDirty) continue;
                 for (uint32_t base = 0; base < g.m; base += kWave) {
                     const uint32_t c = base + lane;
                     bool in = false;
@@ -454,7 +457,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                 __syncthreads();
                 reduce_by(S.xbuf, nullptr, S.pool, wm, S.pool_piv, pool_n, wm, lane);
                 const bool valid = lowest_bit(S.xbuf, wm, lane) < 0;
-                if (lane == 0) S.cstate[K] = valid ? (S.cstate[K] | kValid) : (S.cstate[K] & ~kValid);
+                if (lane == 0) S.cstate[K] = (valid ? (S.cstate[K] | kValid) : (S.cstate[K] & ~kValid)) & ~kDirty;
                 __syncthreads();
             }
         }
