@@ -247,53 +247,41 @@ extern "C" int vibe_profile_read(vibe_graph* G, double* ms, uint64_t* launches) 
     return VIBE_OK;
 }
 
-extern "C" int vibe_decode(vibe_graph* G, const uint8_t* syndromes, uint64_t B, uint64_t* corrections,
-                           uint8_t* observables, vibe_shot_stats* stats, void* stream) {
-    set_error("");
-    int rc = check_common(G, syndromes, B);
-    if (rc) return rc;
-    if (B && (!corrections || (!observables && G->h.k))) return fail(VIBE_EINVAL, "an output pointer is NULL");
-    if (!B) return VIBE_OK;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const DevGraph& g = G->h.dg;
-    const uint32_t bc = chunk_for(g, B, true);
-    const bool in_lds = bp_slab_fits_lds(g) && G->tune_lds != 0;
-    const int bpg = G->tune_grid > 0 ? std::min(G->tune_grid, bp_grid(g, in_lds)) : bp_grid(g, in_lds);
-    const int lg = lsd_grid_for(bc);
-    ChunkBufs W;
-    if ((rc = carve(G, bc, true, in_lds ? 0 : bpg, bpg, lg, &W))) return rc;
-    for (uint64_t s0 = 0; s0 < B; s0 += bc) {
-        const uint32_t n = (uint32_t)std::min<uint64_t>(bc, B - s0);
-        if ((rc = decode_chunk(G, W, syndromes, s0, n, corrections, stats, bpg, lg, st, in_lds))) return rc;
-    }
-    return launch_observables(g, corrections, 0, (uint32_t)std::min<uint64_t>(B, UINT32_MAX), observables, st);
-}
+namespace vibe {
+namespace {
 
-extern "C" int vibe_decode_packed(vibe_graph* G, const uint64_t* syndromes, uint64_t B, uint64_t* corrections,
-                                  uint8_t* observables, vibe_shot_stats* stats, void* stream) {
+// The batched decode of vibe_decode (bytes != NULL) and vibe_decode_packed
+// (words != NULL): chunks of shots through K1-K3, then K4 over the batch.
+// Packed syndromes are expanded chunk by chunk into the handle's input
+// buffer, and that chunk is then decoded as shots 0..n-1 of it.
+int decode_batch(vibe_graph* G, const uint8_t* bytes, const uint64_t* words, uint64_t B, uint64_t* corrections,
+                 uint8_t* observables, vibe_shot_stats* stats, void* stream) {
     set_error("");
-    int rc = check_common(G, syndromes, B);
+    int rc = check_common(G, bytes ? (const void*)bytes : (const void*)words, B);
     if (rc) return rc;
     if (B && (!corrections || (!observables && G->h.k))) return fail(VIBE_EINVAL, "an output pointer is NULL");
     if (!B) return VIBE_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const DevGraph& g = G->h.dg;
     const uint32_t bc = chunk_for(g, B, true);
-    const size_t in_bytes = al256((size_t)bc * (g.m ? g.m : 1));
-    if (G->ws_in.bytes < in_bytes) {
-        if (G->ws_in.base) {
-            hipError_t e = hipDeviceSynchronize();
-            if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before growing the input buffer");
-            (void)hipFree(G->ws_in.base);
-            G->ws_in.base = nullptr;
-            G->ws_in.bytes = 0;
+    uint8_t* u = nullptr;
+    if (words) {
+        const size_t in_bytes = al256((size_t)bc * (g.m ? g.m : 1));
+        if (G->ws_in.bytes < in_bytes) {
+            if (G->ws_in.base) {
+                hipError_t e = hipDeviceSynchronize();
+                if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before growing the input buffer");
+                (void)hipFree(G->ws_in.base);
+                G->ws_in.base = nullptr;
+                G->ws_in.bytes = 0;
+            }
+            void* p = nullptr;
+            if (hipMalloc(&p, in_bytes) != hipSuccess) return fail(VIBE_ENOMEM, "input buffer allocation failed");
+            G->ws_in.base = p;
+            G->ws_in.bytes = in_bytes;
         }
-        void* p = nullptr;
-        if (hipMalloc(&p, in_bytes) != hipSuccess) return fail(VIBE_ENOMEM, "input buffer allocation failed");
-        G->ws_in.base = p;
-        G->ws_in.bytes = in_bytes;
+        u = static_cast<uint8_t*>(G->ws_in.base);
     }
-    uint8_t* u = static_cast<uint8_t*>(G->ws_in.base);
     const bool in_lds = bp_slab_fits_lds(g) && G->tune_lds != 0;
     const int bpg = G->tune_grid > 0 ? std::min(G->tune_grid, bp_grid(g, in_lds)) : bp_grid(g, in_lds);
     const int lg = lsd_grid_for(bc);
@@ -302,19 +290,35 @@ extern "C" int vibe_decode_packed(vibe_graph* G, const uint64_t* syndromes, uint
     const uint32_t wm = g.words_m ? g.words_m : 1;
     for (uint64_t s0 = 0; s0 < B; s0 += bc) {
         const uint32_t n = (uint32_t)std::min<uint64_t>(bc, B - s0);
-        const uint64_t cells = (uint64_t)n * g.m;
-        if (cells) {
-            hipLaunchKernelGGL(unpack_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st,
-                               syndromes + s0 * g.words_m, wm, g.m, (uint64_t)n, u);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return hip_fail(e, "unpack_kernel launch");
+        if (!words) {
+            rc = decode_chunk(G, W, bytes, s0, n, corrections, stats, bpg, lg, st, in_lds);
+        } else {
+            const uint64_t cells = (uint64_t)n * g.m;
+            if (cells) {
+                hipLaunchKernelGGL(unpack_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st,
+                                   words + s0 * g.words_m, wm, g.m, (uint64_t)n, u);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return hip_fail(e, "unpack_kernel launch");
+            }
+            rc = decode_chunk(G, W, u, 0, n, corrections + s0 * g.words_n, stats ? stats + s0 : nullptr, bpg, lg,
+                              st, in_lds);
         }
-        // the chunk's shots are 0..n-1 of the unpacked buffer; outputs shift along
-        if ((rc = decode_chunk(G, W, u, 0, n, corrections + s0 * g.words_n, stats ? stats + s0 : nullptr, bpg, lg,
-                               st, in_lds)))
-            return rc;
+        if (rc) return rc;
     }
     return launch_observables(g, corrections, 0, (uint32_t)std::min<uint64_t>(B, UINT32_MAX), observables, st);
+}
+
+}  // namespace
+}  // namespace vibe
+
+extern "C" int vibe_decode(vibe_graph* G, const uint8_t* syndromes, uint64_t B, uint64_t* corrections,
+                           uint8_t* observables, vibe_shot_stats* stats, void* stream) {
+    return decode_batch(G, syndromes, nullptr, B, corrections, observables, stats, stream);
+}
+
+extern "C" int vibe_decode_packed(vibe_graph* G, const uint64_t* syndromes, uint64_t B, uint64_t* corrections,
+                                  uint8_t* observables, vibe_shot_stats* stats, void* stream) {
+    return decode_batch(G, nullptr, syndromes, B, corrections, observables, stats, stream);
 }
 
 extern "C" int vibe_decode_plain(vibe_graph* G, const uint8_t* syndromes, uint64_t B,
