@@ -15,7 +15,9 @@ arrivals at 0.5x and 0.8x the sustained rate, p50/p99 latency); a ragged
 batch of circuit-level codes at d = 5..13 (rounds = d) decoded as one call
 against one call per code;
 the phenomenological workload (d = 11, 11 rounds, L = 32, T = 50) with
-LSD-0 and with LSD order 10; the backward pass of the differentiable decoder (16 unrolled iterations of
+LSD-0 and with LSD order 10; fitting the channel LLRs and scaling factor
+with the differentiable decoder (d = 5 circuit-level), fitted against
+untuned decoder on held-out shots; the backward pass of the differentiable decoder (16 unrolled iterations of
 the d = 5 circuit-level graph, 4096 shots, L = 32, FP32) with its own
 roofline; the layered (check-serial) schedule on 8192 of the shots; BP+LSD-0
 without ensembling (one member,
@@ -151,6 +153,59 @@ def phenom_leg(P, torch, seed, shots):
     return out
 
 
+def tuning_leg(P, torch, seed, steps=30):
+    """Fit the channel LLRs and one shared scaling factor with the
+    differentiable decoder (K = 8 unrolled iterations, 8 members, 2048
+    training shots of the d = 5 circuit-level graph, 30 Adam steps), then
+    decode 32768 held-out shots with the untuned decoder (priors,
+    alpha = 0.625) and the fitted one, both with L = 32, M = 5, T = 20."""
+    from paper_2508_15743_amd import tune
+    from synth.dem import circuit_dem
+    from synth.sample import permutations, sample
+
+    dem = circuit_dem(5, 5, 1e-3)
+    perms = permutations(dem.n, 32, seed + 7)
+    lam0 = np.log((1 - dem.priors) / dem.priors)
+    K = 8
+    train = torch.from_numpy(sample(dem, 2048, seed + 8).syndromes).to("cuda:0")
+    held = sample(dem, 32768, seed + 9)
+    held_s = torch.from_numpy(held.syndromes).to("cuda:0")
+    Gt = P.Graph.from_dem(dem, perms[:8], L=8, M=1, T_max=K)
+    t1 = time.perf_counter()
+    lam, alpha, losses = tune.fit(Gt, train, K, steps=steps, lam0=lam0)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t1
+
+    def heldout_loss(l, a):
+        return float(Gt.bp_grad(held_s[:2048], torch.tensor(l), torch.full((K,), a))[0].item()) / 2048
+
+    out = {"workload": dem.name, "train_shots": 2048, "members": 8, "K": K, "steps": steps,
+           "fit_seconds": round(fit_s, 2), "loss_train_first_best": [round(losses[0], 5), round(min(losses), 5)],
+           "loss_heldout": {"untuned": round(heldout_loss(lam0, 0.625), 5),
+                            "tuned": round(heldout_loss(lam, alpha), 5)},
+           "alpha_tuned": round(alpha, 5), "lambda_change_rms": round(float(np.sqrt(np.mean((lam - lam0) ** 2))), 5)}
+    Gt.close()
+    for name, pri, a in (("untuned", dem.priors, 0.625), ("tuned", tune.priors_from_llr(lam), alpha)):
+        G = P.Graph(dem.h_indptr, dem.h_indices, pri, dem.l_indptr, dem.l_indices, perms, m=dem.m, n=dem.n,
+                    L=32, M=5, T_max=20, alpha=a)
+        G.decode(held_s[:256])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, obs, st = G.decode(held_s)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        st = st.cpu().numpy()
+        out[name] = {"shots_per_s": round(held.syndromes.shape[0] / dt, 1),
+                     "logical_error_rate": float((obs.cpu().numpy() != held.observables).any(1).mean()),
+                     "lsd_fraction": round(float(((st[:, 0] & 2) != 0).mean()), 5),
+                     "member_iterations_per_shot": round(float(st[:, 7].mean()), 2)}
+        G.close()
+    log(f"tuning: loss/shot {losses[0]:.4f} -> {min(losses):.4f} (held-out {out['loss_heldout']['untuned']} -> "
+        f"{out['loss_heldout']['tuned']}), LER {out['untuned']['logical_error_rate']:.2e} -> "
+        f"{out['tuned']['logical_error_rate']:.2e}, LSD {out['untuned']['lsd_fraction']} -> {out['tuned']['lsd_fraction']}")
+    return out
+
+
 def grad_leg(P, torch, seed, batch, K):
     """Backward pass through K unrolled iterations (the differentiable
     decoder): d = 5 circuit-level graph (rounds 5, p = 1e-3), L = 32 serial
@@ -283,6 +338,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-phenom", action="store_true", help="skip the phenomenological LSD-0 / LSD-10 leg")
+    ap.add_argument("--no-tune", action="store_true", help="skip the parameter-fitting leg")
     ap.add_argument("--phenom-shots", type=int, default=16384)
     ap.add_argument("--grad-batch", type=int, default=4096)
     ap.add_argument("--grad-K", type=int, default=16)
@@ -473,6 +529,8 @@ def main():
         result["grad"] = grad_leg(P, torch, args.seed, args.grad_batch, args.grad_K)
     if not args.no_phenom:
         result["phenomenological"] = phenom_leg(P, torch, args.seed, args.phenom_shots)
+    if not args.no_tune:
+        result["tuning"] = tuning_leg(P, torch, args.seed)
 
     result["plain"] = None
     result["batched_over_plain"] = None

@@ -235,3 +235,39 @@ def test_grad_same_at_every_chunk_width(torch_cuda, bits, schedule):
     with pytest.raises(P.VibeError):
         G.set_grad_width(24)
     G.close()
+
+
+def test_fit_lowers_the_loss_and_gives_a_valid_decoder(torch_cuda):
+    """The fitting loop over the channel LLRs and one shared scaling factor
+    (Adam on the gradient kernel's output): on the d = 5 circuit graph with
+    8 unrolled iterations the loss falls below the starting one, the
+    returned parameters are those of the lowest loss seen, the scaling
+    factor stays in its range, and a decoder built from the fitted priors
+    returns corrections that satisfy H e = s on every shot LSD did not
+    flag."""
+    import paper_2508_15743_amd as P
+    from paper_2508_15743_amd import tune
+
+    torch = torch_cuda
+    dem = circuit_dem(5, 5, 1e-3)
+    perms = permutations(dem.n, 4, 71)
+    G = P.Graph.from_dem(dem, perms, L=4, M=1, T_max=8)
+    s = torch.from_numpy(sample(dem, 512, 72).syndromes).cuda()
+    lam0 = np.log((1 - dem.priors) / dem.priors)
+    lam, alpha, losses = tune.fit(G, s, 8, steps=12, lam0=lam0)
+    assert len(losses) == 13 and min(losses) < 0.97 * losses[0], losses
+    got = float(G.bp_grad(s, torch.tensor(lam), torch.full((8,), alpha))[0].item()) / 512
+    assert abs(got - min(losses)) <= 1e-4 * min(losses), (got, min(losses))
+    assert 0.05 <= alpha <= 1.0 and np.all(np.isfinite(lam)) and lam.min() >= 1e-3
+    G.close()
+    pri = tune.priors_from_llr(lam)
+    np.testing.assert_allclose(np.log((1 - pri) / pri), lam, rtol=1e-9)
+    Gf = P.Graph(dem.h_indptr, dem.h_indices, pri, dem.l_indptr, dem.l_indices, perms, m=dem.m, n=dem.n,
+                 L=4, M=2, T_max=20, alpha=alpha)
+    b = sample(dem, 256, 73)
+    corr, obs, st = Gf.decode(torch.from_numpy(b.syndromes).cuda())
+    e, st = P.unpack_bits(corr, dem.n), st.cpu().numpy()
+    ok = (st[:, 0] & 4) == 0
+    H = dem.dense_h().astype(np.int64)
+    assert np.array_equal((e[ok].astype(np.int64) @ H.T) % 2, b.syndromes[ok])
+    Gf.close()
