@@ -84,6 +84,25 @@ def test_single_check_closed_form(s):
         np.testing.assert_allclose(r["trace"][:, v], exp, rtol=0, atol=1e-15)
 
 
+@pytest.mark.parametrize("schedule", ["serial", "parallel"])
+def test_single_check_per_iteration_scaling(schedule):
+    """P2 with a scaling factor per iteration: on H = [1 ... 1] the posterior
+    after iteration t is lambda_v + (1-2s) alpha_t prod sign min, so each
+    row of the trace carries its own alpha_t.  Breaks on an iteration index
+    off by one or a factor taken from the wrong end of the list."""
+    pri = np.array([0.1, 0.7, 0.05, 0.3, 0.2])
+    lam = O.prior_llr(pri)
+    g = O.OracleGraph(_dem(np.ones((1, 5)), pri))
+    alpha = np.array([0.9, 0.5, 0.75, 0.3])
+    perm = np.array([3, 1, 4, 0, 2]) if schedule == "serial" else None
+    r = O.bp(g, np.array([1]), perm=perm, T=4, alpha=alpha, stop=False, trace=True)
+    for v in range(5):
+        others = [u for u in range(5) if u != v]
+        sg = np.prod(np.sign(lam[others]))
+        exp = lam[v] - alpha * sg * np.min(np.abs(lam[others]))
+        np.testing.assert_allclose(r["trace"][:, v], exp, rtol=0, atol=1e-15)
+
+
 def test_serial_first_iteration_by_hand():
     """Algorithm 1, serial branch: a column updated later in the sweep sees
     messages already refreshed earlier in the same sweep; the parallel branch
