@@ -151,6 +151,16 @@ void vibe_graph_destroy(vibe_graph* g);
 /* Sizes and footprint of a graph. */
 int vibe_graph_info(const vibe_graph* g, vibe_graph_info_t* info);
 
+/* One min-sum scaling factor per iteration (Algorithm 1 with alpha_t in
+   place of a constant): alpha (host, count doubles, each in (0, 1e6]) gives
+   alpha_1 .. alpha_count; iterations past count keep alpha_count.  count = 0
+   returns to cfg->alpha for every iteration.  0..64 is accepted, anything
+   else is VIBE_EINVAL.  The call synchronises the device and applies to
+   later calls; captured sequences (vibe_exec) and servers keep the setting
+   the graph had when they were created.  vibe_bp_grad takes its own
+   factors and is not affected. */
+int vibe_graph_set_alpha(vibe_graph* g, const double* alpha, uint32_t count);
+
 /* Copies the member schedules the graph holds into perms (host, L x n
    uint32 column permutations, or L x m check orders for the layered
    schedule), so that a reference decoder can run the same members

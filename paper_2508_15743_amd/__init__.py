@@ -66,6 +66,7 @@ EXPORTS = {
     "vibe_decode_packed": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p]),
     "vibe_graph_get_schedules": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "vibe_graph_set_alpha": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32]),
     "vibe_decode_plain": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p]),
     "vibe_bp_ensemble": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_int,
@@ -165,6 +166,11 @@ def vibe_decode(handle, syndromes, B, corrections, observables, stats, stream):
 def vibe_decode_packed(handle, words, B, corrections, observables, stats, stream):
     _check(lib().vibe_decode_packed(handle, _ptr(words), B, _ptr(corrections), _ptr(observables),
                                     _ptr(stats), stream))
+
+
+def vibe_graph_set_alpha(handle, alpha):
+    a = np.ascontiguousarray(alpha if alpha is not None else [], dtype=np.float64)
+    _check(lib().vibe_graph_set_alpha(handle, a.ctypes.data if a.size else None, a.size))
 
 
 def vibe_graph_get_schedules(handle, L, length) -> np.ndarray:
@@ -346,6 +352,11 @@ class Graph:
         st = torch.empty((B, 8), dtype=torch.int32, device=w.device) if with_stats else None
         vibe_decode_packed(self.handle, w, B, corr, obs, st, _stream(stream))
         return corr, obs, st
+
+    def set_alpha(self, alpha=None):
+        """One scaling factor per iteration (alpha_1 .. alpha_k; later
+        iterations keep alpha_k); None returns to the constant alpha."""
+        vibe_graph_set_alpha(self.handle, alpha)
 
     def schedules(self) -> np.ndarray:
         """The member schedules the graph holds: [L, n] (or [L, m] layered)."""

@@ -672,6 +672,7 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
             stopped = true;  // cannot be among the first M any more
             break;
         }
+        if (g.alpha_t) x.al = (F)g.alpha_t[t - 1];  // one scaling factor per iteration
         const bool want_post = post_out != nullptr || (a.accumulate_q && t == a.T_run);
         if (want_post) {
             // columns without checks keep L_v = lambda_v

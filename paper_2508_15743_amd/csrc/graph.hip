@@ -389,6 +389,7 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     d.layered = layered ? 1 : 0;
     d.lsd_order = c.lsd_order;
     d.alpha = c.alpha;
+    d.alpha_t = nullptr;
     d.clamp = lim;
     d.ident32 = ident32;
     d.ident64 = ident64;
@@ -449,6 +450,33 @@ extern "C" void vibe_graph_destroy(vibe_graph* g) {
     if (g->ws.base) (void)hipFree(g->ws.base);
     if (g->ws_in.base) (void)hipFree(g->ws_in.base);
     delete g;
+}
+
+extern "C" int vibe_graph_set_alpha(vibe_graph* g, const double* alpha, uint32_t count) {
+    set_error("");
+    if (!g) return fail(VIBE_EINVAL, "graph handle is NULL");
+    if (count > (uint32_t)kMaxT) return fail(VIBE_EINVAL, "count must be in 0..64");
+    if (count == 0) {
+        g->h.dg.alpha_t = nullptr;
+        return VIBE_OK;
+    }
+    if (!alpha) return fail(VIBE_EINVAL, "alpha is NULL");
+    double table[kMaxT];
+    for (uint32_t t = 0; t < (uint32_t)kMaxT; t++) {
+        const double a = alpha[t < count ? t : count - 1];
+        if (!(a > 0.0) || !(a <= 1e6)) return fail(VIBE_EINVAL, "every alpha must be in (0, 1e6]");
+        table[t] = a;
+    }
+    if (!g->h.alpha_dev) {
+        int rc = upload(g->h, (const double*)nullptr, kMaxT, &g->h.alpha_dev);
+        if (rc) return rc;
+    }
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before updating alpha");
+    e = hipMemcpy(const_cast<double*>(g->h.alpha_dev), table, sizeof(table), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy of alpha");
+    g->h.dg.alpha_t = g->h.alpha_dev;
+    return VIBE_OK;
 }
 
 extern "C" int vibe_graph_get_schedules(const vibe_graph* g, uint32_t* perms) {

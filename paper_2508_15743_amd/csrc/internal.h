@@ -81,6 +81,7 @@ struct DevGraph {
     int layered;                // 1: layered (check-serial) schedule; cperm holds the check orders
     uint32_t lsd_order;         // 0 = LSD-0; > 0: combination sweep over the first lsd_order non-pivots
     double alpha, clamp;
+    const double* alpha_t;      // kMaxT scaling factors, one per iteration, or null (alpha throughout)
     uint32_t ident32;           // row state of "no message": clamp, parity 0 (FP32 bits)
     uint64_t ident64;           // the same in FP64 bits
     int all_lam_positive;
@@ -108,6 +109,7 @@ struct GraphHost {
     DevGraph dg;
     std::vector<void*> allocations;
     std::vector<uint32_t> perms;  // the member schedules as given (L x n, or L x m layered)
+    const double* alpha_dev = nullptr;  // device table behind dg.alpha_t once set
 };
 
 // Per-handle workspace, grown on demand and reused across calls.

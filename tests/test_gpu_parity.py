@@ -64,17 +64,22 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-def _bp_parity(torch, dem, L, T, shots, seed, stop, bits=32, schedule="serial"):
+def _bp_parity(torch, dem, L, T, shots, seed, stop, bits=32, schedule="serial", alpha=None):
     import paper_2508_15743_amd as P
 
     G, perms = _graph(dem, L, min(5, L), T, seed, message_bits=bits, schedule=schedule)
+    al = 0.625
+    if alpha is not None:
+        G.set_alpha(alpha)
+        al = np.array([alpha[min(t, len(alpha) - 1)] for t in range(T)])
     b = sample(dem, shots, seed + 1)
     tc, post, eh = G.bp_ensemble(_dev(torch, b.syndromes), T_run=T, stop=stop)
     tc, post, eh = tc.cpu().numpy(), post.cpu().numpy(), P.unpack_bits(eh, dem.n)
     g = O.OracleGraph(dem)
     for i in range(shots):
         for j in range(L):
-            r = O.bp(g, b.syndromes[i], perm=perms[j] if schedule == "serial" else None, T=T, stop=stop)
+            r = O.bp(g, b.syndromes[i], perm=perms[j] if schedule == "serial" else None, T=T, stop=stop,
+                     alpha=al)
             if bits == 64:
                 assert r["t_conv"] == tc[i, j], (i, j)
                 assert np.array_equal(r["ehat"], eh[i, j]), (i, j)
@@ -119,6 +124,43 @@ def test_bp_members_fp64_bit_exact_circuit_full_size(torch_cuda):
 def test_bp_members_fp64_bit_exact_circuit_si1000(torch_cuda):
     # Si1000 rates (Sec. IV.A): same circuit, readout flips at 5p
     _bp_parity(torch_cuda, circuit_dem(5, 5, 2e-3, noise="si1000"), 4, 8, 4, 16, stop=False, bits=64)
+
+
+def test_bp_members_per_iteration_alpha(torch_cuda):
+    """One scaling factor per iteration (vibe_graph_set_alpha), against the
+    oracle run with the same alpha_t: FP64 members bit-identical on the
+    code-capacity graph (a list shorter than T, so later iterations keep the
+    last factor) and on the d = 9 circuit graph, serial and parallel; FP32
+    to the member bar.  Whole FP64 decodes match the oracle's decoder with
+    the same factors, and clearing the list returns to the constant alpha."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    al = [0.9, 0.8, 0.7, 0.6, 0.55, 0.5]
+    _bp_parity(torch, code_capacity_dem(5, 0.08), 8, 32, 40, 81, stop=True, bits=64, alpha=al)
+    _bp_parity(torch, circuit_dem(9, 9, 1e-3), 2, 4, 2, 82, stop=False, bits=64, alpha=al[:4])
+    _bp_parity(torch, circuit_dem(9, 9, 1e-3), 1, 4, 2, 83, stop=False, bits=64, schedule="parallel", alpha=al[:4])
+    _bp_parity(torch, phenomenological_dem(11, 11, 0.01, 0.01), 4, 20, 6, 84, stop=True, alpha=al)
+    dem = code_capacity_dem(5, 0.05)
+    G, perms = _graph(dem, 16, 5, 32, 85, message_bits=64)
+    b = sample(dem, 4000, 86)
+    s = _dev(torch, b.syndromes)
+    c0 = G.decode(s)[0].clone()
+    G.set_alpha(al)
+    e = P.unpack_bits(G.decode(s)[0], dem.n)
+    ref = _oracle_decode_alpha(dem, perms, b.syndromes, 16, 5, 32, np.array(al + [al[-1]] * 26))
+    assert (ref["ehat"] == e).all(1).mean() >= 0.999
+    G.set_alpha(None)
+    assert torch.equal(G.decode(s)[0], c0)
+    with pytest.raises(P.VibeError):
+        G.set_alpha([0.5, 0.0])
+    with pytest.raises(P.VibeError):
+        G.set_alpha([0.5] * 65)
+    G.close()
+
+
+def _oracle_decode_alpha(dem, perms, synd, L, M, T, alpha):
+    return O.decode(O.OracleGraph(dem), perms, synd, L=L, M=M, T=T, alpha=alpha, threads=NT)
 
 
 def test_bp_parallel_schedule_fp64_bit_exact(torch_cuda):
