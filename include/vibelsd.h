@@ -155,9 +155,11 @@ int vibe_graph_info(const vibe_graph* g, vibe_graph_info_t* info);
    place of a constant): alpha (host, count doubles, each in (0, 1e6]) gives
    alpha_1 .. alpha_count; iterations past count keep alpha_count.  count = 0
    returns to cfg->alpha for every iteration.  0..64 is accepted, anything
-   else is VIBE_EINVAL.  The call synchronises the device and applies to
-   later calls; captured sequences (vibe_exec) and servers keep the setting
-   the graph had when they were created.  vibe_bp_grad takes its own
+   else is VIBE_EINVAL.  The factors go to a new device table (512 bytes,
+   freed by vibe_graph_destroy) and apply to later calls.  Work already
+   queued and captured sequences (vibe_exec) keep the table they were given.
+   A server reads the setting whenever it forms a batch, so change it only
+   while no server holding the graph runs.  vibe_bp_grad takes its own
    factors and is not affected. */
 int vibe_graph_set_alpha(vibe_graph* g, const double* alpha, uint32_t count);
 

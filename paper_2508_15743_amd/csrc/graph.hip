@@ -467,15 +467,13 @@ extern "C" int vibe_graph_set_alpha(vibe_graph* g, const double* alpha, uint32_t
         if (!(a > 0.0) || !(a <= 1e6)) return fail(VIBE_EINVAL, "every alpha must be in (0, 1e6]");
         table[t] = a;
     }
-    if (!g->h.alpha_dev) {
-        int rc = upload(g->h, (const double*)nullptr, kMaxT, &g->h.alpha_dev);
-        if (rc) return rc;
-    }
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before updating alpha");
-    e = hipMemcpy(const_cast<double*>(g->h.alpha_dev), table, sizeof(table), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy of alpha");
-    g->h.dg.alpha_t = g->h.alpha_dev;
+    // a new table every call: launches already queued and captured
+    // sequences keep reading the table they were given (512 bytes each,
+    // freed with the graph)
+    const double* dev = nullptr;
+    int rc = upload(g->h, table, kMaxT, &dev);
+    if (rc) return rc;
+    g->h.dg.alpha_t = dev;
     return VIBE_OK;
 }
 

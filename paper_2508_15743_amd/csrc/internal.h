@@ -109,7 +109,6 @@ struct GraphHost {
     DevGraph dg;
     std::vector<void*> allocations;
     std::vector<uint32_t> perms;  // the member schedules as given (L x n, or L x m layered)
-    const double* alpha_dev = nullptr;  // device table behind dg.alpha_t once set
 };
 
 // Per-handle workspace, grown on demand and reused across calls.
