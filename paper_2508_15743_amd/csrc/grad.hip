@@ -733,6 +733,7 @@ const void* grad_fn(uint32_t P) {
 // grad launch limits: blocks (one wavefront each) and their scratch in total
 constexpr uint64_t kGradMaxGrid = 8192;
 constexpr uint64_t kGradScratchBudget = 40ull << 30;
+constexpr size_t kGradMaxLds = 160 * 1024;  // LDS of one workgroup on gfx950
 
 size_t grad_scratch_per_block(const DevGraph& g, uint32_t K, uint32_t P) {
     return grad_layout((size_t)g.E * P + kWave, (size_t)g.n * P, (size_t)g.m * P, K, g.fp64 ? 8 : 4).bytes;
@@ -810,7 +811,9 @@ int build_grad_schedule(vibe_graph* G) {
     uint32_t bestW = kWave;
     double best = -1.0;
     for (uint32_t W : {64u, 32u, 16u}) {
-        size_t cnt = 0, worst = 0;
+        // P shots per wavefront multiply the LDS row state by P
+        if (W < (uint32_t)kWave && grad_lds_bytes(G->h.dg, kWave / W) > kGradMaxLds) continue;
+        size_t cnt = 0;
         for (uint32_t i = 0; i < L; i++) {
             size_t ci = 0;
             for (size_t k = mc[i]; k < mc[i + 1]; k++) {
@@ -825,7 +828,6 @@ int build_grad_schedule(vibe_graph* G) {
                 }
             }
             cnt += ci;
-            worst = std::max(worst, ci);
         }
         // chunk steps per shot, weighted by the cost of a step with P shots
         // side by side (measured on the d = 5 and d = 7 circuit graphs: a
@@ -838,7 +840,6 @@ int build_grad_schedule(vibe_graph* G) {
             best = cost;
             bestW = W;
         }
-        (void)worst;
     }
 #ifdef VIBE_GRAD_WIDTH
     bestW = VIBE_GRAD_WIDTH;  // build-time override, for measurements
@@ -949,6 +950,8 @@ extern "C" int vibe_bp_grad(vibe_graph* G, const uint8_t* syndromes, uint64_t B,
     int rc = build_grad_schedule(G);
     if (rc) return rc;
     const uint32_t P = G->grad_P;
+    if (grad_lds_bytes(g, P) > kGradMaxLds)
+        return fail(VIBE_EUNSUPPORTED, "the gradient's LDS row state exceeds 160 KB (too many checks for this width)");
     const uint64_t units = (B + P - 1) / P * g.L;  // (group of P shots, member)
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t per = grad_scratch_per_block(g, K, P);

@@ -271,3 +271,28 @@ def test_fit_lowers_the_loss_and_gives_a_valid_decoder(torch_cuda):
     H = dem.dense_h().astype(np.int64)
     assert np.array_equal((e[ok].astype(np.int64) @ H.T) % 2, b.syndromes[ok])
     Gf.close()
+
+
+def test_grad_on_the_d17_graph(torch_cuda):
+    """The d = 17 circuit-level graph (m = 3672): the gradient kernel's row
+    state (88 KB of LDS at one shot per wavefront) needs the large-LDS launch
+    and rules out several shots per wavefront.  Two shots and two members,
+    K = 4: the FP32 loss matches the oracle's, and the gradient is finite."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    dem = circuit_dem(17, 17, 1e-3)
+    K, L = 4, 2
+    perms = permutations(dem.n, L, 91)
+    G = P.Graph.from_dem(dem, perms, L=L, M=1, T_max=K)
+    synd = sample(dem, 2, 92).syndromes
+    lam = np.log((1 - dem.priors) / dem.priors)
+    alpha = np.full(K, 0.625)
+    loss, dl, da = G.bp_grad(torch.from_numpy(synd).cuda(), torch.tensor(lam, dtype=torch.float32),
+                             torch.tensor(alpha, dtype=torch.float32))
+    assert G.info()["grad_width"] == 64
+    assert torch.isfinite(dl).all() and torch.isfinite(da).all()
+    g = O.OracleGraph(dem)
+    want = sum(O.bp_loss(g, s, lam, alpha, K, perm)[0] for s in synd for perm in perms)
+    assert abs(loss.item() - want) <= 1e-4 * max(1.0, abs(want)), (loss.item(), want)
+    G.close()
