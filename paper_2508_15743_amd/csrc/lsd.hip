@@ -33,6 +33,8 @@ namespace {
 // so its validity must be computed again (an unchanged cluster keeps it)
 constexpr uint32_t kValid = 1u, kFailed = 2u, kDirty = 4u;
 constexpr size_t kLsdLds = 150 * 1024;  // LDS budget of one LSD wavefront
+// row cache entries: the row's least column not yet held is unknown / none
+constexpr int32_t kRowStale = -2, kRowEmpty = -1;
 
 // Per-shot state.  Everything one lane writes and another reads lives in
 // LDS.  The global part holds the large arrays: the basis vectors, which
@@ -53,6 +55,8 @@ struct LsdMem {
     int32_t* pool_piv;  // m
     int32_t* piv2;      // m
     int32_t* pivcol;    // m
+    int64_t* row_q;     // m: key of the row's least column not yet held (lane 0 only)
+    int32_t* row_v;     // m: that column, kRowEmpty or kRowStale (lane 0 only)
     uint64_t* in_bits;  // words_n
     uint64_t* ebits;    // words_n
     uint64_t* xbuf;     // words_m
@@ -92,11 +96,11 @@ __host__ __device__ inline void lsd_layout(const DevGraph& g, unsigned char* lds
         return p;
     };
     // The arrays only lane 0 touches (best_q, best_v, ccount, picks, added,
-    // pivcol: 32 bytes per check) move to global memory when everything
+    // pivcol, row_q, row_v: 44 bytes per check) move to global memory when everything
     // would not fit in kLsdLds bytes of LDS (graphs with several thousand
     // checks).  Reads and writes by one lane need no cross-lane visibility.
     const size_t all_lds = al8(8 * m) + 2 * al8(8 * wn) + 3 * al8(8 * wm) + 5 * al8(4 * m) + al8(8 * m) +
-                           4 * al8(4 * m);
+                           4 * al8(4 * m) + al8(8 * m) + al8(4 * m);
     const bool priv_glob = all_lds > kLsdLds;
     auto tp = [&](size_t bytes) { return priv_glob ? tg(bytes) : tl(bytes); };
     LsdMem M;
@@ -116,6 +120,8 @@ __host__ __device__ inline void lsd_layout(const DevGraph& g, unsigned char* lds
     M.pool_piv = (int32_t*)tl(4 * m);
     M.piv2 = (int32_t*)tl(4 * m);
     M.pivcol = (int32_t*)tp(4 * m);
+    M.row_q = (int64_t*)tp(8 * m);
+    M.row_v = (int32_t*)tp(4 * m);
     M.ckey = (int64_t*)tg(8 * n);
     M.pool = (uint64_t*)tg(8 * wm * m);
     M.basis2 = (uint64_t*)tg(16 * wm * m);
@@ -338,22 +344,24 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
             S.in_bits[w] = 0;
             S.ebits[w] = 0;
         }
+        if (lane == 0)
+            for (uint32_t c = 0; c < g.m; c++) S.row_v[c] = kRowStale;
         __syncthreads();
         int pool_n = 0, rounds = 0;
 
         for (;;) {
-            // 1. best boundary column of every invalid, growing cluster
-            if (lane == 0)
-                for (int K = 0; K < nk; K++) {
-                    S.best_q[K] = INT64_MAX;
-                    S.best_v[K] = -1;
-                }
-            __syncthreads();
+            // 1. best boundary column of every invalid, growing cluster: the
+            //    least (key, column) over its checks' rows.  Each row's least
+            //    column not yet held is cached across rounds; it changes only
+            //    when one of the row's columns joins, and every check of a
+            //    joining column is marked stale in step 3.  Only lane 0's
+            //    copy of a cache entry is used (readfirstlane).
             for (uint32_t c = 0; c < g.m; c++) {
                 const int32_t cl = uni(S.chk_cl[c]);
                 if (cl < 0) continue;
                 const int32_t R = uni(find_root(S.parent, cl));
                 if (uni(S.cstate[R]) & (kValid | kFailed)) continue;
+                if (uni(S.row_v[c]) != kRowStale) continue;
                 int64_t bq = INT64_MAX;
                 int32_t bv = 0x7fffffff;
                 for (uint32_t p = g.rp[c] + lane; p < g.rp[c + 1]; p += kWave) {
@@ -373,13 +381,31 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                         bv = ov;
                     }
                 }
-                if (lane == 0 && bv != 0x7fffffff &&
-                    (S.best_v[R] < 0 || key_less(bq, bv, S.best_q[R], S.best_v[R]))) {
-                    S.best_q[R] = bq;
-                    S.best_v[R] = bv;
+                if (lane == 0) {
+                    S.row_q[c] = bq;
+                    S.row_v[c] = bv == 0x7fffffff ? kRowEmpty : bv;
                 }
-                __syncthreads();
             }
+            if (lane == 0) {
+                for (int K = 0; K < nk; K++) {
+                    S.best_q[K] = INT64_MAX;
+                    S.best_v[K] = -1;
+                }
+                for (uint32_t c = 0; c < g.m; c++) {
+                    const int32_t cl = S.chk_cl[c];
+                    if (cl < 0) continue;
+                    const int32_t R = find_root(S.parent, cl);
+                    if (S.cstate[R] & (kValid | kFailed)) continue;
+                    const int32_t v = S.row_v[c];
+                    if (v < 0) continue;
+                    const int64_t q = S.row_q[c];
+                    if (S.best_v[R] < 0 || key_less(q, v, S.best_q[R], S.best_v[R])) {
+                        S.best_q[R] = q;
+                        S.best_v[R] = v;
+                    }
+                }
+            }
+            __syncthreads();
             // 2. clusters with an empty boundary fail; collect the picks
             int npick = 0;
             if (lane == 0) {
@@ -411,6 +437,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                     }
                     for (uint32_t q = g.cp[j]; q < g.cp[j + 1]; q++) {
                         const uint32_t c = g.ci[q];
+                        S.row_v[c] = kRowStale;  // j is held now
                         if (S.chk_cl[c] < 0) {
                             S.chk_cl[c] = K;
                         } else {
