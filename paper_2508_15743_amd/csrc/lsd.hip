@@ -57,6 +57,7 @@ struct LsdMem {
     int32_t* pivcol;    // m
     int64_t* row_q;     // m: key of the row's least column not yet held (lane 0 only)
     int32_t* row_v;     // m: that column, kRowEmpty or kRowStale (lane 0 only)
+    int32_t* clist;     // m: the checks held by clusters, in the order they joined (lane 0 only)
     uint64_t* in_bits;  // words_n
     uint64_t* ebits;    // words_n
     uint64_t* xbuf;     // words_m
@@ -96,11 +97,11 @@ __host__ __device__ inline void lsd_layout(const DevGraph& g, unsigned char* lds
         return p;
     };
     // The arrays only lane 0 touches (best_q, best_v, ccount, picks, added,
-    // pivcol, row_q, row_v: 44 bytes per check) move to global memory when everything
+    // pivcol, row_q, row_v, clist: 48 bytes per check) move to global memory when everything
     // would not fit in kLsdLds bytes of LDS (graphs with several thousand
     // checks).  Reads and writes by one lane need no cross-lane visibility.
     const size_t all_lds = al8(8 * m) + 2 * al8(8 * wn) + 3 * al8(8 * wm) + 5 * al8(4 * m) + al8(8 * m) +
-                           4 * al8(4 * m) + al8(8 * m) + al8(4 * m);
+                           4 * al8(4 * m) + al8(8 * m) + 2 * al8(4 * m);
     const bool priv_glob = all_lds > kLsdLds;
     auto tp = [&](size_t bytes) { return priv_glob ? tg(bytes) : tl(bytes); };
     LsdMem M;
@@ -122,6 +123,7 @@ __host__ __device__ inline void lsd_layout(const DevGraph& g, unsigned char* lds
     M.pivcol = (int32_t*)tp(4 * m);
     M.row_q = (int64_t*)tp(8 * m);
     M.row_v = (int32_t*)tp(4 * m);
+    M.clist = (int32_t*)tp(4 * m);
     M.ckey = (int64_t*)tg(8 * n);
     M.pool = (uint64_t*)tg(8 * wm * m);
     M.basis2 = (uint64_t*)tg(16 * wm * m);
@@ -322,11 +324,14 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
         };
 
         // ---- one cluster per flipped check, slots in ascending check order
-        int nk = 0;
+        int nk = 0, ncl = 0;  // ncl: length of clist (kept by lane 0, broadcast per round)
         for (uint32_t base = 0; base < g.m; base += kWave) {
             const uint32_t c = base + lane;
             const bool f = c < g.m && s[c] != 0;
             const uint64_t mask = __ballot(f);
+            if (lane == 0)
+                for (uint64_t mm = mask; mm; mm &= mm - 1)
+                    S.clist[ncl++] = (int32_t)(base + __ffsll((long long)mm) - 1);
             const int pre = __popcll(mask & ((1ull << lane) - 1ull));
             if (c < g.m) {
                 if (f) {
@@ -356,10 +361,10 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
             //    when one of the row's columns joins, and every check of a
             //    joining column is marked stale in step 3.  Only lane 0's
             //    copy of a cache entry is used (readfirstlane).
-            for (uint32_t c = 0; c < g.m; c++) {
-                const int32_t cl = uni(S.chk_cl[c]);
-                if (cl < 0) continue;
-                const int32_t R = uni(find_root(S.parent, cl));
+            ncl = uni(__shfl(ncl, 0));
+            for (int i = 0; i < ncl; i++) {
+                const uint32_t c = (uint32_t)uni(S.clist[i]);
+                const int32_t R = uni(find_root(S.parent, S.chk_cl[c]));
                 if (uni(S.cstate[R]) & (kValid | kFailed)) continue;
                 if (uni(S.row_v[c]) != kRowStale) continue;
                 int64_t bq = INT64_MAX;
@@ -391,10 +396,9 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                     S.best_q[K] = INT64_MAX;
                     S.best_v[K] = -1;
                 }
-                for (uint32_t c = 0; c < g.m; c++) {
-                    const int32_t cl = S.chk_cl[c];
-                    if (cl < 0) continue;
-                    const int32_t R = find_root(S.parent, cl);
+                for (int i = 0; i < ncl; i++) {
+                    const int32_t c = S.clist[i];
+                    const int32_t R = find_root(S.parent, S.chk_cl[c]);
                     if (S.cstate[R] & (kValid | kFailed)) continue;
                     const int32_t v = S.row_v[c];
                     if (v < 0) continue;
@@ -440,6 +444,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                         S.row_v[c] = kRowStale;  // j is held now
                         if (S.chk_cl[c] < 0) {
                             S.chk_cl[c] = K;
+                            S.clist[ncl++] = (int32_t)c;
                         } else {
                             int32_t ra = find_root(S.parent, K), rb = find_root(S.parent, S.chk_cl[c]);
                             if (ra != rb) {
