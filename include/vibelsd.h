@@ -238,9 +238,10 @@ int vibe_lsd(vibe_graph* g, const uint8_t* syndromes, const float* soft, uint64_
  * Ragged batching: several requests, possibly on graphs of different codes,
  * decoded with one persistent BP launch over all of their (shot, member)
  * items, then selection, LSD and observables per request.  Each request's
- * outputs are exactly those vibe_decode produces for it alone.  All graphs
- * of one call must share message_bits and schedule and live on the
- * runtime's device.  A runtime owns the device workspace of its calls;
+ * outputs are exactly those vibe_decode produces for it alone.  Graphs
+ * with the serial and the parallel schedule can share one call (and one
+ * launch); layered graphs are refused (VIBE_EUNSUPPORTED).  All graphs of
+ * one call must share message_bits and live on the runtime's device.  A runtime owns the device workspace of its calls;
  * calls on one runtime must not overlap in time.
  */
 typedef struct vibe_runtime vibe_runtime;

@@ -101,6 +101,7 @@ struct Round {
     size_t lds_bytes = 0, lsd_per_block = 0;
     int grid = 0, lsd_grid = 0;
     bool slab_in_lds = false;
+    bool flood = false;  // some segment uses the parallel schedule
 };
 
 size_t seg_bytes(const DevGraph& g, uint32_t n) {
@@ -119,8 +120,7 @@ int check_requests(const vibe_request* reqs, uint32_t n) {
         const DevGraph& g = r.graph->h.dg;
         const DevGraph& g0 = reqs[0].graph->h.dg;
         if (g.layered) return fail(VIBE_EUNSUPPORTED, "layered-schedule graphs decode one request at a time (vibe_decode)");
-        if (g.fp64 != g0.fp64 || g.flood != g0.flood)
-            return fail(VIBE_EINVAL, "all graphs of a ragged call need the same message_bits and schedule");
+        if (g.fp64 != g0.fp64) return fail(VIBE_EINVAL, "all graphs of a ragged call need the same message_bits");
         if (r.graph->device != reqs[0].graph->device) return fail(VIBE_EINVAL, "all graphs must be on one device");
     }
     return VIBE_OK;
@@ -173,7 +173,7 @@ std::vector<Round> plan(const vibe_request* reqs, uint32_t n_reqs, size_t budget
             const vibe_graph* G = reqs[sg.req].graph;
             const DevGraph& g = G->h.dg;
             fp64 = g.fp64 != 0;
-            flood = g.flood != 0;
+            flood = flood || g.flood != 0;
             r.slab_elems = std::max<uint32_t>(r.slab_elems, std::max<uint32_t>(g.max_chunks, 1) * kWave);
             r.post_elems = std::max<uint32_t>(r.post_elems, g.n + kWave);
             lds_ok = lds_ok && bp_slab_fits_lds(g) && G->tune_lds != 0;
@@ -182,6 +182,7 @@ std::vector<Round> plan(const vibe_request* reqs, uint32_t n_reqs, size_t budget
             r.lsd_per_block = std::max(r.lsd_per_block, lsd_scratch_per_block(g));
         }
         r.slab_in_lds = lds_ok;
+        r.flood = flood;
         r.lds_bytes = lds_ok ? lds_l : lds_global;
         r.grid = bp_grid_for(fp64, flood, lds_ok, r.lds_bytes, true);
         uint64_t total_items = 0, max_n = 0;
@@ -285,7 +286,7 @@ int run_round(const vibe_request* reqs, const Round& r, unsigned char* base, hip
     L.grid = r.grid;
     L.slab_in_lds = r.slab_in_lds ? 1 : 0;
     L.fp64 = reqs[r.segs[0].req].graph->h.dg.fp64;
-    L.flood = reqs[r.segs[0].req].graph->h.dg.flood;
+    L.flood = r.flood ? 1 : 0;
     L.lds_bytes = r.lds_bytes;
     if ((rc = launch_bp_ragged(L, st))) return rc;
     for (size_t j = 0; j < r.segs.size(); j++) {
@@ -752,8 +753,7 @@ extern "C" int vibe_server_create(vibe_graph* const* graphs, uint32_t n_graphs, 
         const DevGraph& g = graphs[i]->h.dg;
         const DevGraph& g0 = graphs[0]->h.dg;
         if (g.layered) return fail(VIBE_EUNSUPPORTED, "layered-schedule graphs decode one request at a time (vibe_decode)");
-        if (g.fp64 != g0.fp64 || g.flood != g0.flood)
-            return fail(VIBE_EINVAL, "all graphs of a server need the same message_bits and schedule");
+        if (g.fp64 != g0.fp64) return fail(VIBE_EINVAL, "all graphs of a server need the same message_bits");
     }
     vibe_server* S = new (std::nothrow) vibe_server();
     if (!S) return fail(VIBE_ENOMEM, "host allocation failed");

@@ -74,6 +74,26 @@ def test_ragged_equals_single(torch_cuda, schedule):
         G.close()
 
 
+def test_ragged_mixed_schedules(torch_cuda):
+    """Serial and parallel (BP+LSD-0) graphs in one ragged call share one
+    persistent launch; every request still equals its single decode, and
+    the same holds with the parallel requests first or last."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    ser, par = _graphs("serial"), _graphs("parallel")
+    gs = [ser[0], par[1], ser[3], par[2], par[0]]
+    sizes = [500, 300, 64, 1, 200]
+    pairs = [(G, _dev(torch, sample(dem, B, 120 + i).syndromes)) for i, ((dem, G), B) in enumerate(zip(gs, sizes))]
+    want = [G.decode(s) for G, s in pairs]
+    rt = P.Runtime()
+    _check_same(torch, rt.decode(pairs), want)
+    _check_same(torch, rt.decode(pairs[::-1])[::-1], want)
+    rt.close()
+    for _, G in ser + par:
+        G.close()
+
+
 def test_ragged_benchmark_graph_mix(torch_cuda):
     """The d = 9 benchmark graph with smaller codes in one launch."""
     import paper_2508_15743_amd as P
