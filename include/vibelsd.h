@@ -82,10 +82,9 @@ typedef struct vibe_config {
                               future work: each member visits the checks one
                               at a time in its own order, every check working
                               from the latest posteriors, mu = L - r_own).
-                              Layered graphs decode through vibe_decode,
-                              vibe_decode_plain, vibe_bp_ensemble and
-                              vibe_lsd; ragged calls, servers and the
-                              gradient refuse them (VIBE_EUNSUPPORTED). */
+                              The gradient refuses layered graphs
+                              (VIBE_EUNSUPPORTED); every decode path takes
+                              them. */
 } vibe_config;
 
 typedef struct vibe_shot_stats {
@@ -238,10 +237,9 @@ int vibe_lsd(vibe_graph* g, const uint8_t* syndromes, const float* soft, uint64_
  * Ragged batching: several requests, possibly on graphs of different codes,
  * decoded with one persistent BP launch over all of their (shot, member)
  * items, then selection, LSD and observables per request.  Each request's
- * outputs are exactly those vibe_decode produces for it alone.  Graphs
- * with the serial and the parallel schedule can share one call (and one
- * launch); layered graphs are refused (VIBE_EUNSUPPORTED).  All graphs of
- * one call must share message_bits and live on the runtime's device.  A runtime owns the device workspace of its calls;
+ * outputs are exactly those vibe_decode produces for it alone.  Graphs of
+ * all three schedules can share one call and one launch.  All graphs of one
+ * call must share message_bits and live on the runtime's device.  A runtime owns the device workspace of its calls;
  * calls on one runtime must not overlap in time.
  */
 typedef struct vibe_runtime vibe_runtime;

@@ -842,9 +842,17 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_tar
         while (j + 1 < r.n_segs && segs[j + 1].item0 <= item) j++;
         const DevGraph g = load_const(&r.segs[j].g);
         const BpLaunch a = load_const(&r.segs[j].a);
+        // one launch may mix schedules: parallel items need the launch's
+        // second slab, serial ones use the first only, and layered ones
+        // (global slabs only) keep messages and posteriors in the first
+        if constexpr (!SLAB_LDS) {
+            if (g.layered) {
+                run_item<F, false, false, true>(g, a, item - segs[j].item0, lds, x);
+                __syncthreads();
+                continue;
+            }
+        }
         if constexpr (FLOOD) {
-            // a launch that holds parallel-schedule segments may hold
-            // serial ones too: those use only the state slab
             if (g.flood)
                 run_item<F, SLAB_LDS, true>(g, a, item - segs[j].item0, lds, x);
             else

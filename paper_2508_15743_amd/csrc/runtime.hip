@@ -119,7 +119,6 @@ int check_requests(const vibe_request* reqs, uint32_t n) {
         if (r.B > (1ull << 40)) return fail(VIBE_EINVAL, "a request is too large");
         const DevGraph& g = r.graph->h.dg;
         const DevGraph& g0 = reqs[0].graph->h.dg;
-        if (g.layered) return fail(VIBE_EUNSUPPORTED, "layered-schedule graphs decode one request at a time (vibe_decode)");
         if (g.fp64 != g0.fp64) return fail(VIBE_EINVAL, "all graphs of a ragged call need the same message_bits");
         if (r.graph->device != reqs[0].graph->device) return fail(VIBE_EINVAL, "all graphs must be on one device");
     }
@@ -752,7 +751,6 @@ extern "C" int vibe_server_create(vibe_graph* const* graphs, uint32_t n_graphs, 
         if (!graphs[i]) return fail(VIBE_EINVAL, "a graph is NULL");
         const DevGraph& g = graphs[i]->h.dg;
         const DevGraph& g0 = graphs[0]->h.dg;
-        if (g.layered) return fail(VIBE_EUNSUPPORTED, "layered-schedule graphs decode one request at a time (vibe_decode)");
         if (g.fp64 != g0.fp64) return fail(VIBE_EINVAL, "all graphs of a server need the same message_bits");
     }
     vibe_server* S = new (std::nothrow) vibe_server();

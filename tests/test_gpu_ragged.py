@@ -75,22 +75,29 @@ def test_ragged_equals_single(torch_cuda, schedule):
 
 
 def test_ragged_mixed_schedules(torch_cuda):
-    """Serial and parallel (BP+LSD-0) graphs in one ragged call share one
-    persistent launch; every request still equals its single decode, and
-    the same holds with the parallel requests first or last."""
+    """Serial, parallel (BP+LSD-0) and layered graphs in one ragged call
+    share one persistent launch; every request still equals its single
+    decode, in either order; a serial + layered call (no parallel segment)
+    as well."""
     import paper_2508_15743_amd as P
 
     torch = torch_cuda
     ser, par = _graphs("serial"), _graphs("parallel")
-    gs = [ser[0], par[1], ser[3], par[2], par[0]]
-    sizes = [500, 300, 64, 1, 200]
+    lay = []
+    for i, dem in enumerate((code_capacity_dem(5, 0.05), circuit_dem(5, 5, 1e-3))):
+        lay.append((dem, P.Graph.from_dem(dem, permutations(dem.m, 8, 60 + i), L=8, M=3, T_max=20,
+                                          schedule="layered")))
+    gs = [ser[0], par[1], lay[0], ser[3], par[2], lay[1], par[0]]
+    sizes = [500, 300, 200, 64, 1, 100, 200]
     pairs = [(G, _dev(torch, sample(dem, B, 120 + i).syndromes)) for i, ((dem, G), B) in enumerate(zip(gs, sizes))]
     want = [G.decode(s) for G, s in pairs]
     rt = P.Runtime()
     _check_same(torch, rt.decode(pairs), want)
     _check_same(torch, rt.decode(pairs[::-1])[::-1], want)
+    sl = [pairs[0], pairs[2], pairs[3], pairs[5]]
+    _check_same(torch, rt.decode(sl), [want[0], want[2], want[3], want[5]])
     rt.close()
-    for _, G in ser + par:
+    for _, G in ser + par + lay:
         G.close()
 
 
