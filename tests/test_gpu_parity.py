@@ -365,6 +365,41 @@ def test_decode_phenomenological_lsd10(torch_cuda):
     _decode_parity(torch_cuda, dem, 32, 5, 50, 3000, 4, 600, bits=64, lsd_order=10)
 
 
+def test_decode_benchmark_configuration(torch_cuda):
+    """The configuration the benchmark times, as it times it: the d = 9
+    circuit graph, L = 32, M = 5, T = 20, FP32, the benchmark's seeds and
+    all 32768 shots in one call (two launch sequences inside the library).
+    Sampled outputs against the oracle shot by shot, 32 shots spread over
+    both launch sequences, to the FP32 bar (BP-decided shots agree, other
+    differences only at rank ties); H e = s on 2048 sampled shots that LSD
+    did not flag; observables from the corrections."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    dem = circuit_dem(9, 9, 1e-3)
+    perms = permutations(dem.n, 32, 2025)
+    b = sample(dem, 32768, 2026)
+    G = P.Graph.from_dem(dem, perms, L=32, M=5, T_max=20, alpha=0.625)
+    corr, obs, st = G.decode(_dev(torch, b.syndromes))
+    st = st.cpu().numpy()
+    rng = np.random.default_rng(7)
+    pick = np.sort(rng.choice(32768, 2048, replace=False))
+    e = P.unpack_bits(corr[torch.from_numpy(pick).cuda()], dem.n)
+    rows = np.repeat(np.arange(dem.m), np.diff(dem.h_indptr))
+    ok = (st[pick, 0] & 4) == 0
+    for k in np.flatnonzero(ok):
+        syn = np.bincount(rows, weights=e[k][dem.h_indices], minlength=dem.m).astype(np.int64) % 2
+        assert np.array_equal(syn, b.syndromes[pick[k]]), pick[k]
+    lo = (e.astype(np.int64) @ dem.dense_l().T.astype(np.int64)) % 2
+    assert np.array_equal(obs.cpu().numpy()[pick], lo.astype(np.uint8))
+    sample_idx = np.sort(rng.choice(32768, 32, replace=False))
+    assert sample_idx.min() < 16384 <= sample_idx.max()
+    ref = _oracle_decode(dem, perms, b.syndromes[sample_idx], 32, 5, 20)
+    e_s = P.unpack_bits(corr[torch.from_numpy(sample_idx).cuda()], dem.n)
+    print(_tie_witness(ref, e_s, st[sample_idx], dem, 32))
+    G.close()
+
+
 def test_decode_code_capacity(torch_cuda):
     _decode_parity(torch_cuda, code_capacity_dem(5, 0.05), 16, 5, 32, 10000, 3, 10000)
 
