@@ -400,6 +400,18 @@ def test_decode_benchmark_configuration(torch_cuda):
     G.close()
 
 
+def test_maximum_ensemble_and_iterations(torch_cuda):
+    """The limits: L = 64 members (member 63 uses the top bit of the
+    per-iteration convergence masks), M = 64, T = 64 iterations.  FP64 BP
+    members bit-identical to the oracle over all 64 iterations, and whole
+    FP64 decodes identical to the oracle's decoder; also M = 1 with L = 64."""
+    dem = code_capacity_dem(5, 0.1)
+    _bp_parity(torch_cuda, dem, 64, 64, 3, 131, stop=False, bits=64)
+    for M, seed in ((64, 132), (1, 133)):
+        agree = _decode_parity(torch_cuda, dem, 64, M, 64, 1500, seed, 1500, bits=64)
+        assert agree >= 0.999
+
+
 def test_decode_code_capacity(torch_cuda):
     _decode_parity(torch_cuda, code_capacity_dem(5, 0.05), 16, 5, 32, 10000, 3, 10000)
 
