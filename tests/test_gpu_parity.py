@@ -491,6 +491,38 @@ def test_decode_zero_and_empty(torch_cuda):
     G.close()
 
 
+def test_priors_above_half_and_unchecked_columns(torch_cuda):
+    """Priors above 1/2 (negative channel LLRs: the zero-syndrome shortcut
+    is off) and columns with no check at all (a member decides them by
+    their prior alone): FP64 members bit-identical to the oracle, whole
+    FP64 decodes identical, and the zero syndrome decoded as the oracle
+    does."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    base = code_capacity_dem(5, 0.05)
+    H = np.concatenate([base.dense_h(), np.zeros((base.m, 2), np.uint8)], axis=1)  # two unchecked columns
+    rng = np.random.default_rng(141)
+    pri = rng.uniform(0.02, 0.3, H.shape[1])
+    pri[[2, 7, 19]] = [0.6, 0.75, 0.55]  # one unchecked column above 1/2, two checked ones
+    lobs = np.concatenate([base.dense_l(), np.zeros((base.dense_l().shape[0], 2), np.uint8)], axis=1)
+    dem = dem_from_dense(H, pri, lobs)
+    _bp_parity(torch, dem, 8, 20, 30, 142, stop=True, bits=64)
+    _bp_parity(torch, dem, 8, 6, 10, 143, stop=False, bits=64)
+    agree = _decode_parity(torch, dem, 16, 5, 32, 3000, 144, 3000, bits=64)
+    assert agree >= 0.999
+    G, perms = _graph(dem, 16, 5, 32, 145, message_bits=64)
+    z = np.zeros((3, dem.m), np.uint8)
+    corr, _, st = G.decode(_dev(torch, z))
+    e, st = P.unpack_bits(corr, dem.n), st.cpu().numpy()
+    ref = _oracle_decode(dem, perms, z, 16, 5, 32)
+    # here no member satisfies s = 0 (columns 2 and 7 decide 1), so LSD runs
+    # on a syndrome with no flipped check and returns e = 0
+    assert np.array_equal(e, ref["ehat"])
+    assert np.array_equal((st[:, 0] & 2) != 0, ref["lsd_used"])
+    G.close()
+
+
 def test_invalid_arguments_rejected(torch_cuda):
     import paper_2508_15743_amd as P
 
