@@ -1,4 +1,4 @@
-// K3: LSD-0 post-processing (paper Sec. III.C), one wavefront per shot.
+// K3: LSD post-processing (paper Sec. III.C; order 0 and higher), one wavefront per shot.
 //
 // Clusters start as the flipped checks.  In every round each cluster that is
 // still invalid adds its best boundary column (lowest soft value, then lowest
