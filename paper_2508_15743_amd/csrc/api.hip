@@ -190,7 +190,10 @@ int check_common(vibe_graph* G, const void* synd, uint64_t B) {
 }
 
 uint32_t chunk_for(const DevGraph& g, uint64_t B, bool decode) {
-    const size_t budget = 4ull << 30;  // workspace of the per-chunk buffers
+    // workspace of the per-chunk buffers: 8 GB holds ~40k shots of the d = 9
+    // circuit graph, so a 32768-shot batch is one persistent launch (each
+    // launch ends in a tail of long items)
+    const size_t budget = 8ull << 30;
     uint64_t bc = budget / per_shot_bytes(g, decode);
     bc = std::max<uint64_t>(256, std::min<uint64_t>(bc, 65536));
     bc = std::min<uint64_t>(bc, (uint64_t)UINT32_MAX / std::max<uint32_t>(g.L, 1));

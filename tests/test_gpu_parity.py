@@ -368,9 +368,8 @@ def test_decode_phenomenological_lsd10(torch_cuda):
 def test_decode_benchmark_configuration(torch_cuda):
     """The configuration the benchmark times, as it times it: the d = 9
     circuit graph, L = 32, M = 5, T = 20, FP32, the benchmark's seeds and
-    all 32768 shots in one call (two launch sequences inside the library).
-    Sampled outputs against the oracle shot by shot, 32 shots spread over
-    both launch sequences, to the FP32 bar (BP-decided shots agree, other
+    all 32768 shots in one call.  Sampled outputs against the oracle shot by
+    shot, 32 shots spread over the batch, to the FP32 bar (BP-decided shots agree, other
     differences only at rank ties); H e = s on 2048 sampled shots that LSD
     did not flag; observables from the corrections."""
     import paper_2508_15743_amd as P
