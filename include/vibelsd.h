@@ -332,7 +332,9 @@ void vibe_server_destroy(vibe_server* s); /* finishes every queued request first
  * (a piecewise-smooth function).  Deterministic: the same inputs give the
  * same bits.  syndromes: device, B x m bytes, row-major.
  * Limits: 1 <= K <= 64, B >= 1, B x L <= 2^24, 0 < eps < 0.5, fewer than
- * 2^24 - 1 edges; VIBE_EINVAL / VIBE_EUNSUPPORTED otherwise.  The first call
+ * 2^24 - 1 edges, and a per-wavefront row state that fits in 160 KB of LDS
+ * (24 bytes per check in FP32, 36 in FP64, per shot of the wavefront: up
+ * to ~6700 checks in FP32); VIBE_EINVAL / VIBE_EUNSUPPORTED otherwise.  The first call
  * on a graph builds its gradient schedule (device memory freed with the
  * graph); every call may grow the graph's workspace, like vibe_decode.
  * Calls on one graph must not overlap.
