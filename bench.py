@@ -15,7 +15,8 @@ arrivals at 0.5x and 0.8x the sustained rate, p50/p99 latency); a ragged
 batch of circuit-level codes at d = 5..13 (rounds = d) decoded as one call
 against one call per code;
 the phenomenological workload (d = 11, 11 rounds, L = 32, T = 50) with
-LSD-0 and with LSD order 10; fitting the channel LLRs and scaling factor
+LSD-0 and with LSD order 10; the code-capacity workload (d = 5, 10^4 shots)
+with its BP edge-update rate; fitting the channel LLRs and scaling factor
 with the differentiable decoder (d = 5 circuit-level), fitted against
 untuned decoder on held-out shots; the backward pass of the differentiable decoder (16 unrolled iterations of
 the d = 5 circuit-level graph, 4096 shots, L = 32, FP32) with its own
@@ -147,9 +148,45 @@ def phenom_leg(P, torch, seed, shots):
         out[f"lsd{order}"] = {"shots_per_s": round(shots / dt, 1),
                               "lsd_fraction": round(float(((st[:, 0] & 2) != 0).mean()), 5),
                               "lsd_kernel_ms": round(prof["lsd"][0], 3),
+                              "bp_kernel_ms": round(prof["bp_ensemble"][0], 3),
+                              "edge_updates_per_s": float(st[:, 7].astype(np.int64).sum()) * dem.nnz
+                              / max(prof["bp_ensemble"][0] / 1e3, 1e-9),
                               "logical_error_rate": float((obs.cpu().numpy() != b.observables).any(1).mean())}
         log(f"phenomenological LSD-{order}: {shots / dt:.0f} shots/s, LSD kernel {prof['lsd'][0]:.1f} ms")
     out["corrections_changed_by_order10"] = int((corr[0] != corr[10]).any(1).sum())
+    return out
+
+
+def code_capacity_leg(P, torch, seed, shots=10000):
+    """The code-capacity workload as configured (colour code d = 5, p = 0.05,
+    10^4 shots; L = 16, M = 5, T = 32, FP32).  Its message slab lives in LDS,
+    so the bound is LDS and issue, not HBM: edge-updates/s and the slab
+    bytes they move through LDS (16 B per edge-update) are reported."""
+    from synth.dem import code_capacity_dem
+    from synth.sample import permutations, sample
+
+    dem = code_capacity_dem(5, 0.05)
+    b = sample(dem, shots, seed + 11)
+    synd = torch.from_numpy(b.syndromes).to("cuda:0")
+    G = P.Graph.from_dem(dem, permutations(dem.n, 16, seed + 10), L=16, M=5, T_max=32)
+    G.decode(synd[:256])
+    torch.cuda.synchronize()
+    P.vibe_profile_enable(G.handle, True)
+    P.vibe_profile_read(G.handle)
+    t1 = time.perf_counter()
+    _, obs, st = G.decode(synd)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    prof = P.vibe_profile_read(G.handle)
+    G.close()
+    st = st.cpu().numpy()
+    eu = float(st[:, 7].astype(np.int64).sum()) * dem.nnz / max(prof["bp_ensemble"][0] / 1e3, 1e-9)
+    out = {"workload": dem.name, "m": dem.m, "n": dem.n, "nnz": dem.nnz, "shots": shots,
+           "shots_per_s": round(shots / dt, 1), "bp_kernel_ms": round(prof["bp_ensemble"][0], 3),
+           "edge_updates_per_s": eu, "lds_slab_bytes_per_s": 16.0 * eu,
+           "lsd_fraction": round(float(((st[:, 0] & 2) != 0).mean()), 5),
+           "logical_error_rate": float((obs.cpu().numpy() != b.observables).any(1).mean())}
+    log(f"code capacity: {shots / dt:.0f} shots/s, {eu:.3g} edge-updates/s")
     return out
 
 
@@ -529,6 +566,7 @@ def main():
         result["grad"] = grad_leg(P, torch, args.seed, args.grad_batch, args.grad_K)
     if not args.no_phenom:
         result["phenomenological"] = phenom_leg(P, torch, args.seed, args.phenom_shots)
+        result["code_capacity"] = code_capacity_leg(P, torch, args.seed)
     if not args.no_tune:
         result["tuning"] = tuning_leg(P, torch, args.seed)
 
