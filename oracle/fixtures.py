@@ -1,0 +1,174 @@
+"""Writes the oracle's per-shot results for the benchmark workloads to
+tests/golden/, so that GPU tests can compare tens of thousands of shots
+shot by shot without running the oracle for hours on the GPU machine.
+
+TEST INFRASTRUCTURE ONLY.  Calls the FP64 oracle (vibelsd_oracle.c through
+oracle.py) on inputs from synth/ and nothing else.
+
+Workloads (the decoder settings of the workload list):
+  circuit_d9   circuit-level colour code d = 9, 9 rounds, Uniform p = 1e-3;
+               L = 32, M = 5, T = 20, alpha = 0.625, LSD-0; permutations
+               seed 2025, the first `shots` of the 32768-shot batch of seed
+               2026 (the benchmark's inputs)
+  phenom_d11   phenomenological colour code d = 11, 11 noisy rounds and a
+               perfect one, p = q = 0.01; L = 32, M = 5, T = 50, alpha =
+               0.625, LSD order 10; permutations seed 2030, 10^5 shots of
+               seed 2031
+
+Per shot it stores a digest of the correction (and, for the circuit
+workload, its set bits), the observables, the flags, the winning member,
+the LSD statistics and the tie witnesses: the smallest |L_v| of any decision
+any member took, the smallest gap between soft values of any LSD rank
+decision, and the weight gap between the chosen candidate and the next.
+
+Usage: python -m oracle.fixtures circuit_d9 --shots 10000 --threads 6
+Long runs save progress every chunk and resume from it.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+WORKLOADS = {
+    "circuit_d9": dict(kind="circuit", d=9, rounds=9, p=1e-3, L=32, M=5, T=20, alpha=0.625, lsd_order=0,
+                       perm_seed=2025, sample_seed=2026, batch=32768, shots=10000, indices=True),
+    "phenom_d11": dict(kind="phenom", d=11, rounds=11, p=0.01, q=0.01, L=32, M=5, T=50, alpha=0.625,
+                       lsd_order=10, perm_seed=2030, sample_seed=2031, batch=100000, shots=100000,
+                       indices=False),
+}
+
+
+def ehat_digest(ehat: np.ndarray) -> np.ndarray:
+    """64-bit digest of each row of a 0/1 matrix [B, n] (blake2b of the
+    little-endian bit-packed row), as uint64."""
+    e = np.ascontiguousarray(np.atleast_2d(ehat), dtype=np.uint8)
+    packed = np.packbits(e, axis=1, bitorder="little")
+    out = np.empty(e.shape[0], np.uint64)
+    for i in range(e.shape[0]):
+        out[i] = int.from_bytes(hashlib.blake2b(packed[i].tobytes(), digest_size=8).digest(), "little")
+    return out
+
+
+def array_digest(a: np.ndarray) -> str:
+    a = np.ascontiguousarray(a)
+    return hashlib.sha256(a.tobytes() + str(a.dtype).encode() + str(a.shape).encode()).hexdigest()[:32]
+
+
+def workload_inputs(name: str, shots: int | None = None):
+    """(dem, perms, batch, spec) of a workload; the batch holds the first
+    `shots` shots of the workload's full batch."""
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    from synth.dem import circuit_dem, phenomenological_dem
+    from synth.sample import permutations, sample
+
+    w = WORKLOADS[name]
+    if w["kind"] == "circuit":
+        dem = circuit_dem(w["d"], w["rounds"], w["p"])
+    else:
+        dem = phenomenological_dem(w["d"], w["rounds"], w["p"], w["q"])
+    perms = permutations(dem.n, w["L"], w["perm_seed"])
+    b = sample(dem, w["batch"], w["sample_seed"])
+    n = w["shots"] if shots is None else shots
+    return dem, perms, b, n
+
+
+def path_for(name: str) -> str:
+    return os.path.join(GOLDEN, f"oracle_{name}.npz")
+
+
+def run(name: str, shots: int | None, threads: int, chunk: int) -> str:
+    from oracle import oracle as O
+
+    w = WORKLOADS[name]
+    dem, perms, b, n = workload_inputs(name, shots)
+    g = O.OracleGraph(dem)
+    part = path_for(name) + ".partial.npz"
+    done = 0
+    acc = {k: [] for k in ("digest", "weight", "obs", "rec", "idx_len", "idx")}
+    if os.path.exists(part):
+        z = np.load(part)
+        if int(z["n_target"]) == n:
+            done = int(z["done"])
+            for k in acc:
+                acc[k] = [z[k]]
+            print(f"{name}: resuming at {done} of {n}", flush=True)
+    t0 = time.time()
+    while done < n:
+        hi = min(n, done + chunk)
+        r = O.decode(g, perms, b.syndromes[done:hi], L=w["L"], M=w["M"], T=w["T"], alpha=w["alpha"],
+                     threads=threads, lsd_order=w["lsd_order"])
+        e = r["ehat"]
+        acc["digest"].append(ehat_digest(e))
+        acc["weight"].append(e.sum(1).astype(np.uint32))
+        acc["obs"].append(r["obs"])
+        acc["rec"].append(r["rec"])
+        nz = [np.flatnonzero(row).astype(np.uint32) for row in e]
+        acc["idx_len"].append(np.array([len(x) for x in nz], np.uint32))
+        acc["idx"].append(np.concatenate(nz) if nz else np.zeros(0, np.uint32))
+        done = hi
+        cat = {k: np.concatenate(v) for k, v in acc.items()}
+        acc = {k: [v] for k, v in cat.items()}
+        np.savez(part, n_target=n, done=done, **cat)
+        print(f"{name}: {done}/{n} shots, {time.time() - t0:.0f} s", flush=True)
+    cat = {k: np.concatenate(v) for k, v in acc.items()}
+    rec = cat["rec"]
+    meta = dict(w, workload=dem.name, m=dem.m, n=dem.n, nnz=dem.nnz, shots=n,
+                syndromes_sha=array_digest(b.syndromes[:n]), perms_sha=array_digest(perms),
+                observables_sha=array_digest(b.observables[:n]))
+    out = dict(
+        meta=np.array(json.dumps(meta)),
+        ehat_digest=cat["digest"],
+        ehat_weight=cat["weight"],
+        obs=cat["obs"].astype(np.uint8),
+        flags=rec[:, 0].astype(np.uint8),
+        winner=rec[:, 1].astype(np.int16),
+        t_win=rec[:, 2].astype(np.uint8),
+        lsd_clusters=rec[:, 4].astype(np.uint32),
+        lsd_largest=rec[:, 5].astype(np.uint32),
+        lsd_rounds=rec[:, 6].astype(np.uint32),
+        min_abs_post=rec[:, 7],
+        min_q_gap=rec[:, 8],
+        w_gap=rec[:, 10],
+    )
+    if w["indices"]:
+        out["ehat_indptr"] = np.concatenate(([0], np.cumsum(cat["idx_len"]))).astype(np.uint32)
+        out["ehat_indices"] = cat["idx"].astype(np.uint16 if dem.n < 65536 else np.uint32)
+    os.makedirs(GOLDEN, exist_ok=True)
+    dst = path_for(name)
+    np.savez_compressed(dst, **out)
+    os.remove(part)
+    print(f"{name}: wrote {dst} ({os.path.getsize(dst)} bytes) in {time.time() - t0:.0f} s", flush=True)
+    return dst
+
+
+def load(name: str) -> dict:
+    """The stored results of a workload (plain arrays; meta as a dict)."""
+    z = np.load(path_for(name))
+    out = {k: z[k] for k in z.files}
+    out["meta"] = json.loads(str(out["meta"]))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("workload", choices=sorted(WORKLOADS))
+    ap.add_argument("--shots", type=int, default=None)
+    ap.add_argument("--threads", type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument("--chunk", type=int, default=240)
+    a = ap.parse_args()
+    run(a.workload, a.shots, a.threads, a.chunk)
+
+
+if __name__ == "__main__":
+    main()

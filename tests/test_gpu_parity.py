@@ -4,28 +4,32 @@ The device runs BP in FP32 (production) or FP64 (message_bits = 64, the
 oracle's precision and operation order).  Bars:
   * FP64 BP, per member: convergence iteration, hard decision and every
     posterior bit-identical to the oracle.
-  * FP32 BP, per member: the convergence iteration and the hard decision are
-    identical; the final posteriors agree to 1e-4 of the largest posterior
-    magnitude of that member.  Rounding in FP32 sums of <= 16 terms adds
-    about 2^-24 of the largest term per operation; over <= 50 iterations of
-    min-sum, which is 1-Lipschitz in its inputs apart from the alpha and
-    column-degree factors that also scale the magnitudes, that stays near
-    1e-6 of the largest magnitude, so 1e-4 leaves two decades of margin.
-    Members with a decision within 1e-3 of zero are skipped (either side
-    of zero is within FP32 error there).
+  * FP32 BP, per (shot, member), elementwise: every posterior within
+    1e-4 * max(|L_v|, 1) of the oracle's L_v, and the hard decision equal on
+    every column whose |L_v| is at least 1e-3.  Min-sum is continuous in its
+    inputs (min, clamp and the signed minimum of a row are continuous), so
+    FP32 and FP64 trajectories part only at a discrete event: a member that
+    converges at another iteration, which needs a decision within rounding
+    of zero somewhere before.  A (shot, member) pair whose convergence
+    iteration differs is excused only if the oracle's decision witness
+    (smallest |L_v| of any decision the member took) is below 1e-3; at
+    least 90% of the pairs must be compared, and the counts are printed.
   * LSD on identical soft input: bit-exact corrections and cluster stats.
   * whole decoder, FP64: identical corrections on >= 99.9% of shots (the
     normalised average is summed in a different order, so only exact
     mathematical ties between soft values can order differently).
-  * whole decoder, FP32: H e = s on every shot LSD did not flag, agreement
-    with the oracle no worse than the oracle's agreement with itself when
-    the priors move by 1e-6 relative (a perturbation of the size of FP32
-    rounding; workloads with uniform priors have exact ties that any
-    rounding breaks), within a 3-sigma binomial margin; the logical error
-    rate lies in the oracle's 95% interval.  Shots a BP member decides agree
-    on >= 99.9%, and every other disagreement is an LSD shot at a rank tie
-    (a gap below 1e-3 of the normalised average's scale) in the oracle's
-    own decode.
+  * whole decoder, FP32 (the tolerance of the online stage, Sec. III.D.2,
+    read as: >= 99.9% of the shots that are not at a tie agree, and every
+    disagreement is at a tie): H e = s on every shot LSD did not flag;
+    shots a BP member decides (on either side) agree on >= 99.9%; every
+    other disagreement is an LSD shot whose oracle decode took a rank
+    decision at a gap below 1e-3 of the normalised average's RMS scale
+    L / sqrt(n); the agreement over the shots that are not excused this way
+    is >= 99.9%, and the overall agreement and the number of excused shots
+    are printed beside the 99.9% figure; the logical error rate lies in the
+    oracle's 95% interval.  Agreement no worse than the oracle's own when its
+    priors move by 1e-6 relative is checked as well (a perturbation of the
+    size of FP32 rounding).
 """
 import os
 
@@ -64,6 +68,33 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
+def _member_bar(r, tc, post, eh, tally, where):
+    """The FP32 bar of one (shot, member) pair against the oracle's run r."""
+    if r["t_conv"] != tc:
+        # a discrete event: only at a decision within rounding of zero
+        assert r["min_abs_post"] < 1e-3, (where, r["t_conv"], tc, r["min_abs_post"])
+        tally["excused"] += 1
+        return
+    ref = r["post"]
+    err = np.abs(post.astype(np.float64) - ref)
+    bar = 1e-4 * np.maximum(np.abs(ref), 1.0)
+    assert (err <= bar).all(), (where, int(np.argmax(err / bar)), float((err / bar).max()))
+    firm = np.abs(ref) >= 1e-3
+    assert np.array_equal(r["ehat"][firm], eh[firm]), where
+    tally["compared"] += 1
+    tally["max_rel"] = max(tally["max_rel"], float((err / np.maximum(np.abs(ref), 1.0)).max()))
+
+
+def _tally_report(tally, what):
+    total = tally["compared"] + tally["excused"]
+    if total == 0:
+        return
+    print(f"{what}: {tally['compared']} of {total} (shot, member) pairs compared elementwise, "
+          f"{tally['excused']} excused at a decision witness < 1e-3; largest |d L| / max(|L|, 1) "
+          f"{tally['max_rel']:.3g}")
+    assert tally["compared"] >= 0.9 * total, tally
+
+
 def _bp_parity(torch, dem, L, T, shots, seed, stop, bits=32, schedule="serial", alpha=None):
     import paper_2508_15743_amd as P
 
@@ -76,6 +107,7 @@ def _bp_parity(torch, dem, L, T, shots, seed, stop, bits=32, schedule="serial", 
     tc, post, eh = G.bp_ensemble(_dev(torch, b.syndromes), T_run=T, stop=stop)
     tc, post, eh = tc.cpu().numpy(), post.cpu().numpy(), P.unpack_bits(eh, dem.n)
     g = O.OracleGraph(dem)
+    tally = {"compared": 0, "excused": 0, "max_rel": 0.0}
     for i in range(shots):
         for j in range(L):
             r = O.bp(g, b.syndromes[i], perm=perms[j] if schedule == "serial" else None, T=T, stop=stop,
@@ -85,13 +117,8 @@ def _bp_parity(torch, dem, L, T, shots, seed, stop, bits=32, schedule="serial", 
                 assert np.array_equal(r["ehat"], eh[i, j]), (i, j)
                 assert np.array_equal(r["post"], post[i, j]), (i, j, np.abs(r["post"] - post[i, j]).max())
                 continue
-            if r["min_abs_post"] < 1e-3:
-                continue  # a decision within FP32 error of zero
-            assert r["t_conv"] == tc[i, j], (i, j)
-            assert np.array_equal(r["ehat"], eh[i, j]), (i, j)
-            scale = max(np.abs(r["post"]).max(), 1.0)
-            err = np.abs(post[i, j].astype(np.float64) - r["post"]).max()
-            assert err <= 1e-4 * scale, (i, j, err, scale)
+            _member_bar(r, tc[i, j], post[i, j], eh[i, j], tally, (i, j))
+    _tally_report(tally, f"{dem.name} {schedule} FP{bits} members")
     G.close()
 
 
@@ -295,26 +322,38 @@ def _oracle_decode(dem, perms, synd, L, M, T, priors=None, schedule="serial", ls
     return O.decode(g, perms, synd, L=L, M=M, T=T, threads=NT, schedule=schedule, lsd_order=lsd_order)
 
 
-def _tie_witness(ref, e, st, dem, L):
-    """The FP32 bar on whole decodes: shots that a BP member decides (on
-    either side) agree with the oracle on >= 99.9%, and every other
-    disagreement sits at a tie.  Such a shot reaches LSD on both sides, and
-    among the oracle's own LSD rank decisions (which column a cluster takes
-    next, the order of a cluster's columns) one has a gap below 1e-3 of the
-    RMS scale of the normalised average, L / sqrt(n): FP32 posteriors, which
-    agree with FP64 to ~1e-6 relative, can order such a pair either way."""
-    n = len(ref["ehat"])
-    agree = (ref["ehat"] == e[:n]).all(1)
-    gpu_lsd = (st[:n, 0] & 2) != 0
-    bp_dec = ~ref["lsd_used"] | ~gpu_lsd
+def _fp32_decode_bar(agree, ref_lsd, gpu_lsd, min_q_gap, L, n_cols):
+    """The FP32 bar on whole decodes, per shot: agree (corrections equal),
+    ref_lsd / gpu_lsd (LSD ran on the oracle / the GPU), min_q_gap (the
+    oracle's rank-decision witness).  Shots a BP member decides (on either
+    side) agree on >= 99.9%.  Every other disagreement sits at a tie: the
+    shot reaches LSD on both sides and among the oracle's own LSD rank
+    decisions (which column a cluster takes next, the order of a cluster's
+    columns) one has a gap below 1e-3 of the RMS scale of the normalised
+    average, L / sqrt(n); FP32 posteriors, which agree with FP64 to ~1e-6
+    relative, can order such a pair either way.  Over the shots that are
+    not at such a tie, agreement is >= 99.9%.  Returns the report line."""
+    agree = np.asarray(agree, bool)
+    bp_dec = ~np.asarray(ref_lsd, bool) | ~np.asarray(gpu_lsd, bool)
+    dq = 1e-3 * L / np.sqrt(n_cols)
+    tie = ~bp_dec & (np.asarray(min_q_gap) < dq)
     if bp_dec.any():
         assert agree[bp_dec].mean() >= 0.999, (agree[bp_dec].mean(), np.flatnonzero(bp_dec & ~agree)[:10])
-    dq = 1e-3 * L / np.sqrt(dem.n)
     rest = ~agree & ~bp_dec
-    assert (ref["min_q_gap"][rest] < dq).all(), (np.flatnonzero(rest), ref["min_q_gap"][rest], dq)
-    return (f"BP-decided {agree[bp_dec].mean() if bp_dec.any() else 1.0:.5f} of {int(bp_dec.sum())}; "
-            f"{int(rest.sum())} LSD disagreements, largest rank gap "
-            f"{ref['min_q_gap'][rest].max() if rest.any() else 0.0:.3g} < {dq:.3g}")
+    assert (min_q_gap[rest] < dq).all(), (np.flatnonzero(rest & (min_q_gap >= dq))[:10], dq)
+    firm = ~tie
+    if firm.any():
+        assert agree[firm].mean() >= 0.999, (agree[firm].mean(), np.flatnonzero(firm & ~agree)[:10])
+    return (f"overall agreement {agree.mean():.5f} of {len(agree)} (target 0.999); "
+            f"{agree[firm].mean() if firm.any() else 1.0:.5f} of the {int(firm.sum())} shots not at a tie; "
+            f"{int(tie.sum())} shots at an LSD rank tie (gap < {dq:.3g}), {int((tie & ~agree).sum())} of them "
+            f"differ; BP-decided {agree[bp_dec].mean() if bp_dec.any() else 1.0:.5f} of {int(bp_dec.sum())}")
+
+
+def _tie_witness(ref, e, st, dem, L):
+    n = len(ref["ehat"])
+    agree = (ref["ehat"] == e[:n]).all(1)
+    return _fp32_decode_bar(agree, ref["lsd_used"], (st[:n, 0] & 2) != 0, ref["min_q_gap"], L, dem.n)
 
 
 def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots, bits=32, schedule="serial", lsd_order=0):
@@ -625,6 +664,7 @@ def _bp_parity_layered(torch, dem, L, T, shots, seed, stop, bits):
     tc, post, eh = G.bp_ensemble(_dev(torch, b.syndromes), T_run=T, stop=stop)
     tc, post, eh = tc.cpu().numpy(), post.cpu().numpy(), P.unpack_bits(eh, dem.n)
     g = O.OracleGraph(dem)
+    tally = {"compared": 0, "excused": 0, "max_rel": 0.0}
     for i in range(shots):
         for j in range(L):
             r = O.bp_layered(g, b.syndromes[i], cperms[j], T=T, stop=stop)
@@ -633,12 +673,8 @@ def _bp_parity_layered(torch, dem, L, T, shots, seed, stop, bits):
                 assert np.array_equal(r["ehat"], eh[i, j]), (i, j)
                 assert np.array_equal(r["post"], post[i, j]), (i, j, np.abs(r["post"] - post[i, j]).max())
                 continue
-            if r["min_abs_post"] < 1e-3:
-                continue
-            assert r["t_conv"] == tc[i, j], (i, j)
-            assert np.array_equal(r["ehat"], eh[i, j]), (i, j)
-            scale = max(np.abs(r["post"]).max(), 1.0)
-            assert np.abs(post[i, j].astype(np.float64) - r["post"]).max() <= 1e-4 * scale
+            _member_bar(r, tc[i, j], post[i, j], eh[i, j], tally, (i, j))
+    _tally_report(tally, f"{dem.name} layered FP{bits} members")
     G.close()
 
 
