@@ -206,6 +206,30 @@ int vibe_decode_plain(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint6
                       uint8_t* observables, vibe_shot_stats* stats, void* stream);
 
 /*
+ * vibe_decode for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as vibe_decode; the outputs equal
+ * vibe_decode's on the same syndromes (every field but the timing-dependent
+ * n_conv and member_iters of the stats).  Every buffer beyond the caller's
+ * inputs and outputs is carved from one static device array of
+ * VIBE_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs
+ * on until the process ends; the call allocates nothing (no hipMalloc, no
+ * events: kernel timing of vibe_profile_enable is not recorded).  The batch
+ * is decoded in chunks of shots whose buffers fit the array, with a BP grid
+ * cut to fit as well, so large graphs run with fewer resident wavefronts
+ * than vibe_decode.  VIBE_EUNSUPPORTED (with nothing queued) when not even
+ * one shot of the graph fits the array.  The packed input of
+ * vibe_decode_packed is not offered here.  Every call on one device shares
+ * that device's array, and each call overwrites it: calls that overlap in
+ * time on one device (on any handles or streams) race and must not be
+ * made.  The array is set up on the first call on each device (with the
+ * graph's device made current for the lookup).
+ */
+#define VIBE_NOALLOC_SCRATCH_BYTES ((uint64_t)256 << 20)
+int vibe_decode_noalloc(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint64_t* corrections,
+                        uint8_t* observables, vibe_shot_stats* stats, void* stream);
+
+/*
  * The BP ensemble alone (Algorithm 1, serial-V, every member), for B shots,
  * without the correction limit: every member runs until its own hard
  * decision satisfies the syndrome (if stop_on_converge) or for exactly

@@ -65,6 +65,8 @@ EXPORTS = {
                               C.c_void_p, C.c_void_p]),
     "vibe_decode_packed": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p]),
+    "vibe_decode_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p]),
     "vibe_graph_get_schedules": (C.c_int, [C.c_void_p, C.c_void_p]),
     "vibe_graph_set_alpha": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32]),
     "vibe_decode_plain": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
@@ -177,6 +179,11 @@ def vibe_graph_get_schedules(handle, L, length) -> np.ndarray:
     out = np.zeros((L, length), dtype=np.uint32)
     _check(lib().vibe_graph_get_schedules(handle, out.ctypes.data))
     return out
+
+
+def vibe_decode_noalloc(handle, syndromes, B, corrections, observables, stats, stream):
+    _check(lib().vibe_decode_noalloc(handle, _ptr(syndromes), B, _ptr(corrections), _ptr(observables),
+                                     _ptr(stats), stream))
 
 
 def vibe_decode_plain(handle, syndromes, B, corrections, observables, stats, stream):
@@ -322,8 +329,11 @@ class Graph:
             raise ValueError("syndromes must be a device tensor")
         return syndromes.contiguous()
 
-    def decode(self, syndromes, plain=False, with_stats=True, stream=None, out=None):
-        """-> (corrections int64 [B, words], observables uint8 [B, k], stats int32 [B, 8])"""
+    def decode(self, syndromes, plain=False, with_stats=True, stream=None, out=None, noalloc=False):
+        """-> (corrections int64 [B, words], observables uint8 [B, k], stats int32 [B, 8]).
+        plain: one launch sequence per shot (vibe_decode_plain); noalloc: the
+        library allocates nothing (vibe_decode_noalloc; pass `out` too for a
+        call that allocates no device memory at all)."""
         import torch
         s = self._synd(syndromes)
         B = s.shape[0]
@@ -334,7 +344,7 @@ class Graph:
             st = torch.empty((B, 8), dtype=torch.int32, device=dev) if with_stats else None
         else:
             corr, obs, st = out
-        fn = vibe_decode_plain if plain else vibe_decode
+        fn = vibe_decode_plain if plain else (vibe_decode_noalloc if noalloc else vibe_decode)
         fn(self.handle, s, B, corr, obs, st, _stream(stream))
         return corr, obs, st
 

@@ -7,6 +7,8 @@
 // K3 (LSD-0 on the queued shots); then K4 (observables) over the whole batch.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 #include "internal.h"
 
@@ -54,13 +56,13 @@ int ensure_workspace(vibe_graph* G, size_t bytes) {
     return VIBE_OK;
 }
 
-// Carve the workspace for chunks of up to `bc` shots.
+// Sizes of the per-chunk buffers for chunks of up to `bc` shots.
 // slab_blocks: blocks that need a message slab in global memory (0 when the
 // slab lives in LDS); post_blocks: blocks of the BP grid (posterior slabs).
-int carve(vibe_graph* G, uint32_t bc, bool decode, int slab_blocks, int post_blocks, int lsd_grid,
-          ChunkBufs* B) {
-    const DevGraph& g = G->h.dg;
-    size_t sizes[11] = {
+constexpr int kBufs = 11;
+size_t carve_sizes(const DevGraph& g, uint32_t bc, bool decode, int slab_blocks, int post_blocks, int lsd_grid,
+                   size_t* sizes) {
+    const size_t s[kBufs] = {
         4ull * bc * g.L,                                   // t_conv
         decode ? 8ull * bc * g.L : 0,                      // weight
         decode ? 8ull * bc * g.L * g.words_n : 0,          // cand
@@ -74,12 +76,18 @@ int carve(vibe_graph* G, uint32_t bc, bool decode, int slab_blocks, int post_blo
         decode ? lsd_scratch_per_block(g) * lsd_grid : 0,  // LSD scratch
     };
     size_t total = 0;
-    for (size_t s : sizes) total += al256(s);
-    int rc = ensure_workspace(G, total);
-    if (rc) return rc;
-    unsigned char* p = static_cast<unsigned char*>(G->ws.base);
-    void* ptrs[11];
-    for (int i = 0; i < 11; i++) {
+    for (int i = 0; i < kBufs; i++) {
+        sizes[i] = s[i];
+        total += al256(s[i]);
+    }
+    return total;
+}
+
+// Point the buffers of B into memory at `base` (256-byte aligned) laid out
+// by carve_sizes.
+void carve_at(unsigned char* p, const size_t* sizes, ChunkBufs* B) {
+    void* ptrs[kBufs];
+    for (int i = 0; i < kBufs; i++) {
         ptrs[i] = sizes[i] ? p : nullptr;
         p += al256(sizes[i]);
     }
@@ -94,6 +102,17 @@ int carve(vibe_graph* G, uint32_t bc, bool decode, int slab_blocks, int post_blo
     B->slab = ptrs[8];
     B->post_slab = ptrs[9];
     B->lsd_scratch = ptrs[10];
+}
+
+// Carve the handle's workspace (grown on demand) for chunks of up to `bc`
+// shots.
+int carve(vibe_graph* G, uint32_t bc, bool decode, int slab_blocks, int post_blocks, int lsd_grid,
+          ChunkBufs* B) {
+    size_t sizes[kBufs];
+    const size_t total = carve_sizes(G->h.dg, bc, decode, slab_blocks, post_blocks, lsd_grid, sizes);
+    int rc = ensure_workspace(G, total);
+    if (rc) return rc;
+    carve_at(static_cast<unsigned char*>(G->ws.base), sizes, B);
     return VIBE_OK;
 }
 
@@ -107,7 +126,7 @@ int memset_async(void* p, size_t bytes, hipStream_t st) { return launch_zero(p, 
 // One chunk of the decoder: shots [shot0, shot0 + n).
 int decode_chunk(vibe_graph* G, const ChunkBufs& W, const uint8_t* synd, uint64_t shot0, uint32_t n,
                  uint64_t* corr, vibe_shot_stats* stats, int bp_blocks, int lsd_grid, hipStream_t st,
-                 bool in_lds) {
+                 bool in_lds, bool timed = true) {
     const DevGraph& g = G->h.dg;
     int rc;
     if ((rc = memset_async(W.cmask, 8ull * n * (kMaxT + 1), st)) ||
@@ -136,9 +155,9 @@ int decode_chunk(vibe_graph* G, const ChunkBufs& W, const uint8_t* synd, uint64_
     b.post_slab = W.post_slab;
     b.counter = W.counters;
     b.grid = (int)std::min<uint64_t>((uint64_t)bp_blocks, (uint64_t)n * g.L);
-    begin_timed(G, 0, st);
+    if (timed) begin_timed(G, 0, st);
     if ((rc = launch_bp(g, b, st))) return rc;
-    end_timed(G, 0, st);
+    if (timed) end_timed(G, 0, st);
     SelectLaunch s{};
     s.n_shots = n;
     s.shot0 = shot0;
@@ -150,9 +169,9 @@ int decode_chunk(vibe_graph* G, const ChunkBufs& W, const uint8_t* synd, uint64_
     s.stats = stats;
     s.fail_list = W.fail_list;
     s.fail_count = W.counters + 1;
-    begin_timed(G, 1, st);
+    if (timed) begin_timed(G, 1, st);
     if ((rc = launch_select(g, s, st))) return rc;
-    end_timed(G, 1, st);
+    if (timed) end_timed(G, 1, st);
     LsdLaunch l{};
     l.syndromes = synd;
     l.shot0 = shot0;
@@ -166,9 +185,9 @@ int decode_chunk(vibe_graph* G, const ChunkBufs& W, const uint8_t* synd, uint64_
     l.scratch = W.lsd_scratch;
     l.scratch_per_block = lsd_scratch_per_block(g);
     l.grid = std::min(lsd_grid, (int)n);
-    begin_timed(G, 2, st);
+    if (timed) begin_timed(G, 2, st);
     if ((rc = launch_lsd(g, l, st))) return rc;
-    end_timed(G, 2, st);
+    if (timed) end_timed(G, 2, st);
     return VIBE_OK;
 }
 
@@ -421,4 +440,102 @@ extern "C" int vibe_lsd(vibe_graph* G, const uint8_t* syndromes, const float* so
     l.scratch_per_block = per;
     l.grid = lg;
     return launch_lsd(g, l, st);
+}
+
+// ---------------------------------------------------------------------------
+// vibe_decode_noalloc: the batched decode with every buffer beyond the
+// caller's inputs and outputs carved from one static device array.  In host
+// code the array's name is only a stand-in; its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+
+namespace vibe {
+namespace {
+
+constexpr size_t kNoallocBytes = (size_t)VIBE_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch` (looked up on the first
+// call on each device, with that device current).
+int scratch_for_device(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(VIBE_EUNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        if (prev != dev && (e = hipSetDevice(dev)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev != dev) (void)hipSetDevice(prev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(VIBE_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    return VIBE_OK;
+}
+
+// A launch plan whose buffers fit `cap` bytes: BP blocks (message and
+// posterior slabs) get at most half of it, LSD blocks at most a quarter and
+// the shots of one chunk the rest.  Returns false if not even one block of
+// each and one shot fit.
+bool noalloc_plan(const DevGraph& g, bool in_lds, int full_grid, uint64_t B, size_t cap, int* bpg, int* lg,
+                  uint32_t* bc, size_t* sizes) {
+    const size_t slab = in_lds ? 0 : msg_bytes(g) * bp_slabs(g) * std::max<size_t>((size_t)g.max_chunks * kWave, 1);
+    const size_t per_block = al256(slab) + al256(msg_bytes(g) * ((size_t)g.n + kWave));
+    const size_t per_lsd = lsd_scratch_per_block(g);
+    int grid = (int)std::min<size_t>((size_t)full_grid, (cap / 2) / per_block);
+    int lsd = (int)std::min<size_t>(512, (cap / 4) / per_lsd);
+    if (grid < 1 || lsd < 1) return false;
+    const size_t fixed = carve_sizes(g, 0, true, in_lds ? 0 : grid, grid, lsd, sizes);
+    if (fixed >= cap) return false;
+    // per-shot bytes plus the 256-byte rounding of each buffer
+    const size_t per_shot = per_shot_bytes(g, true);
+    uint64_t n = (cap - fixed - 256 * kBufs) / per_shot;
+    n = std::min<uint64_t>(n, chunk_for(g, B, true));
+    if (n < 1) return false;
+    lsd = std::min<int>(lsd, (int)std::min<uint64_t>(n, 512));
+    if (carve_sizes(g, (uint32_t)n, true, in_lds ? 0 : grid, grid, lsd, sizes) > cap) return false;
+    *bpg = grid;
+    *lg = lsd;
+    *bc = (uint32_t)n;
+    return true;
+}
+
+}  // namespace
+}  // namespace vibe
+
+extern "C" int vibe_decode_noalloc(vibe_graph* G, const uint8_t* syndromes, uint64_t B, uint64_t* corrections,
+                                   uint8_t* observables, vibe_shot_stats* stats, void* stream) {
+    using namespace vibe;
+    set_error("");
+    int rc = check_common(G, syndromes, B);
+    if (rc) return rc;
+    if (B && (!corrections || (!observables && G->h.k))) return fail(VIBE_EINVAL, "an output pointer is NULL");
+    if (!B) return VIBE_OK;
+    const DevGraph& g = G->h.dg;
+    const bool in_lds = bp_slab_fits_lds(g) && G->tune_lds != 0;
+    const int full = G->tune_grid > 0 ? std::min(G->tune_grid, bp_grid(g, in_lds)) : bp_grid(g, in_lds);
+    int bpg = 0, lg = 0;
+    uint32_t bc = 0;
+    size_t sizes[kBufs];
+    if (!noalloc_plan(g, in_lds, full, B, kNoallocBytes, &bpg, &lg, &bc, sizes))
+        return fail(VIBE_EUNSUPPORTED, "the graph needs more buffer space than the " +
+                                           std::to_string(kNoallocBytes >> 20) +
+                                           " MiB static scratch of vibe_decode_noalloc holds for one shot");
+    unsigned char* base = nullptr;
+    if ((rc = scratch_for_device(G->device, &base))) return rc;
+    ChunkBufs W;
+    carve_at(base, sizes, &W);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (uint64_t s0 = 0; s0 < B; s0 += bc) {
+        const uint32_t n = (uint32_t)std::min<uint64_t>(bc, B - s0);
+        if ((rc = decode_chunk(G, W, syndromes, s0, n, corrections, stats, bpg, lg, st, in_lds, false))) return rc;
+    }
+    return launch_observables(g, corrections, 0, (uint32_t)std::min<uint64_t>(B, UINT32_MAX), observables, st);
 }
