@@ -232,6 +232,7 @@ def decode(g: OracleGraph, perms, synd, L=32, M=5, T=20, alpha=0.625, lim=1e6,
            "converged": (rec[:, 0].astype(np.int64) & 1) == 1,
            "lsd_used": (rec[:, 0].astype(np.int64) & 2) == 2,
            "lsd_failed": (rec[:, 0].astype(np.int64) & 4) == 4,
+           "saturated": (rec[:, 0].astype(np.int64) & 8) == 8,
            "winner": rec[:, 1].astype(np.int64), "t_win": rec[:, 2].astype(np.int64),
            "n_conv": rec[:, 3].astype(np.int64), "min_abs_post": rec[:, 7],
            "min_q_gap": rec[:, 8], "w_gap": rec[:, 10]}

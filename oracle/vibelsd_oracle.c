@@ -65,6 +65,14 @@ static double clamp_sig(double x, double lim, uint64_t *sig) {
     return x;
 }
 
+/* clampd that also records (in *hit, if non-NULL) that the result reached
+   the clamp: |result| >= lim, a message or posterior saturated at +-lim. */
+static double clamp_hit(double x, double lim, int *hit) {
+    double y = clampd(x, lim);
+    if (hit && fabs(y) >= lim) *hit = 1;
+    return y;
+}
+
 /* Check-to-variable message r_{c->v} from the current variable-to-check
    messages mu (indexed by CSR position), Algorithm 1's check update with the
    syndrome sign: (1 - 2 s_c) * alpha * prod sign * min |mu| over N(c)\v.
@@ -106,7 +114,7 @@ static double check_to_var(const ograph *g, const double *mu, const uint8_t *s, 
 static int bp_core(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci, const int *ce,
                    const double *lam, const uint8_t *s, const uint32_t *perm, int T, const double *alpha,
                    double lim, int stop_on_converge, int *t_conv, uint8_t *ehat, double *post, int *iters,
-                   double *min_abs_post, double *trace, uint64_t *sig) {
+                   double *min_abs_post, double *trace, uint64_t *sig, int *saturated) {
     ograph g = {m, n, rp, ri, cp, ci, ce, sig};
     int E = rp[m];
     double *mu = (double *)malloc(sizeof(double) * (E ? E : 1));
@@ -135,12 +143,12 @@ static int bp_core(int m, int n, const int *rp, const int *ri, const int *cp, co
                     rv[j] = check_to_var(&g, mu, s, ci[j], v, a, lim);
                 double L = lv;
                 for (int j = cp[v]; j < cp[v + 1]; j++) L += rv[j];
-                post[v] = clampd(clamp_sig(L, lim, sig), lim);
+                post[v] = clamp_hit(clamp_sig(L, lim, sig), lim, saturated);
                 for (int j = cp[v]; j < cp[v + 1]; j++) {
                     double x = lv;
                     for (int j2 = cp[v]; j2 < cp[v + 1]; j2++)
                         if (j2 != j) x += rv[j2];
-                    mu[ce[j]] = clampd(clamp_sig(x, lim, sig), lim);
+                    mu[ce[j]] = clamp_hit(clamp_sig(x, lim, sig), lim, saturated);
                 }
             }
         } else {
@@ -152,12 +160,12 @@ static int bp_core(int m, int n, const int *rp, const int *ri, const int *cp, co
                 double lv = clampd(lam[v], lim);
                 double L = lv;
                 for (int j = cp[v]; j < cp[v + 1]; j++) L += rv[j];
-                post[v] = clampd(clamp_sig(L, lim, sig), lim);
+                post[v] = clamp_hit(clamp_sig(L, lim, sig), lim, saturated);
                 for (int j = cp[v]; j < cp[v + 1]; j++) {
                     double x = lv;
                     for (int j2 = cp[v]; j2 < cp[v + 1]; j2++)
                         if (j2 != j) x += rv[j2];
-                    mu[ce[j]] = clampd(clamp_sig(x, lim, sig), lim);
+                    mu[ce[j]] = clamp_hit(clamp_sig(x, lim, sig), lim, saturated);
                 }
             }
         }
@@ -185,7 +193,7 @@ int or_bp(int m, int n, const int *rp, const int *ri, const int *cp, const int *
           double lim, int stop_on_converge, int *t_conv, uint8_t *ehat, double *post, int *iters,
           double *min_abs_post, double *trace) {
     return bp_core(m, n, rp, ri, cp, ci, ce, lam, s, perm, T, alpha, lim, stop_on_converge, t_conv, ehat,
-                   post, iters, min_abs_post, trace, NULL);
+                   post, iters, min_abs_post, trace, NULL, NULL);
 }
 
 /*
@@ -202,10 +210,10 @@ int or_bp(int m, int n, const int *rp, const int *ri, const int *cp, const int *
  * After all m checks, the posteriors are L_v clamped; the decision, the
  * convergence test and the outputs are those of or_bp.
  */
-int or_bp_layered(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci, const int *ce,
-                  const double *lam, const uint8_t *s, const uint32_t *cperm, int T, const double *alpha,
-                  double lim, int stop_on_converge, int *t_conv, uint8_t *ehat, double *post, int *iters,
-                  double *min_abs_post, double *trace) {
+static int layered_core(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci, const int *ce,
+                        const double *lam, const uint8_t *s, const uint32_t *cperm, int T, const double *alpha,
+                        double lim, int stop_on_converge, int *t_conv, uint8_t *ehat, double *post, int *iters,
+                        double *min_abs_post, double *trace, int *saturated) {
     ograph g = {m, n, rp, ri, cp, ci, ce, NULL};
     int E = rp[m];
     double *r = (double *)calloc((size_t)(E ? E : 1), sizeof(double));    /* by CSR position */
@@ -233,7 +241,7 @@ int or_bp_layered(int m, int n, const int *rp, const int *ri, const int *cp, con
             int c = (int)cperm[idx];
             for (int k = rp[c]; k < rp[c + 1]; k++) {
                 mraw[k] = Lv[ri[k]] - r[k];
-                mu[k] = clampd(mraw[k], lim);
+                mu[k] = clamp_hit(mraw[k], lim, saturated);
             }
             /* every message of the row from the same mu (check_to_var reads mu by CSR position) */
             for (int k = rp[c]; k < rp[c + 1]; k++) rn[k] = check_to_var(&g, mu, s, c, ri[k], a, lim);
@@ -243,7 +251,7 @@ int or_bp_layered(int m, int n, const int *rp, const int *ri, const int *cp, con
             }
         }
         for (int v = 0; v < n; v++) {
-            post[v] = clampd(Lv[v], lim);
+            post[v] = clamp_hit(Lv[v], lim, saturated);
             ehat[v] = post[v] <= 0.0;
             double aa = fabs(post[v]);
             if (aa < minabs) minabs = aa;
@@ -262,6 +270,14 @@ int or_bp_layered(int m, int n, const int *rp, const int *ri, const int *cp, con
     free(rn);
     free(Lv);
     return 0;
+}
+
+int or_bp_layered(int m, int n, const int *rp, const int *ri, const int *cp, const int *ci, const int *ce,
+                  const double *lam, const uint8_t *s, const uint32_t *cperm, int T, const double *alpha,
+                  double lim, int stop_on_converge, int *t_conv, uint8_t *ehat, double *post, int *iters,
+                  double *min_abs_post, double *trace) {
+    return layered_core(m, n, rp, ri, cp, ci, ce, lam, s, cperm, T, alpha, lim, stop_on_converge, t_conv, ehat,
+                        post, iters, min_abs_post, trace, NULL);
 }
 
 /*
@@ -284,7 +300,7 @@ double or_bp_loss(int m, int n, const int *rp, const int *ri, const int *cp, con
     uint8_t *e = (uint8_t *)malloc(n ? n : 1);
     int tc = 0, it = 0;
     if (sig) *sig = 0;
-    bp_core(m, n, rp, ri, cp, ci, ce, lam, s, perm, K, alpha, lim, 0, &tc, e, L, &it, NULL, NULL, sig);
+    bp_core(m, n, rp, ri, cp, ci, ce, lam, s, perm, K, alpha, lim, 0, &tc, e, L, &it, NULL, NULL, sig, NULL);
     double loss = 0.0;
     for (int c = 0; c < m; c++) {
         double prod = 1.0;
@@ -705,7 +721,9 @@ int or_lsd_key(int m, int n, const int *rp, const int *ri, const int *cp, const 
 }
 
 /* per-shot record written by or_decode_batch, 16 doubles:
-   [0] flags: bit0 BP converged, bit1 LSD used, bit2 LSD failed
+   [0] flags: bit0 BP converged, bit1 LSD used, bit2 LSD failed, bit3 saturated
+       (a message or posterior reached the clamp: in the winner's run, or
+       in any member's if LSD ran)
    [1] winning member (or -1)   [2] its convergence iteration
    [3] number of converged members
    [4] LSD clusters  [5] LSD largest cluster  [6] LSD growth rounds
@@ -738,17 +756,18 @@ static void decode_one(const odec *D, const uint8_t *s, uint8_t *ehat, uint8_t *
     rec[1] = -1;
     rec[8] = INFINITY;
     rec[10] = INFINITY;
+    int *sat = (int *)calloc(L, sizeof(int));
     for (int i = 0; i < L; i++) {
         int iters = 0;
         double mn = INFINITY;
         if (D->schedule == 2)
-            or_bp_layered(D->m, n, D->rp, D->ri, D->cp, D->ci, D->ce, D->lam, s, D->perms + (size_t)i * D->m,
-                          D->T, D->alpha, D->lim, 1, &tc[i], e + (size_t)i * n, post + (size_t)i * n, &iters, &mn,
-                          NULL);
+            layered_core(D->m, n, D->rp, D->ri, D->cp, D->ci, D->ce, D->lam, s, D->perms + (size_t)i * D->m,
+                         D->T, D->alpha, D->lim, 1, &tc[i], e + (size_t)i * n, post + (size_t)i * n, &iters, &mn,
+                         NULL, &sat[i]);
         else
-            or_bp(D->m, n, D->rp, D->ri, D->cp, D->ci, D->ce, D->lam, s,
-                  D->schedule == 0 ? D->perms + (size_t)i * n : NULL, D->T, D->alpha, D->lim, 1,
-                  &tc[i], e + (size_t)i * n, post + (size_t)i * n, &iters, &mn, NULL);
+            bp_core(D->m, n, D->rp, D->ri, D->cp, D->ci, D->ce, D->lam, s,
+                    D->schedule == 0 ? D->perms + (size_t)i * n : NULL, D->T, D->alpha, D->lim, 1,
+                    &tc[i], e + (size_t)i * n, post + (size_t)i * n, &iters, &mn, NULL, NULL, &sat[i]);
         if (mn < minabs_all) minabs_all = mn;
         if (t_members) t_members[i] = tc[i];
     }
@@ -780,7 +799,7 @@ static void decode_one(const odec *D, const uint8_t *s, uint8_t *ehat, uint8_t *
             }
         }
         memcpy(ehat, e + (size_t)best * n, (size_t)n);
-        rec[0] = 1;
+        rec[0] = 1 | (sat[best] ? 8 : 0);
         rec[1] = best;
         rec[2] = tc[best];
         rec[9] = bw;
@@ -809,7 +828,9 @@ static void decode_one(const odec *D, const uint8_t *s, uint8_t *ehat, uint8_t *
         double gap = INFINITY;
         int f = or_lsd_key(D->m, n, D->rp, D->ri, D->cp, D->ci, s, qk, D->lsd_order, D->lam, ehat, st, &gap,
                            NULL, NULL);
-        rec[0] = 2 | (f ? 4 : 0);
+        int any_sat = 0;
+        for (int i = 0; i < L; i++) any_sat |= sat[i];
+        rec[0] = 2 | (f ? 4 : 0) | (any_sat ? 8 : 0);
         rec[4] = st[0];
         rec[5] = st[1];
         rec[6] = st[2];
@@ -821,6 +842,16 @@ static void decode_one(const odec *D, const uint8_t *s, uint8_t *ehat, uint8_t *
         for (int a = D->lp[r]; a < D->lp[r + 1]; a++) par ^= ehat[D->li[a]];
         obs[r] = (uint8_t)par;
     }
+    /* a zero syndrome with every LLR positive is decided without running BP
+       (the decision e = 0 at the first iteration is certain): no saturation
+       is reported for it */
+    {
+        int zero = 1, pos = 1;
+        for (int c = 0; c < D->m; c++) zero &= s[c] == 0;
+        for (int v = 0; v < n; v++) pos &= D->lam[v] > 0.0;
+        if (zero && pos) rec[0] = (double)((int)rec[0] & ~8);
+    }
+    free(sat);
     free(e);
     free(post);
     free(tc);

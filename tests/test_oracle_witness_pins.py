@@ -161,3 +161,32 @@ def test_decode_weight_gap():
     assert out["converged"][0] and out["winner"][0] == 0 and out["t_win"][0] == 1
     assert np.flatnonzero(out["ehat"][0]).tolist() == [0]
     assert out["w_gap"][0] == 0.0
+
+
+SAT_H = np.array([[1, 0, 0], [1, 0, 0], [0, 1, 1]], np.uint8)  # v0 in two checks of degree 1
+
+
+@pytest.mark.parametrize("synd,alpha,flags", [
+    # c0 and c1 unflipped: each sends +alpha * clamp to v0, so L_0 = lambda +
+    # 1.25e6 reaches the clamp; c2 flipped cannot be met by BP (L_1, L_2 stay
+    # positive): LSD runs, and a member saturated
+    ([0, 0, 1], 0.625, 2 | 8),
+    # c0 and c1 flipped: L_0 = lambda - 1.25e6 is clamped, e_0 = 1 converges
+    # at t = 1, and the winner's run saturated
+    ([1, 1, 0], 0.625, 1 | 8),
+    # zero syndrome, every LLR positive: decided without running BP, no flag
+    ([0, 0, 0], 0.625, 1),
+    # c0 flipped, c1 not: the two saturated check messages cancel in L_0 and
+    # every mu stays at |lambda +- 6.25e5| < 1e6; LSD cannot explain c0 alone
+    ([1, 0, 0], 0.625, 2 | 4),
+    # alpha = 0.3: 2 * 0.3e6 + lambda < 1e6, nothing saturates
+    ([0, 0, 1], 0.3, 2),
+    ([1, 1, 0], 0.3, 1),
+])
+def test_saturation_flag_by_hand(synd, alpha, flags):
+    """The saturation witness (flag 8): a message or posterior reached the
+    clamp, in the winner's run or, when LSD ran, in any member's."""
+    g = _graph(SAT_H, np.full(3, 0.1))
+    perms = np.array([[0, 1, 2], [2, 1, 0]], np.uint32)
+    out = O.decode(g, perms, np.array([synd], np.uint8), L=2, M=1, T=4, alpha=alpha, threads=1)
+    assert int(out["rec"][0, 0]) == flags
