@@ -283,13 +283,15 @@ def grad_leg(P, torch, seed, batch, K):
     return res
 
 
-def serving_leg(P, torch, seed, seconds):
+def serving_leg(P, torch, seed, seconds, slots=4):
     """One-shot requests (one window of d rounds each) from circuit-level codes
     d = 9, 13, 17 mixed 50/30/20, each at p = 5e-4 or 1e-3 with equal odds
     (six resident graphs; L/M/T = 32/5/20 at d = 9, 64/7/25 above), through
-    the continuous-batching server: the sustained rate of a burst, then
-    Poisson arrivals at 0.5x and 0.8x that rate with p50/p99 latency from
-    submission to completion."""
+    the continuous-batching server (one graph per batch, each batch admitted
+    by its HBM footprint from the server's pool): the single-shot latency
+    of each code alone, the sustained rate of a burst, then Poisson arrivals
+    at 0.5x and 0.8x that rate with p50/p99 latency from submission to
+    completion, overall and per code."""
     import threading
 
     from synth.dem import circuit_dem
@@ -304,8 +306,24 @@ def serving_leg(P, torch, seed, seconds):
         graphs.append(P.Graph.from_dem(dem, permutations(dem.n, L, seed + d), L=L, M=M, T_max=T, alpha=0.625))
         pools.append(torch.from_numpy(sample(dem, 4096, seed + 300 + d + int(p * 1e4)).syndromes).to("cuda:0"))
     torch.cuda.synchronize()
+    dists = sorted({c[0] for c in cfgs})
+    # single-shot latency of each code alone (p = 1e-3 graphs, one shot per call)
+    alone = {}
+    for gi, (d, p, *_rest) in enumerate(cfgs):
+        if p != 1e-3:
+            continue
+        G = graphs[gi]
+        G.decode(pools[gi][:1])
+        torch.cuda.synchronize()
+        ts = []
+        for i in range(12):
+            t1 = time.perf_counter()
+            G.decode(pools[gi][i + 1:i + 2])
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t1))
+        alone[d] = round(float(np.median(ts)), 3)
     weights = np.array([c[5] for c in cfgs])
-    srv = P.Server(graphs, slots=3, max_batch_requests=512, max_batch_shots=1024)
+    srv = P.Server(graphs, slots=slots, max_batch_requests=512, max_batch_shots=1024)
 
     def run(n, rate):
         which = rng.choice(len(cfgs), size=n, p=weights / weights.sum())
@@ -330,22 +348,32 @@ def serving_leg(P, torch, seed, seconds):
                 time.sleep(1e-5)
             lat.append(srv.wait(tickets[i]))
         th.join()
-        return n / (time.perf_counter() - t0), np.array(lat)
+        code = np.array([cfgs[int(w)][0] for w in which])
+        return n / (time.perf_counter() - t0), np.array(lat), code
 
     run(256, 0)  # warm-up
-    sustained, lat_burst = run(3000, 0)
+    sustained, _, _ = run(3000, 0)
     res = {"codes": [f"circuit_d{d}_r{d}_p{p:g}" for d, p, *_ in cfgs], "mix": [c[5] for c in cfgs],
-           "request": "one shot", "slots": 3, "sustained_requests_per_s": round(sustained, 1), "loads": []}
+           "request": "one shot", "slots": slots, "sustained_requests_per_s": round(sustained, 1),
+           "single_shot_ms_alone": {f"d{d}": alone[d] for d in dists}, "loads": []}
     for rho in (0.5, 0.8):
         rate = rho * sustained
         n = max(200, int(rate * seconds))
-        got, lat = run(n, rate)
+        got, lat, code = run(n, rate)
+        per = {}
+        for d in dists:
+            sel = lat[code == d]
+            if sel.size:
+                per[f"d{d}"] = {"requests": int(sel.size), "p50_ms": round(float(np.percentile(sel, 50)), 3),
+                                "p99_ms": round(float(np.percentile(sel, 99)), 3),
+                                "p50_over_alone": round(float(np.percentile(sel, 50)) / alone[d], 2)}
         res["loads"].append({"offered": rho, "offered_requests_per_s": round(rate, 1),
                              "achieved_requests_per_s": round(got, 1),
                              "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                             "p99_ms": round(float(np.percentile(lat, 99)), 3)})
+                             "p99_ms": round(float(np.percentile(lat, 99)), 3), "per_code": per})
         log(f"serving at {rho:.1f}x of {sustained:.0f} req/s: p50 {np.percentile(lat, 50):.2f} ms, "
-            f"p99 {np.percentile(lat, 99):.2f} ms")
+            f"p99 {np.percentile(lat, 99):.2f} ms; " +
+            ", ".join(f"{k} p50 {v['p50_ms']:.1f} ms ({v['p50_over_alone']}x alone)" for k, v in per.items()))
     res.update(srv.info())
     srv.close()
     for G in graphs:
@@ -412,6 +440,21 @@ def main():
         print(json.dumps({"grad": grad_leg(P, torch, args.seed, args.grad_batch, args.grad_K)}), flush=True)
         return
 
+    # measured HBM ceiling: a 1 GiB device-to-device copy (read + write),
+    # timed with events on the copy's stream
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write) against the {HBM_PEAK_GBS:.0f} GB/s specification")
+
     d, rounds, p = 9, 9, 1e-3
     L, M, T, alpha = 32, 5, 20, 0.625
     t0 = time.time()
@@ -465,6 +508,7 @@ def main():
     launch_shots = max(1, B // max(1, bp_launches // args.steps))
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "measured_peak": round(copy_gbs, 1), "frac_of_measured": round(achieved / copy_gbs, 4),
                 "traffic": measured_traffic(launch_shots),
                 "kernel": "bp_ensemble_kernel",
                 "avg_launch_ms": round(bp_ms / max(bp_launches, 1), 3),

@@ -47,6 +47,12 @@ extern "C" {
 #define VIBE_FLAG_BP_CONVERGED 1u /* the correction is a converged member's */
 #define VIBE_FLAG_LSD_USED 2u     /* no member converged; LSD produced it */
 #define VIBE_FLAG_LSD_FAILED 4u   /* some cluster could not be made valid */
+#define VIBE_FLAG_SATURATED 8u    /* a message or posterior reached +-clamp: in the
+                                     winning member's run, or in any member's
+                                     run when LSD ran (members that stop early
+                                     under the correction limit are not
+                                     counted); never set for a zero syndrome
+                                     decided without running BP */
 
 typedef struct vibe_graph vibe_graph;
 
@@ -306,22 +312,30 @@ void vibe_exec_destroy(vibe_exec* ex); /* synchronises the device first; NULL ac
 int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B, void* stream, int* slab_in_lds, int* grid);
 
 /*
- * Serving: continuous batching over resident graphs.  vibe_server_submit
- * queues one request (any number of shots, up to max_batch_shots) on graph
- * graphs[graph_index] and returns at once; a server thread keeps up to
- * `slots` batches in flight, each on its own stream, and whenever a slot is
- * free launches the queued requests that fit it (first come, first served)
- * as one ragged round, so requests arriving while others run are admitted as
- * slots free up and their work overlaps on the device.  Every request's
- * outputs are exactly those of vibe_decode on it alone.  vibe_server_wait
- * blocks until the request is done and gives its latency from submission to
- * completion (host clock, ms).  The server holds slots x slot_bytes of
- * device memory from creation to destruction; creation fails with
- * VIBE_ENOMEM when that exceeds hbm_budget (0 = no limit).  A request's
- * syndromes must already be on the device when it is submitted (the
- * server's streams do not wait for the caller's), and its buffers must stay
- * valid until its wait returns.  Submit and wait may be called from any
- * thread.
+ * Serving: continuous batching over resident graphs, each request admitted
+ * by its HBM footprint.  vibe_server_submit queues one request (any number
+ * of shots, up to max_batch_shots) on graph graphs[graph_index] and returns
+ * at once.  The server owns one device pool of hbm_budget bytes (0 = room
+ * for `slots` full batches of the graph whose full batch is largest).  A
+ * server thread keeps up to `slots` batches in flight, each on its own
+ * stream; a batch holds requests on one graph, so small codes do not wait
+ * for the long serial chains of large ones, and takes a block of the pool
+ * sized by its own footprint (the decode buffers of its shots, BP slabs for
+ * a grid no larger than its work items, staging, tables).  Whenever a slot
+ * is free the thread takes the oldest queued request and, in order, the
+ * later queued requests on the same graph while the batch still fits the
+ * largest free block and the batch limits; an oldest request that does not
+ * fit yet waits for batches to retire.  Requests arriving while others run
+ * are so admitted as slots and memory free up, and their work overlaps on
+ * the device.  Every request's outputs are exactly those of vibe_decode on
+ * it alone.  vibe_server_wait blocks until the request is done and gives its
+ * latency from submission to completion (host clock, ms).  Submit refuses a
+ * request whose footprint alone exceeds the pool (VIBE_ENOMEM) or needs more
+ * than one round of per-shot buffers (about 4 GB; VIBE_EINVAL).  A
+ * request's syndromes must already be on the device when it is submitted
+ * (the server's streams do not wait for the caller's), and its buffers must
+ * stay valid until its wait returns.  Submit and wait may be called from
+ * any thread.
  */
 typedef struct vibe_server vibe_server;
 
@@ -330,7 +344,7 @@ typedef struct vibe_server_config {
     uint32_t max_batch_requests; /* requests per batch */
     uint32_t max_batch_shots;    /* shots per batch (and per request) */
     uint32_t reserved;           /* set to 0 */
-    uint64_t hbm_budget;         /* bytes of workspace the server may hold, 0 = any */
+    uint64_t hbm_budget;         /* bytes of the device pool, 0 = see above */
 } vibe_server_config;
 
 int vibe_server_create(vibe_graph* const* graphs, uint32_t n_graphs, const vibe_server_config* cfg,
@@ -338,7 +352,10 @@ int vibe_server_create(vibe_graph* const* graphs, uint32_t n_graphs, const vibe_
 int vibe_server_submit(vibe_server* s, uint32_t graph_index, const uint8_t* syndromes, uint64_t B,
                        uint64_t* corrections, uint8_t* observables, vibe_shot_stats* stats, uint64_t* ticket);
 int vibe_server_wait(vibe_server* s, uint64_t ticket, double* latency_ms);
-int vibe_server_info(vibe_server* s, uint64_t* batches, uint64_t* requests, uint64_t* slot_bytes);
+/* Batches launched, requests served, pool bytes, and the most pool bytes
+   batches held at once (any output may be NULL). */
+int vibe_server_info(vibe_server* s, uint64_t* batches, uint64_t* requests, uint64_t* pool_bytes,
+                     uint64_t* peak_bytes);
 void vibe_server_destroy(vibe_server* s); /* finishes every queued request first; NULL accepted */
 
 /*

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvibelsd.so")
 
 VIBE_OK, VIBE_EINVAL, VIBE_ENOMEM, VIBE_EHIP, VIBE_EUNSUPPORTED = 0, -1, -2, -3, -4
-FLAG_BP_CONVERGED, FLAG_LSD_USED, FLAG_LSD_FAILED = 1, 2, 4
+FLAG_BP_CONVERGED, FLAG_LSD_USED, FLAG_LSD_FAILED, FLAG_SATURATED = 1, 2, 4, 8
 STATS_FIELDS = ("flags", "winner", "t_win", "n_conv", "lsd_clusters", "lsd_largest",
                 "lsd_rounds", "member_iters")
 
@@ -94,7 +94,7 @@ EXPORTS = {
                                      C.c_void_p, C.POINTER(C.c_uint64)]),
     "vibe_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_double)]),
     "vibe_server_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
-                                   C.POINTER(C.c_uint64)]),
+                                   C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "vibe_server_destroy": (None, [C.c_void_p]),
     "vibe_last_error": (C.c_char_p, []),
     "vibe_version": (C.c_char_p, []),
@@ -267,7 +267,7 @@ def unpack_bits(words, n: int) -> np.ndarray:
     """[..., ceil(n/64)] int64 words (any device) -> [..., n] uint8 bits."""
     w = words.detach().cpu().numpy() if hasattr(words, "detach") else np.asarray(words)
     w = np.ascontiguousarray(w).view(np.uint64)
-    b = np.unpackbits(w.view(np.uint8).reshape(*w.shape[:-1], -1), axis=-1, bitorder="little")
+    b = np.unpackbits(w.view(np.uint8).reshape(*w.shape[:-1], 8 * w.shape[-1]), axis=-1, bitorder="little")
     return b[..., :n]
 
 
@@ -541,10 +541,12 @@ class Exec:
 
 
 class Server:
-    """Continuous batching over resident graphs.  submit() queues a request
-    (device syndromes, ready when submitted) and returns a ticket at once;
-    wait(ticket) blocks until it is decoded and returns its latency in ms.
-    Outputs are exactly those of Graph.decode on the request alone."""
+    """Continuous batching over resident graphs, admission by HBM footprint
+    (vibe_server_*).  submit() queues a request (device syndromes, ready when
+    submitted) and returns a ticket at once; wait(ticket) blocks until it is
+    decoded and returns its latency in ms.  Outputs are exactly those of
+    Graph.decode on the request alone.  hbm_budget is the device pool in
+    bytes (0: room for `slots` full batches)."""
 
     def __init__(self, graphs, slots=3, max_batch_requests=256, max_batch_shots=4096, hbm_budget=0):
         import torch
@@ -578,9 +580,9 @@ class Server:
         return ms.value
 
     def info(self):
-        b, r, sb = C.c_uint64(), C.c_uint64(), C.c_uint64()
-        _check(lib().vibe_server_info(self.handle, C.byref(b), C.byref(r), C.byref(sb)))
-        return {"batches": b.value, "requests": r.value, "slot_bytes": sb.value}
+        b, r, pb, pk = C.c_uint64(), C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check(lib().vibe_server_info(self.handle, C.byref(b), C.byref(r), C.byref(pb), C.byref(pk)))
+        return {"batches": b.value, "requests": r.value, "pool_bytes": pb.value, "peak_bytes": pk.value}
 
     def close(self):
         if getattr(self, "handle", None):

@@ -165,6 +165,7 @@ int decode_chunk(vibe_graph* G, const ChunkBufs& W, const uint8_t* synd, uint64_
     s.weight = W.weight;
     s.cand = W.cand;
     s.iters = W.iters;
+    s.conv_mask = W.cmask;
     s.corrections = corr;
     s.stats = stats;
     s.fail_list = W.fail_list;

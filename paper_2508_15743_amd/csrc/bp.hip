@@ -235,7 +235,7 @@ __device__ __forceinline__ void fetch(const Ctx<F>& x, Stage<F>& s, uint32_t k, 
 // contribute their previous messages, so every message of the iteration
 // comes from the previous iteration's.
 template <class F, bool SLAB_LDS, bool WANT_POST, bool FLOOD>
-__device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, uint32_t k) {
+__device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, uint32_t k, uint64_t& sat) {
     using P = Prec<F>;
     using B = typename P::B;
     const uint32_t meta = s.meta, v = s.v;
@@ -254,8 +254,8 @@ __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, 
     // ascending check order over the column's consecutive lanes.  Position
     // j of the column is lane b0 + j, read at a constant offset from one
     // base address, eight positions per batch with all reads issued first;
-    // positions outside the column and the edge's own position add an exact
-    // zero (which changes no value, only possibly the sign of a zero
+    // positions outside the column and the edge's own position add an
+    // exact zero (which changes no value, only possibly the sign of a zero
     // result).  On the column's last lane the partial sums of mu are those
     // of L, so L = mu + r there exactly, and one more read hands it to the
     // whole column.
@@ -287,6 +287,8 @@ __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, 
     F L = bperm(b0x4 + 4u * (deg - 1u), mu + r);
     L = P::clamp(L, x.lim);
     mu = P::clamp(mu, x.lim);
+    // saturation witness: lanes whose posterior or message reached the clamp
+    sat |= __ballot(deg && (fabs(L) >= x.lim || fabs(mu) >= x.lim));
     if constexpr (FLOOD) {
         if constexpr (SLAB_LDS)
             x.lmslab[k * kWave + x.lane] = P::bits(mu);
@@ -323,7 +325,7 @@ __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, 
 // kDepth chunks ahead (the suffix states of later chunks are final for the
 // whole sweep).
 template <class F, bool SLAB_LDS, bool WANT_POST, bool FLOOD>
-__device__ __forceinline__ void sweep(const Ctx<F>& x, uint32_t nch, bool first) {
+__device__ __forceinline__ void sweep(const Ctx<F>& x, uint32_t nch, bool first, uint64_t& sat) {
     const uint32_t last = nch - 1;
     Stage<F> ring[kDepth];
 #pragma unroll
@@ -332,7 +334,7 @@ __device__ __forceinline__ void sweep(const Ctx<F>& x, uint32_t nch, bool first)
 #pragma unroll
         for (int d = 0; d < kDepth; d++) {
             if (k + d >= nch) break;
-            sweep_chunk<F, SLAB_LDS, WANT_POST, FLOOD>(x, ring[d], k + d);
+            sweep_chunk<F, SLAB_LDS, WANT_POST, FLOOD>(x, ring[d], k + d, sat);
             fetch<F, SLAB_LDS, FLOOD>(x, ring[d], min(k + d + kDepth, last), first);
         }
     }
@@ -470,7 +472,7 @@ __device__ __forceinline__ void row_reduce(F& m1, F& m2, uint32_t& arg, uint32_t
 // clamped L and the residual updated.
 template <class F>
 __device__ __forceinline__ void layered_sweep(const DevGraph& g, const Ctx<F>& x, const uint32_t* cord,
-                                              bool want_post) {
+                                              bool want_post, uint64_t& sat) {
     using P = Prec<F>;
     const uint32_t lane = x.lane;
     constexpr uint32_t fb = sizeof(F);
@@ -494,6 +496,7 @@ __device__ __forceinline__ void layered_sweep(const DevGraph& g, const Ctx<F>& x
                     if (k < k1) {
                         const F mu = P::clamp(mraw[q], lim);
                         const F aa = fabs(mu);
+                        sat |= __ballot(aa >= lim);
                         par ^= mu < F(0) ? 1u : 0u;
                         if (aa < m1) {
                             m2 = m1;
@@ -523,6 +526,7 @@ __device__ __forceinline__ void layered_sweep(const DevGraph& g, const Ctx<F>& x
                     const uint32_t v = g.ri[k];
                     const F mu = P::clamp(bloadx<F>(x.slb, oL + v * fb, 0) - bload<F>(x.slb, k * fb, 0), lim);
                     const F aa = fabs(mu);
+                    sat |= __ballot(aa >= lim);
                     par ^= mu < F(0) ? 1u : 0u;
                     if (aa < m1) {
                         m2 = m1;
@@ -553,6 +557,7 @@ __device__ __forceinline__ void layered_sweep(const DevGraph& g, const Ctx<F>& x
         const uint32_t j0 = g.cp[v], j1 = g.cp[v + 1];
         if (j0 == j1) continue;  // no check: L_v = lambda_v, decision fixed
         const F L = P::clamp(bloadx<F>(x.slb, oL + v * fb, 0), lim);
+        sat |= __ballot(fabs(L) >= lim);
         if (want_post) x.post[v] = L;
         const bool enew = L <= F(0);
         const bool eold = (x.eb[v >> 6] >> (v & 63)) & 1ull;
@@ -667,6 +672,7 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
 
     uint32_t conv_t = 0, ran = 0;
     bool stopped = false;
+    uint64_t sat = 0;  // lanes that saw a posterior or message reach the clamp (saturation witness)
     for (uint32_t t = 1; t <= a.T_run; t++) {
         if (a.use_M && t >= 2 && preceding_converged(cmask, t, mem, lane) >= g.M) {
             stopped = true;  // cannot be among the first M any more
@@ -681,12 +687,12 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
         for (uint32_t c = lane; c < g.m; c += kWave) pref[c] = ident;
         __syncthreads();
         if constexpr (LAYERED) {
-            layered_sweep<F>(g, x, g.cperm + (size_t)mem * g.m, want_post);
+            layered_sweep<F>(g, x, g.cperm + (size_t)mem * g.m, want_post, sat);
         } else if (nch) {
             if (want_post)
-                sweep<F, SLAB_LDS, true, FLOOD>(x, nch, t == 1);
+                sweep<F, SLAB_LDS, true, FLOOD>(x, nch, t == 1, sat);
             else
-                sweep<F, SLAB_LDS, false, FLOOD>(x, nch, t == 1);
+                sweep<F, SLAB_LDS, false, FLOOD>(x, nch, t == 1, sat);
         }
         __syncthreads();  // every new message stored
         if (post_out) {
@@ -710,9 +716,13 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
         }
     }
 
+    // a run that reached the clamp marks its member in word 0 of the shot's
+    // convergence masks (iterations count from 1, so that word is free)
+    const bool saturated = uni(sat != 0 ? 1u : 0u) != 0;
     if (lane == 0) {
         a.t_conv[rec] = (int32_t)conv_t;
         atomicAdd(&a.iters[shot], ran);
+        if (saturated) atomicOr(reinterpret_cast<unsigned long long*>(&cmask[0]), 1ull << mem);
     }
     if (a.cand && (conv_t || !a.use_M))
         for (uint32_t w = lane; w < g.words_n; w += kWave) a.cand[(size_t)rec * g.words_n + w] = eb[w];

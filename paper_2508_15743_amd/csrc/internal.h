@@ -213,6 +213,7 @@ struct SelectLaunch {
     const double* weight;
     const uint64_t* cand;
     const uint32_t* iters;
+    const uint64_t* conv_mask;    // n_shots x (kMaxT + 1); word 0 = members that saturated, may be null
     uint64_t* corrections;        // global B x words_n (indexed by shot0 + i)
     vibe_shot_stats* stats;       // global, may be null
     uint32_t* fail_list;          // local shot indices that need LSD

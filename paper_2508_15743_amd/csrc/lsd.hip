@@ -599,7 +599,9 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                     st->n_conv = 0;
                     st->member_iters = 0;
                 }
-                st->flags = VIBE_FLAG_LSD_USED | (failed ? VIBE_FLAG_LSD_FAILED : 0u);
+                // keep the saturation flag the selection wrote for this shot
+                st->flags = (a.list ? (st->flags & VIBE_FLAG_SATURATED) : 0u) | VIBE_FLAG_LSD_USED |
+                            (failed ? VIBE_FLAG_LSD_FAILED : 0u);
                 st->lsd_clusters = (uint32_t)nclus;
                 st->lsd_largest = (uint32_t)largest;
                 st->lsd_rounds = (uint32_t)rounds;

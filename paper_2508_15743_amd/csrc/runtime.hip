@@ -10,6 +10,8 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <string>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -300,6 +302,7 @@ int run_round(const vibe_request* reqs, const Round& r, unsigned char* base, hip
         s.weight = reinterpret_cast<const double*>(base + sg.weight);
         s.cand = reinterpret_cast<const uint64_t*>(base + sg.cand);
         s.iters = reinterpret_cast<const uint32_t*>(base + sg.iters);
+        s.conv_mask = reinterpret_cast<const uint64_t*>(base + sg.cmask);
         s.corrections = q.corrections;
         s.stats = q.stats;
         s.fail_list = reinterpret_cast<uint32_t*>(base + sg.fail_list);
@@ -510,16 +513,21 @@ extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B
 }
 
 // ---------------------------------------------------------------------------
-// Serving: continuous batching over resident graphs.
+// Serving: continuous batching over resident graphs, admitted by footprint.
 //
-// Requests are queued by vibe_server_submit.  A server thread keeps up to
-// `slots` batches in flight, each on its own stream with its own
-// preallocated workspace: whenever a slot is free it takes the queued
-// requests (first come, first served) that fit the slot's workspace and
-// launches them as one ragged round, so requests that arrive while other
-// batches run are admitted as soon as a slot frees up and their work
-// overlaps on the device.  HBM held by the server is bounded by slots x
-// slot workspace, fixed at creation.
+// The server owns one device pool of hbm_budget bytes.  Every batch holds
+// requests on one graph, so a batch of a small code never waits for the
+// long serial chains of a large one, and takes a block of the pool sized by
+// its own footprint: the decode workspace of its shots (per-shot buffers;
+// message and posterior slabs for a BP grid no larger than its items; LSD
+// scratch), the staging of its syndromes and outputs, and its copy table.
+// A server thread keeps up to `slots` batches in flight, each on its own
+// stream.  Whenever a slot is free it takes the oldest queued request and,
+// in order, the later queued requests on the same graph, while the batch
+// still fits the largest free block of the pool (and the batch limits);
+// if the oldest request does not fit yet it waits for batches to retire.
+// Requests that arrive while others run are thus admitted as slots and
+// memory free up, and their work overlaps on the device.
 
 namespace {
 
@@ -535,9 +543,9 @@ struct SrvReq {
 struct SrvSlot {
     hipStream_t st = nullptr;
     hipEvent_t done = nullptr;
-    vibe::Workspace ws;       // decode workspace, then staging and copy tables
     std::vector<uint64_t> tickets;
     bool busy = false;
+    size_t blk_off = 0, blk_bytes = 0;  // the batch's block of the pool
     // host tables of the batch in flight (kept until the slot retires)
     std::vector<vibe::BpSeg> segs;
     std::vector<vibe::CopyEntry> copies;
@@ -549,6 +557,81 @@ struct SrvDone {
     double latency_ms = 0.0;
 };
 
+// First-fit allocator over the pool's byte range (host bookkeeping only).
+struct PoolMap {
+    std::map<size_t, size_t> free_;  // offset -> bytes, no two adjacent
+    void reset(size_t bytes) {
+        free_.clear();
+        if (bytes) free_[0] = bytes;
+    }
+    size_t largest() const {
+        size_t b = 0;
+        for (const auto& kv : free_) b = std::max(b, kv.second);
+        return b;
+    }
+    bool take(size_t bytes, size_t* off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes, at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void give(size_t off, size_t bytes) {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+// Where a batch of `shots` shots from `n_req` requests on one graph keeps
+// its buffers, relative to its block.
+struct BatchLayout {
+    vibe::Round round;
+    size_t synd = 0, corr = 0, obs = 0, stats = 0, tab = 0, bytes = 0;
+    bool one_round = false;
+};
+
+BatchLayout batch_layout(vibe_graph* G, uint64_t shots, uint32_t n_req) {
+    BatchLayout L;
+    const vibe::DevGraph& g = G->h.dg;
+    vibe_request r{};
+    r.graph = G;
+    r.syndromes = reinterpret_cast<const uint8_t*>(1);
+    r.corrections = reinterpret_cast<uint64_t*>(1);
+    r.observables = reinterpret_cast<uint8_t*>(1);
+    r.B = std::max<uint64_t>(shots, 1);
+    std::vector<vibe::Round> rs = vibe::plan(&r, 1, vibe::kRaggedBudget);
+    L.one_round = rs.size() == 1;
+    L.round = rs[0];
+    size_t off = vibe::al256(L.round.bytes);
+    L.synd = off;
+    off += vibe::al256(r.B * g.m);
+    L.corr = off;
+    off += vibe::al256(r.B * 8ull * g.words_n);
+    L.obs = off;
+    off += vibe::al256(r.B * std::max<uint32_t>(g.k, 1));
+    L.stats = off;
+    off += vibe::al256(r.B * sizeof(vibe_shot_stats));
+    L.tab = off;
+    off += vibe::al256(sizeof(vibe::CopyEntry) * 4ull * std::max<uint32_t>(n_req, 1));
+    L.bytes = off;
+    return L;
+}
+
 }  // namespace
 
 struct vibe_server {
@@ -556,12 +639,9 @@ struct vibe_server {
     vibe_server_config cfg{};
     int device = 0;
     std::vector<SrvSlot> slots;
-    size_t slot_bytes = 0;
-    // slot layout: decode workspace [0, dec_bytes), then per graph the staged
-    // syndromes, corrections, observables and stats of a batch, then the
-    // copy table
-    size_t dec_bytes = 0, tab_off = 0;
-    std::vector<size_t> st_synd, st_corr, st_obs, st_stats;
+    vibe::Workspace pool;
+    PoolMap map;
+    size_t in_use = 0, peak = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<SrvReq> queue;
@@ -575,43 +655,16 @@ struct vibe_server {
 
 namespace {
 
-// Workspace of a slot: room to decode max_batch_shots shots in one round,
-// whatever the mix of graphs, then staging of those shots per graph and the
-// gather / scatter table.
-void slot_layout(vibe_server& S) {
-    size_t worst = 0;
-    for (vibe_graph* G : S.graphs) {
-        vibe_request r{};
-        r.graph = G;
-        r.syndromes = reinterpret_cast<const uint8_t*>(1);
-        r.corrections = reinterpret_cast<uint64_t*>(1);
-        r.observables = reinterpret_cast<uint8_t*>(1);
-        r.B = S.cfg.max_batch_shots;
-        std::vector<vibe::Round> rs = vibe::plan(&r, 1, vibe::kRaggedBudget);
-        size_t most = 0;
-        for (const vibe::Round& x : rs) most = std::max(most, x.bytes);
-        // a mixed round needs at most every graph's own round at full size
-        worst += most;
+void finish_tickets(vibe_server* S, const std::vector<uint64_t>& tickets, int rc) {
+    const auto now = Clock::now();
+    for (uint64_t t : tickets) {
+        SrvDone& d = S->status[t];
+        d.done = true;
+        d.rc = rc;
+        d.latency_ms = std::chrono::duration<double, std::milli>(now - S->t_submit[t]).count();
+        S->t_submit.erase(t);
     }
-    // one segment per graph in a mixed round: alignment and table slack
-    size_t off = worst + (size_t)(S.graphs.size() + 2) * (16 * 256 + sizeof(vibe::BpSeg));
-    off = vibe::al256(off);
-    S.dec_bytes = off;
-    const uint64_t B = S.cfg.max_batch_shots;
-    for (vibe_graph* G : S.graphs) {
-        const vibe::DevGraph& g = G->h.dg;
-        S.st_synd.push_back(off);
-        off += vibe::al256(B * g.m);
-        S.st_corr.push_back(off);
-        off += vibe::al256(B * 8ull * g.words_n);
-        S.st_obs.push_back(off);
-        off += vibe::al256(B * std::max<uint32_t>(g.k, 1));
-        S.st_stats.push_back(off);
-        off += vibe::al256(B * sizeof(vibe_shot_stats));
-    }
-    S.tab_off = off;
-    off += vibe::al256(sizeof(vibe::CopyEntry) * 4ull * S.cfg.max_batch_requests);
-    S.slot_bytes = off;
+    S->cv_done.notify_all();
 }
 
 void server_loop(vibe_server* S) {
@@ -619,24 +672,20 @@ void server_loop(vibe_server* S) {
     for (;;) {
         std::vector<SrvReq> batch;
         int slot = -1;
+        BatchLayout lay;
+        size_t blk = 0;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            // retire finished batches
+            // retire finished batches and return their blocks to the pool
             for (SrvSlot& sl : S->slots) {
                 if (!sl.busy) continue;
                 hipError_t q = hipEventQuery(sl.done);
                 if (q == hipErrorNotReady) continue;
-                const auto now = Clock::now();
-                for (uint64_t t : sl.tickets) {
-                    SrvDone& d = S->status[t];
-                    d.done = true;
-                    d.rc = q == hipSuccess ? VIBE_OK : VIBE_EHIP;
-                    d.latency_ms = std::chrono::duration<double, std::milli>(now - S->t_submit[t]).count();
-                    S->t_submit.erase(t);
-                }
+                finish_tickets(S, sl.tickets, q == hipSuccess ? VIBE_OK : VIBE_EHIP);
                 sl.tickets.clear();
                 sl.busy = false;
-                S->cv_done.notify_all();
+                S->map.give(sl.blk_off, sl.blk_bytes);
+                S->in_use -= sl.blk_bytes;
             }
             bool any_busy = false;
             for (size_t i = 0; i < S->slots.size(); i++) {
@@ -644,70 +693,114 @@ void server_loop(vibe_server* S) {
                 any_busy = any_busy || S->slots[i].busy;
             }
             if (S->stop && S->queue.empty() && !any_busy) return;
-            if (slot < 0 || S->queue.empty()) {
-                // wait for a submission, or poll the slots in flight
+            if (slot >= 0 && !S->queue.empty()) {
+                // the oldest request's graph, then later requests on it in
+                // order, while the batch fits the largest free block
+                const uint32_t gi = S->queue.front().gi;
+                vibe_graph* G = S->graphs[gi];
+                const size_t room = S->map.largest();
+                // candidates within the batch limits, then the longest
+                // prefix of them whose footprint fits (it grows with the
+                // prefix, so a binary search finds it)
+                std::vector<size_t> pick;
+                std::vector<uint64_t> upto;  // shots of the first k + 1 candidates
+                uint64_t shots = 0;
+                for (size_t i = 0; i < S->queue.size() && pick.size() < S->cfg.max_batch_requests; i++) {
+                    const SrvReq& r = S->queue[i];
+                    if (r.gi != gi) continue;
+                    if (!pick.empty() && shots + r.req.B > S->cfg.max_batch_shots) break;
+                    pick.push_back(i);
+                    shots += r.req.B;
+                    upto.push_back(shots);
+                }
+                auto fits = [&](size_t k, BatchLayout* out) {  // the first k candidates
+                    BatchLayout t = batch_layout(G, upto[k - 1], (uint32_t)k);
+                    if (out) *out = t;
+                    return t.one_round && t.bytes <= room;
+                };
+                size_t lo = 0, hi = pick.size();  // fits(lo) (or lo = 0), !fits(hi + 1)
+                while (lo < hi) {
+                    const size_t mid = (lo + hi + 1) / 2;
+                    if (fits(mid, nullptr))
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                pick.resize(lo);
+                if (lo) fits(lo, &lay);
+                if (pick.empty() && !any_busy) {
+                    // cannot happen for admitted requests (each fits the
+                    // whole pool alone), kept as a guard against a stall
+                    std::vector<uint64_t> t1{S->queue.front().ticket};
+                    S->queue.pop_front();
+                    finish_tickets(S, t1, VIBE_ENOMEM);
+                    continue;
+                }
+                if (!pick.empty() && S->map.take(lay.bytes, &blk)) {
+                    std::deque<SrvReq> rest;
+                    size_t k = 0;
+                    for (size_t i = 0; i < S->queue.size(); i++) {
+                        if (k < pick.size() && pick[k] == i) {
+                            batch.push_back(S->queue[i]);
+                            k++;
+                        } else {
+                            rest.push_back(S->queue[i]);
+                        }
+                    }
+                    S->queue.swap(rest);
+                    S->in_use += lay.bytes;
+                    S->peak = std::max(S->peak, S->in_use);
+                }
+            }
+            if (batch.empty()) {
+                // wait for a submission, or poll the batches in flight
                 S->cv_work.wait_for(lk, std::chrono::microseconds(any_busy ? 20 : 2000));
                 continue;
             }
-            // admit queued requests, first come first served, while the
-            // round fits the slot's workspace
-            uint64_t shots = 0;
-            while (!S->queue.empty() && batch.size() < S->cfg.max_batch_requests) {
-                const SrvReq& r = S->queue.front();
-                if (!batch.empty() && shots + r.req.B > S->cfg.max_batch_shots) break;
-                batch.push_back(r);
-                shots += r.req.B;
-                S->queue.pop_front();
-            }
         }
         // Launch outside the lock: gather the batch's syndromes into one
-        // contiguous block per graph, decode one segment per graph, scatter
-        // the outputs back to the requests' buffers.
+        // contiguous block, decode it as one request, scatter the outputs
+        // back to the requests' buffers.
         SrvSlot& sl = S->slots[slot];
-        unsigned char* base = static_cast<unsigned char*>(sl.ws.base);
-        const size_t G = S->graphs.size();
-        std::vector<uint64_t> rows(G, 0);
-        std::vector<vibe_request> per(G);
+        sl.blk_off = blk;
+        sl.blk_bytes = lay.bytes;
+        unsigned char* base = static_cast<unsigned char*>(S->pool.base) + blk;
+        vibe_graph* Gr = S->graphs[batch[0].gi];
+        const vibe::DevGraph& g = Gr->h.dg;
         sl.copies.clear();
         std::vector<vibe::CopyEntry> scatter;
+        uint64_t rows = 0;
         for (const SrvReq& r : batch) {
-            const vibe::DevGraph& g = r.req.graph->h.dg;
-            const uint64_t r0 = rows[r.gi];
-            rows[r.gi] += r.req.B;
+            const uint64_t r0 = rows;
+            rows += r.req.B;
             if (!r.req.B) continue;
-            sl.copies.push_back({r.req.syndromes, base + S->st_synd[r.gi] + r0 * g.m, r.req.B * g.m});
+            sl.copies.push_back({r.req.syndromes, base + lay.synd + r0 * g.m, r.req.B * g.m});
             const uint64_t cw = 8ull * g.words_n;
-            scatter.push_back({base + S->st_corr[r.gi] + r0 * cw, reinterpret_cast<unsigned char*>(r.req.corrections),
+            scatter.push_back({base + lay.corr + r0 * cw, reinterpret_cast<unsigned char*>(r.req.corrections),
                                r.req.B * cw});
-            if (g.k)
-                scatter.push_back({base + S->st_obs[r.gi] + r0 * g.k, r.req.observables, r.req.B * g.k});
+            if (g.k) scatter.push_back({base + lay.obs + r0 * g.k, r.req.observables, r.req.B * g.k});
             if (r.req.stats)
-                scatter.push_back({base + S->st_stats[r.gi] + r0 * sizeof(vibe_shot_stats),
+                scatter.push_back({base + lay.stats + r0 * sizeof(vibe_shot_stats),
                                    reinterpret_cast<unsigned char*>(r.req.stats), r.req.B * sizeof(vibe_shot_stats)});
         }
         const uint32_t n_gather = (uint32_t)sl.copies.size();
         sl.copies.insert(sl.copies.end(), scatter.begin(), scatter.end());
-        std::vector<vibe_request> reqs;
-        for (size_t gi = 0; gi < G; gi++) {
-            if (!rows[gi]) continue;
-            vibe_request q{};
-            q.graph = S->graphs[gi];
-            q.syndromes = base + S->st_synd[gi];
-            q.B = rows[gi];
-            q.corrections = reinterpret_cast<uint64_t*>(base + S->st_corr[gi]);
-            q.observables = base + S->st_obs[gi];
-            q.stats = reinterpret_cast<vibe_shot_stats*>(base + S->st_stats[gi]);
-            reqs.push_back(q);
-        }
         int rc = VIBE_OK;
-        vibe::CopyEntry* dtab = reinterpret_cast<vibe::CopyEntry*>(base + S->tab_off);
-        if (!reqs.empty()) {
-            std::vector<vibe::Round> rounds = vibe::plan(reqs.data(), (uint32_t)reqs.size(), vibe::kRaggedBudget);
-            if (rounds.size() != 1 || rounds[0].bytes > S->dec_bytes) {
-                rc = vibe::fail(VIBE_ENOMEM, "a batch exceeds the slot workspace");
+        if (rows) {
+            vibe_request q{};
+            q.graph = Gr;
+            q.syndromes = base + lay.synd;
+            q.B = rows;
+            q.corrections = reinterpret_cast<uint64_t*>(base + lay.corr);
+            q.observables = base + lay.obs;
+            q.stats = reinterpret_cast<vibe_shot_stats*>(base + lay.stats);
+            std::vector<vibe::Round> rounds = vibe::plan(&q, 1, vibe::kRaggedBudget);
+            vibe::CopyEntry* dtab = reinterpret_cast<vibe::CopyEntry*>(base + lay.tab);
+            if (rounds.size() != 1 || rounds[0].bytes > lay.round.bytes) {
+                rc = vibe::fail(VIBE_ENOMEM, "internal: a batch outgrew its block");
             } else {
                 const vibe::Round& rd = rounds[0];
-                sl.segs = vibe::seg_table(reqs.data(), rd, base);
+                sl.segs = vibe::seg_table(&q, rd, base);
                 hipError_t e = hipMemcpyAsync(dtab, sl.copies.data(), sizeof(vibe::CopyEntry) * sl.copies.size(),
                                               hipMemcpyHostToDevice, sl.st);
                 if (e == hipSuccess)
@@ -715,19 +808,20 @@ void server_loop(vibe_server* S) {
                                        hipMemcpyHostToDevice, sl.st);
                 if (e != hipSuccess) rc = vibe::hip_fail(e, "hipMemcpyAsync(server tables)");
                 if (!rc) rc = vibe::launch_copies(dtab, n_gather, sl.st);
-                if (!rc) rc = vibe::run_round(reqs.data(), rd, base, sl.st);
+                if (!rc) rc = vibe::run_round(&q, rd, base, sl.st);
                 if (!rc) rc = vibe::launch_copies(dtab + n_gather, (uint32_t)scatter.size(), sl.st);
             }
         }
         std::unique_lock<std::mutex> lk(S->mu);
         if (rc) {
-            for (const SrvReq& r : batch) {
-                SrvDone& d = S->status[r.ticket];
-                d.done = true;
-                d.rc = rc;
-                S->t_submit.erase(r.ticket);
-            }
-            S->cv_done.notify_all();
+            // the stream may still hold work of this batch: wait before the
+            // block goes back to the pool
+            (void)hipStreamSynchronize(sl.st);
+            std::vector<uint64_t> ts;
+            for (const SrvReq& r : batch) ts.push_back(r.ticket);
+            finish_tickets(S, ts, rc);
+            S->map.give(sl.blk_off, sl.blk_bytes);
+            S->in_use -= sl.blk_bytes;
             continue;
         }
         (void)hipEventRecord(sl.done, sl.st);
@@ -752,35 +846,43 @@ extern "C" int vibe_server_create(vibe_graph* const* graphs, uint32_t n_graphs, 
         const DevGraph& g = graphs[i]->h.dg;
         const DevGraph& g0 = graphs[0]->h.dg;
         if (g.fp64 != g0.fp64) return fail(VIBE_EINVAL, "all graphs of a server need the same message_bits");
+        if (graphs[i]->device != graphs[0]->device) return fail(VIBE_EINVAL, "all graphs must be on one device");
+    }
+    // the pool: hbm_budget, or room for `slots` full batches of the graph
+    // with the largest full batch
+    size_t pool = cfg->hbm_budget;
+    if (!pool) {
+        size_t worst = 0;
+        for (uint32_t i = 0; i < n_graphs; i++) {
+            uint64_t b = cfg->max_batch_shots;
+            BatchLayout L = batch_layout(graphs[i], b, cfg->max_batch_requests);
+            while (!L.one_round && b > 1) L = batch_layout(graphs[i], b /= 2, cfg->max_batch_requests);
+            worst = std::max(worst, L.bytes);
+        }
+        pool = worst * cfg->slots;
     }
     vibe_server* S = new (std::nothrow) vibe_server();
     if (!S) return fail(VIBE_ENOMEM, "host allocation failed");
     S->graphs.assign(graphs, graphs + n_graphs);
     S->cfg = *cfg;
-    (void)hipGetDevice(&S->device);
-    slot_layout(*S);
-    if (cfg->hbm_budget && S->slot_bytes * cfg->slots > cfg->hbm_budget) {
-        delete S;
-        return fail(VIBE_ENOMEM, "slots x slot workspace exceed the HBM budget");
-    }
+    S->device = graphs[0]->device;
     S->slots.resize(cfg->slots);
-    int rc = VIBE_OK;
+    int rc = grow(S->pool, pool);
+    if (!rc) S->map.reset(S->pool.bytes);
     for (SrvSlot& sl : S->slots) {
+        if (rc) break;
         hipError_t e;
         // default priority: streams of other priorities are avoided on purpose
         if ((e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess) {
+            (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess)
             rc = hip_fail(e, "server stream or event");
-            break;
-        }
-        if ((rc = grow(sl.ws, S->slot_bytes))) break;
     }
     if (rc) {
         for (SrvSlot& sl : S->slots) {
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.st) (void)hipStreamDestroy(sl.st);
-            if (sl.ws.base) (void)hipFree(sl.ws.base);
         }
+        if (S->pool.base) (void)hipFree(S->pool.base);
         delete S;
         return rc;
     }
@@ -805,6 +907,14 @@ extern "C" int vibe_server_submit(vibe_server* S, uint32_t graph_index, const ui
     r.stats = stats;
     int rc = check_requests(&r, 1);
     if (rc) return rc;
+    // admission by footprint: the request alone must fit the pool (and one
+    // round of per-shot buffers); it is queued until that much is free
+    const BatchLayout L = batch_layout(r.graph, B, 1);
+    if (!L.one_round) return fail(VIBE_EINVAL, "a request needs more than one round of per-shot buffers");
+    if (L.bytes > S->pool.bytes)
+        return fail(VIBE_ENOMEM, "the request's footprint (" + std::to_string(L.bytes) +
+                                     " bytes) exceeds the server's HBM pool (" + std::to_string(S->pool.bytes) +
+                                     " bytes)");
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stop) return fail(VIBE_EINVAL, "the server is shutting down");
     const uint64_t t = S->next_ticket++;
@@ -831,12 +941,14 @@ extern "C" int vibe_server_wait(vibe_server* S, uint64_t ticket, double* latency
     return VIBE_OK;
 }
 
-extern "C" int vibe_server_info(vibe_server* S, uint64_t* batches, uint64_t* requests, uint64_t* slot_bytes) {
+extern "C" int vibe_server_info(vibe_server* S, uint64_t* batches, uint64_t* requests, uint64_t* pool_bytes,
+                                uint64_t* peak_bytes) {
     if (!S) return fail(VIBE_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(S->mu);
     if (batches) *batches = S->batches;
     if (requests) *requests = S->requests;
-    if (slot_bytes) *slot_bytes = S->slot_bytes;
+    if (pool_bytes) *pool_bytes = S->pool.bytes;
+    if (peak_bytes) *peak_bytes = S->peak;
     return VIBE_OK;
 }
 
@@ -852,7 +964,7 @@ extern "C" void vibe_server_destroy(vibe_server* S) {
         if (sl.st) (void)hipStreamSynchronize(sl.st);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.st) (void)hipStreamDestroy(sl.st);
-        if (sl.ws.base) (void)hipFree(sl.ws.base);
     }
+    if (S->pool.base) (void)hipFree(S->pool.base);
     delete S;
 }

@@ -45,6 +45,8 @@ __global__ __launch_bounds__(kWave) void select_kernel(DevGraph g, SelectLaunch 
     }
     who = uni(who);
     const size_t gshot = a.shot0 + shot;
+    // members whose run reached the clamp (word 0 of the shot's masks)
+    const uint64_t sat = a.conv_mask ? a.conv_mask[(size_t)shot * (kMaxT + 1)] : 0ull;
     uint64_t* out = a.corrections + gshot * g.words_n;
     if (nconv) {
         const uint32_t tw = (uint32_t)__shfl(t, who);
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(kWave) void select_kernel(DevGraph g, SelectLaunch 
         for (uint32_t i = lane; i < g.words_n; i += kWave) out[i] = src[i];
         if (lane == 0 && a.stats) {
             vibe_shot_stats st;
-            st.flags = VIBE_FLAG_BP_CONVERGED;
+            st.flags = VIBE_FLAG_BP_CONVERGED | (((sat >> who) & 1ull) ? VIBE_FLAG_SATURATED : 0u);
             st.winner = who;
             st.t_win = tw;
             st.n_conv = nconv;
@@ -65,7 +67,7 @@ __global__ __launch_bounds__(kWave) void select_kernel(DevGraph g, SelectLaunch 
         a.fail_list[slot] = shot;
         if (a.stats) {
             vibe_shot_stats st;
-            st.flags = VIBE_FLAG_LSD_USED;
+            st.flags = VIBE_FLAG_LSD_USED | (sat ? VIBE_FLAG_SATURATED : 0u);
             st.winner = -1;
             st.t_win = 0;
             st.n_conv = 0;

@@ -1,0 +1,118 @@
+"""The HIP path against the oracle at the workloads' own scale, shot by shot,
+using the oracle's per-shot results stored by oracle/fixtures.py.
+
+  * circuit-level d = 9 (the benchmark's graph, settings and seeds): the
+    whole 32768-shot batch decoded in one call as the benchmark times it
+    (FP32), its first 10^4 shots compared with the oracle; the same shots in
+    FP64 messages.
+  * phenomenological d = 11, LSD order 10: 10^5 shots in FP32 and FP64.
+
+Bars (those of test_gpu_parity.py): FP64 corrections identical on >= 99.9%
+of shots; FP32 shots a BP member decides agree on >= 99.9%, every other
+disagreement sits at an LSD rank tie of the oracle's decode, >= 99.9% of
+the shots not at a tie agree; the logical error rate of each side lies in
+the other's 95% (Clopper-Pearson) interval.  The stored results carry
+digests of the inputs, which are checked first.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import fixtures as F
+from parity_helpers import fp32_decode_bar
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_15743_amd as P
+
+    P.lib()
+    return torch
+
+
+def _clopper_pearson(k, n):
+    from scipy.stats import beta
+
+    lo = beta.ppf(0.025, k, n - k + 1) if k else 0.0
+    hi = beta.ppf(0.975, k + 1, n - k) if k < n else 1.0
+    return lo, hi
+
+
+def _load(name):
+    path = F.path_for(name)
+    if not os.path.exists(path):
+        pytest.fail(f"{path} is missing: run python -m oracle.fixtures {name}")
+    ref = F.load(name)
+    dem, perms, b, n = F.workload_inputs(name, ref["meta"]["shots"])
+    meta = ref["meta"]
+    assert meta["syndromes_sha"] == F.array_digest(b.syndromes[:n]), "inputs changed since the fixture"
+    assert meta["perms_sha"] == F.array_digest(perms)
+    assert meta["observables_sha"] == F.array_digest(b.observables[:n])
+    return ref, dem, perms, b, n
+
+
+def _compare(torch, name, bits, whole_batch):
+    import paper_2508_15743_amd as P
+
+    ref, dem, perms, b, n = _load(name)
+    w = F.WORKLOADS[name]
+    G = P.Graph.from_dem(dem, perms, L=w["L"], M=w["M"], T_max=w["T"], alpha=w["alpha"],
+                         lsd_order=w["lsd_order"], message_bits=bits)
+    synd = b.syndromes if whole_batch else b.syndromes[:n]
+    s = torch.from_numpy(synd).to("cuda:0")
+    print(f"{name} FP{bits}: decoding {s.shape[0]} shots in one call", flush=True)
+    corr, obs, st = G.decode(s)
+    torch.cuda.synchronize()
+    G.close()
+    e = P.unpack_bits(corr[:n], dem.n)
+    st = st[:n].cpu().numpy()
+    obs = obs[:n].cpu().numpy()
+    agree = F.ehat_digest(e) == ref["ehat_digest"]
+    if "ehat_indptr" in ref:
+        # the stored set bits agree with the stored digests
+        ip, ix = ref["ehat_indptr"], ref["ehat_indices"]
+        for i in np.flatnonzero(agree)[:50]:
+            assert np.flatnonzero(e[i]).tolist() == ix[ip[i]:ip[i + 1]].tolist()
+    ref_lsd = (ref["flags"] & 2) != 0
+    gpu_lsd = (st[:, 0] & 2) != 0
+    if bits == 64:
+        assert agree.mean() >= 0.999, agree.mean()
+        same_flags = (ref["flags"] == (st[:, 0] & 7)).mean()
+        line = f"agreement {agree.mean():.5f} of {n}, flags equal on {same_flags:.5f}"
+    else:
+        line = fp32_decode_bar(agree, ref_lsd, gpu_lsd, ref["min_q_gap"], w["L"], dem.n)
+    # observables follow the corrections, and the LERs sit in each other's intervals
+    lo_obs = (e.astype(np.int64) @ dem.dense_l().T.astype(np.int64)) % 2
+    assert np.array_equal(obs, lo_obs.astype(np.uint8))
+    true_obs = b.observables[:n]
+    k_ref = int((ref["obs"] != true_obs).any(1).sum())
+    k_gpu = int((obs != true_obs).any(1).sum())
+    lo, hi = _clopper_pearson(k_ref, n)
+    assert lo <= k_gpu / n <= hi, (k_gpu / n, lo, hi)
+    lo2, hi2 = _clopper_pearson(k_gpu, n)
+    assert lo2 <= k_ref / n <= hi2, (k_ref / n, lo2, hi2)
+    print(f"{name} FP{bits}: {line}; LSD on {gpu_lsd.mean():.4f} (oracle {ref_lsd.mean():.4f}); "
+          f"LER {k_gpu / n:.2e} (oracle {k_ref / n:.2e}, 95% interval [{lo:.2e}, {hi:.2e}])", flush=True)
+
+
+def test_circuit_d9_benchmark_batch_fp32(torch_cuda):
+    _compare(torch_cuda, "circuit_d9", 32, whole_batch=True)
+
+
+def test_circuit_d9_fp64(torch_cuda):
+    _compare(torch_cuda, "circuit_d9", 64, whole_batch=False)
+
+
+def test_phenomenological_d11_lsd10_fp32(torch_cuda):
+    _compare(torch_cuda, "phenom_d11", 32, whole_batch=False)
+
+
+def test_phenomenological_d11_lsd10_fp64(torch_cuda):
+    _compare(torch_cuda, "phenom_d11", 64, whole_batch=False)

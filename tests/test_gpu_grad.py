@@ -7,6 +7,8 @@ step).  In FP64 the unrolled iterations follow the oracle's operation order,
 so the loss agrees to rounding and the gradient to the difference quotient's
 own error.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -296,3 +298,77 @@ def test_grad_on_the_d17_graph(torch_cuda):
     want = sum(O.bp_loss(g, s, lam, alpha, K, perm)[0] for s in synd for perm in perms)
     assert abs(loss.item() - want) <= 1e-4 * max(1.0, abs(want)), (loss.item(), want)
     G.close()
+
+
+_K16 = {}
+
+
+def _k16_reference():
+    """The oracle's loss and FD gradient for the K = 16 benchmark
+    configuration, computed once (the items run on a thread pool; the
+    oracle releases the interpreter while it computes)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    if _K16:
+        return _K16
+    dem = circuit_dem(5, 5, 1e-3)
+    K, L = 16, 32
+    perms = permutations(dem.n, L, 2030)  # the benchmark's gradient schedules
+    synd = sample(dem, 4096, 2031).syndromes[:2]
+    # lambda from the priors, moved by up to 1e-3 relative: uniform priors
+    # tie many messages exactly, and every alpha_t then switches an argmin
+    # between a new and an old message somewhere, so no alpha_t would be
+    # smooth; the small move puts the point inside a smooth piece
+    rng = np.random.default_rng(2032)
+    lam = np.log((1 - dem.priors) / dem.priors) * (1.0 + 1e-3 * rng.uniform(-1.0, 1.0, dem.n))
+    alpha = np.full(K, 0.625)
+    idx = np.sort(np.random.default_rng(17).choice(dem.n, 64, replace=False))
+    g = O.OracleGraph(dem)
+    items = [(s, perm) for s in synd for perm in perms]
+
+    def one(it):
+        s, perm = it
+        f = O.bp_loss(g, s, lam, alpha, K, perm)[0]
+        return (f,) + O.fd_grad(g, s, lam, alpha, K, perm, idx=idx)
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        res = list(ex.map(one, items))
+    sel = np.zeros(dem.n, bool)
+    sel[idx] = True
+    _K16.update(dem=dem, K=K, L=L, perms=perms, synd=synd, lam=lam, alpha=alpha,
+                loss=sum(r[0] for r in res), dl=sum(r[1] for r in res), da=sum(r[3] for r in res),
+                okl=np.logical_and.reduce([r[2] for r in res]) & sel,
+                oka=np.logical_and.reduce([r[4] for r in res]))
+    return _K16
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_grad_benchmark_configuration_against_finite_differences(torch_cuda, bits):
+    """The backward configuration of the workload list at its own depth: the
+    d = 5 circuit-level graph, L = 32 serial members, K = 16 unrolled
+    iterations, alpha_t = 0.625 and lambda from the priors (moved by up to
+    1e-3 relative to break exact ties), on two shots of the benchmark's
+    batch (its 131072 items would take the oracle hours).
+    The gradient of the summed loss against the oracle's FP64 central
+    differences on every alpha_t and on 64 sampled columns, wherever the
+    oracle flags the loss smooth in every item: FP64 to 1e-6, FP32 to 2e-3
+    (relative to max(1, |value|)).  At least a quarter of the sampled
+    columns and half of the alpha_t must be smooth."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    R = _k16_reference()
+    dem, K, L = R["dem"], R["K"], R["L"]
+    G = P.Graph.from_dem(dem, R["perms"], L=L, M=5, T_max=20, message_bits=bits)
+    loss, dl, da = _run(torch, G, R["synd"], R["lam"], R["alpha"], bits=bits)
+    G.close()
+    okl, oka = R["okl"], R["oka"]
+    tol = 1e-6 if bits == 64 else 2e-3
+    assert abs(loss - R["loss"]) <= (1e-12 if bits == 64 else 1e-4) * max(1.0, abs(R["loss"])), (loss, R["loss"])
+    assert okl.sum() >= 16 and oka.sum() >= K // 2, (okl.sum(), oka.sum())
+    _close(dl, R["dl"], okl, tol)
+    _close(da, R["da"], oka, tol)
+    rel = lambda a, b, ok: float((np.abs(a - b)[ok] / np.maximum(1.0, np.abs(b)[ok])).max())
+    print(f"K=16 FP{bits}: loss {loss:.6g} (oracle {R['loss']:.6g}); {int(okl.sum())} of 64 columns and "
+          f"{int(oka.sum())} of {K} alpha_t smooth; largest relative error {rel(dl, R['dl'], okl):.2e} "
+          f"(lambda), {rel(da, R['da'], oka):.2e} (alpha)", flush=True)
