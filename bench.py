@@ -408,6 +408,8 @@ def main():
     ap.add_argument("--grad-batch", type=int, default=4096)
     ap.add_argument("--grad-K", type=int, default=16)
     ap.add_argument("--grad-only", action="store_true", help="run only the gradient leg (for profiling)")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving leg")
+    ap.add_argument("--ragged-only", action="store_true", help="run only the ragged leg")
     ap.add_argument("--serving-seconds", type=float, default=3.0, help="length of each offered-load run")
     ap.add_argument("--ragged-shots", type=str, default="128,1024", help="shots per code in the ragged leg")
     ap.add_argument("--copy-probe", action="store_true",
@@ -439,6 +441,13 @@ def main():
     if args.grad_only:
         print(json.dumps({"grad": grad_leg(P, torch, args.seed, args.grad_batch, args.grad_K)}), flush=True)
         return
+    if args.serving_only:
+        print(json.dumps({"serving": serving_leg(P, torch, args.seed, args.serving_seconds)}), flush=True)
+        return
+    if args.ragged_only:
+        print(json.dumps({"ragged": [ragged_leg(P, torch, int(k), args.seed) for k in args.ragged_shots.split(",")]}),
+              flush=True)
+        return
 
     # measured HBM ceiling: a 1 GiB device-to-device copy (read + write),
     # timed with events on the copy's stream
@@ -465,6 +474,21 @@ def main():
         f"in {time.time() - t0:.1f}s")
     G = P.Graph.from_dem(dem, perms, L=L, M=M, T_max=T, alpha=alpha)
     info = G.info()
+    # the ceiling of the BP kernel's own access pattern: every resident
+    # wavefront (24 per CU) streams a slab of this graph's size up and down,
+    # reading and rewriting one 256-byte run per step (vibe_measure_slab_stream)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    waves, region = 24 * cus, 256 * max(int(info["chunks_max"]), 1)
+    sbuf = torch.zeros(waves * region // 4, dtype=torch.float32, device=dev)
+    st_ = torch.cuda.current_stream()
+    P._check(P.lib().vibe_measure_slab_stream(P._ptr(sbuf), region, waves, 2, P._stream(st_)))
+    e0.record(st_)
+    P._check(P.lib().vibe_measure_slab_stream(P._ptr(sbuf), region, waves, 4, P._stream(st_)))
+    e1.record(st_)
+    torch.cuda.synchronize()
+    stream_gbs = 2 * waves * region * 4 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del sbuf
+    log(f"slab stream ceiling: {stream_gbs:.0f} GB/s ({waves} wavefronts x {region} B)")
     synd = torch.from_numpy(batch.syndromes).to(dev)
     B = synd.shape[0]
     words = (dem.n + 63) // 64
@@ -510,11 +534,16 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "measured_peak": round(copy_gbs, 1), "frac_of_measured": round(achieved / copy_gbs, 4),
                 "traffic": measured_traffic(launch_shots),
+                "slab_stream_ceiling": round(stream_gbs, 1),
                 "kernel": "bp_ensemble_kernel",
                 "avg_launch_ms": round(bp_ms / max(bp_launches, 1), 3),
                 "edge_updates_per_s": edge_updates / bp_s if bp_s > 0 else 0.0,
                 "kernel_ms": {k: round(v[0], 2) for k, v in prof.items()}}
 
+    if roofline["traffic"]:
+        moved = roofline["traffic"] / (bp_ms / max(bp_launches, 1) / 1e3) / 1e9
+        roofline["moved_gbs"] = round(moved, 1)
+        roofline["moved_frac_of_slab_stream_ceiling"] = round(moved / stream_gbs, 4)
     result = {
         "metric": "decoded shots/s at d=9 circuit-level p=1e-3, batched vs plain; p99 latency",
         "value": round(shots_per_s, 1),

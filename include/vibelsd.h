@@ -325,7 +325,10 @@ int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B, void* str
  * is free the thread takes the oldest queued request and, in order, the
  * later queued requests on the same graph while the batch still fits the
  * largest free block and the batch limits; an oldest request that does not
- * fit yet waits for batches to retire.  Requests arriving while others run
+ * fit yet waits for batches to retire.  With two or more slots, the last
+ * free slot only takes requests on the cheapest graphs (per-shot work
+ * edges x T_max x L within twice the smallest of the server's graphs), so
+ * their short batches never wait behind the long ones of large codes.  Requests arriving while others run
  * are so admitted as slots and memory free up, and their work overlaps on
  * the device.  Every request's outputs are exactly those of vibe_decode on
  * it alone.  vibe_server_wait blocks until the request is done and gives its
@@ -403,6 +406,18 @@ int vibe_bp_grad(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint32_t K
  */
 int vibe_profile_enable(vibe_graph* g, int enable);
 int vibe_profile_read(vibe_graph* g, double* ms /*[3]*/, uint64_t* launches /*[3]*/);
+
+/*
+ * Measurement of the HBM ceiling for the BP kernel's access pattern: `waves`
+ * wavefronts each stream a private region of region_bytes of buf (device,
+ * waves x region_bytes bytes, float data that is overwritten) `passes` times,
+ * alternately up and down, reading and rewriting one 256-byte run per step
+ * with loads three steps ahead, as the BP sweep and its backward pass move
+ * a message slab.  Bytes moved = 2 x waves x region_bytes x passes; time it
+ * with events on `stream`.  region_bytes: a positive multiple of 256.  For
+ * the benchmark's roofline only; not part of the decode path.
+ */
+int vibe_measure_slab_stream(float* buf, uint64_t region_bytes, uint32_t waves, uint32_t passes, void* stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* vibe_last_error(void);

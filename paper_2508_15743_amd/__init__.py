@@ -96,6 +96,7 @@ EXPORTS = {
     "vibe_server_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                    C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "vibe_server_destroy": (None, [C.c_void_p]),
+    "vibe_measure_slab_stream": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_void_p]),
     "vibe_last_error": (C.c_char_p, []),
     "vibe_version": (C.c_char_p, []),
 }

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvibelsd.so")
-SOURCES = ["graph.hip", "bp.hip", "select.hip", "lsd.hip", "api.hip", "runtime.hip", "grad.hip"]
+SOURCES = ["graph.hip", "bp.hip", "select.hip", "lsd.hip", "api.hip", "runtime.hip", "grad.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

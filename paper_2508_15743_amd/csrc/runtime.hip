@@ -526,6 +526,9 @@ extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B
 // in order, the later queued requests on the same graph, while the batch
 // still fits the largest free block of the pool (and the batch limits);
 // if the oldest request does not fit yet it waits for batches to retire.
+// The last free slot goes only to the cheapest graphs (per-shot work
+// E x T x L within twice the smallest), so short batches never queue behind
+// the long serial chains of large codes.
 // Requests that arrive while others run are thus admitted as slots and
 // memory free up, and their work overlaps on the device.
 
@@ -639,6 +642,7 @@ struct vibe_server {
     vibe_server_config cfg{};
     int device = 0;
     std::vector<SrvSlot> slots;
+    std::vector<bool> cheap;  // per graph: per-shot work within twice the smallest
     vibe::Workspace pool;
     PoolMap map;
     size_t in_use = 0, peak = 0;
@@ -693,10 +697,23 @@ void server_loop(vibe_server* S) {
                 any_busy = any_busy || S->slots[i].busy;
             }
             if (S->stop && S->queue.empty() && !any_busy) return;
-            if (slot >= 0 && !S->queue.empty()) {
-                // the oldest request's graph, then later requests on it in
-                // order, while the batch fits the largest free block
-                const uint32_t gi = S->queue.front().gi;
+            size_t n_free = 0;
+            for (const SrvSlot& sl2 : S->slots) n_free += sl2.busy ? 0 : 1;
+            // the graph of the oldest request that may take the free slot:
+            // the last free slot is kept for the cheapest graphs (per-shot
+            // work E x T x L within twice the smallest), so that their short
+            // batches never wait for the long serial chains of large codes
+            size_t head = S->queue.size();
+            for (size_t i = 0; i < S->queue.size(); i++) {
+                if (n_free > 1 || S->slots.size() == 1 || S->cheap[S->queue[i].gi]) {
+                    head = i;
+                    break;
+                }
+            }
+            if (slot >= 0 && head < S->queue.size()) {
+                // that request's graph, then later requests on it in order,
+                // while the batch fits the largest free block
+                const uint32_t gi = S->queue[head].gi;
                 vibe_graph* G = S->graphs[gi];
                 const size_t room = S->map.largest();
                 // candidates within the batch limits, then the longest
@@ -705,7 +722,7 @@ void server_loop(vibe_server* S) {
                 std::vector<size_t> pick;
                 std::vector<uint64_t> upto;  // shots of the first k + 1 candidates
                 uint64_t shots = 0;
-                for (size_t i = 0; i < S->queue.size() && pick.size() < S->cfg.max_batch_requests; i++) {
+                for (size_t i = head; i < S->queue.size() && pick.size() < S->cfg.max_batch_requests; i++) {
                     const SrvReq& r = S->queue[i];
                     if (r.gi != gi) continue;
                     if (!pick.empty() && shots + r.req.B > S->cfg.max_batch_shots) break;
@@ -731,8 +748,8 @@ void server_loop(vibe_server* S) {
                 if (pick.empty() && !any_busy) {
                     // cannot happen for admitted requests (each fits the
                     // whole pool alone), kept as a guard against a stall
-                    std::vector<uint64_t> t1{S->queue.front().ticket};
-                    S->queue.pop_front();
+                    std::vector<uint64_t> t1{S->queue[head].ticket};
+                    S->queue.erase(S->queue.begin() + (std::ptrdiff_t)head);
                     finish_tickets(S, t1, VIBE_ENOMEM);
                     continue;
                 }
@@ -867,6 +884,17 @@ extern "C" int vibe_server_create(vibe_graph* const* graphs, uint32_t n_graphs, 
     S->cfg = *cfg;
     S->device = graphs[0]->device;
     S->slots.resize(cfg->slots);
+    {
+        double least = 0.0;
+        std::vector<double> work(n_graphs);
+        for (uint32_t i = 0; i < n_graphs; i++) {
+            const DevGraph& g = graphs[i]->h.dg;
+            work[i] = (double)g.E * g.T * g.L;
+            least = i ? std::min(least, work[i]) : work[i];
+        }
+        S->cheap.resize(n_graphs);
+        for (uint32_t i = 0; i < n_graphs; i++) S->cheap[i] = work[i] <= 2.0 * least;
+    }
     int rc = grow(S->pool, pool);
     if (!rc) S->map.reset(S->pool.bytes);
     for (SrvSlot& sl : S->slots) {
