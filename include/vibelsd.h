@@ -189,7 +189,10 @@ int vibe_decode(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint64_t* c
                 uint8_t* observables, vibe_shot_stats* stats, void* stream);
 
 /*
- * vibe_decode with bit-packed syndromes (the a1 ingest variant).
+ * vibe_decode with bit-packed syndromes.  Not a separate operation of the
+ * paper: the same online stage (Sec. III.D.2) taking the syndrome bits of
+ * the decoding problem (Sec. II.B) eight times denser, for callers that
+ * hold them packed.
  *   syndromes    device, B x ceil(m/64) uint64 words, row-major: check c of a
  *                shot is bit (c mod 64) of its word c / 64; bits past m in the
  *                last word are ignored
@@ -205,8 +208,10 @@ int vibe_decode_packed(vibe_graph* g, const uint64_t* syndromes, uint64_t B, uin
 /*
  * The same decoder with one launch sequence per shot: every shot is decoded
  * on its own (ensemble, selection, LSD if needed, observables) before the
- * next one starts.  Same arguments and results as vibe_decode; meant as the
- * per-shot-launch baseline of the batched form.
+ * next one starts.  Not a separate operation of the paper, which decodes one
+ * shot at a time on a CPU (Sec. III.D.2): this is the per-shot-launch
+ * baseline against which the batched form's throughput is measured.  Same
+ * arguments, results and errors as vibe_decode.
  */
 int vibe_decode_plain(vibe_graph* g, const uint8_t* syndromes, uint64_t B, uint64_t* corrections,
                       uint8_t* observables, vibe_shot_stats* stats, void* stream);

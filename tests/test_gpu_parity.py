@@ -755,3 +755,42 @@ def test_saturation_flag(torch_cuda):
     _, _, st = G.decode(_dev(torch, b.syndromes))
     assert not (st[:, 0].cpu().numpy() & 8).any()
     G.close()
+
+
+def test_argument_errors_write_nothing(torch_cuda):
+    """Decode calls report argument errors before anything is queued and
+    leave every output untouched: a NULL syndrome or output pointer, on the
+    batched, packed, per-shot and ragged entry points."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    dem = code_capacity_dem(5, 0.05)
+    G, _ = _graph(dem, 8, 3, 10, 5)
+    s = _dev(torch, sample(dem, 16, 6).syndromes)
+    words = _dev(torch, _pack_rows(sample(dem, 16, 6).syndromes))
+
+    def outs():
+        return (torch.full((16, G.words), -7, dtype=torch.int64, device="cuda:0"),
+                torch.full((16, 1), 9, dtype=torch.uint8, device="cuda:0"),
+                torch.full((16, 8), -5, dtype=torch.int32, device="cuda:0"))
+
+    def untouched(o):
+        torch.cuda.synchronize()
+        return bool((o[0] == -7).all() and (o[1] == 9).all() and (o[2] == -5).all())
+
+    for fn, inp in ((P.vibe_decode, s), (P.vibe_decode_plain, s), (P.vibe_decode_packed, words)):
+        o = outs()
+        with pytest.raises(P.VibeError) as ei:
+            fn(G.handle, None, 16, o[0], o[1], o[2], None)  # no syndromes
+        assert ei.value.code == P.VIBE_EINVAL and untouched(o)
+        with pytest.raises(P.VibeError) as ei:
+            fn(G.handle, inp, 16, None, o[1], o[2], None)  # no corrections
+        assert ei.value.code == P.VIBE_EINVAL and untouched(o)
+    rt = P.Runtime()
+    o = outs()
+    req = P.vibe_request(G.handle.value, s.data_ptr(), 16, None, o[1].data_ptr(), o[2].data_ptr())
+    arr = (P.vibe_request * 1)(req)
+    rc = P.lib().vibe_decode_ragged(rt.handle, arr, 1, None)
+    assert rc == P.VIBE_EINVAL and untouched(o)
+    rt.close()
+    G.close()
