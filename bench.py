@@ -75,26 +75,38 @@ def measured_traffic(launch_shots, profile=PROFILE, sources=KERNEL_SOURCES, key=
     return float(vals["traffic_bytes_per_launch"])
 
 
-def ragged_leg(P, torch, shots, seed):
+def ragged_leg(P, torch, shots, seed, tune=True):
     """Circuit-level codes d = 5, 7, 9, 11, 13 (rounds = d, p = 1e-3) in one
-    ragged call against one vibe_decode per code on the same syndromes."""
+    ragged call against one vibe_decode per code on the same syndromes.
+    With `tune`, each graph is first autotuned on up to 2048 of its shots
+    (slab placement, shots per wavefront, grid) and both paths run with the
+    chosen settings; the choices are reported."""
     from synth.dem import circuit_dem
     from synth.sample import permutations, sample
 
     cfgs = [(5, 32, 5, 20), (7, 32, 5, 20), (9, 32, 5, 20), (11, 32, 5, 20), (13, 64, 7, 25)]
-    pairs = []
+    pairs, tuned = [], []
     for d, L, M, T in cfgs:
         dem = circuit_dem(d, d, 1e-3)
         G = P.Graph.from_dem(dem, permutations(dem.n, L, seed + d), L=L, M=M, T_max=T, alpha=0.625)
-        pairs.append((G, torch.from_numpy(sample(dem, shots, seed + 100 + d).syndromes).to("cuda:0")))
+        s = torch.from_numpy(sample(dem, shots, seed + 100 + d).syndromes).to("cuda:0")
+        if tune:
+            ch = G.autotune(s[:min(shots, 2048)])
+            tuned.append({"code": f"circuit_d{d}_r{d}_p0.001", **{k: ch[k] for k in
+                          ("shots_per_wave", "grid", "slab_in_lds", "from_cache")}, "sample_ms": round(ch["ms"], 2)})
+            log(f"autotune d={d}: {ch}")
+        pairs.append((G, s))
     rt = P.Runtime()
     outs = [P.Runtime.outputs(G, s) for G, s in pairs]
-    rt.decode(pairs, outs=outs)  # warm-up
+    warm = min(shots, 1024)  # kernels, schedules and workspace of the small call
+    rt.decode([(G, s[:warm]) for G, s in pairs])
     torch.cuda.synchronize()
+    log(f"ragged mix: {shots} shots per code, one call")
     t0 = time.perf_counter()
     rt.decode(pairs, outs=outs)
     torch.cuda.synchronize()
     t_ragged = time.perf_counter() - t0
+    log(f"ragged mix: {shots} shots per code, one call per code")
     t0 = time.perf_counter()
     for (G, s), o in zip(pairs, outs):
         G.decode(s, out=o)
@@ -103,7 +115,7 @@ def ragged_leg(P, torch, shots, seed):
     total = shots * len(cfgs)
     res = {"codes": [f"circuit_d{d}_r{d}_p0.001" for d, *_ in cfgs], "shots_per_code": shots,
            "ragged_shots_per_s": round(total / t_ragged, 1), "separate_shots_per_s": round(total / t_sep, 1),
-           "ragged_over_separate": round(t_sep / t_ragged, 3)}
+           "ragged_over_separate": round(t_sep / t_ragged, 3), "autotuned": tuned if tune else None}
     log(f"ragged mix d=5..13: {total / t_ragged:.0f} shots/s in one call, {total / t_sep:.0f} in one call per code")
     rt.close()
     for G, _ in pairs:
@@ -496,6 +508,9 @@ def main():
     obs = torch.empty((B, 1), dtype=torch.uint8, device=dev)
     st = torch.empty((B, 8), dtype=torch.int32, device=dev)
     out = (corr, obs, st)
+    # launch settings: timed on a sample of the batch, kept in the handle
+    tune = G.autotune(synd[:min(B, 4096)])
+    log(f"autotune on {min(B, 4096)} shots: {tune}")
 
     for i in range(args.warmup):
         G.decode(synd, out=out)
@@ -533,7 +548,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "measured_peak": round(copy_gbs, 1), "frac_of_measured": round(achieved / copy_gbs, 4),
-                "traffic": measured_traffic(launch_shots),
+                # the committed counters were taken with one shot per wavefront
+                "traffic": measured_traffic(launch_shots) if tune["shots_per_wave"] == 1 else None,
                 "slab_stream_ceiling": round(stream_gbs, 1),
                 "kernel": "bp_ensemble_kernel",
                 "avg_launch_ms": round(bp_ms / max(bp_launches, 1), 3),
@@ -561,6 +577,7 @@ def main():
                    "m": dem.m, "n": dem.n, "nnz": dem.nnz, "L": L, "M": M, "T_max": T,
                    "alpha": alpha, "lsd_order": 0, "levels": [info["levels_min"], info["levels_max"]]},
         "roofline": roofline,
+        "autotune": {k: tune[k] for k in ("slab_in_lds", "grid", "shots_per_wave", "from_cache")},
         "lsd_fraction": round(lsd_frac, 5),
         "logical_error_rate": ler,
         "mean_member_iterations_per_shot": member_iters / (B * args.steps),

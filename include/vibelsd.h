@@ -307,14 +307,47 @@ int vibe_exec_launch(vibe_exec* ex, void* stream);
 void vibe_exec_destroy(vibe_exec* ex); /* synchronises the device first; NULL accepted */
 
 /*
- * Autotuning of the launch settings of vibe_decode for one graph: times the
- * decode of the given syndromes (device, B x m) with the message slab in
- * LDS (where it fits) or in global memory, and with the BP grid at full,
- * three-quarter and half occupancy; keeps the fastest in the handle.  The
- * decoder's results do not depend on these settings.  Synchronises
- * `stream`.  slab_in_lds and grid (either may be NULL) receive the choice.
+ * Launch settings of the BP ensemble (K1) for one graph.  The ensemble is
+ * (shot, member) work items, each run by one wavefront in the paper's
+ * layout (Sec. III.D.1: the hardware bounds how far the decoders run in
+ * parallel).  Three settings map it onto the GPU; the decoder's results do
+ * not depend on any of them:
+ *   slab_in_lds     1: the member's message slab lives in LDS (only where
+ *                   it fits, one shot per wavefront); 0: global memory.
+ *   grid            persistent BP blocks (0 = as many as fit at once).
+ *   shots_per_wave  1, 2 or 4: one wavefront runs P shots of a member side
+ *                   by side on the member's schedule recut into chunks of
+ *                   64 / P edges (serial schedule only).  On graphs whose
+ *                   64-edge chunks are far from full (the sweep's
+ *                   dependency chain, not its edge count, sets the chunk
+ *                   count) this runs P times the shots per chunk step.
+ * vibe_set_launch applies settings (building the recut schedule on first
+ * use: EUNSUPPORTED for the parallel and layered schedules); settings that
+ * vibe_decode_noalloc uses must be applied before it is called.
+ * vibe_get_launch reads them back (from_cache and ms are 0).
  */
-int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B, void* stream, int* slab_in_lds, int* grid);
+typedef struct vibe_launch {
+    int slab_in_lds;
+    int grid;
+    int shots_per_wave;
+    int from_cache;  /* vibe_autotune: 1 if taken from the shape cache untimed */
+    double ms;       /* vibe_autotune: decode time of the sample (timed run) */
+} vibe_launch_t;
+int vibe_set_launch(vibe_graph* g, const vibe_launch_t* s);
+int vibe_get_launch(const vibe_graph* g, vibe_launch_t* s);
+
+/*
+ * Autotuning: times vibe_decode of the given syndromes (device, B x m) with
+ * the slab in LDS (where it fits) and in global memory and with 1, 2 and 4
+ * shots per wavefront at full occupancy, then the best of those with the BP
+ * grid at 7/8, 3/4, 5/8 and 1/2 of full; applies the fastest to the handle
+ * and stores it in a process-wide cache keyed by the graph's shape (checks,
+ * columns, edges, L, M, T, chunk and level counts, LSD order, precision,
+ * schedule, device) and the batch size class (floor(log2 B)).  A graph of
+ * a cached shape gets the stored settings without timing (from_cache = 1).
+ * Synchronises `stream`.  out (may be NULL) receives the choice.
+ */
+int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B, void* stream, vibe_launch_t* out);
 
 /*
  * Serving: continuous batching over resident graphs, each request admitted

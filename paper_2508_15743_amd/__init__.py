@@ -43,6 +43,11 @@ class vibe_graph_info_t(C.Structure):
                 ("device_bytes", C.c_uint64)]
 
 
+class vibe_launch_t(C.Structure):
+    _fields_ = [("slab_in_lds", C.c_int), ("grid", C.c_int), ("shots_per_wave", C.c_int),
+                ("from_cache", C.c_int), ("ms", C.c_double)]
+
+
 class vibe_request(C.Structure):
     _fields_ = [("graph", C.c_void_p), ("syndromes", C.c_void_p), ("B", C.c_uint64),
                 ("corrections", C.c_void_p), ("observables", C.c_void_p), ("stats", C.c_void_p)]
@@ -86,8 +91,9 @@ EXPORTS = {
     "vibe_exec_create": (C.c_int, [C.POINTER(vibe_request), C.c_uint32, C.POINTER(C.c_void_p)]),
     "vibe_exec_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
     "vibe_exec_destroy": (None, [C.c_void_p]),
-    "vibe_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(C.c_int),
-                                C.POINTER(C.c_int)]),
+    "vibe_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(vibe_launch_t)]),
+    "vibe_set_launch": (C.c_int, [C.c_void_p, C.POINTER(vibe_launch_t)]),
+    "vibe_get_launch": (C.c_int, [C.c_void_p, C.POINTER(vibe_launch_t)]),
     "vibe_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_uint32, C.POINTER(vibe_server_config),
                                      C.POINTER(C.c_void_p)]),
     "vibe_server_submit": (C.c_int, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
@@ -246,10 +252,26 @@ def vibe_exec_destroy(ex):
     lib().vibe_exec_destroy(ex)
 
 
+def _launch_dict(s):
+    return {"slab_in_lds": s.slab_in_lds, "grid": s.grid, "shots_per_wave": s.shots_per_wave,
+            "from_cache": bool(s.from_cache), "ms": s.ms}
+
+
 def vibe_autotune(handle, syndromes, B, stream):
-    lds, grid = C.c_int(), C.c_int()
-    _check(lib().vibe_autotune(handle, _ptr(syndromes), B, stream, C.byref(lds), C.byref(grid)))
-    return lds.value, grid.value
+    s = vibe_launch_t()
+    _check(lib().vibe_autotune(handle, _ptr(syndromes), B, stream, C.byref(s)))
+    return _launch_dict(s)
+
+
+def vibe_set_launch(handle, slab_in_lds=0, grid=0, shots_per_wave=1):
+    s = vibe_launch_t(int(slab_in_lds), int(grid), int(shots_per_wave), 0, 0.0)
+    _check(lib().vibe_set_launch(handle, C.byref(s)))
+
+
+def vibe_get_launch(handle):
+    s = vibe_launch_t()
+    _check(lib().vibe_get_launch(handle, C.byref(s)))
+    return _launch_dict(s)
 
 
 def vibe_profile_enable(handle, enable):
@@ -403,12 +425,24 @@ class Graph:
 
 
 def _graph_autotune(self, syndromes, stream=None):
-    """Time the launch settings of decode() on these syndromes and keep the
-    fastest -> (slab_in_lds, grid)."""
+    """Time the launch settings of decode() on these syndromes (or take them
+    from the per-shape cache) and keep the fastest -> dict with slab_in_lds,
+    grid, shots_per_wave, from_cache, ms."""
     return vibe_autotune(self.handle, self._synd(syndromes), syndromes.shape[0], _stream(stream))
 
 
+def _graph_set_launch(self, slab_in_lds=0, grid=0, shots_per_wave=1):
+    """Apply launch settings (see vibe_set_launch)."""
+    vibe_set_launch(self.handle, slab_in_lds, grid, shots_per_wave)
+
+
+def _graph_get_launch(self):
+    return vibe_get_launch(self.handle)
+
+
 Graph.autotune = _graph_autotune
+Graph.set_launch = _graph_set_launch
+Graph.get_launch = _graph_get_launch
 
 
 def _graph_bp_grad(self, syndromes, lam, alpha, eps=1e-7, stream=None):

@@ -72,7 +72,7 @@ size_t carve_sizes(const DevGraph& g, uint32_t bc, bool decode, int slab_blocks,
         4ull * bc,                                         // fail_list
         64,                                                // counters
         msg_bytes(g) * bp_slabs(g) * slab_blocks * std::max<size_t>((size_t)g.max_chunks * kWave, 1),  // slabs
-        msg_bytes(g) * post_blocks * ((size_t)g.n + kWave),  // posterior slabs
+        msg_bytes(g) * post_blocks * bp_post_elems(g),     // posterior slabs
         decode ? lsd_scratch_per_block(g) * lsd_grid : 0,  // LSD scratch
     };
     size_t total = 0;
@@ -106,10 +106,10 @@ void carve_at(unsigned char* p, const size_t* sizes, ChunkBufs* B) {
 
 // Carve the handle's workspace (grown on demand) for chunks of up to `bc`
 // shots.
-int carve(vibe_graph* G, uint32_t bc, bool decode, int slab_blocks, int post_blocks, int lsd_grid,
-          ChunkBufs* B) {
+int carve(const DevGraph& g, vibe_graph* G, uint32_t bc, bool decode, int slab_blocks, int post_blocks,
+          int lsd_grid, ChunkBufs* B) {
     size_t sizes[kBufs];
-    const size_t total = carve_sizes(G->h.dg, bc, decode, slab_blocks, post_blocks, lsd_grid, sizes);
+    const size_t total = carve_sizes(g, bc, decode, slab_blocks, post_blocks, lsd_grid, sizes);
     int rc = ensure_workspace(G, total);
     if (rc) return rc;
     carve_at(static_cast<unsigned char*>(G->ws.base), sizes, B);
@@ -123,11 +123,11 @@ int lsd_grid_for(uint64_t B) {
 
 int memset_async(void* p, size_t bytes, hipStream_t st) { return launch_zero(p, bytes, st); }
 
-// One chunk of the decoder: shots [shot0, shot0 + n).
-int decode_chunk(vibe_graph* G, const ChunkBufs& W, const uint8_t* synd, uint64_t shot0, uint32_t n,
-                 uint64_t* corr, vibe_shot_stats* stats, int bp_blocks, int lsd_grid, hipStream_t st,
+// One chunk of the decoder: shots [shot0, shot0 + n), on g (the handle's
+// graph, or its view with a recut schedule).
+int decode_chunk(vibe_graph* G, const DevGraph& g, const ChunkBufs& W, const uint8_t* synd, uint64_t shot0,
+                 uint32_t n, uint64_t* corr, vibe_shot_stats* stats, int bp_blocks, int lsd_grid, hipStream_t st,
                  bool in_lds, bool timed = true) {
-    const DevGraph& g = G->h.dg;
     int rc;
     if ((rc = memset_async(W.cmask, 8ull * n * (kMaxT + 1), st)) ||
         (rc = memset_async(W.iters, 4ull * n, st)) || (rc = memset_async(W.qfix, 8ull * n * g.n, st)) ||
@@ -154,7 +154,7 @@ int decode_chunk(vibe_graph* G, const ChunkBufs& W, const uint8_t* synd, uint64_
     b.slab = W.slab;
     b.post_slab = W.post_slab;
     b.counter = W.counters;
-    b.grid = (int)std::min<uint64_t>((uint64_t)bp_blocks, (uint64_t)n * g.L);
+    b.grid = (int)std::min<uint64_t>((uint64_t)bp_blocks, bp_items(g, n));
     if (timed) begin_timed(G, 0, st);
     if ((rc = launch_bp(g, b, st))) return rc;
     if (timed) end_timed(G, 0, st);
@@ -285,7 +285,7 @@ int decode_batch(vibe_graph* G, const uint8_t* bytes, const uint64_t* words, uin
     if (B && (!corrections || (!observables && G->h.k))) return fail(VIBE_EINVAL, "an output pointer is NULL");
     if (!B) return VIBE_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const DevGraph& g = G->h.dg;
+    const DevGraph g = decode_view(G);
     const uint32_t bc = chunk_for(g, B, true);
     uint8_t* u = nullptr;
     if (words) {
@@ -309,12 +309,12 @@ int decode_batch(vibe_graph* G, const uint8_t* bytes, const uint64_t* words, uin
     const int bpg = G->tune_grid > 0 ? std::min(G->tune_grid, bp_grid(g, in_lds)) : bp_grid(g, in_lds);
     const int lg = lsd_grid_for(bc);
     ChunkBufs W;
-    if ((rc = carve(G, bc, true, in_lds ? 0 : bpg, bpg, lg, &W))) return rc;
+    if ((rc = carve(g, G, bc, true, in_lds ? 0 : bpg, bpg, lg, &W))) return rc;
     const uint32_t wm = g.words_m ? g.words_m : 1;
     for (uint64_t s0 = 0; s0 < B; s0 += bc) {
         const uint32_t n = (uint32_t)std::min<uint64_t>(bc, B - s0);
         if (!words) {
-            rc = decode_chunk(G, W, bytes, s0, n, corrections, stats, bpg, lg, st, in_lds);
+            rc = decode_chunk(G, g, W, bytes, s0, n, corrections, stats, bpg, lg, st, in_lds);
         } else {
             const uint64_t cells = (uint64_t)n * g.m;
             if (cells) {
@@ -323,8 +323,8 @@ int decode_batch(vibe_graph* G, const uint8_t* bytes, const uint64_t* words, uin
                 hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return hip_fail(e, "unpack_kernel launch");
             }
-            rc = decode_chunk(G, W, u, 0, n, corrections + s0 * g.words_n, stats ? stats + s0 : nullptr, bpg, lg,
-                              st, in_lds);
+            rc = decode_chunk(G, g, W, u, 0, n, corrections + s0 * g.words_n, stats ? stats + s0 : nullptr, bpg,
+                              lg, st, in_lds);
         }
         if (rc) return rc;
     }
@@ -357,9 +357,9 @@ extern "C" int vibe_decode_plain(vibe_graph* G, const uint8_t* syndromes, uint64
     ChunkBufs W;
     const int blocks = (int)g.L;  // one block per member of the one shot
     const bool in_lds = bp_slab_fits_lds(g);
-    if ((rc = carve(G, 1, true, in_lds ? 0 : blocks, blocks, 1, &W))) return rc;
+    if ((rc = carve(g, G, 1, true, in_lds ? 0 : blocks, blocks, 1, &W))) return rc;
     for (uint64_t s0 = 0; s0 < B; s0++) {
-        if ((rc = decode_chunk(G, W, syndromes, s0, 1, corrections, stats, blocks, 1, st, in_lds))) return rc;
+        if ((rc = decode_chunk(G, g, W, syndromes, s0, 1, corrections, stats, blocks, 1, st, in_lds))) return rc;
         if ((rc = launch_observables(g, corrections, s0, 1, observables, st))) return rc;
     }
     return VIBE_OK;
@@ -380,7 +380,7 @@ extern "C" int vibe_bp_ensemble(vibe_graph* G, const uint8_t* syndromes, uint64_
     const bool in_lds = bp_slab_fits_lds(g);
     const int bpg = bp_grid(g, in_lds);
     ChunkBufs W;
-    if ((rc = carve(G, bc, false, in_lds ? 0 : bpg, bpg, 0, &W))) return rc;
+    if ((rc = carve(g, G, bc, false, in_lds ? 0 : bpg, bpg, 0, &W))) return rc;
     for (uint64_t s0 = 0; s0 < B; s0 += bc) {
         const uint32_t n = (uint32_t)std::min<uint64_t>(bc, B - s0);
         if ((rc = memset_async(W.cmask, 8ull * n * (kMaxT + 1), st)) ||
@@ -488,7 +488,7 @@ int scratch_for_device(int dev, unsigned char** out) {
 bool noalloc_plan(const DevGraph& g, bool in_lds, int full_grid, uint64_t B, size_t cap, int* bpg, int* lg,
                   uint32_t* bc, size_t* sizes) {
     const size_t slab = in_lds ? 0 : msg_bytes(g) * bp_slabs(g) * std::max<size_t>((size_t)g.max_chunks * kWave, 1);
-    const size_t per_block = al256(slab) + al256(msg_bytes(g) * ((size_t)g.n + kWave));
+    const size_t per_block = al256(slab) + al256(msg_bytes(g) * bp_post_elems(g));
     const size_t per_lsd = lsd_scratch_per_block(g);
     int grid = (int)std::min<size_t>((size_t)full_grid, (cap / 2) / per_block);
     int lsd = (int)std::min<size_t>(512, (cap / 4) / per_lsd);
@@ -519,7 +519,7 @@ extern "C" int vibe_decode_noalloc(vibe_graph* G, const uint8_t* syndromes, uint
     if (rc) return rc;
     if (B && (!corrections || (!observables && G->h.k))) return fail(VIBE_EINVAL, "an output pointer is NULL");
     if (!B) return VIBE_OK;
-    const DevGraph& g = G->h.dg;
+    const DevGraph g = decode_view(G);
     const bool in_lds = bp_slab_fits_lds(g) && G->tune_lds != 0;
     const int full = G->tune_grid > 0 ? std::min(G->tune_grid, bp_grid(g, in_lds)) : bp_grid(g, in_lds);
     int bpg = 0, lg = 0;
@@ -536,7 +536,8 @@ extern "C" int vibe_decode_noalloc(vibe_graph* G, const uint8_t* syndromes, uint
     hipStream_t st = static_cast<hipStream_t>(stream);
     for (uint64_t s0 = 0; s0 < B; s0 += bc) {
         const uint32_t n = (uint32_t)std::min<uint64_t>(bc, B - s0);
-        if ((rc = decode_chunk(G, W, syndromes, s0, n, corrections, stats, bpg, lg, st, in_lds, false))) return rc;
+        if ((rc = decode_chunk(G, g, W, syndromes, s0, n, corrections, stats, bpg, lg, st, in_lds, false)))
+            return rc;
     }
     return launch_observables(g, corrections, 0, (uint32_t)std::min<uint64_t>(B, UINT32_MAX), observables, st);
 }

@@ -164,7 +164,20 @@ struct Ctx {
     F al, lim;
     int lane;
     uint32_t lane4, laneF;  // lane * 4, lane * sizeof(F)
+    uint32_t rec4, recF;    // several shots per wavefront: the lane's slot in
+                            // a record of W = 64 / P entries, * 4, * sizeof(F)
 };
+
+// Byte offsets of the fields in a chunk record of W entries per field.
+template <class F, uint32_t W>
+struct RecW {
+    static constexpr uint32_t kV = 4 * W, kLam = 8 * W, kInit = 8 * W + W * (uint32_t)sizeof(F);
+    static constexpr uint32_t kBytes = W * (8 + 2 * (uint32_t)sizeof(F));
+};
+static_assert(RecW<float, 64>::kV == kRecV && RecW<float, 64>::kLam == kRecLam &&
+                  RecW<float, 64>::kInit == rec_init(false) && RecW<float, 64>::kBytes == rec_bytes(false) &&
+                  RecW<double, 64>::kInit == rec_init(true) && RecW<double, 64>::kBytes == rec_bytes(true),
+              "record geometry");
 
 // Every vector memory operation of a chunk step is issued unconditionally
 // (prefetch indices are clamped instead of tested, unused slots store junk
@@ -195,24 +208,26 @@ struct Stage {
     F old;  // parallel schedule: the edge's message of the previous iteration
 };
 
-template <class F, bool SLAB_LDS, bool FLOOD>
+// W: entries per record field (64 / shots per wavefront).  The slab slot
+// of a lane is always chunk * 64 + lane.
+template <class F, bool SLAB_LDS, bool FLOOD, uint32_t W = kWave>
 __device__ __forceinline__ void fetch(const Ctx<F>& x, Stage<F>& s, uint32_t k, bool first) {
     using P = Prec<F>;
     using B = typename P::B;
-    constexpr bool kF64 = sizeof(F) == 8;
+    using R = RecW<F, W>;
     // chunk offset added to the lane offset (a short-lived VGPR); field
     // offsets become instruction immediates
-    const uint32_t base = k * rec_bytes(kF64);
-    const uint32_t o4 = x.lane4 + base, oF = x.laneF + base;
+    const uint32_t base = k * R::kBytes;
+    const uint32_t o4 = (W == kWave ? x.lane4 : x.rec4) + base, oF = (W == kWave ? x.laneF : x.recF) + base;
     s.meta = bload<uint32_t>(x.sch, o4, 0);
-    s.v = bload<uint32_t>(x.sch, o4 + kRecV, 0);
-    s.lam = bload<F>(x.sch, oF + kRecLam, 0);
+    s.v = bload<uint32_t>(x.sch, o4 + R::kV, 0);
+    s.lam = bload<F>(x.sch, oF + R::kLam, 0);
     if constexpr (SLAB_LDS) {
         s.suf = x.lslab[k * kWave + x.lane];
     } else {
         // first sweep: the initial suffix states of the schedule record
         const Rsrc r = first ? x.sch : x.slb;
-        const uint32_t o = first ? oF + rec_init(kF64) : x.laneF + k * kWave * (uint32_t)sizeof(B);
+        const uint32_t o = first ? oF + R::kInit : x.laneF + k * kWave * (uint32_t)sizeof(B);
         s.suf = bload<B>(r, o, 0);
     }
     if constexpr (FLOOD) {
@@ -324,18 +339,18 @@ __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, 
 // The whole sweep: chunks 0 .. nch-1 (nch >= 1), each one's slots loaded
 // kDepth chunks ahead (the suffix states of later chunks are final for the
 // whole sweep).
-template <class F, bool SLAB_LDS, bool WANT_POST, bool FLOOD>
+template <class F, bool SLAB_LDS, bool WANT_POST, bool FLOOD, uint32_t W = kWave>
 __device__ __forceinline__ void sweep(const Ctx<F>& x, uint32_t nch, bool first, uint64_t& sat) {
     const uint32_t last = nch - 1;
     Stage<F> ring[kDepth];
 #pragma unroll
-    for (int d = 0; d < kDepth; d++) fetch<F, SLAB_LDS, FLOOD>(x, ring[d], min((uint32_t)d, last), first);
+    for (int d = 0; d < kDepth; d++) fetch<F, SLAB_LDS, FLOOD, W>(x, ring[d], min((uint32_t)d, last), first);
     for (uint32_t k = 0; k < nch; k += kDepth) {
 #pragma unroll
         for (int d = 0; d < kDepth; d++) {
             if (k + d >= nch) break;
             sweep_chunk<F, SLAB_LDS, WANT_POST, FLOOD>(x, ring[d], k + d, sat);
-            fetch<F, SLAB_LDS, FLOOD>(x, ring[d], min(k + d + kDepth, last), first);
+            fetch<F, SLAB_LDS, FLOOD, W>(x, ring[d], min(k + d + kDepth, last), first);
         }
     }
 }
@@ -346,10 +361,10 @@ struct BStage {
     typename Prec<F>::B msg;
 };
 
-template <class F, bool SLAB_LDS, bool FLOOD>
+template <class F, bool SLAB_LDS, bool FLOOD, uint32_t W = kWave>
 __device__ __forceinline__ void bfetch(const Ctx<F>& x, BStage<F>& s, uint32_t k) {
     using B = typename Prec<F>::B;
-    s.meta = bload<uint32_t>(x.sch, x.lane4 + k * rec_bytes(sizeof(F) == 8), 0);
+    s.meta = bload<uint32_t>(x.sch, (W == kWave ? x.lane4 : x.rec4) + k * RecW<F, W>::kBytes, 0);
     // the sweep's new messages: in the state slab itself (serial), or in the
     // message slab (parallel)
     if constexpr (SLAB_LDS)
@@ -379,18 +394,18 @@ __device__ __forceinline__ void back_chunk(const Ctx<F>& x, const BStage<F>& s, 
 // Backward pass over chunks nch-1 .. 0 (nch >= 1) with loads kDepth chunks
 // ahead.  Edges of one chunk sit in distinct rows, so a chunk is one
 // parallel step.
-template <class F, bool SLAB_LDS, bool FLOOD>
+template <class F, bool SLAB_LDS, bool FLOOD, uint32_t W = kWave>
 __device__ __forceinline__ void backward(const Ctx<F>& x, uint32_t nch, typename Prec<F>::B* running) {
     BStage<F> ring[kDepth];
     auto at = [nch](uint32_t d) { return d < nch ? nch - 1 - d : 0u; };  // d chunks from the end
 #pragma unroll
-    for (int d = 0; d < kDepth; d++) bfetch<F, SLAB_LDS, FLOOD>(x, ring[d], at(d));
+    for (int d = 0; d < kDepth; d++) bfetch<F, SLAB_LDS, FLOOD, W>(x, ring[d], at(d));
     for (uint32_t e = 0; e < nch; e += kDepth) {
 #pragma unroll
         for (int d = 0; d < kDepth; d++) {
             if (e + d >= nch) break;
             back_chunk<F, SLAB_LDS>(x, ring[d], nch - 1 - e - d, running);
-            bfetch<F, SLAB_LDS, FLOOD>(x, ring[d], at(e + d + kDepth));
+            bfetch<F, SLAB_LDS, FLOOD, W>(x, ring[d], at(e + d + kDepth));
         }
     }
 }
@@ -571,6 +586,97 @@ __device__ __forceinline__ void layered_sweep(const DevGraph& g, const Ctx<F>& x
     }
 }
 
+// The outputs of a work item whose syndrome is zero, with every lambda > 0:
+// the first sweep leaves every message positive, so the decision is e = 0
+// and it satisfies s at t = 1.
+__device__ __forceinline__ void zero_item(const DevGraph& g, const BpLaunch& a, uint32_t shot, uint32_t mem,
+                                          int lane) {
+    const uint32_t rec = shot * g.L + mem;
+    uint64_t* cmask = a.conv_mask + (size_t)shot * (kMaxT + 1);
+    if (a.cand)
+        for (uint32_t w = lane; w < g.words_n; w += kWave) a.cand[(size_t)rec * g.words_n + w] = 0;
+    if (lane == 0) {
+        a.t_conv[rec] = 1;
+        if (a.weight) a.weight[rec] = 0.0;
+        atomicOr(reinterpret_cast<unsigned long long*>(&cmask[1]), 1ull << mem);
+        atomicAdd(&a.iters[shot], 1u);
+    }
+}
+
+// The outputs of a finished work item (member mem on shot `shot`): its
+// convergence record, candidate and weight, saturation mark, and its
+// contribution to the normalised average.  eb: its decisions (LDS); post:
+// its posteriors of the last sweep, written by any lane of the wavefront.
+template <class F>
+__device__ __forceinline__ void finish_item(const DevGraph& g, const BpLaunch& a, uint32_t shot, uint32_t mem,
+                                            uint32_t conv_t, uint32_t ran, bool stopped, bool saturated,
+                                            const uint64_t* eb, const F* post, int lane) {
+    const uint32_t rec = shot * g.L + mem;
+    uint64_t* cmask = a.conv_mask + (size_t)shot * (kMaxT + 1);
+    // a run that reached the clamp marks its member in word 0 of the shot's
+    // convergence masks (iterations count from 1, so that word is free)
+    if (lane == 0) {
+        a.t_conv[rec] = (int32_t)conv_t;
+        atomicAdd(&a.iters[shot], ran);
+        if (saturated) atomicOr(reinterpret_cast<unsigned long long*>(&cmask[0]), 1ull << mem);
+    }
+    if (a.cand && (conv_t || !a.use_M))
+        for (uint32_t w = lane; w < g.words_n; w += kWave) a.cand[(size_t)rec * g.words_n + w] = eb[w];
+    if (a.weight && conv_t) {
+        // W(e) = sum_v e_v lambda_v in FP64, ascending v
+        double W = 0.0;
+        for (uint32_t base = 0; base < g.words_n; base += kWave) {
+            const uint32_t w = base + lane;
+            uint64_t nzw = __ballot(w < g.words_n && eb[w] != 0);
+            if (lane == 0) {
+                while (nzw) {
+                    const int bi = __ffsll((long long)nzw) - 1;
+                    nzw &= nzw - 1;
+                    uint64_t xw = eb[base + bi];
+                    while (xw) {
+                        const int bb = __ffsll((long long)xw) - 1;
+                        xw &= xw - 1;
+                        W += g.lam64[(size_t)(base + bi) * 64 + bb];
+                    }
+                }
+            }
+        }
+        if (lane == 0) a.weight[rec] = W;
+    }
+    if (lane == 0 && conv_t) atomicOr(reinterpret_cast<unsigned long long*>(&cmask[conv_t]), 1ull << mem);
+    if (a.accumulate_q && !conv_t && !stopped && ran == a.T_run) {
+        // normalised posterior, summed over the members of a shot with no
+        // converged member, in 2^-56 fixed point (order-independent)
+        uint32_t cnt = 0;
+        for (uint32_t tt = lane + 1; tt <= a.T_run; tt += kWave) cnt += __popcll(load_mask(&cmask[tt]));
+        if (wave_sum_u32(cnt) == 0) {
+            // ||L||^2 summed in ascending v: each lane squares one value of
+            // a block of 64 and the running sum takes them in order (every
+            // lane holds the same sum).  post[v] was written by the lane
+            // that swept v: read it past the L1.
+            double ss = 0.0;
+            for (uint32_t base = 0; base < g.n; base += kWave) {
+                const uint32_t v = base + lane;
+                double sq = 0.0;
+                if (v < g.n) {
+                    const double xv = (double)__hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    sq = xv * xv;
+                }
+                const uint32_t cnt_b = min((uint32_t)kWave, g.n - base);
+                for (uint32_t j = 0; j < cnt_b; j++) ss += readlane_f64(sq, (int)j);
+            }
+            if (uni(ss > 0.0 ? 1u : 0u)) {
+                const double scale = kQScale / sqrt(ss);
+                int64_t* q = a.qfix + (size_t)shot * g.n;
+                for (uint32_t v = lane; v < g.n; v += kWave) {
+                    const double xv = (double)__hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&q[v]), (unsigned long long)llrint(xv * scale));
+                }
+            }
+        }
+    }
+}
+
 template <class F, bool SLAB_LDS, bool FLOOD, bool LAYERED = false>
 __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, uint32_t item, unsigned char* lds,
                                          Ctx<F> x) {
@@ -629,16 +735,7 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
         return;
     }
     if (!any && a.fast_zero && g.all_lam_positive) {
-        // s = 0 with every lambda > 0: the first sweep leaves every message
-        // positive, so the decision is e = 0 and it satisfies s at t = 1.
-        if (a.cand)
-            for (uint32_t w = lane; w < g.words_n; w += kWave) a.cand[(size_t)rec * g.words_n + w] = 0;
-        if (lane == 0) {
-            a.t_conv[rec] = 1;
-            if (a.weight) a.weight[rec] = 0.0;
-            atomicOr(reinterpret_cast<unsigned long long*>(&cmask[1]), 1ull << mem);
-            atomicAdd(&a.iters[shot], 1u);
-        }
+        zero_item(g, a, shot, mem, lane);
         return;
     }
     for (uint32_t w = lane; w < g.words_n; w += kWave) eb[w] = g.e0[w];
@@ -716,68 +813,159 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
         }
     }
 
-    // a run that reached the clamp marks its member in word 0 of the shot's
-    // convergence masks (iterations count from 1, so that word is free)
-    const bool saturated = uni(sat != 0 ? 1u : 0u) != 0;
-    if (lane == 0) {
-        a.t_conv[rec] = (int32_t)conv_t;
-        atomicAdd(&a.iters[shot], ran);
-        if (saturated) atomicOr(reinterpret_cast<unsigned long long*>(&cmask[0]), 1ull << mem);
+    finish_item<F>(g, a, shot, mem, conv_t, ran, stopped, uni(sat != 0 ? 1u : 0u) != 0, eb, post, lane);
+}
+
+// One work item of the multi-shot launch: member mem on the P shots
+// grp * P .. grp * P + P - 1 (those below n_shots) side by side, on the
+// member's schedule recut into chunks of W = 64 / P edges.  Lanes
+// p * W .. p * W + W - 1 run shot p: every lane does what it does for one
+// shot, on its shot's row states, decisions and posteriors (LDS, shot p's
+// copy), so a column's edges are still consecutive lanes.  Each shot
+// finishes on its own (converged, or out of the first M): its outputs are
+// written then, and its lanes go on with work that is never read.  The
+// item ends when every shot has finished.  Global slab, serial schedule,
+// stop on convergence (so a shot's convergence iteration is the iteration
+// it finishes at, and its iterations run are those before it finishes).
+template <class F, int P>
+__device__ __forceinline__ void run_group(const DevGraph& g, const BpLaunch& a, uint32_t item, unsigned char* lds,
+                                          Ctx<F> x) {
+    using PR = Prec<F>;
+    using B = typename PR::B;
+    constexpr uint32_t W = kWave / P;
+    constexpr uint32_t kAll = (1u << P) - 1u;
+    const int lane = x.lane;
+    const uint32_t p = (uint32_t)lane / W;
+    uint64_t* sb0 = reinterpret_cast<uint64_t*>(lds);
+    uint64_t* res0 = sb0 + P * g.words_m;
+    uint64_t* eb0 = res0 + P * g.words_m;
+    B* pref0 = reinterpret_cast<B*>(eb0 + P * g.words_n);
+    F* post0 = x.post;  // P x n posteriors, then 64 trash slots
+    const F* lamv = reinterpret_cast<const F*>(g.lam);
+    const B ident = PR::ident(g);
+    x.lslab = nullptr;
+    x.lmslab = nullptr;
+    x.sb = sb0 + p * g.words_m;
+    x.res = res0 + p * g.words_m;
+    x.eb = eb0 + p * g.words_n;
+    x.pref = pref0 + p * g.m;
+    x.post = post0 + p * g.n;
+    x.trash = post0 + P * g.n;
+    x.rec4 = ((uint32_t)lane % W) * 4u;
+    x.recF = ((uint32_t)lane % W) * (uint32_t)sizeof(F);
+    x.al = (F)g.alpha;
+    x.lim = (F)g.clamp;
+
+    const uint32_t groups = (a.n_shots + P - 1) / P;
+    uint32_t grp, mem;
+    if (a.member_major) {
+        mem = item / groups;
+        grp = item % groups;
+    } else {
+        grp = item / g.L;
+        mem = item % g.L;
     }
-    if (a.cand && (conv_t || !a.use_M))
-        for (uint32_t w = lane; w < g.words_n; w += kWave) a.cand[(size_t)rec * g.words_n + w] = eb[w];
-    if (a.weight && conv_t) {
-        // W(e) = sum_v e_v lambda_v in FP64, ascending v
-        double W = 0.0;
-        for (uint32_t base = 0; base < g.words_n; base += kWave) {
-            const uint32_t w = base + lane;
-            uint64_t nzw = __ballot(w < g.words_n && eb[w] != 0);
+    const uint32_t first = grp * P;
+    const uint32_t nact = uni(min((uint32_t)P, a.n_shots - first));  // shots present (>= 1)
+
+    // ---- syndrome bits of each shot; absent shots read shot `first`'s
+    // bytes and count as finished
+    uint32_t done = 0, nonzero = 0;
+#pragma unroll
+    for (int q = 0; q < P; q++) {
+        const bool act = (uint32_t)q < nact;
+        const uint8_t* s = a.syndromes + (size_t)(a.shot0 + first + (act ? (uint32_t)q : 0u)) * g.m;
+        uint64_t any = 0;
+        for (uint32_t base = 0; base < g.m; base += kWave) {
+            const uint32_t c = base + lane;
+            const uint64_t mask = __ballot(act && c < g.m && s[c] != 0);
             if (lane == 0) {
-                while (nzw) {
-                    const int bi = __ffsll((long long)nzw) - 1;
-                    nzw &= nzw - 1;
-                    uint64_t xw = eb[base + bi];
-                    while (xw) {
-                        const int bb = __ffsll((long long)xw) - 1;
-                        xw &= xw - 1;
-                        W += g.lam64[(size_t)(base + bi) * 64 + bb];
-                    }
-                }
+                sb0[q * g.words_m + base / kWave] = mask;
+                res0[q * g.words_m + base / kWave] = mask;
+            }
+            any |= mask;
+        }
+        if (!act) {
+            done |= 1u << q;
+        } else {
+            uint64_t* cm = a.conv_mask + (size_t)(first + q) * (kMaxT + 1);
+            if (a.use_M && preceding_converged(cm, 1, mem, lane) >= g.M) {
+                // M members of lower index converged at the first iteration
+                if (lane == 0) a.t_conv[(first + q) * g.L + mem] = 0;
+                done |= 1u << q;
+            } else if (!any && a.fast_zero && g.all_lam_positive) {
+                zero_item(g, a, first + q, mem, lane);
+                done |= 1u << q;
             }
         }
-        if (lane == 0) a.weight[rec] = W;
     }
-    if (lane == 0 && conv_t) atomicOr(reinterpret_cast<unsigned long long*>(&cmask[conv_t]), 1ull << mem);
-    if (a.accumulate_q && !conv_t && !stopped && ran == a.T_run) {
-        // normalised posterior, summed over the members of a shot with no
-        // converged member, in 2^-56 fixed point (order-independent)
-        uint32_t cnt = 0;
-        for (uint32_t tt = lane + 1; tt <= a.T_run; tt += kWave) cnt += __popcll(load_mask(&cmask[tt]));
-        if (wave_sum_u32(cnt) == 0) {
-            // ||L||^2 summed in ascending v: each lane squares one value of
-            // a block of 64 and the running sum takes them in order (every
-            // lane holds the same sum).  post[v] was written by the lane
-            // that swept v: read it past the L1.
-            double ss = 0.0;
-            for (uint32_t base = 0; base < g.n; base += kWave) {
-                const uint32_t v = base + lane;
-                double sq = 0.0;
-                if (v < g.n) {
-                    const double xv = (double)__hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    sq = xv * xv;
+    done = uni(done);
+    if (done == kAll) return;
+    for (uint32_t w = lane; w < P * g.words_n; w += kWave) eb0[w] = g.e0[w % g.words_n];
+
+    const uint32_t c0 = uni(g.member_chunk[mem]), nch = uni(g.member_chunk[mem + 1]) - c0;
+    x.sch = make_rsrc(g.sched + (size_t)c0 * RecW<F, W>::kBytes, nch * RecW<F, W>::kBytes);
+
+    uint64_t sat = 0;  // lanes that saw a posterior or message reach the clamp
+    auto sat_of = [&](int q) {
+        const uint64_t mask = ((W == kWave ? ~0ull : (1ull << W) - 1ull)) << (q * W);
+        return uni((sat & mask) != 0 ? 1u : 0u) != 0;
+    };
+    for (uint32_t t = 1; t <= a.T_run; t++) {
+        if (a.use_M && t >= 2) {
+#pragma unroll
+            for (int q = 0; q < P; q++) {
+                if ((done >> q) & 1u) continue;
+                uint64_t* cm = a.conv_mask + (size_t)(first + q) * (kMaxT + 1);
+                if (preceding_converged(cm, t, mem, lane) >= g.M) {
+                    // cannot be among the first M any more
+                    finish_item<F>(g, a, first + q, mem, 0u, t - 1, true, sat_of(q), eb0 + q * g.words_n,
+                                   post0 + q * g.n, lane);
+                    done |= 1u << q;
                 }
-                const uint32_t cnt_b = min((uint32_t)kWave, g.n - base);
-                for (uint32_t j = 0; j < cnt_b; j++) ss += readlane_f64(sq, (int)j);
             }
-            if (uni(ss > 0.0 ? 1u : 0u)) {
-                const double scale = kQScale / sqrt(ss);
-                int64_t* q = a.qfix + (size_t)shot * g.n;
-                for (uint32_t v = lane; v < g.n; v += kWave) {
-                    const double xv = (double)__hip_atomic_load(&post[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    atomicAdd(reinterpret_cast<unsigned long long*>(&q[v]), (unsigned long long)llrint(xv * scale));
-                }
+            done = uni(done);
+            if (done == kAll) return;
+        }
+        if (g.alpha_t) x.al = (F)g.alpha_t[t - 1];
+        const bool want_post = a.accumulate_q && t == a.T_run;
+        if (want_post)  // columns without checks keep L_v = lambda_v
+            for (uint32_t i = lane; i < P * g.n; i += kWave) post0[i] = lamv[i % g.n];
+        for (uint32_t i = lane; i < P * g.m; i += kWave) pref0[i] = ident;
+        __syncthreads();
+        if (nch) {
+            if (want_post)
+                sweep<F, false, true, false, W>(x, nch, t == 1, sat);
+            else
+                sweep<F, false, false, false, W>(x, nch, t == 1, sat);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < P; q++) {
+            if ((done >> q) & 1u) continue;
+            // converged iff the shot's residual s + H e is zero
+            bool nz = false;
+            for (uint32_t w = lane; w < g.words_m; w += kWave) nz |= res0[q * g.words_m + w] != 0;
+            if (__ballot(nz) == 0) {
+                finish_item<F>(g, a, first + q, mem, t, t, false, sat_of(q), eb0 + q * g.words_n,
+                               post0 + q * g.n, lane);
+                done |= 1u << q;
             }
         }
+        done = uni(done);
+        if (done == kAll) return;
+        if (t < a.T_run && nch) {
+            for (uint32_t i = lane; i < P * g.m; i += kWave) pref0[i] = ident;
+            __syncthreads();
+            backward<F, false, false, W>(x, nch, x.pref);
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < P; q++) {
+        if ((done >> q) & 1u) continue;
+        finish_item<F>(g, a, first + q, mem, 0u, a.T_run, false, sat_of(q), eb0 + q * g.words_n,
+                       post0 + q * g.n, lane);
     }
 }
 
@@ -874,6 +1062,64 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_tar
     }
 }
 
+// One launch over the items of one request, P = 2 or 4 shots per
+// wavefront (serial schedule, slab in global memory).
+// occupancy the register allocator aims for with P shots per wavefront
+// (waves per SIMD), the most that keeps every variant free of spills
+template <class F, int P>
+constexpr int multi_waves_target() {
+    return sizeof(F) == 8 || P == 4 ? 4 : 5;
+}
+
+template <class F, int P>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(multi_waves_target<F, P>()))) void bp_multi_kernel(DevGraph g, BpLaunch a) {
+    using B = typename Prec<F>::B;
+    extern __shared__ __align__(16) unsigned char lds[];
+    const uint32_t slab_elems = g.max_chunks * kWave;
+    B* gslab = reinterpret_cast<B*>(a.slab) + (size_t)blockIdx.x * slab_elems;
+    F* post = reinterpret_cast<F*>(a.post_slab) + (size_t)blockIdx.x * (P * g.n + kWave);
+    const Ctx<F> x = block_ctx<F>(gslab, nullptr, slab_elems, post);
+    const uint32_t n_items = (a.n_shots + P - 1) / P * g.L;
+    for (;;) {
+        const uint32_t item = wave_ticket(a.counter, 1u);
+        if (item >= n_items) break;
+        run_group<F, P>(g, a, item, lds, x);
+        __syncthreads();
+    }
+}
+
+// The ragged launch when some request runs several shots per wavefront:
+// every segment on the serial or layered schedule, slabs in global memory;
+// each segment's items follow its own shots per wavefront.
+template <class F>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void bp_ragged_multi_kernel(RaggedLaunch r) {
+    using B = typename Prec<F>::B;
+    using CSeg = const __attribute__((address_space(4))) BpSeg;
+    extern __shared__ __align__(16) unsigned char lds[];
+    CSeg* segs = (CSeg*)r.segs;
+    B* gslab = reinterpret_cast<B*>(r.slab) + (size_t)blockIdx.x * r.slab_elems;
+    F* post = reinterpret_cast<F*>(r.post_slab) + (size_t)blockIdx.x * r.post_elems;
+    const Ctx<F> x = block_ctx<F>(gslab, nullptr, r.slab_elems, post);
+    for (;;) {
+        const uint32_t item = wave_ticket(r.counter, 1u);
+        if (item >= r.n_items) break;
+        uint32_t j = 0;
+        while (j + 1 < r.n_segs && segs[j + 1].item0 <= item) j++;
+        const DevGraph g = load_const(&r.segs[j].g);
+        const BpLaunch a = load_const(&r.segs[j].a);
+        const uint32_t it = item - segs[j].item0;
+        if (g.layered)
+            run_item<F, false, false, true>(g, a, it, lds, x);
+        else if (g.P == 2)
+            run_group<F, 2>(g, a, it, lds, x);
+        else if (g.P == 4)
+            run_group<F, 4>(g, a, it, lds, x);
+        else
+            run_item<F, false, false>(g, a, it, lds, x);
+        __syncthreads();
+    }
+}
+
 __global__ void zero_kernel(uint32_t* p, size_t words) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
         p[i] = 0u;
@@ -886,7 +1132,14 @@ const void* kernel_for_t(bool slab_in_lds, bool ragged) {
     return slab_in_lds ? (const void*)bp_ensemble_kernel<F, true, FLOOD> : (const void*)bp_ensemble_kernel<F, false, FLOOD>;
 }
 
-const void* kernel_for(bool fp64, bool flood, bool slab_in_lds, bool ragged, bool layered = false) {
+const void* kernel_for(bool fp64, bool flood, bool slab_in_lds, bool ragged, bool layered = false, uint32_t P = 1) {
+    // several shots per wavefront (ragged: in some segment): serial
+    // schedule, slab in global memory
+    if (P > 1) {
+        if (ragged) return fp64 ? (const void*)bp_ragged_multi_kernel<double> : (const void*)bp_ragged_multi_kernel<float>;
+        if (P == 2) return fp64 ? (const void*)bp_multi_kernel<double, 2> : (const void*)bp_multi_kernel<float, 2>;
+        return fp64 ? (const void*)bp_multi_kernel<double, 4> : (const void*)bp_multi_kernel<float, 4>;
+    }
     // the layered schedule: one request at a time, slab in global memory
     if (layered) return fp64 ? (const void*)bp_ensemble_kernel<double, false, false, true>
                              : (const void*)bp_ensemble_kernel<float, false, false, true>;
@@ -912,16 +1165,17 @@ int bp_slabs(const DevGraph& g) { return g.flood ? 2 : 1; }
 
 size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds) {
     const size_t mb = g.fp64 ? 8 : 4;
-    size_t b = sizeof(uint64_t) * (2 * (size_t)g.words_m + g.words_n) + mb * g.m;
+    // per shot of the wavefront: syndrome, residual, decisions, row states
+    size_t b = (size_t)g.P * (sizeof(uint64_t) * (2 * (size_t)g.words_m + g.words_n) + mb * g.m);
     if (slab_in_lds) b += bp_slabs(g) * mb * (size_t)g.max_chunks * kWave;
     return b;
 }
 
 
 
-bool bp_slab_fits_lds(const DevGraph& g) { return !g.layered && bp_lds_bytes(g, true) <= 96 * 1024; }
+bool bp_slab_fits_lds(const DevGraph& g) { return !g.layered && g.P == 1 && bp_lds_bytes(g, true) <= 96 * 1024; }
 
-int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged, bool layered) {
+int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged, bool layered, uint32_t P) {
     static int cached_cus = 0;
     if (!cached_cus) {
         int dev = 0;
@@ -932,26 +1186,33 @@ int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool 
     }
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, kernel_for(fp64, flood, slab_in_lds, ragged, layered), kWave, lds_bytes);
+        &per_cu, kernel_for(fp64, flood, slab_in_lds, ragged, layered, P), kWave, lds_bytes);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     if (per_cu > 32) per_cu = 32;
     return per_cu * cached_cus;
 }
 
 int bp_grid(const DevGraph& g, bool slab_in_lds) {
-    return bp_grid_for(g.fp64 != 0, g.flood != 0, slab_in_lds, bp_lds_bytes(g, slab_in_lds), false, g.layered != 0);
+    return bp_grid_for(g.fp64 != 0, g.flood != 0, slab_in_lds, bp_lds_bytes(g, slab_in_lds), false, g.layered != 0,
+                       g.P);
 }
 
 int launch_bp(const DevGraph& g, const BpLaunch& a, hipStream_t st) {
     const bool in_lds = a.slab_in_lds != 0;
     void* args[] = {const_cast<DevGraph*>(&g), const_cast<BpLaunch*>(&a)};
-    return launch_fn(kernel_for(g.fp64 != 0, g.flood != 0, in_lds, false, g.layered != 0), a.grid,
+    if (g.P > 1 && (g.flood || g.layered || in_lds || a.post_out || !a.stop_on_converge))
+        return fail(VIBE_EINVAL, "internal: several shots per wavefront need the serial schedule, a global slab "
+                                 "and stop on convergence");
+    return launch_fn(kernel_for(g.fp64 != 0, g.flood != 0, in_lds, false, g.layered != 0, g.P), a.grid,
                      bp_lds_bytes(g, in_lds), args, st);
 }
 
 int launch_bp_ragged(const RaggedLaunch& r, hipStream_t st) {
     void* args[] = {const_cast<RaggedLaunch*>(&r)};
-    return launch_fn(kernel_for(r.fp64 != 0, r.flood != 0, r.slab_in_lds != 0, true), r.grid, r.lds_bytes, args, st);
+    if (r.multi && (r.flood || r.slab_in_lds))
+        return fail(VIBE_EINVAL, "internal: several shots per wavefront need the serial schedule and a global slab");
+    return launch_fn(kernel_for(r.fp64 != 0, r.flood != 0, r.slab_in_lds != 0, true, false, r.multi ? 2u : 1u), r.grid,
+                     r.lds_bytes, args, st);
 }
 
 int launch_zero(void* p, size_t bytes, hipStream_t st) {

@@ -48,6 +48,110 @@ void free_all(GraphHost& h) {
 
 }  // namespace
 
+// Decode schedules for P = 2 or 4 shots per wavefront.  The 64-edge chunks
+// are recut into chunks of at most W = 64 / P edges, columns kept whole and
+// in slot order; a subset of an independent set of columns is independent,
+// so the sweep computes the same messages.  Two edges of one row lie in
+// different 64-edge chunks, whose order the recut keeps, so the suffix
+// state of every slot for the initial messages (the row's later edges) is
+// the one of the 64-edge schedule and is copied over.  Each recut chunk
+// carries its own largest column degree.
+int build_multi_schedule(vibe_graph* G, uint32_t P) {
+    if (P != 2 && P != 4) return fail(VIBE_EINVAL, "shots per wavefront must be 1, 2 or 4");
+    const uint32_t idx = P / 4;
+    if (G->multi_recs[idx]) return VIBE_OK;
+    const DevGraph& d = G->h.dg;
+    if (d.layered) return fail(VIBE_EUNSUPPORTED, "the layered schedule runs one shot per wavefront");
+    const bool f64 = d.fp64 != 0;
+    const uint32_t W = kWave / P, L = d.L, mb = f64 ? 8u : 4u;
+    std::vector<uint32_t> mc(L + 1);
+    hipError_t e = hipMemcpy(mc.data(), d.member_chunk, 4ull * (L + 1), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(member_chunk)");
+    const size_t nrec = mc[L];
+    const uint32_t rb = rec_bytes(f64), ri0 = rec_init(f64), wrb = rec_bytes_w(f64, W);
+    std::vector<unsigned char> recs(std::max<size_t>(nrec, 1) * rb);
+    if (nrec && (e = hipMemcpy(recs.data(), d.sched, nrec * rb, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(schedule)");
+    std::vector<unsigned char> out;
+    std::vector<uint32_t> gmc(L + 1, 0);
+    std::vector<std::pair<uint32_t, uint32_t>> cols;  // (first slot, degree)
+    uint32_t maxc = 0;
+    for (uint32_t i = 0; i < L; i++) {
+        gmc[i] = (uint32_t)(out.size() / wrb);
+        for (size_t k = mc[i]; k < mc[i + 1]; k++) {
+            const unsigned char* r = recs.data() + k * rb;
+            uint32_t meta[kWave], vv[kWave];
+            std::memcpy(meta, r, sizeof(meta));
+            std::memcpy(vv, r + kRecV, sizeof(vv));
+            cols.clear();
+            for (uint32_t q = 0; q < (uint32_t)kWave;) {
+                const uint32_t deg = (meta[q] >> kMetaDegShift) & 15u;
+                if (!deg) break;
+                cols.push_back({q, deg});
+                q += deg;
+            }
+            size_t a = 0;
+            while (a < cols.size()) {
+                size_t b = a;
+                uint32_t fill = 0, dmax = 0;
+                while (b < cols.size() && fill + cols[b].second <= W) {
+                    fill += cols[b].second;
+                    dmax = std::max(dmax, cols[b].second);
+                    b++;
+                }
+                const size_t at = out.size();
+                out.resize(at + wrb, 0);
+                unsigned char* o = out.data() + at;
+                uint32_t slot = 0;
+                auto put = [&](uint32_t mw, uint32_t v, const unsigned char* lam, const void* init) {
+                    std::memcpy(o + 4 * slot, &mw, 4);
+                    std::memcpy(o + 4 * W + 4 * slot, &v, 4);
+                    if (lam) std::memcpy(o + 8 * W + mb * slot, lam, mb);
+                    std::memcpy(o + 8 * W + mb * W + mb * slot, init, mb);
+                    slot++;
+                };
+                for (size_t cc = a; cc < b; cc++)
+                    for (uint32_t j = 0; j < cols[cc].second; j++) {
+                        const uint32_t q = cols[cc].first + j;
+                        put((meta[q] & ~(15u << kMetaDmaxShift)) | (dmax << kMetaDmaxShift), vv[q],
+                            r + kRecLam + mb * q, r + ri0 + mb * q);
+                    }
+                while (slot < W)  // unused slots: c = v = 0, lambda 0, no message
+                    put(dmax << kMetaDmaxShift, 0u, nullptr, f64 ? (const void*)&d.ident64 : (const void*)&d.ident32);
+                a = b;
+            }
+        }
+        maxc = std::max(maxc, (uint32_t)(out.size() / wrb) - gmc[i]);
+    }
+    gmc[L] = (uint32_t)(out.size() / wrb);
+    if (out.empty()) {  // no edges: one unused record
+        out.assign(wrb, 0);
+        for (uint32_t q = 0; q < W; q++)
+            std::memcpy(out.data() + 8 * W + mb * W + mb * q, f64 ? (const void*)&d.ident64 : (const void*)&d.ident32, mb);
+    }
+    const unsigned char* dr = nullptr;
+    const uint32_t* dm = nullptr;
+    int rc;
+    if ((rc = upload(G->h, out.data(), out.size(), &dr)) || (rc = upload(G->h, gmc.data(), gmc.size(), &dm)))
+        return rc;
+    G->multi_recs[idx] = dr;
+    G->multi_member_chunk[idx] = dm;
+    G->multi_max_chunks[idx] = maxc;
+    return VIBE_OK;
+}
+
+DevGraph decode_view(const vibe_graph* G, bool allow_multi) {
+    DevGraph d = G->h.dg;
+    const uint32_t P = G->tune_P;
+    if (allow_multi && (P == 2 || P == 4) && G->multi_recs[P / 4]) {
+        d.sched = G->multi_recs[P / 4];
+        d.member_chunk = G->multi_member_chunk[P / 4];
+        d.max_chunks = G->multi_max_chunks[P / 4];
+        d.P = P;
+    }
+    return d;
+}
+
 }  // namespace vibe
 
 using namespace vibe;
@@ -384,6 +488,7 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     // the layered schedule keeps its check messages (E) and running
     // posteriors (n) in the slab
     d.max_chunks = layered ? (uint32_t)((E + n + kWave - 1) / kWave) : ch_max;
+    d.P = 1;
     d.fp64 = fp64 ? 1 : 0;
     d.flood = c.schedule == 1 ? 1 : 0;
     d.layered = layered ? 1 : 0;

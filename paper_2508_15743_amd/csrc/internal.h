@@ -35,10 +35,13 @@ constexpr double kQScale = 72057594037927936.0;  // 2^56: fixed point of the LLR
 //   init (B)   : the suffix state of the slot for the initial messages
 //                mu = lambda (row state bits, same width as F)
 // so a record is 64 * (8 + 2 sizeof(F)) bytes: 1024 for FP32, 1536 for FP64.
+// A recut schedule for P shots per wavefront has records of W = 64 / P
+// entries per field (the same fields, at 4W, 8W and 8W + W sizeof(F)).
 constexpr uint32_t kMetaDegShift = 20, kMetaDmaxShift = 24;
 constexpr uint32_t kRecV = 256, kRecLam = 512;  // byte offsets of fields in a record
 inline constexpr uint32_t rec_bytes(bool fp64) { return fp64 ? 1536u : 1024u; }
 inline constexpr uint32_t rec_init(bool fp64) { return fp64 ? 1024u : 768u; }
+inline constexpr uint32_t rec_bytes_w(bool fp64, uint32_t W) { return W * (fp64 ? 24u : 16u); }
 
 // Wave-uniform values.  A value every lane computes identically (a shuffle
 // broadcast, a wave reduction, an LDS word all lanes read) still lives in a
@@ -76,6 +79,8 @@ struct DevGraph {
     uint32_t E;
     uint32_t words_n, words_m;  // ceil(n/64), ceil(m/64)
     uint32_t max_chunks;        // largest chunk count of a member (slab = max_chunks * 64)
+    uint32_t P;                 // shots per wavefront of the schedule in sched: 1 (64-edge
+                                // chunks), or 2 and 4 (chunks recut to 64 / P edges)
     int fp64;                   // message precision: 0 = FP32, 1 = FP64
     int flood;                  // schedule: 0 = serial-V, 1 = parallel (flooding)
     int layered;                // 1: layered (check-serial) schedule; cperm holds the check orders
@@ -92,7 +97,8 @@ struct DevGraph {
     const double* lam64;          // n, FP64 channel LLR (candidate weights)
     const void* lam;              // n, channel LLR in the message precision
     const uint64_t* e0;           // words_n: decisions of columns without checks
-    const unsigned char* sched;   // chunk records of all members, see above
+    const unsigned char* sched;   // chunk records of all members, see above (W = 64 / P
+                                  // entries per field for the recut schedules)
     const uint32_t* member_chunk; // L + 1: chunk range of each member
     const uint32_t* cperm;        // layered schedule: L x m check orders (else unused)
     const uint64_t* lobs;         // k x words_n, bit-packed observable rows
@@ -124,11 +130,17 @@ struct vibe_graph {
     vibe::Workspace ws;
     vibe::Workspace ws_in;  // unpacked syndromes of vibe_decode_packed
     int device = 0;
-    // launch settings chosen by vibe_autotune: slab in LDS (-1 = not tuned,
-    // use LDS whenever it fits; 0 = global; 1 = LDS) and BP grid (0 = full
-    // occupancy)
+    // launch settings chosen by vibe_autotune or vibe_set_launch: slab in
+    // LDS (-1 = not tuned, use LDS whenever it fits; 0 = global; 1 = LDS),
+    // BP grid (0 = full occupancy) and shots per wavefront (1, 2 or 4)
     int tune_lds = -1;
     int tune_grid = 0;
+    uint32_t tune_P = 1;
+    // decode schedules recut for 2 and 4 shots per wavefront (index P / 4),
+    // built on first use
+    const unsigned char* multi_recs[2] = {nullptr, nullptr};
+    const uint32_t* multi_member_chunk[2] = {nullptr, nullptr};
+    uint32_t multi_max_chunks[2] = {0, 0};
     // gradient schedule, built by the first vibe_bp_grad call: the member
     // sweeps recut into chunks of at most grad_width edges, so that one
     // wavefront runs grad_P = 64 / grad_width shots of a member side by side
@@ -196,14 +208,28 @@ struct RaggedLaunch {
     int grid;
     int slab_in_lds;
     int fp64, flood;
+    int multi;             // some segment runs several shots per wavefront
     size_t lds_bytes;      // largest bp_lds_bytes over the segments
 };
 int launch_bp_ragged(const RaggedLaunch& r, hipStream_t st);
-int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged, bool layered = false);
+int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged, bool layered = false,
+                uint32_t P = 1);
 int bp_grid(const DevGraph& g, bool slab_in_lds);
 size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds);
 int bp_slabs(const DevGraph& g);  // slabs per block: 1 (serial), 2 (parallel: states and messages)
 bool bp_slab_fits_lds(const DevGraph& g);
+// posterior slab of one BP block: P x n posteriors, then 64 slots that absorb
+// the stores of lanes that own no column
+inline size_t bp_post_elems(const DevGraph& g) { return (size_t)g.P * g.n + kWave; }
+// BP work items of n shots: (member, group of P shots)
+inline uint64_t bp_items(const DevGraph& g, uint64_t n) { return (n + g.P - 1) / g.P * g.L; }
+
+// The graph as the decoder launches it: the handle's graph with the
+// schedule recut for tune_P shots per wavefront when that is above 1 (and
+// allow_multi), else the 64-edge schedule.
+DevGraph decode_view(const vibe_graph* G, bool allow_multi = true);
+// Build (once) the decode schedule recut for P = 2 or 4 shots per wavefront.
+int build_multi_schedule(vibe_graph* G, uint32_t P);
 int launch_zero(void* p, size_t bytes, hipStream_t st);
 
 struct SelectLaunch {

@@ -14,6 +14,7 @@
 #include <string>
 #include <mutex>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -90,6 +91,7 @@ struct Seg {
     uint32_t req;
     uint64_t shot0;
     uint32_t n;
+    DevGraph g;  // the graph as launched (schedule for its shots per wavefront)
     // workspace offsets of its buffers
     size_t t_conv, weight, cand, cmask, iters, qfix, fail_list;
 };
@@ -104,6 +106,7 @@ struct Round {
     int grid = 0, lsd_grid = 0;
     bool slab_in_lds = false;
     bool flood = false;  // some segment uses the parallel schedule
+    bool multi = false;  // some segment runs several shots per wavefront
 };
 
 size_t seg_bytes(const DevGraph& g, uint32_t n) {
@@ -168,27 +171,34 @@ std::vector<Round> plan(const vibe_request* reqs, uint32_t n_reqs, size_t budget
             return (uint64_t)ga.E * ga.T > (uint64_t)gb.E * gb.T;
         });
         bool lds_ok = true;
-        bool fp64 = false, flood = false;
+        bool fp64 = false, flood = false, multi = false;
         size_t lds_global = 0, lds_l = 0;
+        for (const Seg& sg : r.segs) flood = flood || reqs[sg.req].graph->h.dg.flood != 0;
+        // several shots per wavefront (the autotuner's choice per graph) in
+        // rounds on the serial and layered schedules only
+        for (Seg& sg : r.segs) {
+            sg.g = decode_view(reqs[sg.req].graph, !flood);
+            multi = multi || sg.g.P > 1;
+        }
         for (const Seg& sg : r.segs) {
             const vibe_graph* G = reqs[sg.req].graph;
-            const DevGraph& g = G->h.dg;
+            const DevGraph& g = sg.g;
             fp64 = g.fp64 != 0;
-            flood = flood || g.flood != 0;
             r.slab_elems = std::max<uint32_t>(r.slab_elems, std::max<uint32_t>(g.max_chunks, 1) * kWave);
-            r.post_elems = std::max<uint32_t>(r.post_elems, g.n + kWave);
-            lds_ok = lds_ok && bp_slab_fits_lds(g) && G->tune_lds != 0;
+            r.post_elems = std::max<uint32_t>(r.post_elems, (uint32_t)bp_post_elems(g));
+            lds_ok = lds_ok && !multi && bp_slab_fits_lds(g) && G->tune_lds != 0;
             lds_global = std::max(lds_global, bp_lds_bytes(g, false));
             lds_l = std::max(lds_l, bp_lds_bytes(g, true));
             r.lsd_per_block = std::max(r.lsd_per_block, lsd_scratch_per_block(g));
         }
         r.slab_in_lds = lds_ok;
         r.flood = flood;
+        r.multi = multi;
         r.lds_bytes = lds_ok ? lds_l : lds_global;
-        r.grid = bp_grid_for(fp64, flood, lds_ok, r.lds_bytes, true);
+        r.grid = bp_grid_for(fp64, flood, lds_ok, r.lds_bytes, true, false, multi ? 2u : 1u);
         uint64_t total_items = 0, max_n = 0;
         for (const Seg& sg : r.segs) {
-            total_items += (uint64_t)sg.n * reqs[sg.req].graph->h.dg.L;
+            total_items += bp_items(sg.g, sg.n);
             max_n = std::max<uint64_t>(max_n, sg.n);
         }
         r.grid = (int)std::min<uint64_t>((uint64_t)r.grid, std::max<uint64_t>(total_items, 1));
@@ -242,12 +252,12 @@ std::vector<BpSeg> seg_table(const vibe_request* reqs, const Round& r, unsigned 
     for (size_t j = 0; j < r.segs.size(); j++) {
         const Seg& sg = r.segs[j];
         const vibe_request& q = reqs[sg.req];
-        const DevGraph& g = q.graph->h.dg;
+        const DevGraph& g = sg.g;
         BpSeg& b = t[j];
         std::memset(&b, 0, sizeof(b));
         b.g = g;
         b.item0 = item0;
-        item0 += sg.n * g.L;
+        item0 += (uint32_t)bp_items(g, sg.n);
         BpLaunch& a = b.a;
         a.member_major = 1;
         a.syndromes = q.syndromes;
@@ -277,7 +287,7 @@ int run_round(const vibe_request* reqs, const Round& r, unsigned char* base, hip
     L.segs = reinterpret_cast<const BpSeg*>(base + r.segs_off);
     L.n_segs = (uint32_t)r.segs.size();
     uint64_t items = 0;
-    for (const Seg& sg : r.segs) items += (uint64_t)sg.n * reqs[sg.req].graph->h.dg.L;
+    for (const Seg& sg : r.segs) items += bp_items(sg.g, sg.n);
     L.n_items = (uint32_t)items;
     L.slab = r.slab_in_lds ? nullptr : base + r.slab_off;
     L.post_slab = base + r.post_off;
@@ -288,6 +298,7 @@ int run_round(const vibe_request* reqs, const Round& r, unsigned char* base, hip
     L.slab_in_lds = r.slab_in_lds ? 1 : 0;
     L.fp64 = reqs[r.segs[0].req].graph->h.dg.fp64;
     L.flood = r.flood ? 1 : 0;
+    L.multi = r.multi ? 1 : 0;
     L.lds_bytes = r.lds_bytes;
     if ((rc = launch_bp_ragged(L, st))) return rc;
     for (size_t j = 0; j < r.segs.size(); j++) {
@@ -453,17 +464,102 @@ extern "C" void vibe_exec_destroy(vibe_exec* ex) {
     delete ex;
 }
 
-extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B, void* stream, int* slab_in_lds,
-                             int* grid) {
+namespace vibe {
+namespace {
+
+// Launch settings found by vibe_autotune, per graph shape and batch size
+// class (process-wide): a graph of the same shape reuses them untimed.
+struct TuneKey {
+    int device;
+    uint32_t m, n, E, L, M, T, chunks, levels, lsd_order;
+    int fp64, flood, layered;
+    uint32_t b_log2;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(device, m, n, E, L, M, T, chunks, levels, lsd_order, fp64, flood, layered, b_log2) <
+               std::tie(o.device, o.m, o.n, o.E, o.L, o.M, o.T, o.chunks, o.levels, o.lsd_order, o.fp64, o.flood,
+                        o.layered, o.b_log2);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, vibe_launch_t> g_tune_cache;
+
+TuneKey tune_key(const vibe_graph* g, uint64_t B) {
+    const DevGraph& d = g->h.dg;
+    uint32_t lb = 0;
+    while (lb < 63 && (2ull << lb) <= B) lb++;
+    return TuneKey{g->device, d.m, d.n, d.E, d.L, d.M, d.T, g->h.chunks_max, g->h.levels_max, d.lsd_order,
+                   d.fp64, d.flood, d.layered, lb};
+}
+
+// Whether P shots per wavefront are available for the graph (serial
+// schedule, row state within 96 KB of LDS).
+bool multi_ok(const vibe_graph* g, uint32_t P) {
+    const DevGraph& d = g->h.dg;
+    if (d.flood || d.layered) return false;
+    DevGraph v = d;
+    v.P = P;
+    return bp_lds_bytes(v, false) <= 96 * 1024;
+}
+
+int apply_launch(vibe_graph* g, const vibe_launch_t& s) {
+    const uint32_t P = (uint32_t)s.shots_per_wave;
+    if (P != 1 && P != 2 && P != 4) return fail(VIBE_EINVAL, "shots_per_wave must be 1, 2 or 4");
+    if (s.grid < 0) return fail(VIBE_EINVAL, "grid must be >= 0");
+    if (P > 1) {
+        if (!multi_ok(g, P)) return fail(VIBE_EUNSUPPORTED, "several shots per wavefront need the serial schedule "
+                                                             "and row states within 96 KB of LDS");
+        if (s.slab_in_lds) return fail(VIBE_EINVAL, "several shots per wavefront keep the slab in global memory");
+        int rc = build_multi_schedule(g, P);
+        if (rc) return rc;
+    }
+    g->tune_lds = s.slab_in_lds ? 1 : 0;
+    g->tune_grid = s.grid;
+    g->tune_P = P;
+    return VIBE_OK;
+}
+
+}  // namespace
+}  // namespace vibe
+
+extern "C" int vibe_set_launch(vibe_graph* g, const vibe_launch_t* s) {
+    set_error("");
+    if (!g || !s) return fail(VIBE_EINVAL, "NULL argument");
+    return apply_launch(g, *s);
+}
+
+extern "C" int vibe_get_launch(const vibe_graph* g, vibe_launch_t* s) {
+    set_error("");
+    if (!g || !s) return fail(VIBE_EINVAL, "NULL argument");
+    s->slab_in_lds = g->tune_lds < 0 ? (bp_slab_fits_lds(g->h.dg) ? 1 : 0) : g->tune_lds;
+    s->grid = g->tune_grid;
+    s->shots_per_wave = (int)g->tune_P;
+    s->from_cache = 0;
+    s->ms = 0.0;
+    return VIBE_OK;
+}
+
+extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B, void* stream, vibe_launch_t* out) {
     set_error("");
     if (!g || (B && !syndromes)) return fail(VIBE_EINVAL, "NULL argument");
     if (!B) return fail(VIBE_EINVAL, "B must be >= 1");
+    const TuneKey key = tune_key(g, B);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            vibe_launch_t c = it->second;
+            int rc = apply_launch(g, c);
+            if (rc) return rc;
+            c.from_cache = 1;
+            if (out) *out = c;
+            return VIBE_OK;
+        }
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const DevGraph& d = g->h.dg;
-    const uint64_t words = d.words_n;
     uint64_t* corr = nullptr;
     uint8_t* obs = nullptr;
-    if (hipMalloc(&corr, 8 * B * words) != hipSuccess || hipMalloc(&obs, B * std::max<uint32_t>(d.k, 1)) != hipSuccess) {
+    if (hipMalloc(&corr, 8 * B * d.words_n) != hipSuccess || hipMalloc(&obs, B * std::max<uint32_t>(d.k, 1)) != hipSuccess) {
         if (corr) (void)hipFree(corr);
         return fail(VIBE_ENOMEM, "autotune buffers");
     }
@@ -471,28 +567,58 @@ extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     const int saved_lds = g->tune_lds, saved_grid = g->tune_grid;
-    const bool fits = bp_slab_fits_lds(d);
-    int best_lds = fits ? 1 : 0, best_grid = 0, rc = VIBE_OK;
-    float best_ms = 1e30f;
-    for (int lds = fits ? 1 : 0; lds >= 0 && !rc; lds--) {
-        const int full = bp_grid(d, lds != 0);
-        const int cand[3] = {full, (full * 3) / 4, full / 2};
-        for (int c = 0; c < 3 && !rc; c++) {
-            if (cand[c] < 1) continue;
-            g->tune_lds = lds;
-            g->tune_grid = cand[c];
+    const uint32_t saved_P = g->tune_P;
+    int rc = VIBE_OK;
+    // decode time of the sample with setting s (the first of two runs warms up)
+    auto time_it = [&](const vibe_launch_t& s, float* ms) {
+        int r = apply_launch(g, s);
+        for (int rep = 0; rep < 2 && !r; rep++) {
+            (void)hipEventRecord(e0, st);
+            r = vibe_decode(g, syndromes, B, corr, obs, nullptr, stream);
+            (void)hipEventRecord(e1, st);
+            if (!r && hipEventSynchronize(e1) != hipSuccess) r = fail(VIBE_EHIP, "hipEventSynchronize");
+            if (!r) (void)hipEventElapsedTime(ms, e0, e1);
+        }
+        return r;
+    };
+    // first the slab placement and shots per wavefront at full occupancy,
+    // then the grid for the best of them
+    std::vector<vibe_launch_t> first;
+    if (bp_slab_fits_lds(d)) first.push_back(vibe_launch_t{1, 0, 1, 0, 0.0});
+    first.push_back(vibe_launch_t{0, 0, 1, 0, 0.0});
+    for (int P : {2, 4})
+        if (multi_ok(g, (uint32_t)P)) first.push_back(vibe_launch_t{0, 0, P, 0, 0.0});
+    vibe_launch_t best{0, 0, 1, 0, 1e30};
+    for (const vibe_launch_t& s : first) {
+        float ms = 0.0f;
+        rc = time_it(s, &ms);
+        if (rc == VIBE_ENOMEM) {  // a recut schedule did not fit: not a candidate
+            rc = VIBE_OK;
+            continue;
+        }
+        if (rc) break;
+        if (ms < best.ms) {
+            best = s;
+            best.ms = ms;
+        }
+    }
+    if (!rc) {
+        DevGraph v = d;
+        if (best.shots_per_wave > 1) {
+            (void)apply_launch(g, best);
+            v = decode_view(g);
+        }
+        const int full = bp_grid(v, best.slab_in_lds != 0);
+        const vibe_launch_t base = best;
+        for (int eighths : {7, 6, 5, 4}) {
+            vibe_launch_t s = base;
+            s.grid = full * eighths / 8;
+            if (s.grid < 1) continue;
             float ms = 0.0f;
-            for (int rep = 0; rep < 2 && !rc; rep++) {  // the first run warms up
-                (void)hipEventRecord(e0, st);
-                rc = vibe_decode(g, syndromes, B, corr, obs, nullptr, stream);
-                (void)hipEventRecord(e1, st);
-                if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(VIBE_EHIP, "hipEventSynchronize");
-                if (!rc) (void)hipEventElapsedTime(&ms, e0, e1);
-            }
-            if (!rc && ms < best_ms) {
-                best_ms = ms;
-                best_lds = lds;
-                best_grid = cand[c];
+            if ((rc = time_it(s, &ms))) break;
+            if (ms < best.ms) {
+                best = s;
+                best.ms = ms;
             }
         }
     }
@@ -503,12 +629,15 @@ extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B
     if (rc) {
         g->tune_lds = saved_lds;
         g->tune_grid = saved_grid;
+        g->tune_P = saved_P;
         return rc;
     }
-    g->tune_lds = best_lds;
-    g->tune_grid = best_grid;
-    if (slab_in_lds) *slab_in_lds = best_lds;
-    if (grid) *grid = best_grid;
+    if ((rc = apply_launch(g, best))) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    if (out) *out = best;
     return VIBE_OK;
 }
 
