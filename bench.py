@@ -107,15 +107,18 @@ def ragged_leg(P, torch, shots, seed, tune=True):
     torch.cuda.synchronize()
     t_ragged = time.perf_counter() - t0
     log(f"ragged mix: {shots} shots per code, one call per code")
-    t0 = time.perf_counter()
+    t_code = []
     for (G, s), o in zip(pairs, outs):
+        t0 = time.perf_counter()
         G.decode(s, out=o)
-    torch.cuda.synchronize()
-    t_sep = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t_code.append(time.perf_counter() - t0)
+    t_sep = sum(t_code)
     total = shots * len(cfgs)
     res = {"codes": [f"circuit_d{d}_r{d}_p0.001" for d, *_ in cfgs], "shots_per_code": shots,
            "ragged_shots_per_s": round(total / t_ragged, 1), "separate_shots_per_s": round(total / t_sep, 1),
-           "ragged_over_separate": round(t_sep / t_ragged, 3), "autotuned": tuned if tune else None}
+           "ragged_over_separate": round(t_sep / t_ragged, 3),
+           "separate_s_per_code": [round(t, 3) for t in t_code], "autotuned": tuned if tune else None}
     log(f"ragged mix d=5..13: {total / t_ragged:.0f} shots/s in one call, {total / t_sep:.0f} in one call per code")
     rt.close()
     for G, _ in pairs:

@@ -299,7 +299,7 @@ int vibe_decode_ragged(vibe_runtime* rt, const vibe_request* reqs, uint32_t n_re
  * The requests' device pointers are fixed at creation: refill the syndrome
  * buffers and replay.  A replay writes the same outputs as an eager call on
  * the buffers' contents.  VIBE_EUNSUPPORTED if the requests need more than
- * one round of workspace (about 4 GB of per-shot buffers).
+ * one round of workspace (about 32 GB of per-shot buffers).
  */
 typedef struct vibe_exec vibe_exec;
 int vibe_exec_create(const vibe_request* reqs, uint32_t n_reqs, vibe_exec** out);
@@ -321,6 +321,13 @@ void vibe_exec_destroy(vibe_exec* ex); /* synchronises the device first; NULL ac
  *                   64-edge chunks are far from full (the sweep's
  *                   dependency chain, not its edge count, sets the chunk
  *                   count) this runs P times the shots per chunk step.
+ *   decisions_global -1: automatic; 1: each wavefront keeps its hard
+ *                   decisions in global memory (one mask per chunk, read
+ *                   with the chunk, and a bitmap updated on flips) instead
+ *                   of a bitmap in LDS (0).  On large graphs the bitmap
+ *                   (n / 8 bytes per wavefront) caps how many wavefronts
+ *                   fit in LDS; automatic takes global memory where that
+ *                   lets more reside.  Not with the slab in LDS.
  * vibe_set_launch applies settings (building the recut schedule on first
  * use: EUNSUPPORTED for the parallel and layered schedules); settings that
  * vibe_decode_noalloc uses must be applied before it is called.
@@ -330,6 +337,7 @@ typedef struct vibe_launch {
     int slab_in_lds;
     int grid;
     int shots_per_wave;
+    int decisions_global;
     int from_cache;  /* vibe_autotune: 1 if taken from the shape cache untimed */
     double ms;       /* vibe_autotune: decode time of the sample (timed run) */
 } vibe_launch_t;
@@ -338,8 +346,9 @@ int vibe_get_launch(const vibe_graph* g, vibe_launch_t* s);
 
 /*
  * Autotuning: times vibe_decode of the given syndromes (device, B x m) with
- * the slab in LDS (where it fits) and in global memory and with 1, 2 and 4
- * shots per wavefront at full occupancy, then the best of those with the BP
+ * the slab in LDS (where it fits), and in global memory with 1, 2 and 4
+ * shots per wavefront and decisions in LDS or global memory, each at full
+ * occupancy, then the best of those with the BP
  * grid at 7/8, 3/4, 5/8 and 1/2 of full; applies the fastest to the handle
  * and stores it in a process-wide cache keyed by the graph's shape (checks,
  * columns, edges, L, M, T, chunk and level counts, LSD order, precision,
@@ -372,7 +381,7 @@ int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B, void* str
  * it alone.  vibe_server_wait blocks until the request is done and gives its
  * latency from submission to completion (host clock, ms).  Submit refuses a
  * request whose footprint alone exceeds the pool (VIBE_ENOMEM) or needs more
- * than one round of per-shot buffers (about 4 GB; VIBE_EINVAL).  A
+ * than one round of per-shot buffers (about 32 GB; VIBE_EINVAL).  A
  * request's syndromes must already be on the device when it is submitted
  * (the server's streams do not wait for the caller's), and its buffers must
  * stay valid until its wait returns.  Submit and wait may be called from

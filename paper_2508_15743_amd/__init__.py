@@ -45,7 +45,7 @@ class vibe_graph_info_t(C.Structure):
 
 class vibe_launch_t(C.Structure):
     _fields_ = [("slab_in_lds", C.c_int), ("grid", C.c_int), ("shots_per_wave", C.c_int),
-                ("from_cache", C.c_int), ("ms", C.c_double)]
+                ("decisions_global", C.c_int), ("from_cache", C.c_int), ("ms", C.c_double)]
 
 
 class vibe_request(C.Structure):
@@ -254,7 +254,7 @@ def vibe_exec_destroy(ex):
 
 def _launch_dict(s):
     return {"slab_in_lds": s.slab_in_lds, "grid": s.grid, "shots_per_wave": s.shots_per_wave,
-            "from_cache": bool(s.from_cache), "ms": s.ms}
+            "decisions_global": s.decisions_global, "from_cache": bool(s.from_cache), "ms": s.ms}
 
 
 def vibe_autotune(handle, syndromes, B, stream):
@@ -263,8 +263,8 @@ def vibe_autotune(handle, syndromes, B, stream):
     return _launch_dict(s)
 
 
-def vibe_set_launch(handle, slab_in_lds=0, grid=0, shots_per_wave=1):
-    s = vibe_launch_t(int(slab_in_lds), int(grid), int(shots_per_wave), 0, 0.0)
+def vibe_set_launch(handle, slab_in_lds=0, grid=0, shots_per_wave=1, decisions_global=-1):
+    s = vibe_launch_t(int(slab_in_lds), int(grid), int(shots_per_wave), int(decisions_global), 0, 0.0)
     _check(lib().vibe_set_launch(handle, C.byref(s)))
 
 
@@ -427,13 +427,13 @@ class Graph:
 def _graph_autotune(self, syndromes, stream=None):
     """Time the launch settings of decode() on these syndromes (or take them
     from the per-shape cache) and keep the fastest -> dict with slab_in_lds,
-    grid, shots_per_wave, from_cache, ms."""
+    grid, shots_per_wave, decisions_global, from_cache, ms."""
     return vibe_autotune(self.handle, self._synd(syndromes), syndromes.shape[0], _stream(stream))
 
 
-def _graph_set_launch(self, slab_in_lds=0, grid=0, shots_per_wave=1):
+def _graph_set_launch(self, slab_in_lds=0, grid=0, shots_per_wave=1, decisions_global=-1):
     """Apply launch settings (see vibe_set_launch)."""
-    vibe_set_launch(self.handle, slab_in_lds, grid, shots_per_wave)
+    vibe_set_launch(self.handle, slab_in_lds, grid, shots_per_wave, decisions_global)
 
 
 def _graph_get_launch(self):

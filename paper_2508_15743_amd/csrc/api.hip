@@ -285,7 +285,7 @@ int decode_batch(vibe_graph* G, const uint8_t* bytes, const uint64_t* words, uin
     if (B && (!corrections || (!observables && G->h.k))) return fail(VIBE_EINVAL, "an output pointer is NULL");
     if (!B) return VIBE_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const DevGraph g = decode_view(G);
+    DevGraph g = decode_view(G);
     const uint32_t bc = chunk_for(g, B, true);
     uint8_t* u = nullptr;
     if (words) {
@@ -306,6 +306,7 @@ int decode_batch(vibe_graph* G, const uint8_t* bytes, const uint64_t* words, uin
         u = static_cast<uint8_t*>(G->ws_in.base);
     }
     const bool in_lds = bp_slab_fits_lds(g) && G->tune_lds != 0;
+    if (in_lds) g.dec_global = 0;  // the LDS slab variant keeps decisions in LDS
     const int bpg = G->tune_grid > 0 ? std::min(G->tune_grid, bp_grid(g, in_lds)) : bp_grid(g, in_lds);
     const int lg = lsd_grid_for(bc);
     ChunkBufs W;
@@ -519,8 +520,9 @@ extern "C" int vibe_decode_noalloc(vibe_graph* G, const uint8_t* syndromes, uint
     if (rc) return rc;
     if (B && (!corrections || (!observables && G->h.k))) return fail(VIBE_EINVAL, "an output pointer is NULL");
     if (!B) return VIBE_OK;
-    const DevGraph g = decode_view(G);
+    DevGraph g = decode_view(G);
     const bool in_lds = bp_slab_fits_lds(g) && G->tune_lds != 0;
+    if (in_lds) g.dec_global = 0;  // the LDS slab variant keeps decisions in LDS
     const int full = G->tune_grid > 0 ? std::min(G->tune_grid, bp_grid(g, in_lds)) : bp_grid(g, in_lds);
     int bpg = 0, lg = 0;
     uint32_t bc = 0;

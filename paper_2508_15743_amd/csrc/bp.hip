@@ -166,6 +166,9 @@ struct Ctx {
     uint32_t lane4, laneF;  // lane * 4, lane * sizeof(F)
     uint32_t rec4, recF;    // several shots per wavefront: the lane's slot in
                             // a record of W = 64 / P entries, * 4, * sizeof(F)
+    Rsrc dsl;               // decisions in global memory: the block's decision
+                            // mask of each chunk (bit q: the decision of the
+                            // column that slot q belongs to)
 };
 
 // Byte offsets of the fields in a chunk record of W entries per field.
@@ -188,15 +191,17 @@ static_assert(RecW<float, 64>::kV == kRecV && RecW<float, 64>::kLam == kRecLam &
 #endif
 constexpr int kDepth = VIBE_BP_DEPTH;  // chunks loaded ahead of the one being processed
 // occupancy the register allocator aims for (waves per SIMD): 6 keeps the
-// production kernel (FP32, serial schedule, global slab, one request) within
-// 80 VGPRs without spills; the other FP32 variants need a few more
-// registers and aim for 5, the FP64 ones for 4
+// production kernel (FP32, serial schedule, global slab, one request, or
+// several requests none of which is layered) within 80 VGPRs (with
+// decisions in global memory a few registers spill, outside the chunk
+// loops); the other FP32 variants need more registers and aim for 5, the
+// FP64 ones for 4
 #ifndef VIBE_BP_WAVES_PER_EU
 #define VIBE_BP_WAVES_PER_EU 6
 #endif
-template <class F, bool SLAB_LDS, bool FLOOD, bool RAGGED>
+template <class F, bool SLAB_LDS, bool FLOOD, bool RAGGED, bool WITH_LAYERED = false, bool DG = false>
 constexpr int waves_target() {
-    return sizeof(F) == 8 ? 4 : (!SLAB_LDS && !FLOOD && !RAGGED ? VIBE_BP_WAVES_PER_EU : 5);
+    return sizeof(F) == 8 ? 4 : (!SLAB_LDS && !FLOOD && !(RAGGED && WITH_LAYERED) ? VIBE_BP_WAVES_PER_EU : 5);
 }
 
 // Slot data of one chunk for the sweep, loaded ahead of use.
@@ -205,12 +210,14 @@ struct Stage {
     uint32_t meta, v;
     F lam;
     typename Prec<F>::B suf;
-    F old;  // parallel schedule: the edge's message of the previous iteration
+    F old;        // parallel schedule: the edge's message of the previous iteration
+    uint32_t dm;  // decisions in global memory: the half of the chunk's decision
+                  // mask of the previous sweep that holds this lane's bit
 };
 
 // W: entries per record field (64 / shots per wavefront).  The slab slot
 // of a lane is always chunk * 64 + lane.
-template <class F, bool SLAB_LDS, bool FLOOD, uint32_t W = kWave>
+template <class F, bool SLAB_LDS, bool FLOOD, uint32_t W = kWave, bool DG = false>
 __device__ __forceinline__ void fetch(const Ctx<F>& x, Stage<F>& s, uint32_t k, bool first) {
     using P = Prec<F>;
     using B = typename P::B;
@@ -241,6 +248,12 @@ __device__ __forceinline__ void fetch(const Ctx<F>& x, Stage<F>& s, uint32_t k, 
             m = bload<B>(x.mslb, x.laneF + k * kWave * (uint32_t)sizeof(B), 0);
         s.old = first ? s.lam : P::val(m);
     }
+    if constexpr (DG) {
+        // written by this wavefront's previous sweep (read past the L1);
+        // every chunk column starts at e = 0 in the first sweep
+        const uint32_t m = bloadx<uint32_t>(x.dsl, k * 8u + (((uint32_t)x.lane >> 5) << 2), 0);
+        s.dm = first ? 0u : m;
+    }
 }
 
 // One chunk of the sweep: r_{c->v} = (1 - 2 s_c) alpha prod sign min |mu|
@@ -249,7 +262,7 @@ __device__ __forceinline__ void fetch(const Ctx<F>& x, Stage<F>& s, uint32_t k, 
 // prefix state accumulates them).  Parallel schedule (FLOOD): they
 // contribute their previous messages, so every message of the iteration
 // comes from the previous iteration's.
-template <class F, bool SLAB_LDS, bool WANT_POST, bool FLOOD>
+template <class F, bool SLAB_LDS, bool WANT_POST, bool FLOOD, bool DG = false>
 __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, uint32_t k, uint64_t& sat) {
     using P = Prec<F>;
     using B = typename P::B;
@@ -257,10 +270,11 @@ __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, 
     const uint32_t deg = (meta >> kMetaDegShift) & 15u;  // 0: unused slot (c = 0, v = 0)
     const uint32_t dmax = uni((meta >> kMetaDmaxShift) & 15u);
     const uint32_t c = meta & 0xffffu, seg = (meta >> 16) & 15u;
-    // the three LDS words this edge needs, issued together
+    // the LDS words this edge needs, issued together
     const B pre = x.pref[c];
     const uint64_t sw = x.sb[c >> 6];
-    const uint64_t ew = x.eb[v >> 6];
+    uint64_t ew = 0;
+    if constexpr (!DG) ew = x.eb[v >> 6];
     const B stt = rs_combine<B>(pre, s.suf);
     const bool neg = ((stt & P::kSign) != 0) != (((sw >> (c & 63)) & 1ull) != 0);
     const F rr = x.al * P::val(stt & ~P::kSign);
@@ -316,7 +330,13 @@ __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, 
             bstore<B>(P::bits(mu), x.slb, x.laneF + k * kWave * (uint32_t)sizeof(B), 0);
     }
     const bool enew = L <= F(0);
-    const bool eold = (ew >> (v & 63)) & 1ull;
+    // the column's previous decision: its bit of the decision bitmap, or
+    // this lane's bit of the chunk's decision mask
+    bool eold;
+    if constexpr (DG)
+        eold = ((s.dm >> ((uint32_t)x.lane & 31u)) & 1u) != 0;
+    else
+        eold = (ew >> (v & 63)) & 1ull;
     if (deg) {
         x.pref[c] = rs_combine<B>(pre, rs_encode(FLOOD ? s.old : mu));
         if (enew != eold) {
@@ -327,6 +347,11 @@ __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, 
     if constexpr (WANT_POST) {
         F* dst = (deg && seg == 0) ? x.post + v : x.trash + x.lane;
         *dst = L;
+    }
+    if constexpr (DG) {
+        // the chunk's new decision mask, stored by every lane (the same
+        // value, so that the store is unconditional)
+        bstore<uint64_t>(__ballot(deg && enew), x.dsl, k * 8u, 0);
     }
     // LDS writes of this chunk precede the next chunk's reads; nothing of a
     // later chunk is scheduled into this one (that would keep every stage's
@@ -339,18 +364,18 @@ __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, 
 // The whole sweep: chunks 0 .. nch-1 (nch >= 1), each one's slots loaded
 // kDepth chunks ahead (the suffix states of later chunks are final for the
 // whole sweep).
-template <class F, bool SLAB_LDS, bool WANT_POST, bool FLOOD, uint32_t W = kWave>
+template <class F, bool SLAB_LDS, bool WANT_POST, bool FLOOD, uint32_t W = kWave, bool DG = false>
 __device__ __forceinline__ void sweep(const Ctx<F>& x, uint32_t nch, bool first, uint64_t& sat) {
     const uint32_t last = nch - 1;
     Stage<F> ring[kDepth];
 #pragma unroll
-    for (int d = 0; d < kDepth; d++) fetch<F, SLAB_LDS, FLOOD, W>(x, ring[d], min((uint32_t)d, last), first);
+    for (int d = 0; d < kDepth; d++) fetch<F, SLAB_LDS, FLOOD, W, DG>(x, ring[d], min((uint32_t)d, last), first);
     for (uint32_t k = 0; k < nch; k += kDepth) {
 #pragma unroll
         for (int d = 0; d < kDepth; d++) {
             if (k + d >= nch) break;
-            sweep_chunk<F, SLAB_LDS, WANT_POST, FLOOD>(x, ring[d], k + d, sat);
-            fetch<F, SLAB_LDS, FLOOD, W>(x, ring[d], min(k + d + kDepth, last), first);
+            sweep_chunk<F, SLAB_LDS, WANT_POST, FLOOD, DG>(x, ring[d], k + d, sat);
+            fetch<F, SLAB_LDS, FLOOD, W, DG>(x, ring[d], min(k + d + kDepth, last), first);
         }
     }
 }
@@ -607,10 +632,13 @@ __device__ __forceinline__ void zero_item(const DevGraph& g, const BpLaunch& a, 
 // convergence record, candidate and weight, saturation mark, and its
 // contribution to the normalised average.  eb: its decisions (LDS); post:
 // its posteriors of the last sweep, written by any lane of the wavefront.
-template <class F>
+// DG: the decision bitmap is in global memory, updated by atomics, and is
+// read past the L1.
+template <class F, bool DG = false>
 __device__ __forceinline__ void finish_item(const DevGraph& g, const BpLaunch& a, uint32_t shot, uint32_t mem,
                                             uint32_t conv_t, uint32_t ran, bool stopped, bool saturated,
                                             const uint64_t* eb, const F* post, int lane) {
+    auto ebw = [&](uint32_t w) { return DG ? load_mask(&eb[w]) : eb[w]; };
     const uint32_t rec = shot * g.L + mem;
     uint64_t* cmask = a.conv_mask + (size_t)shot * (kMaxT + 1);
     // a run that reached the clamp marks its member in word 0 of the shot's
@@ -621,18 +649,18 @@ __device__ __forceinline__ void finish_item(const DevGraph& g, const BpLaunch& a
         if (saturated) atomicOr(reinterpret_cast<unsigned long long*>(&cmask[0]), 1ull << mem);
     }
     if (a.cand && (conv_t || !a.use_M))
-        for (uint32_t w = lane; w < g.words_n; w += kWave) a.cand[(size_t)rec * g.words_n + w] = eb[w];
+        for (uint32_t w = lane; w < g.words_n; w += kWave) a.cand[(size_t)rec * g.words_n + w] = ebw(w);
     if (a.weight && conv_t) {
         // W(e) = sum_v e_v lambda_v in FP64, ascending v
         double W = 0.0;
         for (uint32_t base = 0; base < g.words_n; base += kWave) {
             const uint32_t w = base + lane;
-            uint64_t nzw = __ballot(w < g.words_n && eb[w] != 0);
+            uint64_t nzw = __ballot(w < g.words_n && ebw(w) != 0);
             if (lane == 0) {
                 while (nzw) {
                     const int bi = __ffsll((long long)nzw) - 1;
                     nzw &= nzw - 1;
-                    uint64_t xw = eb[base + bi];
+                    uint64_t xw = ebw(base + bi);
                     while (xw) {
                         const int bb = __ffsll((long long)xw) - 1;
                         xw &= xw - 1;
@@ -677,15 +705,23 @@ __device__ __forceinline__ void finish_item(const DevGraph& g, const BpLaunch& a
     }
 }
 
-template <class F, bool SLAB_LDS, bool FLOOD, bool LAYERED = false>
+// DG: decisions in global memory (the chunk decision masks and the bitmap
+// after the block's posteriors, see bp_post_elems), not in LDS.
+template <class F, bool SLAB_LDS, bool FLOOD, bool LAYERED = false, bool DG = false>
 __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, uint32_t item, unsigned char* lds,
                                          Ctx<F> x) {
     using P = Prec<F>;
     using B = typename P::B;
+    static_assert(!DG || (!SLAB_LDS && !LAYERED), "decisions in global memory: chunked sweeps, global slab");
     uint64_t* sb = reinterpret_cast<uint64_t*>(lds);
     uint64_t* res = sb + g.words_m;
     uint64_t* eb = res + g.words_m;
-    B* pref = reinterpret_cast<B*>(eb + g.words_n);
+    B* pref = reinterpret_cast<B*>(DG ? eb : eb + g.words_n);
+    if constexpr (DG) {
+        F* aux = x.post + bp_post_head(g);
+        x.dsl = make_rsrc(aux, g.max_chunks * 8u);
+        eb = reinterpret_cast<uint64_t*>(aux) + g.max_chunks;
+    }
     // LDS variant: the state slab, then (parallel schedule) the message slab;
     // the global slabs are buffer resources set up by the caller
     B* slab = SLAB_LDS ? pref + g.m : nullptr;
@@ -787,9 +823,9 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
             layered_sweep<F>(g, x, g.cperm + (size_t)mem * g.m, want_post, sat);
         } else if (nch) {
             if (want_post)
-                sweep<F, SLAB_LDS, true, FLOOD>(x, nch, t == 1, sat);
+                sweep<F, SLAB_LDS, true, FLOOD, kWave, DG>(x, nch, t == 1, sat);
             else
-                sweep<F, SLAB_LDS, false, FLOOD>(x, nch, t == 1, sat);
+                sweep<F, SLAB_LDS, false, FLOOD, kWave, DG>(x, nch, t == 1, sat);
         }
         __syncthreads();  // every new message stored
         if (post_out) {
@@ -813,7 +849,7 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
         }
     }
 
-    finish_item<F>(g, a, shot, mem, conv_t, ran, stopped, uni(sat != 0 ? 1u : 0u) != 0, eb, post, lane);
+    finish_item<F, DG>(g, a, shot, mem, conv_t, ran, stopped, uni(sat != 0 ? 1u : 0u) != 0, eb, post, lane);
 }
 
 // One work item of the multi-shot launch: member mem on the P shots
@@ -827,7 +863,7 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
 // item ends when every shot has finished.  Global slab, serial schedule,
 // stop on convergence (so a shot's convergence iteration is the iteration
 // it finishes at, and its iterations run are those before it finishes).
-template <class F, int P>
+template <class F, int P, bool DG = false>
 __device__ __forceinline__ void run_group(const DevGraph& g, const BpLaunch& a, uint32_t item, unsigned char* lds,
                                           Ctx<F> x) {
     using PR = Prec<F>;
@@ -839,8 +875,13 @@ __device__ __forceinline__ void run_group(const DevGraph& g, const BpLaunch& a, 
     uint64_t* sb0 = reinterpret_cast<uint64_t*>(lds);
     uint64_t* res0 = sb0 + P * g.words_m;
     uint64_t* eb0 = res0 + P * g.words_m;
-    B* pref0 = reinterpret_cast<B*>(eb0 + P * g.words_n);
+    B* pref0 = reinterpret_cast<B*>(DG ? eb0 : eb0 + P * g.words_n);
     F* post0 = x.post;  // P x n posteriors, then 64 trash slots
+    if constexpr (DG) {  // chunk decision masks, then P decision bitmaps
+        F* aux = post0 + bp_post_head(g);
+        x.dsl = make_rsrc(aux, g.max_chunks * 8u);
+        eb0 = reinterpret_cast<uint64_t*>(aux) + g.max_chunks;
+    }
     const F* lamv = reinterpret_cast<const F*>(g.lam);
     const B ident = PR::ident(g);
     x.lslab = nullptr;
@@ -919,7 +960,7 @@ __device__ __forceinline__ void run_group(const DevGraph& g, const BpLaunch& a, 
                 uint64_t* cm = a.conv_mask + (size_t)(first + q) * (kMaxT + 1);
                 if (preceding_converged(cm, t, mem, lane) >= g.M) {
                     // cannot be among the first M any more
-                    finish_item<F>(g, a, first + q, mem, 0u, t - 1, true, sat_of(q), eb0 + q * g.words_n,
+                    finish_item<F, DG>(g, a, first + q, mem, 0u, t - 1, true, sat_of(q), eb0 + q * g.words_n,
                                    post0 + q * g.n, lane);
                     done |= 1u << q;
                 }
@@ -935,9 +976,9 @@ __device__ __forceinline__ void run_group(const DevGraph& g, const BpLaunch& a, 
         __syncthreads();
         if (nch) {
             if (want_post)
-                sweep<F, false, true, false, W>(x, nch, t == 1, sat);
+                sweep<F, false, true, false, W, DG>(x, nch, t == 1, sat);
             else
-                sweep<F, false, false, false, W>(x, nch, t == 1, sat);
+                sweep<F, false, false, false, W, DG>(x, nch, t == 1, sat);
         }
         __syncthreads();
 #pragma unroll
@@ -947,7 +988,7 @@ __device__ __forceinline__ void run_group(const DevGraph& g, const BpLaunch& a, 
             bool nz = false;
             for (uint32_t w = lane; w < g.words_m; w += kWave) nz |= res0[q * g.words_m + w] != 0;
             if (__ballot(nz) == 0) {
-                finish_item<F>(g, a, first + q, mem, t, t, false, sat_of(q), eb0 + q * g.words_n,
+                finish_item<F, DG>(g, a, first + q, mem, t, t, false, sat_of(q), eb0 + q * g.words_n,
                                post0 + q * g.n, lane);
                 done |= 1u << q;
             }
@@ -964,7 +1005,7 @@ __device__ __forceinline__ void run_group(const DevGraph& g, const BpLaunch& a, 
 #pragma unroll
     for (int q = 0; q < P; q++) {
         if ((done >> q) & 1u) continue;
-        finish_item<F>(g, a, first + q, mem, 0u, a.T_run, false, sat_of(q), eb0 + q * g.words_n,
+        finish_item<F, DG>(g, a, first + q, mem, 0u, a.T_run, false, sat_of(q), eb0 + q * g.words_n,
                        post0 + q * g.n, lane);
     }
 }
@@ -998,21 +1039,22 @@ __device__ __forceinline__ T load_const(const T* p) {
     return v;
 }
 
-// One launch over the items of one request.
-template <class F, bool SLAB_LDS, bool FLOOD, bool LAYERED = false>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_target<F, SLAB_LDS, FLOOD, false>()))) void bp_ensemble_kernel(DevGraph g, BpLaunch a) {
+// One launch over the items of one request.  DG: decisions in global
+// memory.
+template <class F, bool SLAB_LDS, bool FLOOD, bool LAYERED = false, bool DG = false>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_target<F, SLAB_LDS, FLOOD, false, false, DG>()))) void bp_ensemble_kernel(DevGraph g, BpLaunch a) {
     using B = typename Prec<F>::B;
     extern __shared__ __align__(16) unsigned char lds[];
     const uint32_t slab_elems = g.max_chunks * kWave;
     B* gslab = a.slab ? reinterpret_cast<B*>(a.slab) + (size_t)blockIdx.x * slab_elems : nullptr;
     B* gmslab = FLOOD && a.slab ? reinterpret_cast<B*>(a.slab) + ((size_t)gridDim.x + blockIdx.x) * slab_elems : nullptr;
-    F* post = reinterpret_cast<F*>(a.post_slab) + (size_t)blockIdx.x * (g.n + kWave);
+    F* post = reinterpret_cast<F*>(a.post_slab) + (size_t)blockIdx.x * bp_post_elems(g);
     const Ctx<F> x = block_ctx<F>(gslab, gmslab, slab_elems, post);
     const uint32_t n_items = a.n_shots * g.L;
     for (;;) {
         const uint32_t item = wave_ticket(a.counter, 1u);
         if (item >= n_items) break;
-        run_item<F, SLAB_LDS, FLOOD, LAYERED>(g, a, item, lds, x);
+        run_item<F, SLAB_LDS, FLOOD, LAYERED, DG>(g, a, item, lds, x);
         __syncthreads();
     }
 }
@@ -1022,9 +1064,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_tar
 // segs[j].item0 is request j's first.  Every block owns slabs and
 // posteriors sized for the largest graph.  The segment table is read-only
 // for the launch and read through the constant address space, so its
-// fields load as wave-uniform scalars.
-template <class F, bool SLAB_LDS, bool FLOOD>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_target<F, SLAB_LDS, FLOOD, true>()))) void bp_ragged_kernel(RaggedLaunch r) {
+// fields load as wave-uniform scalars.  WITH_LAYERED: some segment may be
+// on the layered schedule (the variant without that item body needs fewer
+// registers).  DG: the other segments keep decisions in global memory.
+template <class F, bool SLAB_LDS, bool FLOOD, bool WITH_LAYERED, bool DG = false>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_target<F, SLAB_LDS, FLOOD, true, WITH_LAYERED, DG>()))) void bp_ragged_kernel(RaggedLaunch r) {
     using B = typename Prec<F>::B;
     using CSeg = const __attribute__((address_space(4))) BpSeg;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -1043,7 +1087,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_tar
         // one launch may mix schedules: parallel items need the launch's
         // second slab, serial ones use the first only, and layered ones
         // (global slabs only) keep messages and posteriors in the first
-        if constexpr (!SLAB_LDS) {
+        if constexpr (!SLAB_LDS && WITH_LAYERED) {
             if (g.layered) {
                 run_item<F, false, false, true>(g, a, item - segs[j].item0, lds, x);
                 __syncthreads();
@@ -1052,11 +1096,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_tar
         }
         if constexpr (FLOOD) {
             if (g.flood)
-                run_item<F, SLAB_LDS, true>(g, a, item - segs[j].item0, lds, x);
+                run_item<F, SLAB_LDS, true, false, DG>(g, a, item - segs[j].item0, lds, x);
             else
-                run_item<F, SLAB_LDS, false>(g, a, item - segs[j].item0, lds, x);
+                run_item<F, SLAB_LDS, false, false, DG>(g, a, item - segs[j].item0, lds, x);
         } else {
-            run_item<F, SLAB_LDS, false>(g, a, item - segs[j].item0, lds, x);
+            run_item<F, SLAB_LDS, false, false, DG>(g, a, item - segs[j].item0, lds, x);
         }
         __syncthreads();
     }
@@ -1071,27 +1115,28 @@ constexpr int multi_waves_target() {
     return sizeof(F) == 8 || P == 4 ? 4 : 5;
 }
 
-template <class F, int P>
+template <class F, int P, bool DG>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(multi_waves_target<F, P>()))) void bp_multi_kernel(DevGraph g, BpLaunch a) {
     using B = typename Prec<F>::B;
     extern __shared__ __align__(16) unsigned char lds[];
     const uint32_t slab_elems = g.max_chunks * kWave;
     B* gslab = reinterpret_cast<B*>(a.slab) + (size_t)blockIdx.x * slab_elems;
-    F* post = reinterpret_cast<F*>(a.post_slab) + (size_t)blockIdx.x * (P * g.n + kWave);
+    F* post = reinterpret_cast<F*>(a.post_slab) + (size_t)blockIdx.x * bp_post_elems(g);
     const Ctx<F> x = block_ctx<F>(gslab, nullptr, slab_elems, post);
     const uint32_t n_items = (a.n_shots + P - 1) / P * g.L;
     for (;;) {
         const uint32_t item = wave_ticket(a.counter, 1u);
         if (item >= n_items) break;
-        run_group<F, P>(g, a, item, lds, x);
+        run_group<F, P, DG>(g, a, item, lds, x);
         __syncthreads();
     }
 }
 
 // The ragged launch when some request runs several shots per wavefront:
 // every segment on the serial or layered schedule, slabs in global memory;
-// each segment's items follow its own shots per wavefront.
-template <class F>
+// each segment's items follow its own shots per wavefront.  DG: the
+// serial segments keep decisions in global memory.
+template <class F, bool DG>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void bp_ragged_multi_kernel(RaggedLaunch r) {
     using B = typename Prec<F>::B;
     using CSeg = const __attribute__((address_space(4))) BpSeg;
@@ -1111,11 +1156,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
         if (g.layered)
             run_item<F, false, false, true>(g, a, it, lds, x);
         else if (g.P == 2)
-            run_group<F, 2>(g, a, it, lds, x);
+            run_group<F, 2, DG>(g, a, it, lds, x);
         else if (g.P == 4)
-            run_group<F, 4>(g, a, it, lds, x);
+            run_group<F, 4, DG>(g, a, it, lds, x);
         else
-            run_item<F, false, false>(g, a, it, lds, x);
+            run_item<F, false, false, false, DG>(g, a, it, lds, x);
         __syncthreads();
     }
 }
@@ -1126,25 +1171,42 @@ __global__ void zero_kernel(uint32_t* p, size_t words) {
 }
 
 template <class F, bool FLOOD>
-const void* kernel_for_t(bool slab_in_lds, bool ragged) {
-    if (ragged)
-        return slab_in_lds ? (const void*)bp_ragged_kernel<F, true, FLOOD> : (const void*)bp_ragged_kernel<F, false, FLOOD>;
-    return slab_in_lds ? (const void*)bp_ensemble_kernel<F, true, FLOOD> : (const void*)bp_ensemble_kernel<F, false, FLOOD>;
+const void* kernel_for_t(bool slab_in_lds, bool ragged, bool layered, bool dg) {
+    if (ragged) {  // layered segments run with global slabs only
+        if (slab_in_lds) return (const void*)bp_ragged_kernel<F, true, FLOOD, false>;
+        if (layered) return (const void*)bp_ragged_kernel<F, false, FLOOD, true>;
+        return dg ? (const void*)bp_ragged_kernel<F, false, FLOOD, false, true>
+                  : (const void*)bp_ragged_kernel<F, false, FLOOD, false>;
+    }
+    if (slab_in_lds) return (const void*)bp_ensemble_kernel<F, true, FLOOD>;
+    return dg ? (const void*)bp_ensemble_kernel<F, false, FLOOD, false, true>
+              : (const void*)bp_ensemble_kernel<F, false, FLOOD>;
 }
 
-const void* kernel_for(bool fp64, bool flood, bool slab_in_lds, bool ragged, bool layered = false, uint32_t P = 1) {
-    // several shots per wavefront (ragged: in some segment): serial
-    // schedule, slab in global memory
+template <class F, bool DG>
+const void* multi_kernel_for(bool ragged, uint32_t P) {
+    if (ragged) return (const void*)bp_ragged_multi_kernel<F, DG>;
+    return P == 2 ? (const void*)bp_multi_kernel<F, 2, DG> : (const void*)bp_multi_kernel<F, 4, DG>;
+}
+
+// ragged: layered = some segment is layered, P > 1 = some segment runs
+// several shots per wavefront; dg: decisions in global memory (the
+// non-layered items; the slab in global memory)
+const void* kernel_for(bool fp64, bool flood, bool slab_in_lds, bool ragged, bool layered = false, uint32_t P = 1,
+                       bool dg = false) {
+    // several shots per wavefront: serial schedule, slab in global memory
     if (P > 1) {
-        if (ragged) return fp64 ? (const void*)bp_ragged_multi_kernel<double> : (const void*)bp_ragged_multi_kernel<float>;
-        if (P == 2) return fp64 ? (const void*)bp_multi_kernel<double, 2> : (const void*)bp_multi_kernel<float, 2>;
-        return fp64 ? (const void*)bp_multi_kernel<double, 4> : (const void*)bp_multi_kernel<float, 4>;
+        if (fp64) return dg ? multi_kernel_for<double, true>(ragged, P) : multi_kernel_for<double, false>(ragged, P);
+        return dg ? multi_kernel_for<float, true>(ragged, P) : multi_kernel_for<float, false>(ragged, P);
     }
     // the layered schedule: one request at a time, slab in global memory
-    if (layered) return fp64 ? (const void*)bp_ensemble_kernel<double, false, false, true>
-                             : (const void*)bp_ensemble_kernel<float, false, false, true>;
-    if (fp64) return flood ? kernel_for_t<double, true>(slab_in_lds, ragged) : kernel_for_t<double, false>(slab_in_lds, ragged);
-    return flood ? kernel_for_t<float, true>(slab_in_lds, ragged) : kernel_for_t<float, false>(slab_in_lds, ragged);
+    if (layered && !ragged) return fp64 ? (const void*)bp_ensemble_kernel<double, false, false, true>
+                                        : (const void*)bp_ensemble_kernel<float, false, false, true>;
+    if (fp64)
+        return flood ? kernel_for_t<double, true>(slab_in_lds, ragged, layered, dg)
+                     : kernel_for_t<double, false>(slab_in_lds, ragged, layered, dg);
+    return flood ? kernel_for_t<float, true>(slab_in_lds, ragged, layered, dg)
+                 : kernel_for_t<float, false>(slab_in_lds, ragged, layered, dg);
 }
 
 int launch_fn(const void* fn, int grid, size_t lds, void** args, hipStream_t st) {
@@ -1165,8 +1227,11 @@ int bp_slabs(const DevGraph& g) { return g.flood ? 2 : 1; }
 
 size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds) {
     const size_t mb = g.fp64 ? 8 : 4;
-    // per shot of the wavefront: syndrome, residual, decisions, row states
-    size_t b = (size_t)g.P * (sizeof(uint64_t) * (2 * (size_t)g.words_m + g.words_n) + mb * g.m);
+    // per shot of the wavefront: syndrome, residual, decisions (unless in
+    // global memory: never with the slab in LDS), row states
+    const bool dec_lds = slab_in_lds || !g.dec_global;
+    const size_t words = 2 * (size_t)g.words_m + (dec_lds ? g.words_n : 0);
+    size_t b = (size_t)g.P * (sizeof(uint64_t) * words + mb * g.m);
     if (slab_in_lds) b += bp_slabs(g) * mb * (size_t)g.max_chunks * kWave;
     return b;
 }
@@ -1175,7 +1240,8 @@ size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds) {
 
 bool bp_slab_fits_lds(const DevGraph& g) { return !g.layered && g.P == 1 && bp_lds_bytes(g, true) <= 96 * 1024; }
 
-int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged, bool layered, uint32_t P) {
+int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged, bool layered, uint32_t P,
+                bool dec_global) {
     static int cached_cus = 0;
     if (!cached_cus) {
         int dev = 0;
@@ -1186,15 +1252,24 @@ int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool 
     }
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, kernel_for(fp64, flood, slab_in_lds, ragged, layered, P), kWave, lds_bytes);
+        &per_cu, kernel_for(fp64, flood, slab_in_lds, ragged, layered, P, dec_global), kWave, lds_bytes);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     if (per_cu > 32) per_cu = 32;
     return per_cu * cached_cus;
 }
 
+bool dec_global_pays(const DevGraph& g) {
+    if (g.layered) return false;
+    DevGraph a = g, b = g;
+    a.dec_global = 0;
+    b.dec_global = 1;
+    // the LDS slab variant keeps decisions in LDS: compare global slabs
+    return bp_grid(b, false) > bp_grid(a, false);
+}
+
 int bp_grid(const DevGraph& g, bool slab_in_lds) {
     return bp_grid_for(g.fp64 != 0, g.flood != 0, slab_in_lds, bp_lds_bytes(g, slab_in_lds), false, g.layered != 0,
-                       g.P);
+                       g.P, g.dec_global != 0);
 }
 
 int launch_bp(const DevGraph& g, const BpLaunch& a, hipStream_t st) {
@@ -1203,16 +1278,22 @@ int launch_bp(const DevGraph& g, const BpLaunch& a, hipStream_t st) {
     if (g.P > 1 && (g.flood || g.layered || in_lds || a.post_out || !a.stop_on_converge))
         return fail(VIBE_EINVAL, "internal: several shots per wavefront need the serial schedule, a global slab "
                                  "and stop on convergence");
-    return launch_fn(kernel_for(g.fp64 != 0, g.flood != 0, in_lds, false, g.layered != 0, g.P), a.grid,
-                     bp_lds_bytes(g, in_lds), args, st);
+    if (g.dec_global && (g.layered || in_lds))
+        return fail(VIBE_EINVAL, "internal: decisions in global memory need a chunked schedule and a global slab");
+    return launch_fn(kernel_for(g.fp64 != 0, g.flood != 0, in_lds, false, g.layered != 0, g.P, g.dec_global != 0),
+                     a.grid, bp_lds_bytes(g, in_lds), args, st);
 }
 
 int launch_bp_ragged(const RaggedLaunch& r, hipStream_t st) {
     void* args[] = {const_cast<RaggedLaunch*>(&r)};
     if (r.multi && (r.flood || r.slab_in_lds))
         return fail(VIBE_EINVAL, "internal: several shots per wavefront need the serial schedule and a global slab");
-    return launch_fn(kernel_for(r.fp64 != 0, r.flood != 0, r.slab_in_lds != 0, true, false, r.multi ? 2u : 1u), r.grid,
-                     r.lds_bytes, args, st);
+    if (r.dec_global && (r.slab_in_lds || (r.layered && !r.multi)))
+        return fail(VIBE_EINVAL, "internal: decisions in global memory need global slabs (and no layered segment "
+                                 "outside the multi-shot launch)");
+    return launch_fn(kernel_for(r.fp64 != 0, r.flood != 0, r.slab_in_lds != 0, true, r.layered != 0,
+                                r.multi ? 2u : 1u, r.dec_global != 0),
+                     r.grid, r.lds_bytes, args, st);
 }
 
 int launch_zero(void* p, size_t bytes, hipStream_t st) {

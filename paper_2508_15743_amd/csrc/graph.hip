@@ -149,6 +149,7 @@ DevGraph decode_view(const vibe_graph* G, bool allow_multi) {
         d.max_chunks = G->multi_max_chunks[P / 4];
         d.P = P;
     }
+    if (!d.layered) d.dec_global = G->tune_dec < 0 ? (dec_global_pays(d) ? 1 : 0) : G->tune_dec;
     return d;
 }
 
@@ -489,6 +490,7 @@ extern "C" int vibe_graph_create(uint32_t m, uint32_t n, const uint32_t* h_indpt
     // posteriors (n) in the slab
     d.max_chunks = layered ? (uint32_t)((E + n + kWave - 1) / kWave) : ch_max;
     d.P = 1;
+    d.dec_global = 0;
     d.fp64 = fp64 ? 1 : 0;
     d.flood = c.schedule == 1 ? 1 : 0;
     d.layered = layered ? 1 : 0;

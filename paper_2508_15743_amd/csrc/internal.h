@@ -81,6 +81,9 @@ struct DevGraph {
     uint32_t max_chunks;        // largest chunk count of a member (slab = max_chunks * 64)
     uint32_t P;                 // shots per wavefront of the schedule in sched: 1 (64-edge
                                 // chunks), or 2 and 4 (chunks recut to 64 / P edges)
+    int dec_global;             // BP decisions in global memory (per-chunk decision
+                                // masks and a bitmap, after the block's posteriors)
+                                // instead of a bitmap in LDS
     int fp64;                   // message precision: 0 = FP32, 1 = FP64
     int flood;                  // schedule: 0 = serial-V, 1 = parallel (flooding)
     int layered;                // 1: layered (check-serial) schedule; cperm holds the check orders
@@ -136,6 +139,7 @@ struct vibe_graph {
     int tune_lds = -1;
     int tune_grid = 0;
     uint32_t tune_P = 1;
+    int tune_dec = -1;  // decisions in global memory: -1 = where that raises occupancy
     // decode schedules recut for 2 and 4 shots per wavefront (index P / 4),
     // built on first use
     const unsigned char* multi_recs[2] = {nullptr, nullptr};
@@ -209,25 +213,42 @@ struct RaggedLaunch {
     int slab_in_lds;
     int fp64, flood;
     int multi;             // some segment runs several shots per wavefront
+    int layered;           // some segment is on the layered schedule
+    int dec_global;        // the non-layered segments keep decisions in global memory
     size_t lds_bytes;      // largest bp_lds_bytes over the segments
 };
 int launch_bp_ragged(const RaggedLaunch& r, hipStream_t st);
 int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged, bool layered = false,
-                uint32_t P = 1);
+                uint32_t P = 1, bool dec_global = false);
 int bp_grid(const DevGraph& g, bool slab_in_lds);
 size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds);
 int bp_slabs(const DevGraph& g);  // slabs per block: 1 (serial), 2 (parallel: states and messages)
 bool bp_slab_fits_lds(const DevGraph& g);
-// posterior slab of one BP block: P x n posteriors, then 64 slots that absorb
-// the stores of lanes that own no column
-inline size_t bp_post_elems(const DevGraph& g) { return (size_t)g.P * g.n + kWave; }
+// posterior slab of one BP block, in message-precision elements: P x n
+// posteriors, then 64 slots that absorb the stores of lanes that own no
+// column, padded to 8 bytes; with decisions in global memory, then one
+// decision mask per chunk and P decision bitmaps of words_n words.  Every
+// size is a multiple of 8 bytes, so that each block's area (and, in a
+// ragged launch, the largest of them) keeps 8-byte alignment.
+__host__ __device__ inline size_t bp_post_head(const DevGraph& g) {
+    const size_t per8 = g.fp64 ? 1 : 2;  // elements per 8 bytes
+    return ((size_t)g.P * g.n + kWave + per8 - 1) / per8 * per8;
+}
+__host__ __device__ inline size_t bp_post_elems(const DevGraph& g) {
+    if (!g.dec_global) return bp_post_head(g);
+    return bp_post_head(g) + ((size_t)g.max_chunks + (size_t)g.P * g.words_n) * (g.fp64 ? 1 : 2);
+}
 // BP work items of n shots: (member, group of P shots)
 inline uint64_t bp_items(const DevGraph& g, uint64_t n) { return (n + g.P - 1) / g.P * g.L; }
 
 // The graph as the decoder launches it: the handle's graph with the
 // schedule recut for tune_P shots per wavefront when that is above 1 (and
-// allow_multi), else the 64-edge schedule.
+// allow_multi), else the 64-edge schedule; decisions in global memory as
+// tune_dec says (automatic: where that lets more wavefronts reside).
 DevGraph decode_view(const vibe_graph* G, bool allow_multi = true);
+// Whether decisions in global memory let more BP wavefronts reside than a
+// decision bitmap in LDS (g.dec_global ignored).
+bool dec_global_pays(const DevGraph& g);
 // Build (once) the decode schedule recut for P = 2 or 4 shots per wavefront.
 int build_multi_schedule(vibe_graph* G, uint32_t P);
 int launch_zero(void* p, size_t bytes, hipStream_t st);

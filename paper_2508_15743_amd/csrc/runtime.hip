@@ -107,6 +107,8 @@ struct Round {
     bool slab_in_lds = false;
     bool flood = false;  // some segment uses the parallel schedule
     bool multi = false;  // some segment runs several shots per wavefront
+    bool layered = false;  // some segment is on the layered schedule
+    bool dec_global = false;  // chunked segments keep decisions in global memory
 };
 
 size_t seg_bytes(const DevGraph& g, uint32_t n) {
@@ -173,20 +175,45 @@ std::vector<Round> plan(const vibe_request* reqs, uint32_t n_reqs, size_t budget
         bool lds_ok = true;
         bool fp64 = false, flood = false, multi = false;
         size_t lds_global = 0, lds_l = 0;
-        for (const Seg& sg : r.segs) flood = flood || reqs[sg.req].graph->h.dg.flood != 0;
-        // several shots per wavefront (the autotuner's choice per graph) in
-        // rounds on the serial and layered schedules only
+        bool layered = false;
+        for (const Seg& sg : r.segs) {
+            flood = flood || reqs[sg.req].graph->h.dg.flood != 0;
+            layered = layered || reqs[sg.req].graph->h.dg.layered != 0;
+        }
+        // several shots per wavefront (the autotuner's choice per graph)
+        // only in rounds where every serial segment runs them: the launch
+        // then needs the multi-shot kernel, whose lower occupancy would slow
+        // the other segments' items
+        bool all_multi = !flood;
         for (Seg& sg : r.segs) {
-            sg.g = decode_view(reqs[sg.req].graph, !flood);
+            const vibe_graph* G = reqs[sg.req].graph;
+            if (!G->h.dg.layered) all_multi = all_multi && decode_view(G).P > 1;
+        }
+        for (Seg& sg : r.segs) {
+            sg.g = decode_view(reqs[sg.req].graph, all_multi);
             multi = multi || sg.g.P > 1;
         }
+        // slabs in LDS only if every segment's fits (with its decisions in
+        // LDS) and no graph was tuned otherwise
         for (const Seg& sg : r.segs) {
-            const vibe_graph* G = reqs[sg.req].graph;
+            DevGraph g = sg.g;
+            g.dec_global = 0;
+            lds_ok = lds_ok && !multi && bp_slab_fits_lds(g) && reqs[sg.req].graph->tune_lds != 0;
+        }
+        // decisions in global memory for every chunked segment if one of
+        // them wants it (a graph whose decision bitmap would cap the
+        // launch's occupancy); not with LDS slabs, and the launch without
+        // several shots per wavefront has no such variant with layered
+        // segments
+        bool dg = false;
+        for (const Seg& sg : r.segs) dg = dg || (!sg.g.layered && sg.g.dec_global);
+        if (lds_ok || (layered && !multi)) dg = false;
+        for (Seg& sg : r.segs) sg.g.dec_global = (dg && !sg.g.layered) ? 1 : 0;
+        for (const Seg& sg : r.segs) {
             const DevGraph& g = sg.g;
             fp64 = g.fp64 != 0;
             r.slab_elems = std::max<uint32_t>(r.slab_elems, std::max<uint32_t>(g.max_chunks, 1) * kWave);
             r.post_elems = std::max<uint32_t>(r.post_elems, (uint32_t)bp_post_elems(g));
-            lds_ok = lds_ok && !multi && bp_slab_fits_lds(g) && G->tune_lds != 0;
             lds_global = std::max(lds_global, bp_lds_bytes(g, false));
             lds_l = std::max(lds_l, bp_lds_bytes(g, true));
             r.lsd_per_block = std::max(r.lsd_per_block, lsd_scratch_per_block(g));
@@ -194,8 +221,10 @@ std::vector<Round> plan(const vibe_request* reqs, uint32_t n_reqs, size_t budget
         r.slab_in_lds = lds_ok;
         r.flood = flood;
         r.multi = multi;
+        r.layered = layered;
+        r.dec_global = dg;
         r.lds_bytes = lds_ok ? lds_l : lds_global;
-        r.grid = bp_grid_for(fp64, flood, lds_ok, r.lds_bytes, true, false, multi ? 2u : 1u);
+        r.grid = bp_grid_for(fp64, flood, lds_ok, r.lds_bytes, true, layered, multi ? 2u : 1u, r.dec_global);
         uint64_t total_items = 0, max_n = 0;
         for (const Seg& sg : r.segs) {
             total_items += bp_items(sg.g, sg.n);
@@ -299,6 +328,8 @@ int run_round(const vibe_request* reqs, const Round& r, unsigned char* base, hip
     L.fp64 = reqs[r.segs[0].req].graph->h.dg.fp64;
     L.flood = r.flood ? 1 : 0;
     L.multi = r.multi ? 1 : 0;
+    L.layered = r.layered ? 1 : 0;
+    L.dec_global = r.dec_global ? 1 : 0;
     L.lds_bytes = r.lds_bytes;
     if ((rc = launch_bp_ragged(L, st))) return rc;
     for (size_t j = 0; j < r.segs.size(); j++) {
@@ -338,7 +369,9 @@ int run_round(const vibe_request* reqs, const Round& r, unsigned char* base, hip
     return VIBE_OK;
 }
 
-constexpr size_t kRaggedBudget = 4ull << 30;  // per-shot buffers of one round
+// per-shot buffers of one round: large batches of large codes run as few
+// rounds (each ends in a launch tail) within a fraction of the 288 GB HBM
+constexpr size_t kRaggedBudget = 32ull << 30;
 
 }  // namespace
 
@@ -505,6 +538,11 @@ int apply_launch(vibe_graph* g, const vibe_launch_t& s) {
     const uint32_t P = (uint32_t)s.shots_per_wave;
     if (P != 1 && P != 2 && P != 4) return fail(VIBE_EINVAL, "shots_per_wave must be 1, 2 or 4");
     if (s.grid < 0) return fail(VIBE_EINVAL, "grid must be >= 0");
+    if (s.decisions_global < -1 || s.decisions_global > 1) return fail(VIBE_EINVAL, "decisions_global must be -1, 0 or 1");
+    if (s.decisions_global == 1 && s.slab_in_lds)
+        return fail(VIBE_EINVAL, "decisions in global memory need the slab in global memory");
+    if (s.decisions_global == 1 && g->h.dg.layered)
+        return fail(VIBE_EUNSUPPORTED, "the layered schedule keeps its decisions in LDS");
     if (P > 1) {
         if (!multi_ok(g, P)) return fail(VIBE_EUNSUPPORTED, "several shots per wavefront need the serial schedule "
                                                              "and row states within 96 KB of LDS");
@@ -515,6 +553,7 @@ int apply_launch(vibe_graph* g, const vibe_launch_t& s) {
     g->tune_lds = s.slab_in_lds ? 1 : 0;
     g->tune_grid = s.grid;
     g->tune_P = P;
+    g->tune_dec = s.decisions_global;
     return VIBE_OK;
 }
 
@@ -533,6 +572,7 @@ extern "C" int vibe_get_launch(const vibe_graph* g, vibe_launch_t* s) {
     s->slab_in_lds = g->tune_lds < 0 ? (bp_slab_fits_lds(g->h.dg) ? 1 : 0) : g->tune_lds;
     s->grid = g->tune_grid;
     s->shots_per_wave = (int)g->tune_P;
+    s->decisions_global = g->tune_dec;
     s->from_cache = 0;
     s->ms = 0.0;
     return VIBE_OK;
@@ -566,7 +606,7 @@ extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    const int saved_lds = g->tune_lds, saved_grid = g->tune_grid;
+    const int saved_lds = g->tune_lds, saved_grid = g->tune_grid, saved_dec = g->tune_dec;
     const uint32_t saved_P = g->tune_P;
     int rc = VIBE_OK;
     // decode time of the sample with setting s (the first of two runs warms up)
@@ -584,11 +624,12 @@ extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B
     // first the slab placement and shots per wavefront at full occupancy,
     // then the grid for the best of them
     std::vector<vibe_launch_t> first;
-    if (bp_slab_fits_lds(d)) first.push_back(vibe_launch_t{1, 0, 1, 0, 0.0});
-    first.push_back(vibe_launch_t{0, 0, 1, 0, 0.0});
-    for (int P : {2, 4})
-        if (multi_ok(g, (uint32_t)P)) first.push_back(vibe_launch_t{0, 0, P, 0, 0.0});
-    vibe_launch_t best{0, 0, 1, 0, 1e30};
+    if (bp_slab_fits_lds(d)) first.push_back(vibe_launch_t{1, 0, 1, 0, 0, 0.0});
+    for (int P : {1, 2, 4})
+        if (P == 1 || multi_ok(g, (uint32_t)P))
+            for (int dec : {0, 1})
+                if (!d.layered || dec == 0) first.push_back(vibe_launch_t{0, 0, P, dec, 0, 0.0});
+    vibe_launch_t best{0, 0, 1, 0, 0, 1e30};
     for (const vibe_launch_t& s : first) {
         float ms = 0.0f;
         rc = time_it(s, &ms);
@@ -603,11 +644,9 @@ extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B
         }
     }
     if (!rc) {
-        DevGraph v = d;
-        if (best.shots_per_wave > 1) {
-            (void)apply_launch(g, best);
-            v = decode_view(g);
-        }
+        (void)apply_launch(g, best);
+        DevGraph v = decode_view(g);
+        if (best.slab_in_lds) v.dec_global = 0;
         const int full = bp_grid(v, best.slab_in_lds != 0);
         const vibe_launch_t base = best;
         for (int eighths : {7, 6, 5, 4}) {
@@ -630,6 +669,7 @@ extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B
         g->tune_lds = saved_lds;
         g->tune_grid = saved_grid;
         g->tune_P = saved_P;
+        g->tune_dec = saved_dec;
         return rc;
     }
     if ((rc = apply_launch(g, best))) return rc;

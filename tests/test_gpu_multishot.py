@@ -1,4 +1,5 @@
-"""Several shots per wavefront (through the C ABI).
+"""Launch settings of K1 (through the C ABI): several shots per wavefront
+and decisions in global memory.
 
 With shots_per_wave = P > 1 one wavefront runs P shots of a member side by
 side on the member's schedule recut into chunks of 64 / P edges.  The recut
@@ -6,10 +7,13 @@ keeps the sweep (a part of a set of independent columns is independent, and
 the order of the 64-edge chunks is kept), and every message is computed by
 the same operations in the same order, so the outputs must equal those of
 one shot per wavefront bit for bit, in FP32 and FP64 alike, for batches
-that do not fill the last group of P shots.  The FP64 decodes are also
-compared with the oracle on a sample of shots (Sec. III.D.2; Algorithm 1's
-serial sweep).  The same holds in ragged launches that mix graphs with
-different P, in captured replays and in the no-allocation entry point.
+that do not fill the last group of P shots.  Decisions kept in global
+memory (per-chunk masks and a bitmap) instead of LDS change only where the
+same bits are stored, so they too must give identical outputs.  The FP64
+decodes are also compared with the oracle on a sample of shots (Sec.
+III.D.2; Algorithm 1's serial sweep).  The same holds in ragged launches
+that mix graphs with different settings, in captured replays and in the
+no-allocation entry point.
 """
 import numpy as np
 import pytest
@@ -65,11 +69,12 @@ def test_multishot_equals_one_shot_per_wave(torch_cuda, bits):
         G = P.Graph.from_dem(dem, permutations(dem.n, L, 60 + i), L=L, M=M, T_max=T, message_bits=bits)
         synd = sample(dem, 301, 70 + i).syndromes  # 301 = 4 * 75 + 1: the last group is ragged
         s = _dev(torch, synd)
-        G.set_launch(slab_in_lds=0, shots_per_wave=1)
+        G.set_launch(slab_in_lds=0, shots_per_wave=1, decisions_global=0)
         ref = G.decode(s)
-        for Pw in (2, 4):
-            G.set_launch(slab_in_lds=0, shots_per_wave=Pw)
-            assert G.get_launch()["shots_per_wave"] == Pw
+        for Pw, dec in ((1, 1), (2, 0), (2, 1), (4, 0), (4, 1)):
+            G.set_launch(slab_in_lds=0, shots_per_wave=Pw, decisions_global=dec)
+            got_l = G.get_launch()
+            assert (got_l["shots_per_wave"], got_l["decisions_global"]) == (Pw, dec)
             got = G.decode(s)
             _same(torch, got, ref)
             # batches smaller than one group
@@ -115,8 +120,8 @@ def test_multishot_in_ragged_capture_and_noalloc(torch_cuda):
         gs.append((dem, G))
         ss.append(_dev(torch, sample(dem, [37, 150, 5, 64][i], 80 + i).syndromes))
     # one graph per setting, plus a layered one in the same launch
-    for (_, G), Pw in zip(gs, (4, 2, 1, 4)):
-        G.set_launch(shots_per_wave=Pw)
+    for (_, G), Pw, dec in zip(gs, (4, 2, 1, 4), (0, 1, 1, 0)):
+        G.set_launch(shots_per_wave=Pw, decisions_global=dec)
     demL = circuit_dem(5, 5, 1e-3)
     GL = P.Graph.from_dem(demL, permutations(demL.m, 16, 9), L=16, M=5, T_max=20, schedule="layered")
     sL = _dev(torch, sample(demL, 40, 10).syndromes)
@@ -137,6 +142,13 @@ def test_multishot_in_ragged_capture_and_noalloc(torch_cuda):
     # the no-allocation entry point runs the chosen setting too
     for (_, G), s, want in zip(gs, ss, single):
         _same(torch, G.decode(s, noalloc=True), want)
+    # every serial graph on one shot per wavefront: a launch of the plain
+    # ragged kernel with decisions in global memory for all of them
+    for (_, G), dec in zip(gs, (1, 0, 0, 0)):
+        G.set_launch(shots_per_wave=1, decisions_global=dec)
+    pairs2 = [(G, s) for (_, G), s in zip(gs, ss)]
+    for a, b in zip(P.Runtime().decode(pairs2), single[:4]):
+        _same(torch, a, b)
     for _, G in gs:
         G.close()
     GL.close()
@@ -178,6 +190,9 @@ def test_set_launch_rejects_what_it_cannot_run(torch_cuda):
     assert e.value.code == P.VIBE_EINVAL
     with pytest.raises(P.VibeError) as e:
         G.set_launch(slab_in_lds=1, shots_per_wave=2)
+    assert e.value.code == P.VIBE_EINVAL
+    with pytest.raises(P.VibeError) as e:
+        G.set_launch(slab_in_lds=1, decisions_global=1)
     assert e.value.code == P.VIBE_EINVAL
     Gp = P.Graph.from_dem(dem, permutations(dem.n, 1, 1), L=1, M=1, T_max=10, schedule="parallel")
     with pytest.raises(P.VibeError) as e:
