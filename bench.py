@@ -75,12 +75,15 @@ def measured_traffic(launch_shots, profile=PROFILE, sources=KERNEL_SOURCES, key=
     return float(vals["traffic_bytes_per_launch"])
 
 
-def ragged_leg(P, torch, shots, seed, tune=True):
+def ragged_leg(P, torch, shots, seed, tune=True, per_call=20000):
     """Circuit-level codes d = 5, 7, 9, 11, 13 (rounds = d, p = 1e-3) in one
     ragged call against one vibe_decode per code on the same syndromes.
     With `tune`, each graph is first autotuned on up to 2048 of its shots
-    (slab placement, shots per wavefront, grid) and both paths run with the
-    chosen settings; the choices are reported."""
+    (slab placement, shots per wavefront, decision placement, grid) and
+    both paths run with the chosen settings; the choices are reported.
+    More than `per_call` shots per code run as several calls of at most
+    that many per code on both paths (20000 per code fit one round of the
+    ragged planner: one persistent BP launch over the five codes)."""
     from synth.dem import circuit_dem
     from synth.sample import permutations, sample
 
@@ -93,29 +96,39 @@ def ragged_leg(P, torch, shots, seed, tune=True):
         if tune:
             ch = G.autotune(s[:min(shots, 2048)])
             tuned.append({"code": f"circuit_d{d}_r{d}_p0.001", **{k: ch[k] for k in
-                          ("shots_per_wave", "grid", "slab_in_lds", "from_cache")}, "sample_ms": round(ch["ms"], 2)})
+                          ("shots_per_wave", "decisions_global", "grid", "slab_in_lds", "from_cache")},
+                          "sample_ms": round(ch["ms"], 2)})
             log(f"autotune d={d}: {ch}")
         pairs.append((G, s))
     rt = P.Runtime()
     outs = [P.Runtime.outputs(G, s) for G, s in pairs]
+    pieces = [(a, min(a + per_call, shots)) for a in range(0, shots, per_call)]
     warm = min(shots, 1024)  # kernels, schedules and workspace of the small call
     rt.decode([(G, s[:warm]) for G, s in pairs])
     torch.cuda.synchronize()
-    log(f"ragged mix: {shots} shots per code, one call")
+    log(f"ragged mix: {shots} shots per code, {len(pieces)} ragged call(s)")
     t0 = time.perf_counter()
-    rt.decode(pairs, outs=outs)
-    torch.cuda.synchronize()
+    for a, b in pieces:
+        rt.decode([(G, s[a:b]) for G, s in pairs], outs=[tuple(x[a:b] for x in o) for o in outs])
+        torch.cuda.synchronize()
+        if len(pieces) > 1:
+            log(f"  ragged call over shots {a}..{b} of each code done at {time.perf_counter() - t0:.1f}s")
     t_ragged = time.perf_counter() - t0
-    log(f"ragged mix: {shots} shots per code, one call per code")
+    log(f"ragged mix: {shots} shots per code, {len(pieces)} call(s) per code")
     t_code = []
     for (G, s), o in zip(pairs, outs):
         t0 = time.perf_counter()
-        G.decode(s, out=o)
+        for a, b in pieces:
+            G.decode(s[a:b], out=tuple(x[a:b] for x in o))
+            if len(pieces) > 1:
+                torch.cuda.synchronize()
+                log(f"  call over shots {a}..{b} of one code done at {time.perf_counter() - t0:.1f}s")
         torch.cuda.synchronize()
         t_code.append(time.perf_counter() - t0)
     t_sep = sum(t_code)
     total = shots * len(cfgs)
     res = {"codes": [f"circuit_d{d}_r{d}_p0.001" for d, *_ in cfgs], "shots_per_code": shots,
+           "calls_per_code": len(pieces),
            "ragged_shots_per_s": round(total / t_ragged, 1), "separate_shots_per_s": round(total / t_sep, 1),
            "ragged_over_separate": round(t_sep / t_ragged, 3),
            "separate_s_per_code": [round(t, 3) for t in t_code], "autotuned": tuned if tune else None}
