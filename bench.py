@@ -432,6 +432,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-phenom", action="store_true", help="skip the phenomenological LSD-0 / LSD-10 leg")
     ap.add_argument("--no-tune", action="store_true", help="skip the parameter-fitting leg")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the headline graph with the default launch settings (profiling runs)")
     ap.add_argument("--phenom-shots", type=int, default=16384)
     ap.add_argument("--grad-batch", type=int, default=4096)
     ap.add_argument("--grad-K", type=int, default=16)
@@ -525,8 +527,11 @@ def main():
     st = torch.empty((B, 8), dtype=torch.int32, device=dev)
     out = (corr, obs, st)
     # launch settings: timed on a sample of the batch, kept in the handle
-    tune = G.autotune(synd[:min(B, 4096)])
-    log(f"autotune on {min(B, 4096)} shots: {tune}")
+    if args.no_autotune:
+        tune = {**G.get_launch(), "from_cache": False}
+    else:
+        tune = G.autotune(synd[:min(B, 4096)])
+        log(f"autotune on {min(B, 4096)} shots: {tune}")
 
     for i in range(args.warmup):
         G.decode(synd, out=out)
@@ -564,8 +569,10 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "measured_peak": round(copy_gbs, 1), "frac_of_measured": round(achieved / copy_gbs, 4),
-                # the committed counters were taken with one shot per wavefront
-                "traffic": measured_traffic(launch_shots) if tune["shots_per_wave"] == 1 else None,
+                # the committed counters were taken with the default settings:
+                # one shot per wavefront, decisions in LDS
+                "traffic": (measured_traffic(launch_shots)
+                            if tune["shots_per_wave"] == 1 and tune["decisions_global"] != 1 else None),
                 "slab_stream_ceiling": round(stream_gbs, 1),
                 "kernel": "bp_ensemble_kernel",
                 "avg_launch_ms": round(bp_ms / max(bp_launches, 1), 3),
@@ -593,7 +600,8 @@ def main():
                    "m": dem.m, "n": dem.n, "nnz": dem.nnz, "L": L, "M": M, "T_max": T,
                    "alpha": alpha, "lsd_order": 0, "levels": [info["levels_min"], info["levels_max"]]},
         "roofline": roofline,
-        "autotune": {k: tune[k] for k in ("slab_in_lds", "grid", "shots_per_wave", "from_cache")},
+        "autotune": {k: tune[k] for k in ("slab_in_lds", "grid", "shots_per_wave", "decisions_global",
+                                          "from_cache")},
         "lsd_fraction": round(lsd_frac, 5),
         "logical_error_rate": ler,
         "mean_member_iterations_per_shot": member_iters / (B * args.steps),

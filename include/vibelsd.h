@@ -327,7 +327,10 @@ void vibe_exec_destroy(vibe_exec* ex); /* synchronises the device first; NULL ac
  *                   of a bitmap in LDS (0).  On large graphs the bitmap
  *                   (n / 8 bytes per wavefront) caps how many wavefronts
  *                   fit in LDS; automatic takes global memory where that
- *                   lets more reside.  Not with the slab in LDS.
+ *                   lets more reside and the launch has more work items
+ *                   than reside with the bitmap in LDS (a small batch is
+ *                   bound by its serial chains, which the global masks
+ *                   lengthen).  Not with the slab in LDS.
  * vibe_set_launch applies settings (building the recut schedule on first
  * use: EUNSUPPORTED for the parallel and layered schedules); settings that
  * vibe_decode_noalloc uses must be applied before it is called.

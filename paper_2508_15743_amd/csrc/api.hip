@@ -285,8 +285,9 @@ int decode_batch(vibe_graph* G, const uint8_t* bytes, const uint64_t* words, uin
     if (B && (!corrections || (!observables && G->h.k))) return fail(VIBE_EINVAL, "an output pointer is NULL");
     if (!B) return VIBE_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    DevGraph g = decode_view(G);
+    DevGraph g = decode_view(G, true, B);
     const uint32_t bc = chunk_for(g, B, true);
+    if (bc < B) g = decode_view(G, true, bc);
     uint8_t* u = nullptr;
     if (words) {
         const size_t in_bytes = al256((size_t)bc * (g.m ? g.m : 1));
@@ -520,7 +521,7 @@ extern "C" int vibe_decode_noalloc(vibe_graph* G, const uint8_t* syndromes, uint
     if (rc) return rc;
     if (B && (!corrections || (!observables && G->h.k))) return fail(VIBE_EINVAL, "an output pointer is NULL");
     if (!B) return VIBE_OK;
-    DevGraph g = decode_view(G);
+    DevGraph g = decode_view(G, true, B);
     const bool in_lds = bp_slab_fits_lds(g) && G->tune_lds != 0;
     if (in_lds) g.dec_global = 0;  // the LDS slab variant keeps decisions in LDS
     const int full = G->tune_grid > 0 ? std::min(G->tune_grid, bp_grid(g, in_lds)) : bp_grid(g, in_lds);

@@ -140,7 +140,7 @@ int build_multi_schedule(vibe_graph* G, uint32_t P) {
     return VIBE_OK;
 }
 
-DevGraph decode_view(const vibe_graph* G, bool allow_multi) {
+DevGraph decode_view(const vibe_graph* G, bool allow_multi, uint64_t shots) {
     DevGraph d = G->h.dg;
     const uint32_t P = G->tune_P;
     if (allow_multi && (P == 2 || P == 4) && G->multi_recs[P / 4]) {
@@ -149,7 +149,18 @@ DevGraph decode_view(const vibe_graph* G, bool allow_multi) {
         d.max_chunks = G->multi_max_chunks[P / 4];
         d.P = P;
     }
-    if (!d.layered) d.dec_global = G->tune_dec < 0 ? (dec_global_pays(d) ? 1 : 0) : G->tune_dec;
+    if (!d.layered) {
+        if (G->tune_dec >= 0) {
+            d.dec_global = G->tune_dec;
+        } else {
+            // automatic: only a launch with more items than fit at once with
+            // the decisions in LDS gains from more residency (a small batch
+            // is bound by its chains, which the global masks lengthen)
+            d.dec_global = 0;
+            const uint64_t items = shots == UINT64_MAX ? UINT64_MAX : bp_items(d, shots);
+            if (items > (uint64_t)bp_grid(d, false) && dec_global_pays(d)) d.dec_global = 1;
+        }
+    }
     return d;
 }
 

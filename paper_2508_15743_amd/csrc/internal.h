@@ -241,11 +241,12 @@ __host__ __device__ inline size_t bp_post_elems(const DevGraph& g) {
 // BP work items of n shots: (member, group of P shots)
 inline uint64_t bp_items(const DevGraph& g, uint64_t n) { return (n + g.P - 1) / g.P * g.L; }
 
-// The graph as the decoder launches it: the handle's graph with the
-// schedule recut for tune_P shots per wavefront when that is above 1 (and
-// allow_multi), else the 64-edge schedule; decisions in global memory as
-// tune_dec says (automatic: where that lets more wavefronts reside).
-DevGraph decode_view(const vibe_graph* G, bool allow_multi = true);
+// The graph as the decoder launches it for `shots` shots: the handle's graph
+// with the schedule recut for tune_P shots per wavefront when that is above
+// 1 (and allow_multi), else the 64-edge schedule; decisions in global memory
+// as tune_dec says (automatic: where that lets more wavefronts reside and
+// the work items outnumber those that reside with decisions in LDS).
+DevGraph decode_view(const vibe_graph* G, bool allow_multi = true, uint64_t shots = UINT64_MAX);
 // Whether decisions in global memory let more BP wavefronts reside than a
 // decision bitmap in LDS (g.dec_global ignored).
 bool dec_global_pays(const DevGraph& g);

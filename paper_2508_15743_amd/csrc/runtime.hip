@@ -190,7 +190,7 @@ std::vector<Round> plan(const vibe_request* reqs, uint32_t n_reqs, size_t budget
             if (!G->h.dg.layered) all_multi = all_multi && decode_view(G).P > 1;
         }
         for (Seg& sg : r.segs) {
-            sg.g = decode_view(reqs[sg.req].graph, all_multi);
+            sg.g = decode_view(reqs[sg.req].graph, all_multi, sg.n);
             multi = multi || sg.g.P > 1;
         }
         // slabs in LDS only if every segment's fits (with its decisions in
@@ -645,7 +645,7 @@ extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B
     }
     if (!rc) {
         (void)apply_launch(g, best);
-        DevGraph v = decode_view(g);
+        DevGraph v = decode_view(g, true, B);
         if (best.slab_in_lds) v.dec_global = 0;
         const int full = bp_grid(v, best.slab_in_lds != 0);
         const vibe_launch_t base = best;
