@@ -202,3 +202,29 @@ def test_set_launch_rejects_what_it_cannot_run(torch_cuda):
     assert G.get_launch()["shots_per_wave"] == 1
     G.close()
     Gp.close()
+
+
+def test_decisions_global_parallel_schedule_and_ragged(torch_cuda):
+    """Decisions in global memory on the parallel (flooding) schedule, alone
+    and in a ragged launch mixing it with a serial graph: identical to the
+    decisions in LDS."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    dems = [circuit_dem(5, 5, 1e-3), phenomenological_dem(7, 7, 0.01, 0.01)]
+    Gp = P.Graph.from_dem(dems[0], permutations(dems[0].n, 1, 31), L=1, M=1, T_max=20, schedule="parallel")
+    Gs = P.Graph.from_dem(dems[1], permutations(dems[1].n, 24, 32), L=24, M=5, T_max=30)
+    ss = [_dev(torch, sample(d, 333, 40 + i).syndromes) for i, d in enumerate(dems)]
+    for G in (Gp, Gs):
+        G.set_launch(decisions_global=0)
+    ref = [Gp.decode(ss[0]), Gs.decode(ss[1])]
+    for G in (Gp, Gs):
+        G.set_launch(decisions_global=1)
+    _same(torch, Gp.decode(ss[0]), ref[0])
+    _same(torch, Gs.decode(ss[1]), ref[1])
+    rt = P.Runtime()
+    for a, b in zip(rt.decode([(Gp, ss[0]), (Gs, ss[1])]), ref):
+        _same(torch, a, b)
+    rt.close()
+    Gp.close()
+    Gs.close()
