@@ -149,7 +149,8 @@ GRAD_BYTES_PER_EDGE_ITER = 20.0
 def phenom_leg(P, torch, seed, shots):
     """The phenomenological workload as configured (colour code d = 11, 11
     noisy rounds and a perfect one, p = q = 0.01; L = 32, M = 5, T = 50,
-    FP32): LSD-0 against LSD order 10 on the same seeded shots."""
+    FP32): LSD-0 against LSD order 10 on the same seeded shots, each graph
+    autotuned first on 4096 of them."""
     from synth.dem import phenomenological_dem
     from synth.sample import permutations, sample
 
@@ -162,6 +163,7 @@ def phenom_leg(P, torch, seed, shots):
     for order in (0, 10):
         G = P.Graph.from_dem(dem, perms, L=32, M=5, T_max=50, lsd_order=order)
         G.decode(synd[:256])
+        ch = G.autotune(synd[:min(shots, 4096)])
         torch.cuda.synchronize()
         P.vibe_profile_enable(G.handle, True)
         P.vibe_profile_read(G.handle)
@@ -179,17 +181,21 @@ def phenom_leg(P, torch, seed, shots):
                               "bp_kernel_ms": round(prof["bp_ensemble"][0], 3),
                               "edge_updates_per_s": float(st[:, 7].astype(np.int64).sum()) * dem.nnz
                               / max(prof["bp_ensemble"][0] / 1e3, 1e-9),
-                              "logical_error_rate": float((obs.cpu().numpy() != b.observables).any(1).mean())}
-        log(f"phenomenological LSD-{order}: {shots / dt:.0f} shots/s, LSD kernel {prof['lsd'][0]:.1f} ms")
+                              "logical_error_rate": float((obs.cpu().numpy() != b.observables).any(1).mean()),
+                              "autotune": {k: ch[k] for k in ("slab_in_lds", "grid", "shots_per_wave",
+                                                               "decisions_global", "from_cache")}}
+        log(f"phenomenological LSD-{order}: {shots / dt:.0f} shots/s, LSD kernel {prof['lsd'][0]:.1f} ms "
+            f"(autotuned: {ch})")
     out["corrections_changed_by_order10"] = int((corr[0] != corr[10]).any(1).sum())
     return out
 
 
 def code_capacity_leg(P, torch, seed, shots=10000):
     """The code-capacity workload as configured (colour code d = 5, p = 0.05,
-    10^4 shots; L = 16, M = 5, T = 32, FP32).  Its message slab lives in LDS,
-    so the bound is LDS and issue, not HBM: edge-updates/s and the slab
-    bytes they move through LDS (16 B per edge-update) are reported."""
+    10^4 shots; L = 16, M = 5, T = 32, FP32), autotuned first on 4096 of its
+    shots.  Its message slab fits in LDS, so the bound is LDS and issue, not
+    HBM: edge-updates/s and the slab bytes they move (16 B per edge-update)
+    are reported."""
     from synth.dem import code_capacity_dem
     from synth.sample import permutations, sample
 
@@ -198,6 +204,7 @@ def code_capacity_leg(P, torch, seed, shots=10000):
     synd = torch.from_numpy(b.syndromes).to("cuda:0")
     G = P.Graph.from_dem(dem, permutations(dem.n, 16, seed + 10), L=16, M=5, T_max=32)
     G.decode(synd[:256])
+    ch = G.autotune(synd[:min(shots, 4096)])
     torch.cuda.synchronize()
     P.vibe_profile_enable(G.handle, True)
     P.vibe_profile_read(G.handle)
@@ -213,8 +220,10 @@ def code_capacity_leg(P, torch, seed, shots=10000):
            "shots_per_s": round(shots / dt, 1), "bp_kernel_ms": round(prof["bp_ensemble"][0], 3),
            "edge_updates_per_s": eu, "lds_slab_bytes_per_s": 16.0 * eu,
            "lsd_fraction": round(float(((st[:, 0] & 2) != 0).mean()), 5),
-           "logical_error_rate": float((obs.cpu().numpy() != b.observables).any(1).mean())}
-    log(f"code capacity: {shots / dt:.0f} shots/s, {eu:.3g} edge-updates/s")
+           "logical_error_rate": float((obs.cpu().numpy() != b.observables).any(1).mean()),
+           "autotune": {k: ch[k] for k in ("slab_in_lds", "grid", "shots_per_wave", "decisions_global",
+                                            "from_cache")}}
+    log(f"code capacity: {shots / dt:.0f} shots/s, {eu:.3g} edge-updates/s (autotuned: {ch})")
     return out
 
 

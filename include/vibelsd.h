@@ -310,10 +310,12 @@ void vibe_exec_destroy(vibe_exec* ex); /* synchronises the device first; NULL ac
  * Launch settings of the BP ensemble (K1) for one graph.  The ensemble is
  * (shot, member) work items, each run by one wavefront in the paper's
  * layout (Sec. III.D.1: the hardware bounds how far the decoders run in
- * parallel).  Three settings map it onto the GPU; the decoder's results do
+ * parallel).  Four settings map it onto the GPU; the decoder's results do
  * not depend on any of them:
  *   slab_in_lds     1: the member's message slab lives in LDS (only where
  *                   it fits, one shot per wavefront); 0: global memory.
+ *                   Before any setting is applied: LDS where it fits and
+ *                   lets as many wavefronts reside as a global slab.
  *   grid            persistent BP blocks (0 = as many as fit at once).
  *   shots_per_wave  1, 2 or 4: one wavefront runs P shots of a member side
  *                   by side on the member's schedule recut into chunks of

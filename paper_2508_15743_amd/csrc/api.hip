@@ -306,7 +306,7 @@ int decode_batch(vibe_graph* G, const uint8_t* bytes, const uint64_t* words, uin
         }
         u = static_cast<uint8_t*>(G->ws_in.base);
     }
-    const bool in_lds = bp_slab_fits_lds(g) && G->tune_lds != 0;
+    const bool in_lds = use_lds_slab(G, g);
     if (in_lds) g.dec_global = 0;  // the LDS slab variant keeps decisions in LDS
     const int bpg = G->tune_grid > 0 ? std::min(G->tune_grid, bp_grid(g, in_lds)) : bp_grid(g, in_lds);
     const int lg = lsd_grid_for(bc);
@@ -522,7 +522,7 @@ extern "C" int vibe_decode_noalloc(vibe_graph* G, const uint8_t* syndromes, uint
     if (B && (!corrections || (!observables && G->h.k))) return fail(VIBE_EINVAL, "an output pointer is NULL");
     if (!B) return VIBE_OK;
     DevGraph g = decode_view(G, true, B);
-    const bool in_lds = bp_slab_fits_lds(g) && G->tune_lds != 0;
+    const bool in_lds = use_lds_slab(G, g);
     if (in_lds) g.dec_global = 0;  // the LDS slab variant keeps decisions in LDS
     const int full = G->tune_grid > 0 ? std::min(G->tune_grid, bp_grid(g, in_lds)) : bp_grid(g, in_lds);
     int bpg = 0, lg = 0;

@@ -1258,6 +1258,14 @@ int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool 
     return per_cu * cached_cus;
 }
 
+bool use_lds_slab(const vibe_graph* G, const DevGraph& g) {
+    if (G->tune_lds == 0 || !bp_slab_fits_lds(g)) return false;
+    if (G->tune_lds > 0) return true;
+    DevGraph d = g;
+    d.dec_global = 0;
+    return bp_grid(d, true) >= bp_grid(d, false);
+}
+
 bool dec_global_pays(const DevGraph& g) {
     if (g.layered) return false;
     DevGraph a = g, b = g;

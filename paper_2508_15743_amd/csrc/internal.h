@@ -250,6 +250,11 @@ DevGraph decode_view(const vibe_graph* G, bool allow_multi = true, uint64_t shot
 // Whether decisions in global memory let more BP wavefronts reside than a
 // decision bitmap in LDS (g.dec_global ignored).
 bool dec_global_pays(const DevGraph& g);
+// Whether the decoder keeps g's message slab in LDS: where it fits and the
+// handle says so; automatic (tune_lds < 0): where it fits and costs no
+// residency (a slab in LDS that leaves room for fewer wavefronts than a
+// global slab runs slower: the chunk chain's latency then binds).
+bool use_lds_slab(const vibe_graph* G, const DevGraph& g);
 // Build (once) the decode schedule recut for P = 2 or 4 shots per wavefront.
 int build_multi_schedule(vibe_graph* G, uint32_t P);
 int launch_zero(void* p, size_t bytes, hipStream_t st);

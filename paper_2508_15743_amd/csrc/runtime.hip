@@ -198,7 +198,7 @@ std::vector<Round> plan(const vibe_request* reqs, uint32_t n_reqs, size_t budget
         for (const Seg& sg : r.segs) {
             DevGraph g = sg.g;
             g.dec_global = 0;
-            lds_ok = lds_ok && !multi && bp_slab_fits_lds(g) && reqs[sg.req].graph->tune_lds != 0;
+            lds_ok = lds_ok && !multi && use_lds_slab(reqs[sg.req].graph, g);
         }
         // decisions in global memory for every chunked segment if one of
         // them wants it (a graph whose decision bitmap would cap the
@@ -569,7 +569,7 @@ extern "C" int vibe_set_launch(vibe_graph* g, const vibe_launch_t* s) {
 extern "C" int vibe_get_launch(const vibe_graph* g, vibe_launch_t* s) {
     set_error("");
     if (!g || !s) return fail(VIBE_EINVAL, "NULL argument");
-    s->slab_in_lds = g->tune_lds < 0 ? (bp_slab_fits_lds(g->h.dg) ? 1 : 0) : g->tune_lds;
+    s->slab_in_lds = use_lds_slab(g, g->h.dg) ? 1 : 0;
     s->grid = g->tune_grid;
     s->shots_per_wave = (int)g->tune_P;
     s->decisions_global = g->tune_dec;

@@ -71,8 +71,10 @@ def test_multishot_equals_one_shot_per_wave(torch_cuda, bits):
         s = _dev(torch, synd)
         G.set_launch(slab_in_lds=0, shots_per_wave=1, decisions_global=0)
         ref = G.decode(s)
-        for Pw, dec in ((1, 1), (2, 0), (2, 1), (4, 0), (4, 1)):
-            G.set_launch(slab_in_lds=0, shots_per_wave=Pw, decisions_global=dec)
+        # the slab in LDS (where it fits: the code-capacity and d = 7
+        # phenomenological graphs), then the global-slab settings
+        for lds, Pw, dec in ((1, 1, 0), (0, 1, 1), (0, 2, 0), (0, 2, 1), (0, 4, 0), (0, 4, 1)):
+            G.set_launch(slab_in_lds=lds, shots_per_wave=Pw, decisions_global=dec)
             got_l = G.get_launch()
             assert (got_l["shots_per_wave"], got_l["decisions_global"]) == (Pw, dec)
             got = G.decode(s)
