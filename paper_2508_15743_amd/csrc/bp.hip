@@ -24,9 +24,20 @@
 // order through wave shuffles, as in a column-by-column decoder, and nothing
 // is contracted into fused multiply-adds, so the FP64 variant reproduces a
 // plain FP64 decoder bit for bit.  The chain of chunks is the critical path:
-// both passes load their slots four chunks ahead.  Hard decisions, the
-// residual syndrome s + H e and the syndrome are bit-packed in LDS;
-// convergence is a ballot.
+// both passes load their slots three chunks ahead.  The residual syndrome
+// s + H e and the syndrome are bit-packed in LDS, and so are the hard
+// decisions (or, on graphs where that bitmap would cap residency, they sit
+// in global memory: a mask per chunk read with the chunk's slots, and a
+// bitmap updated on flips); convergence is a ballot.
+//
+// Launch variants (none changes a result): the slab in LDS for small
+// graphs; P = 2 or 4 shots of a member per wavefront on the member's
+// schedule recut into chunks of 64 / P edges; several requests on
+// different graphs in one persistent launch (ragged).
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -1242,20 +1253,27 @@ bool bp_slab_fits_lds(const DevGraph& g) { return !g.layered && g.P == 1 && bp_l
 
 int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged, bool layered, uint32_t P,
                 bool dec_global) {
-    static int cached_cus = 0;
-    if (!cached_cus) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-        cached_cus = prop.multiProcessorCount;
-    }
+    // resident blocks of a kernel variant at an LDS size, per device: an
+    // occupancy query per launch plan is cheap but not free, so the answers
+    // are kept (a few variants and sizes per graph)
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void*, size_t>, int> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const void* fn = kernel_for(fp64, flood, slab_in_lds, ragged, layered, P, dec_global);
+    const auto key = std::make_tuple(dev, fn, lds_bytes);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, kernel_for(fp64, flood, slab_in_lds, ragged, layered, P, dec_global), kWave, lds_bytes);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWave, lds_bytes);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     if (per_cu > 32) per_cu = 32;
-    return per_cu * cached_cus;
+    const int grid = per_cu * prop.multiProcessorCount;
+    cache[key] = grid;
+    return grid;
 }
 
 bool use_lds_slab(const vibe_graph* G, const DevGraph& g) {
