@@ -428,6 +428,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=1 << 15)
+    ap.add_argument("--distance", type=int, default=9,
+                    help="circuit-level code distance of the timed workload (profiling runs; 9 is the metric's)")
+    ap.add_argument("--decisions-global", type=int, default=-1, choices=(-1, 0, 1),
+                    help="with --no-autotune: K1 decision placement (-1 automatic)")
     ap.add_argument("--plain-shots", type=int, default=64)
     ap.add_argument("--latency-batches", type=int, default=200)
     ap.add_argument("--latency-batch", type=int, default=64)
@@ -503,8 +507,8 @@ def main():
     del a, b
     log(f"device copy: {copy_gbs:.0f} GB/s (read + write) against the {HBM_PEAK_GBS:.0f} GB/s specification")
 
-    d, rounds, p = 9, 9, 1e-3
-    L, M, T, alpha = 32, 5, 20, 0.625
+    d, rounds, p = args.distance, args.distance, 1e-3
+    L, M, T, alpha = (32, 5, 20, 0.625) if d <= 11 else (64, 7, 25, 0.625)
     t0 = time.time()
     dem = circuit_dem(d, rounds, p)
     perms = permutations(dem.n, L, args.seed)
@@ -537,6 +541,7 @@ def main():
     out = (corr, obs, st)
     # launch settings: timed on a sample of the batch, kept in the handle
     if args.no_autotune:
+        G.set_launch(decisions_global=args.decisions_global)
         tune = {**G.get_launch(), "from_cache": False}
     else:
         tune = G.autotune(synd[:min(B, 4096)])
