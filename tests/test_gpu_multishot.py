@@ -230,3 +230,41 @@ def test_decisions_global_parallel_schedule_and_ragged(torch_cuda):
     rt.close()
     Gp.close()
     Gs.close()
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_settings_on_unusual_inputs(torch_cuda, bits):
+    """Priors above 1/2 (the zero-syndrome shortcut off), columns in no
+    check, zero syndromes, a per-iteration scaling table, and the
+    correction limits M = 1 and M = L: every launch setting gives the
+    outputs of the default one, and the FP64 decode is the oracle's."""
+    import paper_2508_15743_amd as P
+    from oracle import oracle as O
+    from synth.dem import dem_from_dense
+
+    torch = torch_cuda
+    base = code_capacity_dem(5, 0.05)
+    H = np.concatenate([base.dense_h(), np.zeros((base.m, 2), np.uint8)], axis=1)
+    rng = np.random.default_rng(151)
+    pri = rng.uniform(0.02, 0.3, H.shape[1])
+    pri[[2, 7, 19]] = [0.6, 0.75, 0.55]
+    lobs = np.concatenate([base.dense_l(), np.zeros((base.dense_l().shape[0], 2), np.uint8)], axis=1)
+    dem = dem_from_dense(H, pri, lobs)
+    synd = sample(dem, 203, 152).syndromes
+    synd[:7] = 0  # zero syndromes at the head of the batch
+    s = _dev(torch, synd)
+    for M in (1, 5, 16):
+        perms = permutations(dem.n, 16, 153 + M)
+        G = P.Graph.from_dem(dem, perms, L=16, M=M, T_max=24, message_bits=bits)
+        G.set_alpha(np.linspace(0.5, 0.9, 24))
+        G.set_launch(slab_in_lds=1)
+        ref = G.decode(s)
+        for lds, Pw, dec in ((0, 1, 0), (0, 1, 1), (0, 2, 1), (0, 4, 0)):
+            G.set_launch(slab_in_lds=lds, shots_per_wave=Pw, decisions_global=dec)
+            _same(torch, G.decode(s), ref)
+        if bits == 64:
+            want = O.decode(O.OracleGraph(dem), G.schedules(), synd, L=16, M=M, T=24,
+                            alpha=np.linspace(0.5, 0.9, 24), threads=8)
+            e = P.unpack_bits(ref[0], dem.n)
+            assert (want["ehat"] == e).all(1).mean() >= 0.999
+        G.close()
