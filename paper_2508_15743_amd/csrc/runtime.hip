@@ -609,9 +609,13 @@ extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B
     const int saved_lds = g->tune_lds, saved_grid = g->tune_grid, saved_dec = g->tune_dec;
     const uint32_t saved_P = g->tune_P;
     int rc = VIBE_OK;
-    // decode time of the sample with setting s (the first of two runs warms up)
-    auto time_it = [&](const vibe_launch_t& s, float* ms) {
+    // decode time of the sample with setting s (the first of two runs warms
+    // up); *skip: the setting could not be applied for want of memory (a
+    // recut schedule), so it is no candidate
+    auto time_it = [&](const vibe_launch_t& s, float* ms, bool* skip) {
         int r = apply_launch(g, s);
+        *skip = r == VIBE_ENOMEM;
+        if (*skip) return VIBE_OK;
         for (int rep = 0; rep < 2 && !r; rep++) {
             (void)hipEventRecord(e0, st);
             r = vibe_decode(g, syndromes, B, corr, obs, nullptr, stream);
@@ -630,19 +634,19 @@ extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B
             for (int dec : {0, 1})
                 if (!d.layered || dec == 0) first.push_back(vibe_launch_t{0, 0, P, dec, 0, 0.0});
     vibe_launch_t best{0, 0, 1, 0, 0, 1e30};
+    bool timed = false;
     for (const vibe_launch_t& s : first) {
         float ms = 0.0f;
-        rc = time_it(s, &ms);
-        if (rc == VIBE_ENOMEM) {  // a recut schedule did not fit: not a candidate
-            rc = VIBE_OK;
-            continue;
-        }
-        if (rc) break;
+        bool skip = false;
+        if ((rc = time_it(s, &ms, &skip))) break;
+        if (skip) continue;
+        timed = true;
         if (ms < best.ms) {
             best = s;
             best.ms = ms;
         }
     }
+    if (!rc && !timed) rc = fail(VIBE_ENOMEM, "autotune: no launch setting could be applied");
     if (!rc) {
         (void)apply_launch(g, best);
         DevGraph v = decode_view(g, true, B);
@@ -654,8 +658,9 @@ extern "C" int vibe_autotune(vibe_graph* g, const uint8_t* syndromes, uint64_t B
             s.grid = full * eighths / 8;
             if (s.grid < 1) continue;
             float ms = 0.0f;
-            if ((rc = time_it(s, &ms))) break;
-            if (ms < best.ms) {
+            bool skip = false;
+            if ((rc = time_it(s, &ms, &skip))) break;
+            if (!skip && ms < best.ms) {
                 best = s;
                 best.ms = ms;
             }
