@@ -1120,7 +1120,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_tar
 // One launch over the items of one request, P = 2 or 4 shots per
 // wavefront (serial schedule, slab in global memory).
 // occupancy the register allocator aims for with P shots per wavefront
-// (waves per SIMD), the most that keeps every variant free of spills
+// (waves per SIMD): the FP32 variants fit it without spills, the FP64 ones
+// spill a few registers
 template <class F, int P>
 constexpr int multi_waves_target() {
     return sizeof(F) == 8 || P == 4 ? 4 : 5;
