@@ -88,9 +88,24 @@ def _compare(torch, name, bits, whole_batch):
         line = f"agreement {agree.mean():.5f} of {n}, flags equal on {same_flags:.5f}"
     else:
         line = fp32_decode_bar(agree, ref_lsd, gpu_lsd, ref["min_q_gap"], w["L"], dem.n)
+    # every correction LSD did not flag satisfies H e = s
+    ok = (st[:, 0] & 4) == 0
+    for c in range(dem.m):
+        cols = dem.h_indices[dem.h_indptr[c]:dem.h_indptr[c + 1]]
+        par = np.bitwise_xor.reduce(e[:, cols], axis=1) if len(cols) else np.zeros(n, np.uint8)
+        assert np.array_equal(par[ok], synd[:n][ok, c]), c
     # observables follow the corrections, and the LERs sit in each other's intervals
     lo_obs = (e.astype(np.int64) @ dem.dense_l().T.astype(np.int64)) % 2
     assert np.array_equal(obs, lo_obs.astype(np.uint8))
+    diff = ~agree
+    if diff.any():
+        # the disagreements: how many are corrections of the same weight, and
+        # how many leave the same logical observable as the oracle's
+        same_obs = float((obs[diff] == ref["obs"][diff]).all(1).mean())
+        same_w = float((e[diff].sum(1) == ref["ehat_weight"][diff]).mean())
+        line += f"; of the {int(diff.sum())} differing corrections {same_w:.4f} have the oracle's weight, " \
+                f"{same_obs:.4f} its observables"
+
     true_obs = b.observables[:n]
     k_ref = int((ref["obs"] != true_obs).any(1).sum())
     k_gpu = int((obs != true_obs).any(1).sum())
