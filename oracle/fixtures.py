@@ -44,7 +44,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 WORKLOADS = {
     "circuit_d9": dict(kind="circuit", d=9, rounds=9, p=1e-3, L=32, M=5, T=20, alpha=0.625, lsd_order=0,
-                       perm_seed=2025, sample_seed=2026, batch=32768, shots=10000, indices=True),
+                       perm_seed=2025, sample_seed=2026, batch=32768, shots=20000, indices=True),
     "phenom_d11": dict(kind="phenom", d=11, rounds=11, p=0.01, q=0.01, L=32, M=5, T=50, alpha=0.625,
                        lsd_order=10, perm_seed=2030, sample_seed=2031, batch=100000, shots=100000,
                        indices=False),

@@ -3,7 +3,7 @@ using the oracle's per-shot results stored by oracle/fixtures.py.
 
   * circuit-level d = 9 (the benchmark's graph, settings and seeds): the
     whole 32768-shot batch decoded in one call as the benchmark times it
-    (FP32), its first 10^4 shots compared with the oracle; the same shots in
+    (FP32), its first 2 x 10^4 shots compared with the oracle; the same shots in
     FP64 messages.
   * phenomenological d = 11, LSD order 10: 10^5 shots in FP32 and FP64.
 
