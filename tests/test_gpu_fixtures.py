@@ -87,7 +87,7 @@ def _compare(torch, name, bits, whole_batch):
         same_flags = (ref["flags"] == (st[:, 0] & 7)).mean()
         line = f"agreement {agree.mean():.5f} of {n}, flags equal on {same_flags:.5f}"
     else:
-        line = fp32_decode_bar(agree, ref_lsd, gpu_lsd, ref["min_q_gap"], w["L"], dem.n)
+        line = fp32_decode_bar(agree, ref_lsd, gpu_lsd, ref["min_q_gap"], w["L"], dem.n, ref["min_abs_post"])
     # every correction LSD did not flag satisfies H e = s
     ok = (st[:, 0] & 4) == 0
     for c in range(dem.m):

@@ -326,7 +326,8 @@ def _oracle_decode(dem, perms, synd, L, M, T, priors=None, schedule="serial", ls
 def _tie_witness(ref, e, st, dem, L):
     n = len(ref["ehat"])
     agree = (ref["ehat"] == e[:n]).all(1)
-    return fp32_decode_bar(agree, ref["lsd_used"], (st[:n, 0] & 2) != 0, ref["min_q_gap"], L, dem.n)
+    return fp32_decode_bar(agree, ref["lsd_used"], (st[:n, 0] & 2) != 0, ref["min_q_gap"], L, dem.n,
+                           ref["min_abs_post"])
 
 
 def _decode_parity(torch, dem, L, M, T, shots, seed, oracle_shots, bits=32, schedule="serial", lsd_order=0):
