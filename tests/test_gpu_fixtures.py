@@ -103,6 +103,9 @@ def _compare(torch, name, bits, whole_batch):
         # how many leave the same logical observable as the oracle's
         same_obs = float((obs[diff] == ref["obs"][diff]).all(1).mean())
         same_w = float((e[diff].sum(1) == ref["ehat_weight"][diff]).mean())
+        # a tie between equally good corrections rarely changes the logical
+        # class (measured: never, on both workloads)
+        assert same_obs >= 0.95, same_obs
         line += f"; of the {int(diff.sum())} differing corrections {same_w:.4f} have the oracle's weight, " \
                 f"{same_obs:.4f} its observables"
 
