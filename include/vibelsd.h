@@ -333,6 +333,10 @@ void vibe_exec_destroy(vibe_exec* ex); /* synchronises the device first; NULL ac
  *                   than reside with the bitmap in LDS (a small batch is
  *                   bound by its serial chains, which the global masks
  *                   lengthen).  Not with the slab in LDS.
+ * A launch whose work items all reside at once (no more than the grid)
+ * runs a variant that loads more chunks ahead at fewer wavefronts per SIMD
+ * (FP32, serial schedule, slab in global memory, one shot per wavefront,
+ * decisions in LDS); its results are those of the persistent kernel.
  * vibe_set_launch applies settings (building the recut schedule on first
  * use: EUNSUPPORTED for the parallel and layered schedules); settings that
  * vibe_decode_noalloc uses must be applied before it is called.

@@ -154,7 +154,10 @@ int decode_chunk(vibe_graph* G, const DevGraph& g, const ChunkBufs& W, const uin
     b.slab = W.slab;
     b.post_slab = W.post_slab;
     b.counter = W.counters;
-    b.grid = (int)std::min<uint64_t>((uint64_t)bp_blocks, bp_items(g, n));
+    const uint64_t items = bp_items(g, n);
+    b.grid = (int)std::min<uint64_t>((uint64_t)bp_blocks, items);
+    // every item resident at once: the deeper prefetch ring pays
+    b.latency = items <= (uint64_t)std::min(bp_blocks, bp_latency_grid(g, in_lds)) ? 1 : 0;
     if (timed) begin_timed(G, 0, st);
     if ((rc = launch_bp(g, b, st))) return rc;
     if (timed) end_timed(G, 0, st);

@@ -201,6 +201,12 @@ static_assert(RecW<float, 64>::kV == kRecV && RecW<float, 64>::kLam == kRecLam &
 #define VIBE_BP_DEPTH 3
 #endif
 constexpr int kDepth = VIBE_BP_DEPTH;  // chunks loaded ahead of the one being processed
+// The latency variant: a launch whose work items all reside at once is bound
+// by each item's chain of chunk steps, not by the slab stream, and loading
+// six chunks ahead shortens each step (single shots of the d = 9 and d = 13
+// circuit graphs: 8% and 12% faster); the deeper ring needs the registers
+// of 4 waves per SIMD, which such a launch does not miss.
+constexpr int kLatDepth = 6;
 // occupancy the register allocator aims for (waves per SIMD): 6 keeps the
 // production kernel (FP32, serial schedule, global slab, one request, or
 // several requests none of which is layered) within 80 VGPRs (with
@@ -375,18 +381,18 @@ __device__ __forceinline__ void sweep_chunk(const Ctx<F>& x, const Stage<F>& s, 
 // The whole sweep: chunks 0 .. nch-1 (nch >= 1), each one's slots loaded
 // kDepth chunks ahead (the suffix states of later chunks are final for the
 // whole sweep).
-template <class F, bool SLAB_LDS, bool WANT_POST, bool FLOOD, uint32_t W = kWave, bool DG = false>
+template <class F, bool SLAB_LDS, bool WANT_POST, bool FLOOD, uint32_t W = kWave, bool DG = false, int D = kDepth>
 __device__ __forceinline__ void sweep(const Ctx<F>& x, uint32_t nch, bool first, uint64_t& sat) {
     const uint32_t last = nch - 1;
-    Stage<F> ring[kDepth];
+    Stage<F> ring[D];
 #pragma unroll
-    for (int d = 0; d < kDepth; d++) fetch<F, SLAB_LDS, FLOOD, W, DG>(x, ring[d], min((uint32_t)d, last), first);
-    for (uint32_t k = 0; k < nch; k += kDepth) {
+    for (int d = 0; d < D; d++) fetch<F, SLAB_LDS, FLOOD, W, DG>(x, ring[d], min((uint32_t)d, last), first);
+    for (uint32_t k = 0; k < nch; k += D) {
 #pragma unroll
-        for (int d = 0; d < kDepth; d++) {
+        for (int d = 0; d < D; d++) {
             if (k + d >= nch) break;
             sweep_chunk<F, SLAB_LDS, WANT_POST, FLOOD, DG>(x, ring[d], k + d, sat);
-            fetch<F, SLAB_LDS, FLOOD, W, DG>(x, ring[d], min(k + d + kDepth, last), first);
+            fetch<F, SLAB_LDS, FLOOD, W, DG>(x, ring[d], min(k + d + D, last), first);
         }
     }
 }
@@ -430,18 +436,18 @@ __device__ __forceinline__ void back_chunk(const Ctx<F>& x, const BStage<F>& s, 
 // Backward pass over chunks nch-1 .. 0 (nch >= 1) with loads kDepth chunks
 // ahead.  Edges of one chunk sit in distinct rows, so a chunk is one
 // parallel step.
-template <class F, bool SLAB_LDS, bool FLOOD, uint32_t W = kWave>
+template <class F, bool SLAB_LDS, bool FLOOD, uint32_t W = kWave, int D = kDepth>
 __device__ __forceinline__ void backward(const Ctx<F>& x, uint32_t nch, typename Prec<F>::B* running) {
-    BStage<F> ring[kDepth];
+    BStage<F> ring[D];
     auto at = [nch](uint32_t d) { return d < nch ? nch - 1 - d : 0u; };  // d chunks from the end
 #pragma unroll
-    for (int d = 0; d < kDepth; d++) bfetch<F, SLAB_LDS, FLOOD, W>(x, ring[d], at(d));
-    for (uint32_t e = 0; e < nch; e += kDepth) {
+    for (int d = 0; d < D; d++) bfetch<F, SLAB_LDS, FLOOD, W>(x, ring[d], at(d));
+    for (uint32_t e = 0; e < nch; e += D) {
 #pragma unroll
-        for (int d = 0; d < kDepth; d++) {
+        for (int d = 0; d < D; d++) {
             if (e + d >= nch) break;
             back_chunk<F, SLAB_LDS>(x, ring[d], nch - 1 - e - d, running);
-            bfetch<F, SLAB_LDS, FLOOD, W>(x, ring[d], at(e + d + kDepth));
+            bfetch<F, SLAB_LDS, FLOOD, W>(x, ring[d], at(e + d + D));
         }
     }
 }
@@ -718,7 +724,7 @@ __device__ __forceinline__ void finish_item(const DevGraph& g, const BpLaunch& a
 
 // DG: decisions in global memory (the chunk decision masks and the bitmap
 // after the block's posteriors, see bp_post_elems), not in LDS.
-template <class F, bool SLAB_LDS, bool FLOOD, bool LAYERED = false, bool DG = false>
+template <class F, bool SLAB_LDS, bool FLOOD, bool LAYERED = false, bool DG = false, int D = kDepth>
 __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, uint32_t item, unsigned char* lds,
                                          Ctx<F> x) {
     using P = Prec<F>;
@@ -834,9 +840,9 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
             layered_sweep<F>(g, x, g.cperm + (size_t)mem * g.m, want_post, sat);
         } else if (nch) {
             if (want_post)
-                sweep<F, SLAB_LDS, true, FLOOD, kWave, DG>(x, nch, t == 1, sat);
+                sweep<F, SLAB_LDS, true, FLOOD, kWave, DG, D>(x, nch, t == 1, sat);
             else
-                sweep<F, SLAB_LDS, false, FLOOD, kWave, DG>(x, nch, t == 1, sat);
+                sweep<F, SLAB_LDS, false, FLOOD, kWave, DG, D>(x, nch, t == 1, sat);
         }
         __syncthreads();  // every new message stored
         if (post_out) {
@@ -855,7 +861,7 @@ __device__ __forceinline__ void run_item(const DevGraph& g, const BpLaunch& a, u
         if (!LAYERED && t < a.T_run && nch) {
             for (uint32_t c = lane; c < g.m; c += kWave) pref[c] = ident;
             __syncthreads();
-            backward<F, SLAB_LDS, FLOOD>(x, nch, pref);
+            backward<F, SLAB_LDS, FLOOD, kWave, D>(x, nch, pref);
             __syncthreads();
         }
     }
@@ -1051,9 +1057,9 @@ __device__ __forceinline__ T load_const(const T* p) {
 }
 
 // One launch over the items of one request.  DG: decisions in global
-// memory.
-template <class F, bool SLAB_LDS, bool FLOOD, bool LAYERED = false, bool DG = false>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_target<F, SLAB_LDS, FLOOD, false, false, DG>()))) void bp_ensemble_kernel(DevGraph g, BpLaunch a) {
+// memory; D: chunks loaded ahead (kLatDepth: the latency variant).
+template <class F, bool SLAB_LDS, bool FLOOD, bool LAYERED = false, bool DG = false, int D = kDepth>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(D > kDepth ? 4 : waves_target<F, SLAB_LDS, FLOOD, false, false, DG>()))) void bp_ensemble_kernel(DevGraph g, BpLaunch a) {
     using B = typename Prec<F>::B;
     extern __shared__ __align__(16) unsigned char lds[];
     const uint32_t slab_elems = g.max_chunks * kWave;
@@ -1065,7 +1071,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_tar
     for (;;) {
         const uint32_t item = wave_ticket(a.counter, 1u);
         if (item >= n_items) break;
-        run_item<F, SLAB_LDS, FLOOD, LAYERED, DG>(g, a, item, lds, x);
+        run_item<F, SLAB_LDS, FLOOD, LAYERED, DG, D>(g, a, item, lds, x);
         __syncthreads();
     }
 }
@@ -1205,7 +1211,11 @@ const void* multi_kernel_for(bool ragged, uint32_t P) {
 // several shots per wavefront; dg: decisions in global memory (the
 // non-layered items; the slab in global memory)
 const void* kernel_for(bool fp64, bool flood, bool slab_in_lds, bool ragged, bool layered = false, uint32_t P = 1,
-                       bool dg = false) {
+                       bool dg = false, bool latency = false) {
+    // the latency variant: one request, FP32, serial schedule, global slab,
+    // one shot per wavefront, decisions in LDS
+    if (latency && !fp64 && !flood && !slab_in_lds && !ragged && !layered && P == 1 && !dg)
+        return (const void*)bp_ensemble_kernel<float, false, false, false, false, kLatDepth>;
     // several shots per wavefront: serial schedule, slab in global memory
     if (P > 1) {
         if (fp64) return dg ? multi_kernel_for<double, true>(ragged, P) : multi_kernel_for<double, false>(ragged, P);
@@ -1253,7 +1263,7 @@ size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds) {
 bool bp_slab_fits_lds(const DevGraph& g) { return !g.layered && g.P == 1 && bp_lds_bytes(g, true) <= 96 * 1024; }
 
 int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged, bool layered, uint32_t P,
-                bool dec_global) {
+                bool dec_global, bool latency) {
     // resident blocks of a kernel variant at an LDS size, per device: an
     // occupancy query per launch plan is cheap but not free, so the answers
     // are kept (a few variants and sizes per graph)
@@ -1261,7 +1271,7 @@ int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool 
     static std::map<std::tuple<int, const void*, size_t>, int> cache;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    const void* fn = kernel_for(fp64, flood, slab_in_lds, ragged, layered, P, dec_global);
+    const void* fn = kernel_for(fp64, flood, slab_in_lds, ragged, layered, P, dec_global, latency);
     const auto key = std::make_tuple(dev, fn, lds_bytes);
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
@@ -1299,6 +1309,11 @@ int bp_grid(const DevGraph& g, bool slab_in_lds) {
                        g.P, g.dec_global != 0);
 }
 
+int bp_latency_grid(const DevGraph& g, bool slab_in_lds) {
+    if (g.fp64 || g.flood || g.layered || slab_in_lds || g.P != 1 || g.dec_global) return 0;
+    return bp_grid_for(false, false, false, bp_lds_bytes(g, false), false, false, 1, false, true);
+}
+
 int launch_bp(const DevGraph& g, const BpLaunch& a, hipStream_t st) {
     const bool in_lds = a.slab_in_lds != 0;
     void* args[] = {const_cast<DevGraph*>(&g), const_cast<BpLaunch*>(&a)};
@@ -1307,7 +1322,11 @@ int launch_bp(const DevGraph& g, const BpLaunch& a, hipStream_t st) {
                                  "and stop on convergence");
     if (g.dec_global && (g.layered || in_lds))
         return fail(VIBE_EINVAL, "internal: decisions in global memory need a chunked schedule and a global slab");
-    return launch_fn(kernel_for(g.fp64 != 0, g.flood != 0, in_lds, false, g.layered != 0, g.P, g.dec_global != 0),
+    if (a.latency && !bp_latency_grid(g, in_lds))
+        return fail(VIBE_EINVAL, "internal: the latency variant needs FP32, the serial schedule, a global slab, "
+                                 "one shot per wavefront and decisions in LDS");
+    return launch_fn(kernel_for(g.fp64 != 0, g.flood != 0, in_lds, false, g.layered != 0, g.P, g.dec_global != 0,
+                                a.latency != 0),
                      a.grid, bp_lds_bytes(g, in_lds), args, st);
 }
 

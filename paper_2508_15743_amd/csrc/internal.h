@@ -190,6 +190,7 @@ struct BpLaunch {
     uint32_t* counter;         // work counter
     int grid;
     int slab_in_lds;           // which kernel variant to launch
+    int latency;               // the latency variant (every item resident at once)
 };
 int launch_bp(const DevGraph& g, const BpLaunch& a, hipStream_t st);
 
@@ -219,7 +220,11 @@ struct RaggedLaunch {
 };
 int launch_bp_ragged(const RaggedLaunch& r, hipStream_t st);
 int bp_grid_for(bool fp64, bool flood, bool slab_in_lds, size_t lds_bytes, bool ragged, bool layered = false,
-                uint32_t P = 1, bool dec_global = false);
+                uint32_t P = 1, bool dec_global = false, bool latency = false);
+// Resident blocks of the latency variant of K1 for g (0 where g has none:
+// FP64, another schedule, slab in LDS, several shots per wavefront,
+// decisions in global memory).
+int bp_latency_grid(const DevGraph& g, bool slab_in_lds);
 int bp_grid(const DevGraph& g, bool slab_in_lds);
 size_t bp_lds_bytes(const DevGraph& g, bool slab_in_lds);
 int bp_slabs(const DevGraph& g);  // slabs per block: 1 (serial), 2 (parallel: states and messages)

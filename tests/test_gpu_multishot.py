@@ -91,6 +91,28 @@ def test_multishot_equals_one_shot_per_wave(torch_cuda, bits):
         G.close()
 
 
+def test_latency_variant_equals_persistent(torch_cuda):
+    """A launch whose work items all reside at once runs the variant of K1
+    with the deeper prefetch ring (FP32, serial schedule, global slab, one
+    shot per wavefront, decisions in LDS); it loads the same chunks ahead of
+    the same operations, so its outputs equal those of the persistent kernel
+    bit for bit.  A grid below the item count forces the persistent one."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    for i, (label, mk, L, M, T) in enumerate(SPECS):
+        dem = mk()
+        G = P.Graph.from_dem(dem, permutations(dem.n, L, 160 + i), L=L, M=M, T_max=T)
+        s = _dev(torch, sample(dem, 64, 170 + i).syndromes)
+        for B in (1, 3, 64):
+            sb = s[:B].contiguous()
+            G.set_launch(slab_in_lds=0, shots_per_wave=1, decisions_global=0)
+            fast = G.decode(sb)
+            G.set_launch(slab_in_lds=0, grid=max(1, B * L // 2), shots_per_wave=1, decisions_global=0)
+            _same(torch, fast, G.decode(sb))
+        G.close()
+
+
 def test_multishot_schedule_shape(torch_cuda):
     """The recut schedule of a graph whose 64-edge chunks are far from full
     needs fewer chunk steps per shot: for the d = 5 circuit graph, 4 shots
