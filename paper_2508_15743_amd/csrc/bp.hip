@@ -1084,8 +1084,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(D > kDept
 // fields load as wave-uniform scalars.  WITH_LAYERED: some segment may be
 // on the layered schedule (the variant without that item body needs fewer
 // registers).  DG: the other segments keep decisions in global memory.
-template <class F, bool SLAB_LDS, bool FLOOD, bool WITH_LAYERED, bool DG = false>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_target<F, SLAB_LDS, FLOOD, true, WITH_LAYERED, DG>()))) void bp_ragged_kernel(RaggedLaunch r) {
+template <class F, bool SLAB_LDS, bool FLOOD, bool WITH_LAYERED, bool DG = false, int D = kDepth>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(D > kDepth ? 4 : waves_target<F, SLAB_LDS, FLOOD, true, WITH_LAYERED, DG>()))) void bp_ragged_kernel(RaggedLaunch r) {
     using B = typename Prec<F>::B;
     using CSeg = const __attribute__((address_space(4))) BpSeg;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -1117,7 +1117,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(waves_tar
             else
                 run_item<F, SLAB_LDS, false, false, DG>(g, a, item - segs[j].item0, lds, x);
         } else {
-            run_item<F, SLAB_LDS, false, false, DG>(g, a, item - segs[j].item0, lds, x);
+            run_item<F, SLAB_LDS, false, false, DG, D>(g, a, item - segs[j].item0, lds, x);
         }
         __syncthreads();
     }
@@ -1212,10 +1212,11 @@ const void* multi_kernel_for(bool ragged, uint32_t P) {
 // non-layered items; the slab in global memory)
 const void* kernel_for(bool fp64, bool flood, bool slab_in_lds, bool ragged, bool layered = false, uint32_t P = 1,
                        bool dg = false, bool latency = false) {
-    // the latency variant: one request, FP32, serial schedule, global slab,
-    // one shot per wavefront, decisions in LDS
-    if (latency && !fp64 && !flood && !slab_in_lds && !ragged && !layered && P == 1 && !dg)
-        return (const void*)bp_ensemble_kernel<float, false, false, false, false, kLatDepth>;
+    // the latency variant: FP32, serial schedule, global slab, one shot per
+    // wavefront, decisions in LDS
+    if (latency && !fp64 && !flood && !slab_in_lds && !layered && P == 1 && !dg)
+        return ragged ? (const void*)bp_ragged_kernel<float, false, false, false, false, kLatDepth>
+                      : (const void*)bp_ensemble_kernel<float, false, false, false, false, kLatDepth>;
     // several shots per wavefront: serial schedule, slab in global memory
     if (P > 1) {
         if (fp64) return dg ? multi_kernel_for<double, true>(ragged, P) : multi_kernel_for<double, false>(ragged, P);
@@ -1337,8 +1338,11 @@ int launch_bp_ragged(const RaggedLaunch& r, hipStream_t st) {
     if (r.dec_global && (r.slab_in_lds || (r.layered && !r.multi)))
         return fail(VIBE_EINVAL, "internal: decisions in global memory need global slabs (and no layered segment "
                                  "outside the multi-shot launch)");
+    if (r.latency && (r.fp64 || r.flood || r.slab_in_lds || r.layered || r.multi || r.dec_global))
+        return fail(VIBE_EINVAL, "internal: the latency variant needs FP32, the serial schedule, global slabs, "
+                                 "one shot per wavefront and decisions in LDS");
     return launch_fn(kernel_for(r.fp64 != 0, r.flood != 0, r.slab_in_lds != 0, true, r.layered != 0,
-                                r.multi ? 2u : 1u, r.dec_global != 0),
+                                r.multi ? 2u : 1u, r.dec_global != 0, r.latency != 0),
                      r.grid, r.lds_bytes, args, st);
 }
 

@@ -216,6 +216,7 @@ struct RaggedLaunch {
     int multi;             // some segment runs several shots per wavefront
     int layered;           // some segment is on the layered schedule
     int dec_global;        // the non-layered segments keep decisions in global memory
+    int latency;           // the latency variant (every item resident at once)
     size_t lds_bytes;      // largest bp_lds_bytes over the segments
 };
 int launch_bp_ragged(const RaggedLaunch& r, hipStream_t st);

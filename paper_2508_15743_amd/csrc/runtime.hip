@@ -109,6 +109,7 @@ struct Round {
     bool multi = false;  // some segment runs several shots per wavefront
     bool layered = false;  // some segment is on the layered schedule
     bool dec_global = false;  // chunked segments keep decisions in global memory
+    bool latency = false;     // every item resident at once: the deeper prefetch ring
 };
 
 size_t seg_bytes(const DevGraph& g, uint32_t n) {
@@ -231,6 +232,10 @@ std::vector<Round> plan(const vibe_request* reqs, uint32_t n_reqs, size_t budget
             max_n = std::max<uint64_t>(max_n, sg.n);
         }
         r.grid = (int)std::min<uint64_t>((uint64_t)r.grid, std::max<uint64_t>(total_items, 1));
+        if (!fp64 && !flood && !lds_ok && !layered && !multi && !dg)
+            r.latency = total_items <= (uint64_t)r.grid &&
+                        total_items <= (uint64_t)bp_grid_for(false, false, false, r.lds_bytes, true, false, 1u,
+                                                             false, true);
         r.lsd_grid = (int)std::min<uint64_t>(512, std::max<uint64_t>(max_n, 1));
         // layout: [zeroed: counters | per-segment cmask, iters, qfix, fail count]
         //         [per-segment t_conv, weight, cand, fail_list] [segment table]
@@ -330,6 +335,7 @@ int run_round(const vibe_request* reqs, const Round& r, unsigned char* base, hip
     L.multi = r.multi ? 1 : 0;
     L.layered = r.layered ? 1 : 0;
     L.dec_global = r.dec_global ? 1 : 0;
+    L.latency = r.latency ? 1 : 0;
     L.lds_bytes = r.lds_bytes;
     if ((rc = launch_bp_ragged(L, st))) return rc;
     for (size_t j = 0; j < r.segs.size(); j++) {

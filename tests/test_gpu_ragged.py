@@ -95,6 +95,38 @@ def test_ragged_equals_single(torch_cuda, schedule):
         G.close()
 
 
+def test_ragged_latency_variant(torch_cuda):
+    """A ragged round whose items all reside at once (FP32, serial, global
+    slabs) runs the variant with the deeper prefetch ring; each request
+    equals its single decode on the persistent kernel (forced by a grid
+    below the item count) bit for bit, eagerly and in captured replays."""
+    import paper_2508_15743_amd as P
+
+    torch = torch_cuda
+    gs = _graphs()
+    sizes = [3, 1, 2, 5]
+    pairs = [(G, _dev(torch, sample(dem, B, 190 + i).syndromes)) for i, ((dem, G), B) in enumerate(zip(gs, sizes))]
+    want = []
+    for (dem, G), (_, s), B in zip(gs, pairs, sizes):
+        G.set_launch(slab_in_lds=0, grid=max(1, B * G.info()["L"] // 2))
+        want.append(G.decode(s))
+        G.set_launch()
+    rt = P.Runtime()
+    _check_same(torch, rt.decode(pairs), want)
+    ex = P.Exec(pairs)
+    for _ in range(3):
+        outs = ex.launch()
+        torch.cuda.synchronize()
+        snap = [tuple(t.clone() for t in o) for o in outs]
+        rt.decode([(G, s.clone()) for G, s in pairs])  # eager work between replays
+        torch.cuda.synchronize()
+        _check_same(torch, snap, want)
+    ex.close()
+    rt.close()
+    for _, G in gs:
+        G.close()
+
+
 def test_ragged_mixed_schedules(torch_cuda):
     """Serial, parallel (BP+LSD-0) and layered graphs in one ragged call
     share one persistent launch; every request still equals its single
