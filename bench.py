@@ -462,7 +462,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the decoder shards by shots with no exchange, "
-              "so a multi-GPU figure is not part of this build.", file=sys.stderr)
+              "so the figure it reports is one GPU's throughput.", file=sys.stderr)
         sys.exit(2)
 
     import torch

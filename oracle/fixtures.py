@@ -1,6 +1,6 @@
 """Writes the oracle's per-shot results for the benchmark workloads to
 tests/golden/, so that GPU tests can compare tens of thousands of shots
-shot by shot without running the oracle for hours on the GPU machine.
+shot by shot without running the oracle for hours in the test run.
 
 TEST INFRASTRUCTURE ONLY.  Calls the FP64 oracle (vibelsd_oracle.c through
 oracle.py) on inputs from synth/ and nothing else.
