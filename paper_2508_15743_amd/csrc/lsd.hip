@@ -5,13 +5,19 @@
 // index), judged on the state at the start of the round; clusters that come
 // to share a check merge (union-find, smallest slot is the root).  A cluster
 // is valid when s restricted to its checks lies in the span of its columns.
-// Validity uses one pool of bit-packed basis vectors over the checks, kept in
-// insertion order: vectors of different clusters have disjoint supports, so
-// reducing a cluster's syndrome by the whole pool only ever touches that
-// cluster's own vectors.  At the end, the columns of valid clusters are
-// ranked and eliminated in rank order; a column is a pivot iff it is
-// independent of the earlier ones, and every basis vector carries its
-// combination of pivot columns, so reducing s yields the solution.
+// Validity uses one pool of bit-packed basis vectors over the checks:
+// vectors of different clusters have disjoint supports, so reducing a
+// cluster's syndrome by the whole pool only ever touches that cluster's own
+// vectors.  At the end, the columns of valid clusters are ranked and
+// eliminated in rank order; a column is a pivot iff it is independent of
+// the earlier ones, and every basis vector carries its combination of pivot
+// columns, so reducing s yields the solution.  Both bases are kept in
+// reduced echelon form (each vector is 1 at its own pivot and 0 at every
+// other vector's pivot): a reduction then takes exactly the vectors whose
+// pivot bit is set in the input and forms their sum in parallel.  The
+// reduced vector, the pivots, the solution and the combinations are those
+// of the elimination in insertion order, since a vector of the span is fixed
+// by its bits at the pivots.
 //
 // Higher orders (lsd_order > 0) add the higher-order search that LSD-0
 // leaves out (Sec. III.D.1 step 5), read as the combination sweep of ordered
@@ -63,6 +69,8 @@ struct LsdMem {
     uint64_t* xbuf;     // words_m
     uint64_t* cbuf;     // words_m
     uint64_t* dbuf;     // words_m: a candidate's change of the pivot solution
+    uint64_t* hbuf;     // words_m: one bit per basis vector (a reduction's vectors)
+    uint64_t* fbuf;     // words_m: one bit per basis vector (vectors to clear a new pivot from)
     // global
     int32_t* cols;      // n
     int32_t* sorted;    // n
@@ -100,7 +108,7 @@ __host__ __device__ inline void lsd_layout(const DevGraph& g, unsigned char* lds
     // pivcol, row_q, row_v, clist: 48 bytes per check) move to global memory when everything
     // would not fit in kLsdLds bytes of LDS (graphs with several thousand
     // checks).  Reads and writes by one lane need no cross-lane visibility.
-    const size_t all_lds = al8(8 * m) + 2 * al8(8 * wn) + 3 * al8(8 * wm) + 5 * al8(4 * m) + al8(8 * m) +
+    const size_t all_lds = al8(8 * m) + 2 * al8(8 * wn) + 5 * al8(8 * wm) + 5 * al8(4 * m) + al8(8 * m) +
                            4 * al8(4 * m) + al8(8 * m) + 2 * al8(4 * m);
     const bool priv_glob = all_lds > kLsdLds;
     auto tp = [&](size_t bytes) { return priv_glob ? tg(bytes) : tl(bytes); };
@@ -111,6 +119,8 @@ __host__ __device__ inline void lsd_layout(const DevGraph& g, unsigned char* lds
     M.xbuf = (uint64_t*)tl(8 * wm);
     M.cbuf = (uint64_t*)tl(8 * wm);
     M.dbuf = (uint64_t*)tl(8 * wm);
+    M.hbuf = (uint64_t*)tl(8 * wm);
+    M.fbuf = (uint64_t*)tl(8 * wm);
     M.chk_cl = (int32_t*)tl(4 * m);
     M.parent = (int32_t*)tl(4 * m);
     M.cstate = (uint32_t*)tl(4 * m);
@@ -165,21 +175,100 @@ __device__ inline bool key_less(int64_t qa, int32_t a, int64_t qb, int32_t b) {
     return qa < qb || (qa == qb && a < b);
 }
 
-// xbuf ^= pool vectors in insertion order wherever xbuf has the vector's
-// pivot bit set; optionally the combination words follow along.
+__device__ inline uint64_t uni64(uint64_t x) {
+    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+}
+
+// x ^= the basis vectors whose pivot bit is set in x, comb (if given) ^=
+// their combination words.  The basis is in reduced echelon form, so these
+// are the vectors that the reduction in insertion order adds, and their sum
+// does not depend on the order.  hit (LDS) receives one bit per vector.
+// Word w of every vector is read and written only by lane w mod 64, so the
+// basis needs no cross-lane visibility in global memory.
 __device__ void reduce_by(uint64_t* x, uint64_t* comb, const uint64_t* vecs, size_t stride,
-                          const int32_t* piv, int count, uint32_t wm, int lane) {
-    for (int i = 0; i < count; i++) {
-        const int32_t p = uni(piv[i]);
-        __syncthreads();
-        const uint32_t hit = uni((uint32_t)((x[p >> 6] >> (p & 63)) & 1ull));
-        if (!hit) continue;
-        const uint64_t* b = vecs + (size_t)i * stride;
-        for (uint32_t w = lane; w < wm; w += kWave) {
-            x[w] ^= b[w];
-            if (comb) comb[w] ^= b[wm + w];
+                          const int32_t* piv, int count, uint32_t wm, uint64_t* hit, int lane) {
+    __syncthreads();
+    const int nblk = (count + kWave - 1) / kWave;
+    for (int b = 0; b < nblk; b++) {
+        const int j = b * kWave + lane;
+        bool h = false;
+        if (j < count) {
+            const int32_t p = piv[j];
+            h = (x[p >> 6] >> (p & 63)) & 1ull;
+        }
+        const uint64_t mask = __ballot(h);
+        if (lane == 0) hit[b] = mask;
+    }
+    __syncthreads();
+    for (uint32_t w = lane; w < wm; w += kWave) {
+        uint64_t acc = 0, cacc = 0;
+        for (int b = 0; b < nblk; b++) {
+            uint64_t mask = uni64(hit[b]);
+            while (mask) {
+                // up to eight vectors per step, their loads in flight together
+                uint64_t t[8], c[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    t[u] = 0;
+                    c[u] = 0;
+                    if (mask) {
+                        const size_t i = (size_t)b * kWave + (size_t)(__ffsll((long long)mask) - 1);
+                        mask &= mask - 1;
+                        t[u] = vecs[i * stride + w];
+                        if (comb) c[u] = vecs[i * stride + wm + w];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    acc ^= t[u];
+                    cacc ^= c[u];
+                }
+            }
+        }
+        x[w] ^= acc;
+        if (comb) comb[w] ^= cacc;
+    }
+    __syncthreads();
+}
+
+// Appends x (reduced by the basis of count vectors, lowest set bit p) with
+// its combination words comb (if given) as vector count, pivot p, and clears
+// bit p from every earlier vector that has it (xor x and comb), so the
+// basis stays in reduced echelon form.  flag (LDS) receives one bit per
+// earlier vector; the lane that holds word p / 64 of the vectors finds them.
+__device__ void basis_append(uint64_t* vecs, size_t stride, int32_t* piv, int count, const uint64_t* x,
+                             const uint64_t* comb, int p, uint32_t wm, uint64_t* flag, int lane) {
+    const uint32_t W = (uint32_t)p >> 6;
+    const uint64_t bit = 1ull << (p & 63);
+    const int nblk = (count + kWave - 1) / kWave;
+    for (uint32_t w = lane; w < wm; w += kWave) {
+        if (w != W) continue;
+        for (int b = 0; b < nblk; b++) {
+            uint64_t f = 0;
+#pragma unroll 8
+            for (int u = 0; u < kWave; u++) {
+                const int j = b * kWave + u;
+                if (j < count && (vecs[(size_t)j * stride + w] & bit)) f |= 1ull << u;
+            }
+            flag[b] = f;
         }
     }
+    __syncthreads();
+    for (uint32_t w = lane; w < wm; w += kWave) {
+        const uint64_t xw = x[w], cw = comb ? comb[w] : 0;
+        for (int b = 0; b < nblk; b++) {
+            uint64_t mask = uni64(flag[b]);
+            while (mask) {
+                const size_t i = (size_t)b * kWave + (size_t)(__ffsll((long long)mask) - 1);
+                mask &= mask - 1;
+                vecs[i * stride + w] ^= xw;
+                if (comb) vecs[i * stride + wm + w] ^= cw;
+            }
+        }
+        vecs[(size_t)count * stride + w] = xw;
+        if (comb) vecs[(size_t)count * stride + wm + w] = cw;
+    }
+    if (lane == 0) piv[count] = p;
     __syncthreads();
 }
 
@@ -464,11 +553,10 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                 int32_t col = 0;
                 if (lane == 0) col = S.added[i];
                 column_vector(g, S.xbuf, (uint32_t)uni(__shfl(col, 0)), lane);
-                reduce_by(S.xbuf, nullptr, S.pool, wm, S.pool_piv, pool_n, wm, lane);
+                reduce_by(S.xbuf, nullptr, S.pool, wm, S.pool_piv, pool_n, wm, S.hbuf, lane);
                 const int p = lowest_bit(S.xbuf, wm, lane);
                 if (p >= 0) {
-                    for (uint32_t w = lane; w < wm; w += kWave) S.pool[(size_t)pool_n * wm + w] = S.xbuf[w];
-                    if (lane == 0) S.pool_piv[pool_n] = p;
+                    basis_append(S.pool, wm, S.pool_piv, pool_n, S.xbuf, nullptr, p, wm, S.fbuf, lane);
                     pool_n++;
                 }
                 __syncthreads();
@@ -487,7 +575,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                     if (lane == 0) S.xbuf[base / kWave] = mask;
                 }
                 __syncthreads();
-                reduce_by(S.xbuf, nullptr, S.pool, wm, S.pool_piv, pool_n, wm, lane);
+                reduce_by(S.xbuf, nullptr, S.pool, wm, S.pool_piv, pool_n, wm, S.hbuf, lane);
                 const bool valid = lowest_bit(S.xbuf, wm, lane) < 0;
                 if (lane == 0) S.cstate[K] = (valid ? (S.cstate[K] | kValid) : (S.cstate[K] & ~kValid)) & ~kDirty;
                 __syncthreads();
@@ -532,18 +620,13 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
             const uint32_t v = (uint32_t)uni(ald32(&S.sorted[i]));
             column_vector(g, S.xbuf, v, lane);
             for (uint32_t w = lane; w < wm; w += kWave) S.cbuf[w] = 0;
-            reduce_by(S.xbuf, S.cbuf, S.basis2, 2 * (size_t)wm, S.piv2, nb, wm, lane);
+            reduce_by(S.xbuf, S.cbuf, S.basis2, 2 * (size_t)wm, S.piv2, nb, wm, S.hbuf, lane);
             const int p = lowest_bit(S.xbuf, wm, lane);
             if (p >= 0) {
                 if (lane == 0) S.cbuf[nb >> 6] ^= 1ull << (nb & 63);
                 __syncthreads();
-                uint64_t* dst = S.basis2 + (size_t)nb * 2 * wm;
-                for (uint32_t w = lane; w < wm; w += kWave) {
-                    dst[w] = S.xbuf[w];
-                    dst[wm + w] = S.cbuf[w];
-                }
+                basis_append(S.basis2, 2 * (size_t)wm, S.piv2, nb, S.xbuf, S.cbuf, p, wm, S.fbuf, lane);
                 if (lane == 0) {
-                    S.piv2[nb] = p;
                     S.pivcol[nb] = (int32_t)v;
                     if (g.lsd_order) S.pidx[v] = nb;
                 }
@@ -572,7 +655,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
         }
         for (uint32_t w = lane; w < wm; w += kWave) S.cbuf[w] = 0;
         __syncthreads();
-        reduce_by(S.xbuf, S.cbuf, S.basis2, 2 * (size_t)wm, S.piv2, nb, wm, lane);
+        reduce_by(S.xbuf, S.cbuf, S.basis2, 2 * (size_t)wm, S.piv2, nb, wm, S.hbuf, lane);
         if (lane == 0)
             for (int i = 0; i < nb; i++)
                 if ((S.cbuf[i >> 6] >> (i & 63)) & 1ull) {
