@@ -84,6 +84,7 @@ struct LsdMem {
     int32_t* ck;        // n: one cluster's columns, ascending (lane 0 only)
     int32_t* fl;        // n: one cluster's non-pivot ordinals, rank order (lane 0 only)
     uint64_t* reps;     // n x words_m: pivot combination of each non-pivot column
+    int priv_lds;       // the per-check arrays marked "lane 0 only" are in LDS too
 };
 
 __host__ __device__ inline size_t al8(size_t x) { return (x + 7) & ~(size_t)7; }
@@ -113,6 +114,7 @@ __host__ __device__ inline void lsd_layout(const DevGraph& g, unsigned char* lds
     const bool priv_glob = all_lds > kLsdLds;
     auto tp = [&](size_t bytes) { return priv_glob ? tg(bytes) : tl(bytes); };
     LsdMem M;
+    M.priv_lds = priv_glob ? 0 : 1;
     M.best_q = (int64_t*)tp(8 * m);
     M.in_bits = (uint64_t*)tl(8 * wn);
     M.ebits = (uint64_t*)tl(8 * wn);
@@ -396,6 +398,32 @@ __device__ void combination_sweep(const DevGraph& g, const LsdMem& S, int nk, in
     }
 }
 
+// The least (key, column) over the columns of row c not yet held, formed by
+// the whole wavefront (every lane receives it; column INT32_MAX: none).
+template <class KeyF>
+__device__ inline void row_least(const DevGraph& g, const LsdMem& S, uint32_t c, KeyF key, int lane, int64_t& bq,
+                                 int32_t& bv) {
+    bq = INT64_MAX;
+    bv = 0x7fffffff;
+    for (uint32_t p = g.rp[c] + lane; p < g.rp[c + 1]; p += kWave) {
+        const uint32_t v = g.ri[p];
+        if ((S.in_bits[v >> 6] >> (v & 63)) & 1ull) continue;
+        const int64_t kq = key(v);
+        if (key_less(kq, (int32_t)v, bq, bv)) {
+            bq = kq;
+            bv = (int32_t)v;
+        }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const int64_t oq = __shfl_xor(bq, off);
+        const int32_t ov = __shfl_xor(bv, off);
+        if (key_less(oq, ov, bq, bv)) {
+            bq = oq;
+            bv = ov;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int lane = threadIdx.x;
@@ -448,33 +476,90 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
             //    least (key, column) over its checks' rows.  Each row's least
             //    column not yet held is cached across rounds; it changes only
             //    when one of the row's columns joins, and every check of a
-            //    joining column is marked stale in step 3.  Only lane 0's
-            //    copy of a cache entry is used (readfirstlane).
+            //    joining column is marked stale in step 3.
+            // 2. clusters with an empty boundary fail; the others pick, in
+            //    cluster order.
             ncl = uni(__shfl(ncl, 0));
+            int npick = 0;
+            if (S.priv_lds) {
+                // Every per-check array is in LDS: each lane takes its own
+                // checks of the list, the whole wavefront scans each stale
+                // row, and the least (key, column) of a cluster is formed by
+                // LDS atomics, the key first, then the column among the
+                // checks that reach that key.
+                for (int K = lane; K < nk; K += kWave) {
+                    S.best_q[K] = INT64_MAX;
+                    S.best_v[K] = 0x7fffffff;
+                }
+                __syncthreads();
+                for (int kb = 0; kb < ncl; kb += kWave) {
+                    const int i = kb + lane;
+                    int32_t c = 0, R = 0;
+                    bool act = false;
+                    if (i < ncl) {
+                        c = S.clist[i];
+                        R = find_root(S.parent, S.chk_cl[c]);
+                        act = !(S.cstate[R] & (kValid | kFailed));
+                    }
+                    uint64_t stale = __ballot(act && S.row_v[c] == kRowStale);
+                    while (stale) {
+                        const int b = __ffsll((long long)stale) - 1;
+                        stale &= stale - 1;
+                        const uint32_t cc = (uint32_t)uni(__shfl(c, b));
+                        int64_t bq;
+                        int32_t bv;
+                        row_least(g, S, cc, key, lane, bq, bv);
+                        if (lane == 0) {
+                            S.row_q[cc] = bq;
+                            S.row_v[cc] = bv == 0x7fffffff ? kRowEmpty : bv;
+                        }
+                    }
+                    __syncthreads();
+                    if (act && S.row_v[c] >= 0)
+                        __hip_atomic_fetch_min(&S.best_q[R], S.row_q[c], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                __syncthreads();
+                for (int kb = 0; kb < ncl; kb += kWave) {
+                    const int i = kb + lane;
+                    if (i < ncl) {
+                        const int32_t c = S.clist[i];
+                        const int32_t R = find_root(S.parent, S.chk_cl[c]);
+                        const int32_t v = S.row_v[c];
+                        if (!(S.cstate[R] & (kValid | kFailed)) && v >= 0 && S.row_q[c] == S.best_q[R])
+                            __hip_atomic_fetch_min(&S.best_v[R], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+                __syncthreads();
+                for (int kb = 0; kb < nk; kb += kWave) {
+                    const int K = kb + lane;
+                    bool pick = false;
+                    int32_t v = 0;
+                    if (K < nk && S.parent[K] == K && !(S.cstate[K] & (kValid | kFailed))) {
+                        v = S.best_v[K];
+                        pick = v != 0x7fffffff;
+                        if (!pick) S.cstate[K] |= kFailed;
+                    }
+                    const uint64_t pm = __ballot(pick);
+                    if (pick) {
+                        const int at = npick + __popcll(pm & ((1ull << lane) - 1ull));
+                        S.picks[2 * at] = K;
+                        S.picks[2 * at + 1] = v;
+                    }
+                    npick += __popcll(pm);
+                }
+                __syncthreads();
+            } else {
+            // The per-check arrays are in global memory: lane 0 keeps them,
+            // and only lane 0's copy of a cache entry is used (readfirstlane).
             for (int i = 0; i < ncl; i++) {
                 const uint32_t c = (uint32_t)uni(S.clist[i]);
                 const int32_t R = uni(find_root(S.parent, S.chk_cl[c]));
                 if (uni(S.cstate[R]) & (kValid | kFailed)) continue;
                 if (uni(S.row_v[c]) != kRowStale) continue;
-                int64_t bq = INT64_MAX;
-                int32_t bv = 0x7fffffff;
-                for (uint32_t p = g.rp[c] + lane; p < g.rp[c + 1]; p += kWave) {
-                    const uint32_t v = g.ri[p];
-                    if ((S.in_bits[v >> 6] >> (v & 63)) & 1ull) continue;
-                    const int64_t kq = key(v);
-                    if (key_less(kq, (int32_t)v, bq, bv)) {
-                        bq = kq;
-                        bv = (int32_t)v;
-                    }
-                }
-                for (int off = kWave / 2; off > 0; off >>= 1) {
-                    const int64_t oq = __shfl_xor(bq, off);
-                    const int32_t ov = __shfl_xor(bv, off);
-                    if (key_less(oq, ov, bq, bv)) {
-                        bq = oq;
-                        bv = ov;
-                    }
-                }
+                int64_t bq;
+                int32_t bv;
+                row_least(g, S, c, key, lane, bq, bv);
                 if (lane == 0) {
                     S.row_q[c] = bq;
                     S.row_v[c] = bv == 0x7fffffff ? kRowEmpty : bv;
@@ -499,8 +584,6 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                 }
             }
             __syncthreads();
-            // 2. clusters with an empty boundary fail; collect the picks
-            int npick = 0;
             if (lane == 0) {
                 for (int K = 0; K < nk; K++) {
                     if (S.parent[K] != K || (S.cstate[K] & (kValid | kFailed))) continue;
@@ -515,6 +598,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
             }
             npick = uni(__shfl(npick, 0));
             __syncthreads();
+            }
             if (!npick) break;
             rounds++;
             // 3. apply every pick: the column joins, its checks join, clusters
@@ -562,8 +646,14 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                 __syncthreads();
             }
             // 5. validity of every live cluster that changed and has not failed
-            for (int K = 0; K < nk; K++) {
-                if (uni(S.parent[K]) != K || (uni(S.cstate[K]) & (kFailed | kDirty)) != kDirty) continue;
+            //    (found 64 clusters at a time, taken in cluster order)
+            for (int kb = 0; kb < nk; kb += kWave) {
+              const int K0 = kb + lane;
+              uint64_t dm = __ballot(K0 < nk && S.parent[K0] == K0 &&
+                                     (S.cstate[K0] & (kFailed | kDirty)) == kDirty);
+              while (dm) {
+                const int K = kb + __ffsll((long long)dm) - 1;
+                dm &= dm - 1;
                 for (uint32_t base = 0; base < g.m; base += kWave) {
                     const uint32_t c = base + lane;
                     bool in = false;
@@ -579,6 +669,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                 const bool valid = lowest_bit(S.xbuf, wm, lane) < 0;
                 if (lane == 0) S.cstate[K] = (valid ? (S.cstate[K] | kValid) : (S.cstate[K] & ~kValid)) & ~kDirty;
                 __syncthreads();
+              }
             }
         }
 
