@@ -475,8 +475,9 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
             // 1. best boundary column of every invalid, growing cluster: the
             //    least (key, column) over its checks' rows.  Each row's least
             //    column not yet held is cached across rounds; it changes only
-            //    when one of the row's columns joins, and every check of a
-            //    joining column is marked stale in step 3.
+            //    when that column joins, and step 3 marks such rows stale
+            //    (another column of the row joining leaves the least where it
+            //    is).
             // 2. clusters with an empty boundary fail; the others pick, in
             //    cluster order.
             ncl = uni(__shfl(ncl, 0));
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(kWave) void lsd_kernel(DevGraph g, LsdLaunch a) {
                     }
                     for (uint32_t q = g.cp[j]; q < g.cp[j + 1]; q++) {
                         const uint32_t c = g.ci[q];
-                        S.row_v[c] = kRowStale;  // j is held now
+                        if (S.row_v[c] == (int32_t)j) S.row_v[c] = kRowStale;  // j is held now
                         if (S.chk_cl[c] < 0) {
                             S.chk_cl[c] = K;
                             S.clist[ncl++] = (int32_t)c;
