@@ -24,7 +24,8 @@
 // order through wave shuffles, as in a column-by-column decoder, and nothing
 // is contracted into fused multiply-adds, so the FP64 variant reproduces a
 // plain FP64 decoder bit for bit.  The chain of chunks is the critical path:
-// both passes load their slots three chunks ahead.  The residual syndrome
+// both passes load their slots three chunks ahead (six in the latency
+// variant).  The residual syndrome
 // s + H e and the syndrome are bit-packed in LDS, and so are the hard
 // decisions (or, on graphs where that bitmap would cap residency, they sit
 // in global memory: a mask per chunk read with the chunk's slots, and a
@@ -33,7 +34,9 @@
 // Launch variants (none changes a result): the slab in LDS for small
 // graphs; P = 2 or 4 shots of a member per wavefront on the member's
 // schedule recut into chunks of 64 / P edges; several requests on
-// different graphs in one persistent launch (ragged).
+// different graphs in one persistent launch (ragged); and, for a launch
+// whose items all reside at once, the deeper prefetch ring at four waves
+// per SIMD (the latency variant).
 #include <map>
 #include <mutex>
 #include <tuple>
